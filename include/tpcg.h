@@ -1,0 +1,202 @@
+/*
+ * tpcg: spectral two-level preconditioned conjugate gradients for the
+ * SIMP-scaled linear-elastic system K(rho) u = f on one AMD MI355X (gfx950).
+ *
+ * The operation follows Alexandersen & Lazarov, "Robust topology optimisation
+ * of microstructural details without length scale separation - using a
+ * spectral coarse basis preconditioner" (arXiv:1411.3923):
+ *   - K u = f from bilinear (2D, plane stress) or trilinear (3D) elements on a
+ *     uniform mesh of unit elements, C(x) = E(x) C0 with unit reference
+ *     modulus (Sec. 2.1);
+ *   - K_e = (E_min + (E0 - E_min) rho_e^p) K0 (Sec. 2.2, element stiffness);
+ *   - compliance f^T u and its self-adjoint sensitivity (Sec. 2.2, Sec. 4.2);
+ *   - a coarse space from local generalised eigenproblems K_w psi =
+ *     lambda diag(K_w) psi, multiplied by a partition of unity, with the
+ *     Galerkin coarse matrix R_c K R_c^T (Sec. 2.4, Sec. 3.2);
+ *   - that coarse space used inside a Krylov preconditioner for the SPD
+ *     system (Sec. 2.4.2); here the two-level additive Schwarz form
+ *     M^-1 = sum_j R_j^T A_j^-1 R_j + R_c^T K_c^-1 R_c inside PCG;
+ *   - the density filter and smoothed Heaviside projection with their chain
+ *     rule (Sec. 4.3), at several thresholds (Sec. 4.4).
+ *
+ * Index conventions (all arrays):
+ *   node    n = ix + (nelx+1) * (iy + (nely+1) * iz)
+ *   dof       = dim * n + c                         (c: 0 = x, 1 = y, 2 = z)
+ *   element e = ex + nelx * (ey + nely * ez)
+ *   Element nodes run counter-clockwise from (ex, ey); in 3D the bottom face
+ *   (ez) first, then the top face.
+ *
+ * Conventions for every entry point:
+ *   - Array arguments marked "dev" are caller-owned device pointers to
+ *     contiguous float64 data laid out [nsys][...]; the library never frees,
+ *     keeps or reallocates them. "host" arguments are ordinary host memory.
+ *   - Work is enqueued on the stream given to tpcg_build_partition. Entry
+ *     points return after enqueueing, except tpcg_pcg_solve and
+ *     tpcg_build_coarse_basis, which return when their results are complete
+ *     (pcg_solve fills `info` on the host).
+ *   - A handle is not thread-safe; separate handles are independent.
+ *   - Negative status codes mean the outputs are unspecified. TPCG_EHIP is
+ *     sticky: destroy the handle. tpcg_last_error gives a message.
+ */
+#ifndef TPCG_H
+#define TPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpcg_handle tpcg_handle;
+
+typedef enum {
+  TPCG_OK = 0,
+  TPCG_ENOCONV = 1,      /* warning: maxit reached; outputs valid */
+  TPCG_EINVAL = -1,      /* bad argument (size, null pointer, unsupported setting) */
+  TPCG_ENOMEM = -2,      /* device allocation failed */
+  TPCG_EHIP = -3,        /* HIP runtime error (sticky) */
+  TPCG_ENOTSPD = -4,     /* non-positive pivot in a Cholesky factorisation */
+  TPCG_EBREAKDOWN = -5,  /* PCG breakdown: p^T K p <= 0, r^T z <= 0 or NaN */
+  TPCG_ESTATE = -6       /* call order: preconditioner used before it is built */
+} tpcg_status;
+
+typedef enum { TPCG_FP64 = 0, TPCG_MIXED = 1 } tpcg_precision;
+
+/* Problem description. Sizes are in elements. */
+typedef struct {
+  int32_t dim;          /* 2 (Q4 plane stress) or 3 (H8) */
+  int32_t nel[3];       /* elements per axis; nel[2] = 1 in 2D */
+  double E0;            /* solid modulus (paper: E_max = 1) */
+  double Emin;          /* void modulus (paper: 1e-9) */
+  double penal;         /* SIMP exponent p */
+  double nu;            /* Poisson ratio, < 0.5 */
+  int32_t sub;          /* subdomain (unit cell) edge s in elements; nel % sub == 0 */
+  int32_t overlap;      /* element layers of overlap; only 1 is supported */
+  int32_t ncoarse;      /* k: coarse vectors per subdomain */
+  int32_t nsys_max;     /* systems (realisations) solved together, 1..4 */
+  int32_t precision;    /* tpcg_precision */
+  int32_t eig_iters;    /* subspace iterations for the local eigenproblems (0: default 40) */
+  int32_t eig_extra;    /* extra (guard) vectors in the subspace (0: default k, capped at 16 total) */
+  double eig_shift;     /* shift sigma of the shift-invert eigensolver (0: default 1e-5) */
+} tpcg_problem;
+
+/* Per-system result of tpcg_pcg_solve. */
+typedef struct {
+  int32_t iters;        /* PCG iterations taken */
+  int32_t status;       /* tpcg_status of this system */
+  double relres;        /* ||r_k||_2 / ||P f||_2 of the recursive residual */
+  double true_relres;   /* ||P (f - K u)||_2 / ||P f||_2 recomputed at exit */
+  double seconds;       /* wall time of the whole batched solve */
+} tpcg_info;
+
+/*
+ * Create a handle for the structured mesh in `prob` with the supports in
+ * `fixed_mask` (host, uint8 [n_dof], nonzero = displacement prescribed zero,
+ * Sec. 2.1 Dirichlet parts per component). Builds the subdomain partition:
+ * subdomain j is the j-th unit cell of sub^dim elements (Sec. 2.4: the coarse
+ * cells are the unit cells); its unknowns are the nodes of the closed cell,
+ * i.e. the cell grown by one element layer with zero displacement on the
+ * grown boundary. Subdomains are numbered x fastest. `stream` is a
+ * hipStream_t (NULL: the default stream). Returns TPCG_EINVAL for
+ * nel % sub != 0, dim not in {2,3}, overlap != 1, ncoarse < 1 or larger
+ * than the subdomain's DOFs, nsys_max not in 1..4, or subdomain blocks too
+ * large for the on-chip factor kernels.
+ */
+int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask,
+                         void* stream, tpcg_handle** out);
+
+/* Device bytes a handle for `prob` with `nsys` systems allocates (admission). */
+size_t tpcg_workspace_bytes(const tpcg_problem* prob, int32_t nsys);
+
+/*
+ * Build the two-level preconditioner for the physical densities rho_phys
+ * (dev [nsys][n_el]). The spectral basis (Sec. 2.4, discrete eigenproblem
+ * weighted by diag(K_j^N), Sec. 3.2) is computed once, from system `rep`
+ * (the robust formulation uses the dilated realisation, Sec. 5.3): for every
+ * subdomain the k smallest eigenpairs of the Neumann matrix of the cell's own
+ * elements (physical supports kept), times the partition of unity
+ * chi_j(n) = 1/(number of subdomains containing n). For every system it then
+ * factors the local Dirichlet matrices A_j (principal submatrices of K) and the
+ * coarse matrix K_c = Phi^T K Phi (coarse projection equation). Blocks until
+ * done. Returns TPCG_ENOTSPD if a factorisation meets a non-positive pivot.
+ */
+int tpcg_build_coarse_basis(tpcg_handle* h, const double* rho_phys, int32_t nsys, int32_t rep);
+
+/*
+ * y = P K(rho) P x with K assembled from E_e = E_min + (E0 - E_min) rho_e^p
+ * times the unit element matrix (Sec. 2.2), P zeroing the supported DOFs.
+ * rho_phys dev [nsys][n_el], x and y dev [nsys][n_dof]. Matrix-free.
+ */
+int tpcg_apply_K(tpcg_handle* h, const double* rho_phys, const double* x, double* y, int32_t nsys);
+
+/*
+ * z = M^-1 r for the preconditioner built by tpcg_build_coarse_basis
+ * (Sec. 2.4.2 with the two-level additive Schwarz form). r and z dev
+ * [nsys][n_dof]; nsys must equal the nsys of the build. TPCG_ESTATE if the
+ * preconditioner has not been built.
+ */
+int tpcg_apply_precond(tpcg_handle* h, const double* r, double* z, int32_t nsys);
+
+/*
+ * Solve K(rho_s) u_s = P f_s for all systems with PCG preconditioned by
+ * M^-1 (Sec. 2.4.2). u (dev [nsys][n_dof]) holds the initial guess on entry
+ * (zeros: cold start; the previous design's solution: warm start, Sec. 5.2)
+ * and the solution on exit. Stops system s when ||r||_2 <= rtol ||P f_s||_2
+ * or after maxit iterations. The preconditioner may be stale (built for an
+ * older rho); the solution is still that of the new rho. info: host [nsys].
+ * Returns the worst status over the systems.
+ */
+int tpcg_pcg_solve(tpcg_handle* h, const double* rho_phys, const double* f, double* u,
+                   int32_t nsys, double rtol, int32_t maxit, tpcg_info* info);
+
+/*
+ * Compliance c_s = f_s^T u_s (dev [nsys]) and, if dc is not NULL, the element
+ * sensitivities dc/drho_e = -p (E0 - E_min) rho_e^(p-1) u_e^T K0 u_e
+ * (dev [nsys][n_el]) (Sec. 4.2: self-adjoint, no adjoint solve).
+ */
+int tpcg_compliance_and_sensitivity(tpcg_handle* h, const double* rho_phys, const double* u,
+                                    const double* f, int32_t nsys, double* c, double* dc);
+
+/*
+ * Density filter and smoothed Heaviside projection (Sec. 4.3):
+ * rho_tilde = W rho with hat weights max(0, rmin - distance between element
+ * centres), truncated at the mesh boundary and renormalised (rmin <= 1: no
+ * filtering); rho_phys[s] = H(rho_tilde; beta, eta[s]) for each threshold
+ * (Sec. 4.4). rho dev [n_el], eta host [nsys], rho_tilde dev [n_el],
+ * rho_phys dev [nsys][n_el].
+ */
+int tpcg_filter_project(tpcg_handle* h, const double* rho, double rmin, double beta,
+                        const double* eta, int32_t nsys, double* rho_tilde, double* rho_phys);
+
+/*
+ * Chain rule through projection and filter (Sec. 4.3):
+ * dc_drho[s][i] = sum_e dc_drho_phys[s][e] H'(rho_tilde_e; beta, eta[s]) W[e][i].
+ * rho_tilde dev [n_el], dc_drho_phys and dc_drho dev [nsys][n_el], eta host [nsys].
+ */
+int tpcg_filter_project_adjoint(tpcg_handle* h, const double* rho_tilde, double rmin, double beta,
+                                const double* eta, int32_t nsys, const double* dc_drho_phys,
+                                double* dc_drho);
+
+/*
+ * Copy the coarse basis out (diagnostics and tests): phi dev
+ * [n_sub][n_loc][k] (chi-weighted basis vectors on the subdomain's closed-cell
+ * DOFs, node x fastest then component; may be NULL), lambda host [n_sub][k]
+ * Ritz values and resid host [n_sub][k] residual norms ||S x - lambda x||_2
+ * of the diagonally scaled problem (either may be NULL).
+ */
+int tpcg_export_coarse_basis(tpcg_handle* h, double* phi, double* lambda, double* resid);
+
+/* Sizes of the handle's structures: out[0] n_dof, out[1] n_el, out[2] n_sub,
+ * out[3] n_loc, out[4] k, out[5] local block size, out[6] local block count,
+ * out[7] coarse block size, out[8] coarse block count. */
+int tpcg_query(const tpcg_handle* h, int64_t* out9);
+
+const char* tpcg_last_error(const tpcg_handle* h);
+void tpcg_destroy(tpcg_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPCG_H */

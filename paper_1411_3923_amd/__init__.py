@@ -1,0 +1,224 @@
+"""tpcg: spectral two-level PCG for SIMP elasticity on AMD MI355X.
+
+Thin ctypes binding of libtpcg.so (C-ABI declared in include/tpcg.h). The
+binding only marshals arguments: every step of the computation runs in the
+library's HIP kernels. PyTorch provides device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Problem", "Handle", "TpcgError", "load_library", "FP64", "MIXED"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libtpcg.so")
+_lib = None
+
+FP64 = 0
+MIXED = 1
+
+STATUS = {0: "OK", 1: "ENOCONV", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
+          -5: "EBREAKDOWN", -6: "ESTATE"}
+
+
+class TpcgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tpcg error {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    """Mirror of tpcg_problem."""
+    _fields_ = [("dim", ctypes.c_int32), ("nel", ctypes.c_int32 * 3),
+                ("E0", ctypes.c_double), ("Emin", ctypes.c_double),
+                ("penal", ctypes.c_double), ("nu", ctypes.c_double),
+                ("sub", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("ncoarse", ctypes.c_int32), ("nsys_max", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("eig_iters", ctypes.c_int32),
+                ("eig_extra", ctypes.c_int32), ("eig_shift", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    """Mirror of tpcg_info."""
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("true_relres", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_basis",
+           "tpcg_apply_K", "tpcg_apply_precond", "tpcg_pcg_solve",
+           "tpcg_compliance_and_sensitivity", "tpcg_filter_project",
+           "tpcg_filter_project_adjoint", "tpcg_export_coarse_basis", "tpcg_query",
+           "tpcg_last_error", "tpcg_destroy"]
+
+
+def load_library(path: str | None = None):
+    """Load libtpcg.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with `python -m paper_1411_3923_amd.build`")
+    lib = ctypes.CDLL(p)
+    P, I32, D, V = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    lib.tpcg_build_partition.argtypes = [ctypes.POINTER(Problem), P, V, ctypes.POINTER(P)]
+    lib.tpcg_workspace_bytes.argtypes = [ctypes.POINTER(Problem), I32]
+    lib.tpcg_workspace_bytes.restype = ctypes.c_size_t
+    lib.tpcg_build_coarse_basis.argtypes = [P, P, I32, I32]
+    lib.tpcg_apply_K.argtypes = [P, P, P, P, I32]
+    lib.tpcg_apply_precond.argtypes = [P, P, P, I32]
+    lib.tpcg_pcg_solve.argtypes = [P, P, P, P, I32, D, I32, ctypes.POINTER(Info)]
+    lib.tpcg_compliance_and_sensitivity.argtypes = [P, P, P, P, I32, P, P]
+    lib.tpcg_filter_project.argtypes = [P, P, D, D, ctypes.POINTER(D), I32, P, P]
+    lib.tpcg_filter_project_adjoint.argtypes = [P, P, D, D, ctypes.POINTER(D), I32, P, P]
+    lib.tpcg_export_coarse_basis.argtypes = [P, P, P, P]
+    lib.tpcg_query.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.tpcg_last_error.argtypes = [P]
+    lib.tpcg_last_error.restype = ctypes.c_char_p
+    lib.tpcg_destroy.argtypes = [P]
+    lib.tpcg_destroy.restype = None
+    for name in EXPORTS:
+        getattr(lib, name)
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.0, nu=0.3,
+                 precision=FP64, eig_iters=0, eig_extra=0, eig_shift=0.0) -> Problem:
+    pr = Problem()
+    pr.dim = dim
+    nel = tuple(nel) + (1,) * (3 - len(nel))
+    pr.nel[0], pr.nel[1], pr.nel[2] = nel[0], nel[1], nel[2] if dim == 3 else 1
+    pr.E0, pr.Emin, pr.penal, pr.nu = E0, Emin, penal, nu
+    pr.sub, pr.overlap, pr.ncoarse, pr.nsys_max = sub, 1, ncoarse, nsys_max
+    pr.precision, pr.eig_iters, pr.eig_extra, pr.eig_shift = precision, eig_iters, eig_extra, eig_shift
+    return pr
+
+
+def _ptr(t, dtype=None, n=None):
+    """Device pointer of a contiguous CUDA tensor (argument checks only)."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """Owns a tpcg_handle: partition, preconditioner and workspace on one GPU."""
+
+    def __init__(self, problem: Problem, fixed_mask, stream=None):
+        import numpy as np
+        import torch
+        self.lib = load_library()
+        self.problem = problem
+        fm = np.ascontiguousarray(np.asarray(fixed_mask, dtype=np.uint8))
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = self.lib.tpcg_build_partition(ctypes.byref(problem), fm.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise TpcgError(rc, "tpcg_build_partition failed (see stderr)")
+        self.h = h
+        q = (ctypes.c_int64 * 9)()
+        self.lib.tpcg_query(self.h, q)
+        (self.n_dof, self.n_el, self.n_sub, self.n_loc, self.k, self.nb, self.nblk,
+         self.nbc, self.nblkc) = list(q)
+
+    def _check(self, rc, allow_warn=False):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise TpcgError(rc, self.lib.tpcg_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tpcg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_coarse_basis(self, rho_phys, rep=0):
+        import torch
+        nsys = rho_phys.numel() // self.n_el
+        return self._check(self.lib.tpcg_build_coarse_basis(
+            self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el), nsys, rep))
+
+    def apply_K(self, rho_phys, x, y):
+        import torch
+        nsys = x.numel() // self.n_dof
+        self._check(self.lib.tpcg_apply_K(self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el),
+                                          _ptr(x, torch.float64, nsys * self.n_dof),
+                                          _ptr(y, torch.float64, nsys * self.n_dof), nsys))
+        return y
+
+    def apply_precond(self, r, z):
+        import torch
+        nsys = r.numel() // self.n_dof
+        self._check(self.lib.tpcg_apply_precond(self.h, _ptr(r, torch.float64, nsys * self.n_dof),
+                                                _ptr(z, torch.float64, nsys * self.n_dof), nsys))
+        return z
+
+    def pcg_solve(self, rho_phys, f, u, rtol=1e-8, maxit=1000):
+        import torch
+        nsys = f.numel() // self.n_dof
+        info = (Info * nsys)()
+        rc = self.lib.tpcg_pcg_solve(self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el),
+                                     _ptr(f, torch.float64, nsys * self.n_dof),
+                                     _ptr(u, torch.float64, nsys * self.n_dof), nsys, rtol, maxit,
+                                     info)
+        self._check(rc, allow_warn=True)
+        return [dict(iters=i.iters, status=i.status, relres=i.relres,
+                     true_relres=i.true_relres, seconds=i.seconds) for i in info]
+
+    def compliance_and_sensitivity(self, rho_phys, u, f, c, dc=None):
+        import torch
+        nsys = u.numel() // self.n_dof
+        self._check(self.lib.tpcg_compliance_and_sensitivity(
+            self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el),
+            _ptr(u, torch.float64, nsys * self.n_dof), _ptr(f, torch.float64, nsys * self.n_dof),
+            nsys, _ptr(c, torch.float64, nsys),
+            _ptr(dc, torch.float64, nsys * self.n_el) if dc is not None else None))
+        return c, dc
+
+    def filter_project(self, rho, rmin, beta, etas, rho_tilde, rho_phys):
+        import torch
+        nsys = len(etas)
+        eta = (ctypes.c_double * nsys)(*etas)
+        self._check(self.lib.tpcg_filter_project(
+            self.h, _ptr(rho, torch.float64, self.n_el), rmin, beta, eta, nsys,
+            _ptr(rho_tilde, torch.float64, self.n_el), _ptr(rho_phys, torch.float64, nsys * self.n_el)))
+        return rho_tilde, rho_phys
+
+    def filter_project_adjoint(self, rho_tilde, rmin, beta, etas, dc_drho_phys, dc_drho):
+        import torch
+        nsys = len(etas)
+        eta = (ctypes.c_double * nsys)(*etas)
+        self._check(self.lib.tpcg_filter_project_adjoint(
+            self.h, _ptr(rho_tilde, torch.float64, self.n_el), rmin, beta, eta, nsys,
+            _ptr(dc_drho_phys, torch.float64, nsys * self.n_el),
+            _ptr(dc_drho, torch.float64, nsys * self.n_el)))
+        return dc_drho
+
+    def export_coarse_basis(self):
+        import numpy as np
+        import torch
+        phi = torch.empty(self.n_sub * self.n_loc * self.k, dtype=torch.float64, device="cuda")
+        lam = np.zeros((self.n_sub, self.k))
+        res = np.zeros((self.n_sub, self.k))
+        self._check(self.lib.tpcg_export_coarse_basis(
+            self.h, _ptr(phi), lam.ctypes.data_as(ctypes.c_void_p), res.ctypes.data_as(ctypes.c_void_p)))
+        return phi.view(self.n_sub, self.n_loc, self.k), lam, res

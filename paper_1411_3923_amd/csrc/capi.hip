@@ -1,0 +1,461 @@
+// C-ABI entry points: handle lifecycle, argument checks and the batched PCG
+// driver (Sec. 2.4.2: PCG on the SPD system with the two-level
+// preconditioner; the robust formulation's realisations solved together,
+// Sec. 4.4).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "btri.h"
+
+using namespace tpcg;
+
+namespace {
+
+constexpr int kPollEvery = 4;   // PCG iterations between convergence polls
+
+int fail(tpcg_handle* hh, int code, const std::string& msg) {
+  if (hh) reinterpret_cast<Handle*>(hh)->err = msg;
+  return code;
+}
+
+Handle* H(tpcg_handle* h) { return reinterpret_cast<Handle*>(h); }
+const Handle* H(const tpcg_handle* h) { return reinterpret_cast<const Handle*>(h); }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Derive the geometry; returns an error message or "" when the problem is usable.
+std::string make_geometry(const tpcg_problem& pr, Geometry& g) {
+  if (pr.dim != 2 && pr.dim != 3) return "dim must be 2 or 3";
+  const int d = pr.dim;
+  std::memset(&g, 0, sizeof(g));
+  g.dim = d;
+  g.nelx = pr.nel[0];
+  g.nely = pr.nel[1];
+  g.nelz = d == 3 ? pr.nel[2] : 1;
+  if (g.nelx < 1 || g.nely < 1 || g.nelz < 1) return "element counts must be positive";
+  g.s = pr.sub;
+  if (g.s < 1) return "sub must be positive";
+  if (g.nelx % g.s || g.nely % g.s || (d == 3 && g.nelz % g.s))
+    return "element counts must be multiples of sub";
+  if (pr.overlap != 1) return "only overlap = 1 is supported";
+  if (!(pr.nu > -1.0 && pr.nu < 0.5)) return "nu must lie in (-1, 0.5)";
+  if (!(pr.Emin > 0.0) || !(pr.E0 >= pr.Emin)) return "need 0 < Emin <= E0";
+  if (!(pr.penal >= 1.0)) return "penal must be >= 1";
+  g.nnx = g.nelx + 1;
+  g.nny = g.nely + 1;
+  g.nnz = d == 3 ? g.nelz + 1 : 1;
+  g.nnodes = (int64_t)g.nnx * g.nny * g.nnz;
+  g.ndof = d * g.nnodes;
+  g.nel = (int64_t)g.nelx * g.nely * g.nelz;
+  g.gx = g.nelx / g.s;
+  g.gy = g.nely / g.s;
+  g.gz = d == 3 ? g.nelz / g.s : 1;
+  g.nsub = g.gx * g.gy * g.gz;
+  g.bn = g.s + 1;
+  g.nbox = d == 3 ? g.bn * g.bn * g.bn : g.bn * g.bn;
+  g.nloc = d * g.nbox;
+  g.nb = d == 3 ? d * g.bn * g.bn : d * g.bn;
+  g.nblk = g.bn;
+  g.k = pr.ncoarse;
+  if (g.k < 1 || g.k > kMaxK) return "ncoarse must lie in 1..16";
+  if (g.k > g.nloc) return "ncoarse exceeds the subdomain's DOFs";
+  // coarse blocks along the axis with the most subdomains
+  const int cnt[3] = {g.gx, g.gy, g.gz};
+  g.caxis = 0;
+  for (int a = 1; a < d; ++a)
+    if (cnt[a] > cnt[g.caxis]) g.caxis = a;
+  g.nblkc = cnt[g.caxis];
+  g.nbc = g.k * (g.nsub / g.nblkc);
+  g.nt = g.nsub * g.k;
+  g.ebn = g.s + 3;
+  g.nebox = d == 3 ? g.ebn * g.ebn * g.ebn : g.ebn * g.ebn;
+  g.ndpe = d == 3 ? 24 : 8;
+  return "";
+}
+
+// Limits of the block-tridiagonal factor kernels (checked when the
+// preconditioner is built; the matrix-free operator has none).
+std::string precond_limits(const Geometry& g) {
+  if (g.nb > kMaxNb || (g.nb & 1))
+    return "subdomain node rows/layers give blocks larger than 96 or of odd size";
+  if (g.nbc > kMaxNb || (g.nbc & 1))
+    return "coarse blocks are larger than 96 or of odd size";
+  return "";
+}
+
+struct Sizes {
+  size_t persistent, setup_peak;
+};
+
+Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
+  const int mixed = pr.precision == TPCG_MIXED;
+  const int msub = std::min(kMaxSub, g.k + (pr.eig_extra > 0 ? pr.eig_extra : g.k));
+  const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
+  const size_t cfsz = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+  const size_t ts = mixed ? 4 : 8;
+  size_t p = 0;
+  p += g.ndof + sizeof(double) * g.ndpe * g.ndpe;
+  p += sizeof(double) * (size_t)g.nsub * g.nloc * g.k * (mixed ? 1.5 : 1.0);
+  p += 2 * sizeof(double) * (size_t)g.nsub * msub;
+  p += ts * nsys * g.nsub * fsz;
+  p += sizeof(double) * nsys * cfsz;
+  p += 4 * sizeof(double) * nsys * g.ndof;
+  p += ts * nsys * (size_t)g.nsub * g.nloc;
+  p += 2 * sizeof(double) * nsys * (size_t)g.nt;
+  p += sizeof(double) * kNumPartSlots * kMaxSys * kMaxParts + 4096;
+  size_t eig = sizeof(double) * ((size_t)g.nsub * fsz + (size_t)g.nsub * g.nloc * (1 + 2 * msub));
+  size_t coarse = sizeof(double) * (size_t)g.nsub * g.nebox * g.dim * g.k;
+  size_t local = mixed ? sizeof(double) * g.nsub * fsz : 0;
+  return {p, std::max(eig, std::max(coarse, local))};
+}
+
+template <typename T>
+int alloc(T*& p, size_t n) {
+  void* v = nullptr;
+  if (hipMalloc(&v, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return TPCG_ENOMEM;
+  p = reinterpret_cast<T*>(v);
+  return TPCG_OK;
+}
+
+void release(Handle* h) {
+  if (!h) return;
+  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phi32, h->lam, h->eres, h->lfac, h->cfac,
+                  h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts, h->istate,
+                  h->dflag};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  if (h->hpoll) hipHostFree(h->hpoll);
+  for (auto& e : h->ev)
+    if (e) hipEventDestroy(e);
+  if (h->t0) hipEventDestroy(h->t0);
+  if (h->t1) hipEventDestroy(h->t1);
+}
+
+int check_hip(Handle* h, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    h->sticky = 1;
+    h->err = std::string(where) + ": " + hipGetErrorString(e);
+    return TPCG_EHIP;
+  }
+  return TPCG_OK;
+}
+
+Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int enabled) {
+  Gate g;
+  g.parts = h->parts;
+  g.istate = h->istate;
+  g.np = parts_for(h->g.nnodes);
+  g.rr_slot = rr_slot;
+  g.it = it;
+  g.maxit = maxit;
+  g.tol2 = tol2;
+  g.enabled = enabled;
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, void* stream,
+                         tpcg_handle** out) {
+  if (!prob || !fixed_mask || !out) return TPCG_EINVAL;
+  *out = nullptr;
+  Geometry g;
+  std::string msg = make_geometry(*prob, g);
+  if (!msg.empty()) {
+    fprintf(stderr, "tpcg_build_partition: %s\n", msg.c_str());
+    return TPCG_EINVAL;
+  }
+  if (prob->nsys_max < 1 || prob->nsys_max > kMaxSys) {
+    fprintf(stderr, "tpcg_build_partition: nsys_max must lie in 1..%d\n", kMaxSys);
+    return TPCG_EINVAL;
+  }
+  if (prob->precision != TPCG_FP64 && prob->precision != TPCG_MIXED) return TPCG_EINVAL;
+  Handle* h = new (std::nothrow) Handle();
+  if (!h) return TPCG_ENOMEM;
+  h->prob = *prob;
+  h->g = g;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  h->mixed = prob->precision == TPCG_MIXED;
+  h->msub = std::min(kMaxSub, g.k + (prob->eig_extra > 0 ? prob->eig_extra : g.k));
+  if (h->msub > g.nloc) h->msub = g.nloc;
+  const int ns = prob->nsys_max;
+  int e = TPCG_OK;
+  e |= alloc(h->fixed, g.ndof);
+  e |= alloc(h->K0, (size_t)g.ndpe * g.ndpe);
+  e |= alloc(h->r, ns * (size_t)g.ndof);
+  e |= alloc(h->z, ns * (size_t)g.ndof);
+  e |= alloc(h->p, ns * (size_t)g.ndof);
+  e |= alloc(h->q, ns * (size_t)g.ndof);
+  e |= alloc(h->parts, (size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys);
+  e |= alloc(h->istate, (size_t)kNumState * kMaxSys);
+  e |= alloc(h->dflag, 4);
+  if (e != TPCG_OK) {
+    release(h);
+    delete h;
+    fprintf(stderr, "tpcg_build_partition: out of device memory\n");
+    return TPCG_ENOMEM;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), 2 * kMaxSys * sizeof(int)) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&h->t0) != hipSuccess || hipEventCreate(&h->t1) != hipSuccess) {
+    release(h);
+    delete h;
+    return TPCG_EHIP;
+  }
+  std::vector<double> K0((size_t)g.ndpe * g.ndpe);
+  element_stiffness(g.dim, prob->nu, K0.data());
+  hipMemcpy(h->K0, K0.data(), sizeof(double) * K0.size(), hipMemcpyHostToDevice);
+  hipMemcpy(h->fixed, fixed_mask, g.ndof, hipMemcpyHostToDevice);
+  hipMemset(h->istate, 0, sizeof(int) * kNumState * kMaxSys);
+  hipMemset(h->parts, 0, sizeof(double) * ((size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys));
+  if (check_hip(h, "tpcg_build_partition") != TPCG_OK) {
+    fprintf(stderr, "%s\n", h->err.c_str());
+    release(h);
+    delete h;
+    return TPCG_EHIP;
+  }
+  *out = reinterpret_cast<tpcg_handle*>(h);
+  return TPCG_OK;
+}
+
+size_t tpcg_workspace_bytes(const tpcg_problem* prob, int32_t nsys) {
+  if (!prob) return 0;
+  Geometry g;
+  if (!make_geometry(*prob, g).empty()) return 0;
+  Sizes s = sizes(*prob, g, nsys);
+  return s.persistent + s.setup_peak;
+}
+
+int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsys, int32_t rep) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!rho_phys) return fail(hh, TPCG_EINVAL, "rho_phys is NULL");
+  if (nsys < 1 || nsys > h->prob.nsys_max) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  if (rep < 0 || rep >= nsys) return fail(hh, TPCG_EINVAL, "rep out of range");
+  const Geometry& g = h->g;
+  std::string lim = precond_limits(g);
+  if (!lim.empty()) return fail(hh, TPCG_EINVAL, lim);
+  h->basis_ready = 0;
+  if (!h->phi) {
+    // preconditioner storage for nsys_max systems, allocated on first build
+    const int ns = h->prob.nsys_max;
+    const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
+    const size_t cfsz = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+    const size_t ts = h->mixed ? 4 : 8;
+    int e = TPCG_OK;
+    e |= alloc(h->phi, (size_t)g.nsub * g.nloc * g.k);
+    if (h->mixed) e |= alloc(h->phi32, (size_t)g.nsub * g.nloc * g.k);
+    e |= alloc(h->lam, (size_t)g.nsub * h->msub);
+    e |= alloc(h->eres, (size_t)g.nsub * h->msub);
+    unsigned char* lf = nullptr;
+    e |= alloc(lf, ts * ns * g.nsub * fsz);
+    h->lfac = lf;
+    e |= alloc(h->cfac, ns * cfsz);
+    unsigned char* zl = nullptr;
+    e |= alloc(zl, ts * ns * (size_t)g.nsub * g.nloc);
+    h->zloc = zl;
+    e |= alloc(h->yc, ns * (size_t)g.nt);
+    e |= alloc(h->xc, ns * (size_t)g.nt);
+    if (e != TPCG_OK) return fail(hh, TPCG_ENOMEM, "out of device memory for the preconditioner");
+  }
+  return build_preconditioner(*h, rho_phys, nsys, rep);
+}
+
+int tpcg_apply_K(tpcg_handle* hh, const double* rho_phys, const double* x, double* y, int32_t nsys) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!rho_phys || !x || !y) return fail(hh, TPCG_EINVAL, "NULL array");
+  if (!aligned16(x) || !aligned16(y)) return fail(hh, TPCG_EINVAL, "vectors must be 16-byte aligned");
+  if (nsys < 1 || nsys > h->prob.nsys_max) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  Gate nog = make_gate(h, kPartRR0, 0, 1, 0.0, 0);
+  launch_apply_K(*h, rho_phys, x, y, nsys, -1, nog, h->stream);
+  return check_hip(h, "tpcg_apply_K");
+}
+
+int tpcg_apply_precond(tpcg_handle* hh, const double* r, double* z, int32_t nsys) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
+  if (!r || !z) return fail(hh, TPCG_EINVAL, "NULL array");
+  if (nsys != h->nsys_built) return fail(hh, TPCG_EINVAL, "nsys differs from the build");
+  Gate nog = make_gate(h, kPartRR0, 0, 1, 0.0, 0);
+  launch_precond(*h, r, z, nsys, nog, kPartAux, kPartAux, 0, h->stream);
+  return check_hip(h, "tpcg_apply_precond");
+}
+
+int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, double* u,
+                   int32_t nsys, double rtol, int32_t maxit, tpcg_info* info) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
+  if (!rho_phys || !f || !u || !info) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (!aligned16(f) || !aligned16(u)) return fail(hh, TPCG_EINVAL, "vectors must be 16-byte aligned");
+  if (nsys != h->nsys_built) return fail(hh, TPCG_EINVAL, "nsys differs from the build");
+  if (!(rtol > 0.0) || maxit < 0) return fail(hh, TPCG_EINVAL, "rtol must be > 0 and maxit >= 0");
+  hipStream_t st = h->stream;
+  const double tol2 = rtol * rtol;
+  const int flexible = h->mixed;
+  const auto wall0 = std::chrono::steady_clock::now();
+  hipEventRecord(h->t0, st);
+  // r0 = P (f - K u0); z0 = M^-1 r0; p0 = z0
+  Gate g0 = make_gate(h, kPartRR0, 0, maxit, tol2, 1);
+  Gate nog = g0;
+  nog.enabled = 0;
+  launch_apply_K(*h, rho_phys, u, h->q, nsys, -1, nog, st);
+  launch_residual_init(*h, f, u, h->q, nsys, st);
+  launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, kPartRZ0, flexible, st);
+  launch_update_p(*h, nsys, g0, flexible, 1, st);
+  int it = 0;
+  int chunk = 0;
+  bool done = maxit == 0;
+  while (!done) {
+    for (int c = 0; c < kPollEvery && it < maxit; ++c, ++it) {
+      const int rr_now = (it & 1) ? kPartRR1 : kPartRR0;
+      const int rr_next = (it & 1) ? kPartRR0 : kPartRR1;
+      const int rz_next = (it & 1) ? kPartRZ0 : kPartRZ1;
+      Gate gi = make_gate(h, rr_now, it, maxit, tol2, 1);
+      Gate gn = make_gate(h, rr_next, it + 1, maxit, tol2, 1);
+      launch_apply_K(*h, rho_phys, h->p, h->q, nsys, kPartPQ, gi, st);
+      launch_update_xr(*h, u, nsys, gi, st);
+      launch_precond(*h, h->r, h->z, nsys, gn, rz_next, rz_next, flexible, st);
+      launch_update_p(*h, nsys, gn, flexible, 0, st);
+    }
+    const int slot = chunk & 1;
+    Gate gp = make_gate(h, (it & 1) ? kPartRR1 : kPartRR0, it, maxit, tol2, 1);
+    launch_poll(*h, nsys, gp, st);
+    hipMemcpyAsync(h->hpoll + slot * kMaxSys, h->istate + kStPoll * kMaxSys, sizeof(int) * kMaxSys,
+                   hipMemcpyDeviceToHost, st);
+    hipEventRecord(h->ev[slot], st);
+    if (it >= maxit) break;
+    if (chunk > 0) {
+      const int prev = slot ^ 1;
+      if (hipEventSynchronize(h->ev[prev]) != hipSuccess) break;
+      int running = 0;
+      for (int s = 0; s < nsys; ++s) running |= h->hpoll[prev * kMaxSys + s];
+      if (!running) done = true;
+    }
+    ++chunk;
+  }
+  // summary: true residual with a fresh K u
+  Gate gf = make_gate(h, (it & 1) ? kPartRR1 : kPartRR0, it, maxit, tol2, 1);
+  launch_apply_K(*h, rho_phys, u, h->q, nsys, -1, nog, st);
+  double* dout = h->parts + (size_t)kNumPartSlots * kMaxSys * kMaxParts;   // 4 * kMaxSys spare
+  launch_summary(*h, f, nsys, gf, dout, st);
+  hipEventRecord(h->t1, st);
+  double hout[4 * kMaxSys];
+  hipMemcpyAsync(hout, dout, sizeof(double) * 4 * nsys, hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  int rc = check_hip(h, "tpcg_pcg_solve");
+  if (rc != TPCG_OK) return rc;
+  float ms = 0.0f;
+  hipEventElapsedTime(&ms, h->t0, h->t1);
+  (void)wall0;
+  int worst = TPCG_OK;
+  for (int s = 0; s < nsys; ++s) {
+    info[s].iters = (int)hout[4 * s + 0];
+    info[s].status = (int)hout[4 * s + 1];
+    info[s].relres = hout[4 * s + 2];
+    info[s].true_relres = hout[4 * s + 3];
+    info[s].seconds = ms * 1e-3;
+    const int st_s = info[s].status;
+    if (st_s < 0 && (worst >= 0 || st_s < worst)) worst = st_s;
+    else if (worst == TPCG_OK && st_s > 0) worst = st_s;
+  }
+  if (worst == TPCG_EBREAKDOWN) h->err = "PCG breakdown (p^T K p <= 0, r^T z <= 0 or NaN)";
+  else if (worst == TPCG_ENOCONV) h->err = "maxit reached before rtol";
+  return worst;
+}
+
+int tpcg_compliance_and_sensitivity(tpcg_handle* hh, const double* rho_phys, const double* u,
+                                    const double* f, int32_t nsys, double* c, double* dc) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!rho_phys || !u || !f || !c) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (nsys < 1 || nsys > h->prob.nsys_max) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  launch_compliance_sens(*h, rho_phys, u, f, nsys, c, dc, h->stream);
+  return check_hip(h, "tpcg_compliance_and_sensitivity");
+}
+
+int tpcg_filter_project(tpcg_handle* hh, const double* rho, double rmin, double beta,
+                        const double* eta, int32_t nsys, double* rho_tilde, double* rho_phys) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!rho || !eta || !rho_tilde || !rho_phys) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (nsys < 1 || nsys > kMaxSys) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  if (!(beta > 0.0)) return fail(hh, TPCG_EINVAL, "beta must be > 0");
+  if (rmin > 8.0) return fail(hh, TPCG_EINVAL, "rmin above 8 elements is not supported");
+  launch_filter_project(*h, rho, rmin, beta, eta, nsys, rho_tilde, rho_phys, h->stream);
+  return check_hip(h, "tpcg_filter_project");
+}
+
+int tpcg_filter_project_adjoint(tpcg_handle* hh, const double* rho_tilde, double rmin, double beta,
+                                const double* eta, int32_t nsys, const double* dc_drho_phys,
+                                double* dc_drho) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!rho_tilde || !eta || !dc_drho_phys || !dc_drho) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (nsys < 1 || nsys > kMaxSys) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  if (!(beta > 0.0)) return fail(hh, TPCG_EINVAL, "beta must be > 0");
+  if (rmin > 8.0) return fail(hh, TPCG_EINVAL, "rmin above 8 elements is not supported");
+  launch_filter_project_adjoint(*h, rho_tilde, rmin, beta, eta, nsys, dc_drho_phys, dc_drho,
+                                h->stream);
+  return check_hip(h, "tpcg_filter_project_adjoint");
+}
+
+int tpcg_export_coarse_basis(tpcg_handle* hh, double* phi, double* lambda, double* resid) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
+  const Geometry& g = h->g;
+  hipStreamSynchronize(h->stream);
+  if (phi)
+    hipMemcpy(phi, h->phi, sizeof(double) * (size_t)g.nsub * g.nloc * g.k, hipMemcpyDeviceToDevice);
+  std::vector<double> tmp((size_t)g.nsub * h->msub);
+  for (int which = 0; which < 2; ++which) {
+    double* dst = which == 0 ? lambda : resid;
+    if (!dst) continue;
+    hipMemcpy(tmp.data(), which == 0 ? h->lam : h->eres, sizeof(double) * tmp.size(),
+              hipMemcpyDeviceToHost);
+    for (int j = 0; j < g.nsub; ++j)
+      for (int i = 0; i < g.k; ++i) dst[(size_t)j * g.k + i] = tmp[(size_t)j * h->msub + i];
+  }
+  return check_hip(h, "tpcg_export_coarse_basis");
+}
+
+int tpcg_query(const tpcg_handle* hh, int64_t* out) {
+  const Handle* h = H(hh);
+  if (!h || !out) return TPCG_EINVAL;
+  const Geometry& g = h->g;
+  int64_t v[9] = {g.ndof, g.nel, g.nsub, g.nloc, g.k, g.nb, g.nblk, g.nbc, g.nblkc};
+  std::memcpy(out, v, sizeof(v));
+  return TPCG_OK;
+}
+
+const char* tpcg_last_error(const tpcg_handle* hh) {
+  const Handle* h = H(hh);
+  return h ? h->err.c_str() : "null handle";
+}
+
+void tpcg_destroy(tpcg_handle* hh) {
+  Handle* h = H(hh);
+  if (!h) return;
+  hipStreamSynchronize(h->stream);
+  release(h);
+  delete h;
+}
+
+}  // extern "C"

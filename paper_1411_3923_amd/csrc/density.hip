@@ -1,0 +1,217 @@
+// Density pipeline and compliance sensitivities.
+//   filter:      rho_tilde_e = sum_i w_ei rho_i / sum_i w_ei,
+//                w_ei = max(0, rmin - |x_e - x_i|) over element centres
+//                (Sec. 4.3; truncated at the mesh boundary)
+//   projection:  rho_bar = [tanh(b eta) + tanh(b (rho_tilde - eta))] /
+//                          [tanh(b eta) + tanh(b (1 - eta))]   (Sec. 4.3)
+//   chain rule:  dc/drho_i = sum_e dc/drho_bar_e H'(rho_tilde_e) w_ei / sum_k w_ek
+//   compliance:  c = f^T u; dc/drho_bar_e = -p (E0 - E_min) rho_e^(p-1) u_e^T K0 u_e
+//                (Sec. 2.2 objective, Sec. 4.2)
+#include "tpcg_internal.h"
+
+namespace tpcg {
+
+namespace {
+
+struct Etas {
+  double v[kMaxSys];
+};
+
+__device__ inline void elem_coords(const Geometry& g, int64_t e, int& ex, int& ey, int& ez) {
+  ex = (int)(e % g.nelx);
+  ey = (int)((e / g.nelx) % g.nely);
+  ez = (int)(e / ((int64_t)g.nelx * g.nely));
+}
+
+// sum of the hat weights around element (ex, ey, ez) inside the mesh
+__device__ inline double weight_sum(const Geometry& g, int ex, int ey, int ez, double rmin, int R) {
+  double s = 0.0;
+  const int R3 = g.dim == 3 ? R : 0;
+  for (int dz = -R3; dz <= R3; ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const int x = ex + dx, y = ey + dy, z = ez + dz;
+        if (x < 0 || x >= g.nelx || y < 0 || y >= g.nely || z < 0 || z >= g.nelz) continue;
+        const double w = rmin - sqrt((double)(dx * dx + dy * dy + dz * dz));
+        if (w > 0.0) s += w;
+      }
+  return s;
+}
+
+__device__ inline double heaviside(double x, double beta, double eta) {
+  return (tanh(beta * eta) + tanh(beta * (x - eta))) / (tanh(beta * eta) + tanh(beta * (1.0 - eta)));
+}
+
+__device__ inline double heaviside_d(double x, double beta, double eta) {
+  const double t = tanh(beta * (x - eta));
+  return beta * (1.0 - t * t) / (tanh(beta * eta) + tanh(beta * (1.0 - eta)));
+}
+
+__global__ __launch_bounds__(kThreads) void k_filter_project(Geometry g, const double* __restrict__ rho,
+                                                            double rmin, double beta, Etas eta,
+                                                            int nsys, double* __restrict__ rt,
+                                                            double* __restrict__ rb) {
+  const int R = rmin > 1.0 ? (int)ceil(rmin) - 1 : 0;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < g.nel;
+       e += (int64_t)gridDim.x * kThreads) {
+    double v;
+    if (R == 0) {
+      v = rho[e];
+    } else {
+      int ex, ey, ez;
+      elem_coords(g, e, ex, ey, ez);
+      double num = 0.0, den = 0.0;
+      const int R3 = g.dim == 3 ? R : 0;
+      for (int dz = -R3; dz <= R3; ++dz)
+        for (int dy = -R; dy <= R; ++dy)
+          for (int dx = -R; dx <= R; ++dx) {
+            const int x = ex + dx, y = ey + dy, z = ez + dz;
+            if (x < 0 || x >= g.nelx || y < 0 || y >= g.nely || z < 0 || z >= g.nelz) continue;
+            const double w = rmin - sqrt((double)(dx * dx + dy * dy + dz * dz));
+            if (w <= 0.0) continue;
+            num += w * rho[x + (int64_t)g.nelx * (y + (int64_t)g.nely * z)];
+            den += w;
+          }
+      v = num / den;
+    }
+    rt[e] = v;
+    for (int s = 0; s < nsys; ++s) rb[(size_t)s * g.nel + e] = heaviside(v, beta, eta.v[s]);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_filter_project_adjoint(
+    Geometry g, const double* __restrict__ rt, double rmin, double beta, Etas eta, int nsys,
+    const double* __restrict__ gin, double* __restrict__ out) {
+  const int R = rmin > 1.0 ? (int)ceil(rmin) - 1 : 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nel;
+       i += (int64_t)gridDim.x * kThreads) {
+    double acc[kMaxSys] = {0.0, 0.0, 0.0, 0.0};
+    if (R == 0) {
+      for (int s = 0; s < nsys; ++s)
+        acc[s] = gin[(size_t)s * g.nel + i] * heaviside_d(rt[i], beta, eta.v[s]);
+    } else {
+      int ix, iy, iz;
+      elem_coords(g, i, ix, iy, iz);
+      const int R3 = g.dim == 3 ? R : 0;
+      for (int dz = -R3; dz <= R3; ++dz)
+        for (int dy = -R; dy <= R; ++dy)
+          for (int dx = -R; dx <= R; ++dx) {
+            const int x = ix + dx, y = iy + dy, z = iz + dz;
+            if (x < 0 || x >= g.nelx || y < 0 || y >= g.nely || z < 0 || z >= g.nelz) continue;
+            const double w = rmin - sqrt((double)(dx * dx + dy * dy + dz * dz));
+            if (w <= 0.0) continue;
+            const int64_t e = x + (int64_t)g.nelx * (y + (int64_t)g.nely * z);
+            const double ws = w / weight_sum(g, x, y, z, rmin, R);
+            for (int s = 0; s < nsys; ++s)
+              acc[s] += ws * gin[(size_t)s * g.nel + e] * heaviside_d(rt[e], beta, eta.v[s]);
+          }
+    }
+    for (int s = 0; s < nsys; ++s) out[(size_t)s * g.nel + i] = acc[s];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sensitivity(Geometry g, const double* __restrict__ rho,
+                                                         const double* __restrict__ u,
+                                                         const uint8_t* __restrict__ fixed,
+                                                         const double* __restrict__ K0,
+                                                         double E0, double Emin, double penal,
+                                                         double* __restrict__ dc) {
+  __shared__ double K0s[576];
+  const int sys = blockIdx.y;
+  const int nd = g.ndpe, d = g.dim;
+  for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
+  __syncthreads();
+  const double* us = u + (size_t)sys * g.ndof;
+  const double* rs = rho + (size_t)sys * g.nel;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < g.nel;
+       e += (int64_t)gridDim.x * kThreads) {
+    int ex, ey, ez;
+    elem_coords(g, e, ex, ey, ez);
+    const int64_t n0 = ex + (int64_t)g.nnx * (ey + (int64_t)g.nny * ez);
+    const int64_t lay = (int64_t)g.nnx * g.nny;
+    int64_t nodes[8] = {n0, n0 + 1, n0 + 1 + g.nnx, n0 + g.nnx, 0, 0, 0, 0};
+    const int na = d == 3 ? 8 : 4;
+    if (d == 3)
+      for (int a = 0; a < 4; ++a) nodes[4 + a] = nodes[a] + lay;
+    double ue[24];
+    for (int a = 0; a < na; ++a)
+      for (int c = 0; c < d; ++c) {
+        const int64_t dof = d * nodes[a] + c;
+        ue[d * a + c] = fixed[dof] ? 0.0 : us[dof];
+      }
+    double q = 0.0;
+    for (int a = 0; a < nd; ++a) {
+      double t = 0.0;
+      for (int b = 0; b < nd; ++b) t += K0s[a * nd + b] * ue[b];
+      q += ue[a] * t;
+    }
+    const double r = rs[e];
+    const double rp1 = penal == 3.0 ? r * r : pow(r, penal - 1.0);
+    dc[(size_t)sys * g.nel + e] = -penal * (E0 - Emin) * rp1 * q;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_fu_parts(Geometry g, const double* __restrict__ f,
+                                                      const double* __restrict__ u,
+                                                      const uint8_t* __restrict__ fixed,
+                                                      double* __restrict__ parts) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.y;
+  const size_t off = (size_t)sys * g.ndof;
+  double a = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
+       n += (int64_t)gridDim.x * kThreads)
+    for (int c = 0; c < g.dim; ++c) {
+      const int64_t i = g.dim * n + c;
+      if (!fixed[i]) a += f[off + i] * u[off + i];
+    }
+  const double s = block_sum(a, sh);
+  if (threadIdx.x == 0) part_slot(parts, kPartAux, sys)[blockIdx.x] = s;
+}
+
+__global__ void k_fu_final(const double* __restrict__ parts, int np, double* __restrict__ c) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.x;
+  const double v = sum_parts(part_slot(const_cast<double*>(parts), kPartAux, sys), np, sh);
+  if (threadIdx.x == 0) c[sys] = v;
+}
+
+int elem_blocks(int64_t n) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+void launch_filter_project(const Handle& h, const double* rho, double rmin, double beta,
+                           const double* eta, int nsys, double* rho_tilde, double* rho_phys,
+                           hipStream_t st) {
+  Etas e{};
+  for (int s = 0; s < nsys; ++s) e.v[s] = eta[s];
+  hipLaunchKernelGGL(k_filter_project, dim3(elem_blocks(h.g.nel)), dim3(kThreads), 0, st, h.g,
+                     rho, rmin, beta, e, nsys, rho_tilde, rho_phys);
+}
+
+void launch_filter_project_adjoint(const Handle& h, const double* rho_tilde, double rmin,
+                                   double beta, const double* eta, int nsys, const double* g,
+                                   double* out, hipStream_t st) {
+  Etas e{};
+  for (int s = 0; s < nsys; ++s) e.v[s] = eta[s];
+  hipLaunchKernelGGL(k_filter_project_adjoint, dim3(elem_blocks(h.g.nel)), dim3(kThreads), 0, st,
+                     h.g, rho_tilde, rmin, beta, e, nsys, g, out);
+}
+
+void launch_compliance_sens(const Handle& h, const double* rho, const double* u, const double* f,
+                            int nsys, double* c, double* dc, hipStream_t st) {
+  const int np = parts_for(h.g.nnodes);
+  hipLaunchKernelGGL(k_fu_parts, dim3(np, nsys), dim3(kThreads), 0, st, h.g, f, u, h.fixed,
+                     h.parts);
+  hipLaunchKernelGGL(k_fu_final, dim3(nsys), dim3(kThreads), 0, st, h.parts, np, c);
+  if (dc) {
+    const tpcg_problem& pr = h.prob;
+    hipLaunchKernelGGL(k_sensitivity, dim3(elem_blocks(h.g.nel), nsys), dim3(kThreads), 0, st,
+                       h.g, rho, u, h.fixed, h.K0, pr.E0, pr.Emin, pr.penal, dc);
+  }
+}
+
+}  // namespace tpcg

@@ -1,0 +1,199 @@
+// Two-level additive Schwarz preconditioner application (Sec. 2.4.2 with the
+// additive form; coarse space of Sec. 2.4):
+//   z = sum_j R_j^T A_j^-1 R_j r + Phi K_c^-1 Phi^T r
+// in three launches:
+//   1. restriction y_c = Phi^T r            (one workgroup per subdomain)
+//   2. block-tridiagonal solves: A_j^-1 R_j r for every (system, subdomain)
+//      and K_c^-1 y_c for every system, in one grid (coarse workgroups first,
+//      so the long sequential coarse solves start early)
+//   3. extension z(n) = sum_{j owns n} (A_j^-1 R_j r)(n) + Phi(n) x_c, with the
+//      fused partial sums of r.z (and r.z_old for the flexible beta).
+#include "btri.h"
+
+namespace tpcg {
+
+namespace {
+
+// global DOF of local DOF l of subdomain (jx, jy, jz)
+__device__ inline int64_t box_dof(const Geometry& g, int jx, int jy, int jz, int l) {
+  const int d = g.dim;
+  const int ln = l / d, c = l - ln * d;
+  const int lx = ln % g.bn;
+  const int rest = ln / g.bn;
+  const int ly = rest % g.bn;
+  const int lz = rest / g.bn;
+  const int64_t n = (int64_t)(g.s * jx + lx) +
+                    (int64_t)g.nnx * ((g.s * jy + ly) + (int64_t)g.nny * (g.s * jz + lz));
+  return d * n + c;
+}
+
+__device__ inline void sub_coords(const Geometry& g, int j, int& jx, int& jy, int& jz) {
+  jx = j % g.gx;
+  jy = (j / g.gx) % g.gy;
+  jz = j / (g.gx * g.gy);
+}
+
+template <typename P>
+__global__ __launch_bounds__(kThreads) void k_restrict(Geometry g, const P* __restrict__ phi,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ yc, int nsys,
+                                                       Gate gate) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  int jx, jy, jz;
+  sub_coords(g, j, jx, jy, jz);
+  const int k = g.k;
+  const P* ph = phi + (size_t)j * g.nloc * k;
+  for (int sys = 0; sys < nsys; ++sys) {
+    if (!gate_running(gate, sys, sh)) continue;
+    const double* rs = r + (size_t)sys * g.ndof;
+    double acc[kMaxK];
+#pragma unroll
+    for (int m = 0; m < kMaxK; ++m) acc[m] = 0.0;
+    for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+      const double rv = rs[box_dof(g, jx, jy, jz, l)];
+#pragma unroll
+      for (int m = 0; m < kMaxK; ++m)
+        if (m < k) acc[m] += (double)ph[(size_t)l * k + m] * rv;
+    }
+    for (int m = 0; m < k; ++m) {
+      const double v = block_sum(acc[m], sh);
+      if (threadIdx.x == 0) yc[(size_t)sys * g.nt + coarse_index(g, jx, jy, jz, m)] = v;
+    }
+  }
+}
+
+// grid.x = nsys (coarse) + nsys * nsub (local). Local factors in T.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_block_solves(
+    Geometry g, const double* __restrict__ r, const T* __restrict__ lfac, T* __restrict__ zloc,
+    const double* __restrict__ cfac, const double* __restrict__ yc, double* __restrict__ xc,
+    int nsys, Gate gate) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  if (b < nsys) {
+    const int sys = b;
+    if (!gate_running(gate, sys, sh)) return;
+    const double* fac = cfac + (size_t)sys * g.nblkc * 2 * g.nbc * g.nbc;
+    const double* ys = yc + (size_t)sys * g.nt;
+    double* xs = xc + (size_t)sys * g.nt;
+    const int nbc = g.nbc;
+    btri_solve<double>(
+        fac, nbc, g.nblkc, [&](int bb, int i) { return ys[bb * nbc + i]; },
+        [&](int bb, int i) -> double& { return xs[bb * nbc + i]; }, smem);
+    return;
+  }
+  const int idx = b - nsys;
+  const int sys = idx / g.nsub;
+  const int j = idx - sys * g.nsub;
+  if (!gate_running(gate, sys, sh)) return;
+  int jx, jy, jz;
+  sub_coords(g, j, jx, jy, jz);
+  const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
+  const T* fac = lfac + ((size_t)sys * g.nsub + j) * fsz;
+  const double* rs = r + (size_t)sys * g.ndof;
+  T* zs = zloc + ((size_t)sys * g.nsub + j) * g.nloc;
+  const int nb = g.nb;
+  btri_solve<T>(
+      fac, nb, g.nblk, [&](int bb, int i) { return rs[box_dof(g, jx, jy, jz, bb * nb + i)]; },
+      [&](int bb, int i) -> T& { return zs[bb * nb + i]; }, smem);
+}
+
+template <typename T, typename P>
+__global__ __launch_bounds__(kThreads) void k_extend(
+    Geometry g, const double* __restrict__ r, double* __restrict__ z, const T* __restrict__ zloc,
+    const P* __restrict__ phi, const double* __restrict__ xc, const uint8_t* __restrict__ fixed,
+    double* __restrict__ parts, int rz_slot, int flexible, Gate gate) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.y;
+  if (!gate_running(gate, sys, sh)) return;
+  const int d = g.dim, s = g.s, k = g.k;
+  const double* rs = r + (size_t)sys * g.ndof;
+  double* zs = z + (size_t)sys * g.ndof;
+  const T* zl = zloc + (size_t)sys * g.nsub * g.nloc;
+  const double* xs = xc + (size_t)sys * g.nt;
+  double arz = 0.0, arzo = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
+       n += (int64_t)gridDim.x * kThreads) {
+    const int ix = (int)(n % g.nnx);
+    const int iy = (int)((n / g.nnx) % g.nny);
+    const int iz = (int)(n / ((int64_t)g.nnx * g.nny));
+    const int x0 = ix == 0 ? 0 : (ix - 1) / s, x1 = min(g.gx - 1, ix / s);
+    const int y0 = iy == 0 ? 0 : (iy - 1) / s, y1 = min(g.gy - 1, iy / s);
+    int z0 = 0, z1 = 0;
+    if (d == 3) { z0 = iz == 0 ? 0 : (iz - 1) / s; z1 = min(g.gz - 1, iz / s); }
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int jz = z0; jz <= z1; ++jz)
+      for (int jy = y0; jy <= y1; ++jy)
+        for (int jx = x0; jx <= x1; ++jx) {
+          const int j = jx + g.gx * (jy + g.gy * jz);
+          const int ln = (ix - s * jx) + g.bn * ((iy - s * jy) + g.bn * (iz - s * jz));
+          const T* zj = zl + (size_t)j * g.nloc + (size_t)d * ln;
+          const P* pj = phi + ((size_t)j * g.nloc + (size_t)d * ln) * k;
+          const double* xj = xs + coarse_index(g, jx, jy, jz, 0);
+          for (int c = 0; c < d; ++c) {
+            double v = (double)zj[c];
+            for (int m = 0; m < k; ++m) v += (double)pj[c * k + m] * xj[m];
+            acc[c] += v;
+          }
+        }
+    for (int c = 0; c < d; ++c) {
+      const int64_t i = d * n + c;
+      const double zn = fixed[i] ? 0.0 : acc[c];
+      const double ri = rs[i];
+      if (flexible) arzo += ri * zs[i];
+      zs[i] = zn;
+      arz += ri * zn;
+    }
+  }
+  const double v = block_sum(arz, sh);
+  if (threadIdx.x == 0) part_slot(parts, rz_slot, sys)[blockIdx.x] = v;
+  if (flexible) {
+    const double w = block_sum(arzo, sh);
+    if (threadIdx.x == 0) part_slot(parts, kPartRZO, sys)[blockIdx.x] = w;
+  }
+}
+
+template <typename T>
+void solves_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
+  const Geometry& g = h.g;
+  const size_t lds = std::max(btri_solve_lds<T>(g.nb), btri_solve_lds<double>(g.nbc));
+  static bool attr_set[2] = {false, false};
+  if (!attr_set[sizeof(T) == 8]) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_block_solves<T>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();   // an unsupported size must not leave a stale error behind
+    attr_set[sizeof(T) == 8] = true;
+  }
+  dim3 grid(nsys + nsys * g.nsub);
+  hipLaunchKernelGGL(k_block_solves<T>, grid, dim3(kThreads), lds, st, g, r,
+                     reinterpret_cast<const T*>(h.lfac), reinterpret_cast<T*>(h.zloc), h.cfac,
+                     h.yc, h.xc, nsys, gate);
+}
+
+}  // namespace
+
+void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
+                    int rz_slot, int rz_keep_slot, int flexible, hipStream_t st) {
+  (void)rz_keep_slot;
+  const Geometry& g = h.g;
+  dim3 egrid(parts_for(g.nnodes), nsys);
+  if (h.mixed) {
+    hipLaunchKernelGGL(k_restrict<float>, dim3(g.nsub), dim3(kThreads), 0, st, g, h.phi32, r,
+                       h.yc, nsys, gate);
+    solves_launch<float>(h, r, nsys, gate, st);
+    hipLaunchKernelGGL((k_extend<float, float>), egrid, dim3(kThreads), 0, st, g, r, z,
+                       reinterpret_cast<const float*>(h.zloc), h.phi32, h.xc, h.fixed, h.parts,
+                       rz_slot, flexible, gate);
+  } else {
+    hipLaunchKernelGGL(k_restrict<double>, dim3(g.nsub), dim3(kThreads), 0, st, g, h.phi, r,
+                       h.yc, nsys, gate);
+    solves_launch<double>(h, r, nsys, gate, st);
+    hipLaunchKernelGGL((k_extend<double, double>), egrid, dim3(kThreads), 0, st, g, r, z,
+                       reinterpret_cast<const double*>(h.zloc), h.phi, h.xc, h.fixed, h.parts,
+                       rz_slot, flexible, gate);
+  }
+}
+
+}  // namespace tpcg

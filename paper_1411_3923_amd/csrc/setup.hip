@@ -1,0 +1,816 @@
+// Construction of the two-level preconditioner (Sec. 2.4, Sec. 3.2, Sec. 5.3):
+//   1. Neumann matrices K_j^N of each cell (its own elements only, physical
+//      supports kept) of the representative system, scaled to
+//      S_j = D^-1/2 K_j^N D^-1/2 with D = diag(K_j^N), and factored shifted.
+//   2. The k smallest eigenpairs of S_j by shift-invert block subspace
+//      iteration (classical Gram-Schmidt twice) and a final Rayleigh-Ritz
+//      step; psi = D^-1/2 x solves K_j^N psi = lambda D psi.
+//   3. Phi_j = chi_j psi_j with chi_j(n) = 1 / (subdomains containing n).
+//   4. Per system: W_j = K Phi_j on the cell grown by one node layer, the
+//      Galerkin blocks Phi_l^T W_j of K_c = Phi^T K Phi, and the coarse factor.
+//   5. Per system: local Dirichlet matrices A_j (principal submatrices of
+//      the supported K on the closed-cell DOFs) and their factors.
+// All factors are block-tridiagonal Cholesky factors (see btri.h).
+#include <algorithm>
+#include <vector>
+
+#include "btri.h"
+
+namespace tpcg {
+
+namespace {
+
+constexpr double kFixedDiag = 1.0e3;   // decoupled supported DOFs of S_j sit far above its spectrum
+
+__device__ inline int corner_of(int dx, int dy, int dz) {
+  // counter-clockwise in the x-y plane, bottom face first
+  return (dy ? (dx ? 2 : 3) : (dx ? 1 : 0)) + 4 * dz;
+}
+
+struct NodeRef {
+  int gx, gy, gz, c;
+  int64_t dof;
+};
+
+__device__ inline NodeRef local_node(const Geometry& g, int jx, int jy, int jz, int l) {
+  const int d = g.dim;
+  const int ln = l / d;
+  NodeRef n;
+  n.c = l - ln * d;
+  const int lx = ln % g.bn, rest = ln / g.bn;
+  n.gx = g.s * jx + lx;
+  n.gy = g.s * jy + rest % g.bn;
+  n.gz = g.s * jz + rest / g.bn;
+  n.dof = (int64_t)d * (n.gx + (int64_t)g.nnx * (n.gy + (int64_t)g.nny * n.gz)) + n.c;
+  return n;
+}
+
+// Sum over the elements that contain both nodes of E_e K0[a_r d + c_r][a_c d + c_c].
+// cell_only restricts to the elements of subdomain (jx, jy, jz).
+__device__ double pair_stiffness(const Geometry& g, const NodeRef& a, const NodeRef& b,
+                                 const double* __restrict__ rho, const double* __restrict__ K0,
+                                 double E0, double Emin, double penal, bool cell_only, int jx,
+                                 int jy, int jz) {
+  if (abs(a.gx - b.gx) > 1 || abs(a.gy - b.gy) > 1 || abs(a.gz - b.gz) > 1) return 0.0;
+  const int d = g.dim;
+  int xl = max(a.gx, b.gx) - 1, xh = min(a.gx, b.gx);
+  int yl = max(a.gy, b.gy) - 1, yh = min(a.gy, b.gy);
+  int zl = 0, zh = 0;
+  if (d == 3) { zl = max(a.gz, b.gz) - 1; zh = min(a.gz, b.gz); }
+  xl = max(xl, 0); yl = max(yl, 0); zl = max(zl, 0);
+  xh = min(xh, g.nelx - 1); yh = min(yh, g.nely - 1);
+  if (d == 3) zh = min(zh, g.nelz - 1);
+  if (cell_only) {
+    xl = max(xl, g.s * jx); xh = min(xh, g.s * jx + g.s - 1);
+    yl = max(yl, g.s * jy); yh = min(yh, g.s * jy + g.s - 1);
+    if (d == 3) { zl = max(zl, g.s * jz); zh = min(zh, g.s * jz + g.s - 1); }
+  }
+  const int nd = g.ndpe;
+  double v = 0.0;
+  for (int ez = zl; ez <= zh; ++ez)
+    for (int ey = yl; ey <= yh; ++ey)
+      for (int ex = xl; ex <= xh; ++ex) {
+        const int64_t e = ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez);
+        const double E = simp_modulus(rho[e], E0, Emin, penal);
+        const int ar = corner_of(a.gx - ex, a.gy - ey, d == 3 ? a.gz - ez : 0);
+        const int ac = corner_of(b.gx - ex, b.gy - ey, d == 3 ? b.gz - ez : 0);
+        v += E * K0[(d * ar + a.c) * nd + d * ac + b.c];
+      }
+  return v;
+}
+
+struct MatParams {
+  double E0, Emin, penal, shift;
+};
+
+// Fill block-tridiagonal storage. kind 0: Dirichlet A_j of every system in
+// grid.y; kind 1: scaled shifted Neumann S_j + shift I of one system, and
+// dis[j][l] = D_l^-1/2 (0 on supported DOFs). grid.x = nsub * nblk.
+__global__ __launch_bounds__(kThreads) void k_assemble(Geometry g, const double* __restrict__ rho,
+                                                      const uint8_t* __restrict__ fixed,
+                                                      const double* __restrict__ K0,
+                                                      double* __restrict__ out, double* __restrict__ dis,
+                                                      MatParams mp, int kind) {
+  const int j = blockIdx.x / g.nblk;
+  const int b = blockIdx.x - j * g.nblk;
+  const int sys = blockIdx.y;
+  int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const double* rs = rho + (size_t)sys * g.nel;
+  const int nb = g.nb;
+  const size_t msz = (size_t)nb * nb;
+  double* blk = out + (((size_t)sys * g.nsub + j) * g.nblk + b) * 2 * msz;
+  const bool neu = kind == 1;
+  for (int e = threadIdx.x; e < 2 * nb * nb; e += kThreads) {
+    const int slot = e / (nb * nb);
+    const int rc = e - slot * nb * nb;
+    const int r = rc / nb, c = rc - (rc / nb) * nb;
+    double v = 0.0;
+    if (!(slot == 1 && b == 0)) {
+      const int lr = b * nb + r;
+      const int lc = (b - slot) * nb + c;
+      const NodeRef A = local_node(g, jx, jy, jz, lr);
+      const NodeRef B = local_node(g, jx, jy, jz, lc);
+      if (fixed[A.dof] || fixed[B.dof]) {
+        v = (lr == lc) ? (neu ? kFixedDiag + mp.shift : 1.0) : 0.0;
+      } else {
+        v = pair_stiffness(g, A, B, rs, K0, mp.E0, mp.Emin, mp.penal, neu, jx, jy, jz);
+        if (neu) {
+          const double da = pair_stiffness(g, A, A, rs, K0, mp.E0, mp.Emin, mp.penal, true, jx, jy, jz);
+          const double db = pair_stiffness(g, B, B, rs, K0, mp.E0, mp.Emin, mp.penal, true, jx, jy, jz);
+          v = v / sqrt(da * db) + (lr == lc ? mp.shift : 0.0);
+        }
+      }
+    }
+    blk[slot * msz + (size_t)r * nb + c] = v;
+  }
+  if (neu && dis) {
+    for (int i = threadIdx.x; i < nb; i += kThreads) {
+      const int l = b * nb + i;
+      const NodeRef A = local_node(g, jx, jy, jz, l);
+      double v = 0.0;
+      if (!fixed[A.dof])
+        v = 1.0 / sqrt(pair_stiffness(g, A, A, rs, K0, mp.E0, mp.Emin, mp.penal, true, jx, jy, jz));
+      dis[(size_t)j * g.nloc + l] = v;
+    }
+  }
+}
+
+// In-place block-tridiagonal Cholesky (FP64), one workgroup per matrix:
+// A_bb <- D_b = L_bb^-1, A_{b,b-1} <- B_b = L_{b,b-1}. flag[0] |= 1 on a
+// non-positive pivot (the pivot is then replaced by 1 to keep going).
+__global__ __launch_bounds__(kThreads) void k_btri_factor(double* __restrict__ fac, int nb, int nblk,
+                                                         int* __restrict__ flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ld = lds_ld(nb);
+  double* buf0 = reinterpret_cast<double*>(smem);
+  double* buf1 = buf0 + (size_t)nb * ld;
+  const size_t msz = (size_t)nb * nb;
+  double* F = fac + (size_t)blockIdx.x * nblk * 2 * msz;
+  const int t = threadIdx.x;
+  double* Xa = buf0;   // receives A_bb, then L_bb
+  double* Yb = buf1;   // holds B_b from the previous step
+  for (int b = 0; b < nblk; ++b) {
+    double* Ab = F + (size_t)b * 2 * msz;
+    for (int e = t; e < nb * nb; e += kThreads) Xa[(e / nb) * ld + e % nb] = Ab[e];
+    __syncthreads();
+    if (b > 0) {
+      // A_bb -= B_b B_b^T (lower triangle)
+      for (int e = t; e < nb * nb; e += kThreads) {
+        const int i = e / nb, jj = e - (e / nb) * nb;
+        if (jj <= i) {
+          double s = 0.0;
+          for (int c = 0; c < nb; ++c) s += Yb[i * ld + c] * Yb[jj * ld + c];
+          Xa[i * ld + jj] -= s;
+        }
+      }
+      __syncthreads();
+    }
+    // right-looking Cholesky of Xa (lower)
+    for (int c = 0; c < nb; ++c) {
+      if (t == 0) {
+        double piv = Xa[c * ld + c];
+        if (!(piv > 0.0)) {
+          flag[0] = 1;
+          piv = 1.0;
+        }
+        Xa[c * ld + c] = sqrt(piv);
+      }
+      __syncthreads();
+      const double dcc = Xa[c * ld + c];
+      for (int i = c + 1 + t; i < nb; i += kThreads) Xa[i * ld + c] /= dcc;
+      __syncthreads();
+      const int n2 = nb - c - 1;
+      for (int e = t; e < n2 * n2; e += kThreads) {
+        const int i = c + 1 + e / n2, jj = c + 1 + e % n2;
+        if (jj <= i) Xa[i * ld + jj] -= Xa[i * ld + c] * Xa[jj * ld + c];
+      }
+      __syncthreads();
+    }
+    // D_b = L_bb^-1 into Yb (B_b is no longer needed), column by column
+    if (t < nb) {
+      const int jj = t;
+      for (int i = 0; i < nb; ++i) {
+        double v;
+        if (i < jj) v = 0.0;
+        else if (i == jj) v = 1.0 / Xa[i * ld + i];
+        else {
+          double s = 0.0;
+          for (int c = jj; c < i; ++c) s += Xa[i * ld + c] * Yb[c * ld + jj];
+          v = -s / Xa[i * ld + i];
+        }
+        Yb[i * ld + jj] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < nb * nb; e += kThreads) Ab[e] = Yb[(e / nb) * ld + e % nb];
+    if (b + 1 < nblk) {
+      // B_{b+1} = A_{b+1,b} D_b^T, in place row by row (thread i owns row i)
+      double* An = F + ((size_t)(b + 1) * 2 + 1) * msz;
+      for (int e = t; e < nb * nb; e += kThreads) Xa[(e / nb) * ld + e % nb] = An[e];
+      __syncthreads();
+      if (t < nb) {
+        const int i = t;
+        for (int jj = nb - 1; jj >= 0; --jj) {
+          double s = 0.0;
+          for (int c = 0; c <= jj; ++c) s += Xa[i * ld + c] * Yb[jj * ld + c];
+          Xa[i * ld + jj] = s;
+        }
+      }
+      __syncthreads();
+      for (int e = t; e < nb * nb; e += kThreads) An[e] = Xa[(e / nb) * ld + e % nb];
+      // B_{b+1} stays in Xa for the next update; Yb becomes the next receiver
+      double* tmp = Xa;
+      Xa = Yb;
+      Yb = tmp;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Subspace iteration for the local eigenproblems
+// ---------------------------------------------------------------------------
+
+__device__ inline double hash_uniform(uint64_t a) {
+  // splitmix64 finaliser, mapped to [-1, 1)
+  a += 0x9E3779B97F4A7C15ull;
+  a = (a ^ (a >> 30)) * 0xBF58476D1CE4E5B9ull;
+  a = (a ^ (a >> 27)) * 0x94D049BB133111EBull;
+  a ^= a >> 31;
+  return (double)(a >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_eig_init(Geometry g, double* __restrict__ X,
+                                                      const double* __restrict__ dis, int m) {
+  const int j = blockIdx.x;
+  for (int e = threadIdx.x; e < g.nloc * m; e += kThreads) {
+    const int l = e / m;
+    const double v = dis[(size_t)j * g.nloc + l] > 0.0
+                         ? hash_uniform(((uint64_t)j * g.nloc + l) * 64 + (e - l * m))
+                         : 0.0;
+    X[(size_t)j * g.nloc * m + e] = v;
+  }
+}
+
+// Classical Gram-Schmidt applied twice, column by column, on X[j] (nloc x m,
+// row-major) in place; supported DOFs are zeroed first.
+__global__ __launch_bounds__(kThreads) void k_eig_orth(Geometry g, double* __restrict__ X,
+                                                      const double* __restrict__ dis, int m) {
+  __shared__ double sh[4];
+  __shared__ double hq[kMaxSub];
+  const int j = blockIdx.x;
+  double* Xj = X + (size_t)j * g.nloc * m;
+  const double* dj = dis + (size_t)j * g.nloc;
+  for (int l = threadIdx.x; l < g.nloc; l += kThreads)
+    if (dj[l] == 0.0)
+      for (int r = 0; r < m; ++r) Xj[(size_t)l * m + r] = 0.0;
+  __syncthreads();
+  for (int r = 0; r < m; ++r) {
+    for (int pass = 0; pass < 2; ++pass) {
+      if (r > 0) {
+        double acc[kMaxSub];
+        for (int q = 0; q < kMaxSub; ++q) acc[q] = 0.0;
+        for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+          const double xr = Xj[(size_t)l * m + r];
+          for (int q = 0; q < r; ++q) acc[q] += Xj[(size_t)l * m + q] * xr;
+        }
+        for (int q = 0; q < r; ++q) {
+          const double v = block_sum(acc[q], sh);
+          if (threadIdx.x == 0) hq[q] = v;
+        }
+        __syncthreads();
+        for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+          double v = Xj[(size_t)l * m + r];
+          for (int q = 0; q < r; ++q) v -= hq[q] * Xj[(size_t)l * m + q];
+          Xj[(size_t)l * m + r] = v;
+        }
+        __syncthreads();
+      }
+    }
+    double a = 0.0;
+    for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+      const double v = Xj[(size_t)l * m + r];
+      a += v * v;
+    }
+    const double nr = sqrt(block_sum(a, sh));
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    for (int l = threadIdx.x; l < g.nloc; l += kThreads) Xj[(size_t)l * m + r] *= inv;
+    __syncthreads();
+  }
+}
+
+// Y = (L L^T)^-1 X for every subdomain, m right-hand sides (FP64).
+__global__ __launch_bounds__(kThreads) void k_btri_solve_multi(const double* __restrict__ fac,
+                                                              int nb, int nblk, int m,
+                                                              const double* __restrict__ X,
+                                                              double* __restrict__ Y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ld = lds_ld(nb);
+  double* M = reinterpret_cast<double*>(smem);
+  double* va = M + (size_t)nb * ld;
+  double* vb = va + (size_t)nb * m;
+  double* red = vb + (size_t)nb * m;
+  const size_t msz = (size_t)nb * nb;
+  const size_t n = (size_t)nb * nblk;
+  const double* F = fac + (size_t)blockIdx.x * nblk * 2 * msz;
+  const double* Xj = X + (size_t)blockIdx.x * n * m;
+  double* Yj = Y + (size_t)blockIdx.x * n * m;
+  const int t = threadIdx.x;
+  const int Q = kThreads / nb;
+  const int L = (nb + Q - 1) / Q;
+  const int i = t % nb, q = t / nb;
+  auto load = [&](const double* src) {
+    for (int e = t; e < nb * nb; e += kThreads) M[(e / nb) * ld + e % nb] = src[e];
+  };
+  // parts of M v (or M^T v) for all m columns of v, then the fixed-order sum
+  auto gemv = [&](const double* v, bool trans) {
+    if (q < Q) {
+      double acc[kMaxSub];
+      for (int r = 0; r < kMaxSub; ++r) acc[r] = 0.0;
+      const int c0 = q * L, c1 = min(nb, c0 + L);
+      for (int c = c0; c < c1; ++c) {
+        const double a = trans ? M[c * ld + i] : M[i * ld + c];
+        for (int r = 0; r < m; ++r) acc[r] += a * v[c * m + r];
+      }
+      for (int r = 0; r < m; ++r) red[((size_t)q * nb + i) * m + r] = acc[r];
+    }
+    __syncthreads();
+  };
+  auto sum = [&](int e) {
+    const int ii = e / m, r = e - (e / m) * m;
+    double s = 0.0;
+    for (int qq = 0; qq < Q; ++qq) s += red[((size_t)qq * nb + ii) * m + r];
+    return s;
+  };
+  // forward: y_b = D_b (x_b - B_b y_{b-1})
+  for (int b = 0; b < nblk; ++b) {
+    __syncthreads();
+    for (int e = t; e < nb * m; e += kThreads) va[e] = Xj[(size_t)b * nb * m + e];
+    if (b > 0) {
+      load(F + ((size_t)b * 2 + 1) * msz);
+      __syncthreads();
+      gemv(vb, false);
+      for (int e = t; e < nb * m; e += kThreads) va[e] -= sum(e);
+    }
+    __syncthreads();
+    load(F + (size_t)b * 2 * msz);
+    __syncthreads();
+    gemv(va, false);
+    for (int e = t; e < nb * m; e += kThreads) {
+      const double y = sum(e);
+      vb[e] = y;
+      Yj[(size_t)b * nb * m + e] = y;
+    }
+  }
+  // backward: x_b = D_b^T (y_b - B_{b+1}^T x_{b+1})
+  for (int b = nblk - 1; b >= 0; --b) {
+    __syncthreads();
+    for (int e = t; e < nb * m; e += kThreads) va[e] = Yj[(size_t)b * nb * m + e];
+    if (b < nblk - 1) {
+      load(F + ((size_t)(b + 1) * 2 + 1) * msz);
+      __syncthreads();
+      gemv(vb, true);
+      for (int e = t; e < nb * m; e += kThreads) va[e] -= sum(e);
+    }
+    __syncthreads();
+    load(F + (size_t)b * 2 * msz);
+    __syncthreads();
+    gemv(va, true);
+    for (int e = t; e < nb * m; e += kThreads) {
+      const double x = sum(e);
+      vb[e] = x;
+      Yj[(size_t)b * nb * m + e] = x;
+    }
+  }
+}
+
+// Y = S X with S = D^-1/2 K^N D^-1/2 applied element by element over the
+// cell's own elements (supported DOFs excluded).
+__global__ __launch_bounds__(kThreads) void k_neumann_apply(Geometry g, const double* __restrict__ rho,
+                                                           const double* __restrict__ K0,
+                                                           const double* __restrict__ dis,
+                                                           const double* __restrict__ X,
+                                                           double* __restrict__ Y, int m,
+                                                           MatParams mp) {
+  __shared__ double K0s[576];
+  const int j = blockIdx.x;
+  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const int d = g.dim, nd = g.ndpe;
+  for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
+  __syncthreads();
+  const double* dj = dis + (size_t)j * g.nloc;
+  const double* Xj = X + (size_t)j * g.nloc * m;
+  double* Yj = Y + (size_t)j * g.nloc * m;
+  for (int ln = threadIdx.x; ln < g.nbox; ln += kThreads) {
+    const int lx = ln % g.bn, ly = (ln / g.bn) % g.bn, lz = ln / (g.bn * g.bn);
+    double acc[3][kMaxSub];
+    for (int c = 0; c < 3; ++c)
+      for (int r = 0; r < kMaxSub; ++r) acc[c][r] = 0.0;
+    const int na = d == 3 ? 8 : 4;
+    for (int a = 0; a < na; ++a) {
+      const int dx = (a & 3) == 1 || (a & 3) == 2, dy = (a & 3) >= 2, dz = a >= 4;
+      const int ex = lx - dx, ey = ly - dy, ez = lz - dz;   // cell-local element
+      if (ex < 0 || ex >= g.s || ey < 0 || ey >= g.s || (d == 3 && (ez < 0 || ez >= g.s))) continue;
+      const int gex = g.s * jx + ex, gey = g.s * jy + ey, gez = g.s * jz + ez;
+      const double E = simp_modulus(
+          rho[gex + (int64_t)g.nelx * (gey + (int64_t)g.nely * gez)], mp.E0, mp.Emin, mp.penal);
+      for (int bnode = 0; bnode < na; ++bnode) {
+        const int bx = ex + ((bnode & 3) == 1 || (bnode & 3) == 2);
+        const int by = ey + ((bnode & 3) >= 2);
+        const int bz = ez + (bnode >= 4);
+        const int lb = bx + g.bn * (by + g.bn * bz);
+        for (int cc = 0; cc < d; ++cc) {
+          const int l2 = d * lb + cc;
+          const double s2 = dj[l2];
+          if (s2 == 0.0) continue;
+          for (int c = 0; c < d; ++c) {
+            const double kv = E * K0s[(d * a + c) * nd + d * bnode + cc] * s2;
+            for (int r = 0; r < m; ++r) acc[c][r] += kv * Xj[(size_t)l2 * m + r];
+          }
+        }
+      }
+    }
+    for (int c = 0; c < d; ++c) {
+      const int l = d * ln + c;
+      const double s1 = dj[l];
+      for (int r = 0; r < m; ++r) Yj[(size_t)l * m + r] = s1 * acc[c][r];
+    }
+  }
+}
+
+__device__ inline int axis_mult(int i, int s, int nel) {
+  return (i % s == 0 && i > 0 && i < nel) ? 2 : 1;
+}
+
+// Rayleigh-Ritz on span(X) with SX = S X: H = X^T S X, H = Q Theta Q^T
+// (cyclic Jacobi), Ritz vectors X Q in ascending order; writes the Ritz
+// values, the residual norms ||S x - theta x|| and Phi_j = chi D^-1/2 (X Q)[:, :k].
+__global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* __restrict__ X,
+                                                    const double* __restrict__ SX,
+                                                    const double* __restrict__ dis, int m,
+                                                    double* __restrict__ lam,
+                                                    double* __restrict__ eres,
+                                                    double* __restrict__ phi) {
+  __shared__ double sh[4];
+  __shared__ double H[kMaxSub * kMaxSub];
+  __shared__ double Qm[kMaxSub * kMaxSub];
+  __shared__ double th[kMaxSub];
+  __shared__ int ord[kMaxSub];
+  const int j = blockIdx.x;
+  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const double* Xj = X + (size_t)j * g.nloc * m;
+  const double* Sj = SX + (size_t)j * g.nloc * m;
+  for (int a = 0; a < m; ++a) {
+    double acc[kMaxSub];
+    for (int r = 0; r < kMaxSub; ++r) acc[r] = 0.0;
+    for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+      const double xa = Xj[(size_t)l * m + a];
+      for (int r = 0; r < m; ++r) acc[r] += xa * Sj[(size_t)l * m + r];
+    }
+    for (int r = 0; r < m; ++r) {
+      const double v = block_sum(acc[r], sh);
+      if (threadIdx.x == 0) H[a * kMaxSub + r] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // symmetrise, then cyclic Jacobi
+    for (int a = 0; a < m; ++a)
+      for (int b = a + 1; b < m; ++b) {
+        const double v = 0.5 * (H[a * kMaxSub + b] + H[b * kMaxSub + a]);
+        H[a * kMaxSub + b] = H[b * kMaxSub + a] = v;
+      }
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) Qm[a * kMaxSub + b] = a == b ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double off = 0.0, dia = 0.0;
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) {
+          const double v = H[a * kMaxSub + b];
+          if (a == b) dia += v * v; else off += v * v;
+        }
+      if (off <= 1e-30 * dia) break;
+      for (int p = 0; p < m; ++p)
+        for (int qq = p + 1; qq < m; ++qq) {
+          const double apq = H[p * kMaxSub + qq];
+          if (apq == 0.0) continue;
+          const double app = H[p * kMaxSub + p], aqq = H[qq * kMaxSub + qq];
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          const double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
+          for (int r = 0; r < m; ++r) {
+            const double hp = H[r * kMaxSub + p], hq = H[r * kMaxSub + qq];
+            H[r * kMaxSub + p] = c * hp - s * hq;
+            H[r * kMaxSub + qq] = s * hp + c * hq;
+          }
+          for (int r = 0; r < m; ++r) {
+            const double hp = H[p * kMaxSub + r], hq = H[qq * kMaxSub + r];
+            H[p * kMaxSub + r] = c * hp - s * hq;
+            H[qq * kMaxSub + r] = s * hp + c * hq;
+          }
+          for (int r = 0; r < m; ++r) {
+            const double qp = Qm[r * kMaxSub + p], qv = Qm[r * kMaxSub + qq];
+            Qm[r * kMaxSub + p] = c * qp - s * qv;
+            Qm[r * kMaxSub + qq] = s * qp + c * qv;
+          }
+        }
+    }
+    for (int a = 0; a < m; ++a) { th[a] = H[a * kMaxSub + a]; ord[a] = a; }
+    for (int a = 1; a < m; ++a) {          // insertion sort, ascending
+      const int o = ord[a];
+      int b = a - 1;
+      while (b >= 0 && th[ord[b]] > th[o]) { ord[b + 1] = ord[b]; --b; }
+      ord[b + 1] = o;
+    }
+  }
+  __syncthreads();
+  // residuals and the basis
+  double racc[kMaxSub];
+  for (int r = 0; r < kMaxSub; ++r) racc[r] = 0.0;
+  const int k = g.k;
+  for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+    const double sd = dis[(size_t)j * g.nloc + l];
+    const int ln = l / g.dim;
+    const int lx = ln % g.bn, ly = (ln / g.bn) % g.bn, lz = ln / (g.bn * g.bn);
+    int mult = axis_mult(g.s * jx + lx, g.s, g.nelx) * axis_mult(g.s * jy + ly, g.s, g.nely);
+    if (g.dim == 3) mult *= axis_mult(g.s * jz + lz, g.s, g.nelz);
+    const double chi = 1.0 / mult;
+    for (int i = 0; i < m; ++i) {
+      const int o = ord[i];
+      double xv = 0.0, sv = 0.0;
+      for (int r = 0; r < m; ++r) {
+        xv += Xj[(size_t)l * m + r] * Qm[r * kMaxSub + o];
+        sv += Sj[(size_t)l * m + r] * Qm[r * kMaxSub + o];
+      }
+      const double res = sv - th[o] * xv;
+      racc[i] += res * res;
+      if (i < k) phi[((size_t)j * g.nloc + l) * k + i] = chi * sd * xv;
+    }
+  }
+  for (int i = 0; i < m; ++i) {
+    const double v = block_sum(racc[i], sh);
+    if (threadIdx.x == 0) {
+      lam[(size_t)j * m + i] = th[ord[i]];
+      eres[(size_t)j * m + i] = sqrt(v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Galerkin coarse matrix
+// ---------------------------------------------------------------------------
+
+// W[j][en][c][m] = (K Phi_j) at the node en of the cell grown by one node
+// layer (zero outside the mesh).
+__global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double* __restrict__ rho,
+                                                      const double* __restrict__ K0,
+                                                      const uint8_t* __restrict__ fixed,
+                                                      const double* __restrict__ phi,
+                                                      double* __restrict__ W, MatParams mp) {
+  __shared__ double K0s[576];
+  const int j = blockIdx.x;
+  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const int d = g.dim, nd = g.ndpe, k = g.k;
+  for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
+  __syncthreads();
+  const double* ph = phi + (size_t)j * g.nloc * k;
+  double* Wj = W + (size_t)j * g.nebox * d * k;
+  const int e = g.ebn;
+  for (int en = threadIdx.x; en < g.nebox; en += kThreads) {
+    const int ex_ = en % e, ey_ = (en / e) % e, ez_ = en / (e * e);
+    const int nx = g.s * jx - 1 + ex_, ny = g.s * jy - 1 + ey_;
+    const int nz = d == 3 ? g.s * jz - 1 + ez_ : 0;
+    double acc[3][kMaxK];
+    for (int c = 0; c < 3; ++c)
+      for (int mm = 0; mm < kMaxK; ++mm) acc[c][mm] = 0.0;
+    const bool in_mesh = nx >= 0 && nx < g.nnx && ny >= 0 && ny < g.nny && nz >= 0 && nz < g.nnz;
+    if (in_mesh) {
+      const int na = d == 3 ? 8 : 4;
+      for (int a = 0; a < na; ++a) {
+        const int dx = (a & 3) == 1 || (a & 3) == 2, dy = (a & 3) >= 2, dz = a >= 4;
+        const int elx = nx - dx, ely = ny - dy, elz = nz - dz;
+        if (elx < 0 || elx >= g.nelx || ely < 0 || ely >= g.nely) continue;
+        if (d == 3 && (elz < 0 || elz >= g.nelz)) continue;
+        const double E = simp_modulus(rho[elx + (int64_t)g.nelx * (ely + (int64_t)g.nely * elz)],
+                                      mp.E0, mp.Emin, mp.penal);
+        for (int bnode = 0; bnode < na; ++bnode) {
+          const int bx = elx + ((bnode & 3) == 1 || (bnode & 3) == 2);
+          const int by = ely + ((bnode & 3) >= 2);
+          const int bz = elz + (bnode >= 4);
+          const int lx = bx - g.s * jx, ly = by - g.s * jy, lz = d == 3 ? bz - g.s * jz : 0;
+          if (lx < 0 || lx > g.s || ly < 0 || ly > g.s || lz < 0 || lz > (d == 3 ? g.s : 0)) continue;
+          const int lb = lx + g.bn * (ly + g.bn * lz);
+          for (int cc = 0; cc < d; ++cc) {
+            const double* pv = ph + ((size_t)d * lb + cc) * k;
+            for (int c = 0; c < d; ++c) {
+              const double kv = E * K0s[(d * a + c) * nd + d * bnode + cc];
+              for (int mm = 0; mm < k; ++mm) acc[c][mm] += kv * pv[mm];
+            }
+          }
+        }
+      }
+    }
+    for (int c = 0; c < d; ++c) {
+      const bool fx = in_mesh && fixed[(int64_t)d * (nx + (int64_t)g.nnx * (ny + (int64_t)g.nny * nz)) + c];
+      for (int mm = 0; mm < k; ++mm)
+        Wj[((size_t)en * d + c) * k + mm] = (in_mesh && !fx) ? acc[c][mm] : 0.0;
+    }
+  }
+}
+
+// Blocks Phi_l^T W_j of K_c for every neighbour l of j whose coarse block is
+// j's block or the next one (the lower part of the block-tridiagonal
+// storage). grid.x = nsub * 3^d.
+__global__ __launch_bounds__(kThreads) void k_coarse_assemble(Geometry g, const double* __restrict__ phi,
+                                                             const double* __restrict__ W,
+                                                             double* __restrict__ cf) {
+  __shared__ double sh[4];
+  const int nnb = g.dim == 3 ? 27 : 9;
+  const int j = blockIdx.x / nnb;
+  const int o = blockIdx.x - j * nnb;
+  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = g.dim == 3 ? o / 9 - 1 : 0;
+  const int lx = jx + ox, ly = jy + oy, lz = jz + oz;
+  if (lx < 0 || lx >= g.gx || ly < 0 || ly >= g.gy || lz < 0 || lz >= g.gz) return;
+  const int k = g.k, d = g.dim;
+  const int Rb = coarse_index(g, lx, ly, lz, 0), Cb = coarse_index(g, jx, jy, jz, 0);
+  const int rblk = Rb / g.nbc, cblk = Cb / g.nbc;
+  int slot;
+  if (rblk == cblk) slot = 0;
+  else if (rblk == cblk + 1) slot = 1;
+  else return;
+  const int l = lx + g.gx * (ly + g.gy * lz);
+  const double* pl = phi + (size_t)l * g.nloc * k;
+  const double* Wj = W + (size_t)j * g.nebox * d * k;
+  // nodes of box l inside the extended box of j
+  const int x0 = max(g.s * lx, g.s * jx - 1), x1 = min(g.s * lx + g.s, g.s * jx + g.s + 1);
+  const int y0 = max(g.s * ly, g.s * jy - 1), y1 = min(g.s * ly + g.s, g.s * jy + g.s + 1);
+  int z0 = 0, z1 = 0;
+  if (d == 3) { z0 = max(g.s * lz, g.s * jz - 1); z1 = min(g.s * lz + g.s, g.s * jz + g.s + 1); }
+  const int nxr = x1 - x0 + 1, nyr = y1 - y0 + 1, nzr = z1 - z0 + 1;
+  const int cnt = nxr * nyr * nzr;
+  double* blk = cf + ((size_t)rblk * 2 + slot) * g.nbc * g.nbc;
+  const int rin = Rb - rblk * g.nbc, cin = Cb - cblk * g.nbc;
+  const int e = g.ebn;
+  for (int mr = 0; mr < k; ++mr) {
+    double acc[kMaxK];
+    for (int mm = 0; mm < kMaxK; ++mm) acc[mm] = 0.0;
+    for (int idx = threadIdx.x; idx < cnt; idx += kThreads) {
+      const int nx = x0 + idx % nxr, ny = y0 + (idx / nxr) % nyr, nz = z0 + idx / (nxr * nyr);
+      const int lb = (nx - g.s * lx) + g.bn * ((ny - g.s * ly) + g.bn * (nz - g.s * lz));
+      const int eb = (nx - g.s * jx + 1) + e * ((ny - g.s * jy + 1) + e * (d == 3 ? nz - g.s * jz + 1 : 0));
+      for (int c = 0; c < d; ++c) {
+        const double pv = pl[((size_t)d * lb + c) * k + mr];
+        const double* wv = Wj + ((size_t)eb * d + c) * k;
+        for (int mm = 0; mm < k; ++mm) acc[mm] += pv * wv[mm];
+      }
+    }
+    for (int mm = 0; mm < k; ++mm) {
+      const double v = block_sum(acc[mm], sh);
+      if (threadIdx.x == 0) blk[(size_t)(rin + mr) * g.nbc + cin + mm] = v;
+    }
+  }
+}
+
+__global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    b[i] = (float)a[i];
+}
+
+template <typename T>
+T* dalloc(size_t n, int& err) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) { err = TPCG_ENOMEM; return nullptr; }
+  return reinterpret_cast<T*>(p);
+}
+
+void factor(Handle& h, double* fac, int nmat, int nb, int nblk) {
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_btri_factor),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();   // an unsupported size must not leave a stale error behind
+    attr = true;
+  }
+  const size_t lds = 2 * sizeof(double) * (size_t)nb * lds_ld(nb);
+  hipLaunchKernelGGL(k_btri_factor, dim3(nmat), dim3(kThreads), lds, h.stream, fac, nb, nblk,
+                     h.dflag);
+}
+
+}  // namespace
+
+int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
+  const Geometry& g = h.g;
+  hipStream_t st = h.stream;
+  const tpcg_problem& pr = h.prob;
+  int err = TPCG_OK;
+  const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
+  const size_t cfsz = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+  const int m = h.msub;
+  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 40;
+  MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
+
+  hipMemsetAsync(h.dflag, 0, 4 * sizeof(int), st);
+
+  // --- 1-3: spectral basis from system `rep` ---
+  double* nfac = dalloc<double>(g.nsub * fsz, err);
+  double* dis = dalloc<double>((size_t)g.nsub * g.nloc, err);
+  double* X = dalloc<double>((size_t)g.nsub * g.nloc * m, err);
+  double* Y = dalloc<double>((size_t)g.nsub * g.nloc * m, err);
+  if (err) {
+    hipFree(nfac); hipFree(dis); hipFree(X); hipFree(Y);
+    h.err = "out of device memory for the eigensolver";
+    return err;
+  }
+  const double* rrep = rho + (size_t)rep * g.nel;
+  hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g, rrep,
+                     h.fixed, h.K0, nfac, dis, mp, 1);
+  factor(h, nfac, g.nsub, g.nb, g.nblk);
+  hipLaunchKernelGGL(k_eig_init, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
+  hipLaunchKernelGGL(k_eig_orth, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_btri_solve_multi),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();   // an unsupported size must not leave a stale error behind
+    attr = true;
+  }
+  const int Qm = kThreads / g.nb;
+  const size_t slds = sizeof(double) * ((size_t)g.nb * lds_ld(g.nb) + 2 * (size_t)g.nb * m +
+                                        (size_t)Qm * g.nb * m);
+  for (int it = 0; it < iters; ++it) {
+    hipLaunchKernelGGL(k_btri_solve_multi, dim3(g.nsub), dim3(kThreads), slds, st, nfac, g.nb,
+                       g.nblk, m, X, Y);
+    hipLaunchKernelGGL(k_eig_orth, dim3(g.nsub), dim3(kThreads), 0, st, g, Y, dis, m);
+    std::swap(X, Y);
+  }
+  hipLaunchKernelGGL(k_neumann_apply, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis, X,
+                     Y, m, mp);
+  hipLaunchKernelGGL(k_eig_rr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, Y, dis, m, h.lam,
+                     h.eres, h.phi);
+  if (h.mixed) {
+    const int64_t n = (int64_t)g.nsub * g.nloc * g.k;
+    hipLaunchKernelGGL(k_to_float, dim3(1024), dim3(kThreads), 0, st, h.phi, h.phi32, n);
+  }
+  hipStreamSynchronize(st);
+  hipFree(nfac); hipFree(X); hipFree(Y); hipFree(dis);
+
+  // --- 4: coarse matrices and factors, per system ---
+  double* W = dalloc<double>((size_t)g.nsub * g.nebox * g.dim * g.k, err);
+  if (err) { h.err = "out of device memory for the coarse operator"; return err; }
+  hipMemsetAsync(h.cfac, 0, sizeof(double) * cfsz * nsys, st);
+  const int nnb = g.dim == 3 ? 27 : 9;
+  for (int sys = 0; sys < nsys; ++sys) {
+    const double* rs = rho + (size_t)sys * g.nel;
+    hipLaunchKernelGGL(k_coarse_W, dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0, h.fixed,
+                       h.phi, W, mp);
+    hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi, W,
+                       h.cfac + sys * cfsz);
+  }
+  factor(h, h.cfac, nsys, g.nbc, g.nblkc);
+  hipStreamSynchronize(st);
+  hipFree(W);
+
+  // --- 5: local Dirichlet factors (FP64; demoted to FP32 in mixed mode one
+  // system at a time) ---
+  if (!h.mixed) {
+    double* lf = reinterpret_cast<double*>(h.lfac);
+    hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, nsys), dim3(kThreads), 0, st, g, rho,
+                       h.fixed, h.K0, lf, nullptr, mp, 0);
+    factor(h, lf, nsys * g.nsub, g.nb, g.nblk);
+  } else {
+    double* lf = dalloc<double>(g.nsub * fsz, err);
+    if (err) { h.err = "out of device memory for the local factors"; return err; }
+    for (int sys = 0; sys < nsys; ++sys) {
+      hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g,
+                         rho + (size_t)sys * g.nel, h.fixed, h.K0, lf, nullptr, mp, 0);
+      factor(h, lf, g.nsub, g.nb, g.nblk);
+      hipLaunchKernelGGL(k_to_float, dim3(4096), dim3(kThreads), 0, st, lf,
+                         reinterpret_cast<float*>(h.lfac) + (size_t)sys * g.nsub * fsz,
+                         (int64_t)g.nsub * fsz);
+    }
+    hipStreamSynchronize(st);
+    hipFree(lf);
+  }
+  hipStreamSynchronize(st);
+
+  int flag[4] = {0, 0, 0, 0};
+  hipMemcpy(flag, h.dflag, sizeof(flag), hipMemcpyDeviceToHost);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    h.err = std::string("HIP error during setup: ") + hipGetErrorString(e);
+    h.sticky = 1;
+    return TPCG_EHIP;
+  }
+  if (flag[0]) {
+    h.err = "non-positive pivot in a block Cholesky factorisation";
+    return TPCG_ENOTSPD;
+  }
+  h.nsys_built = nsys;
+  h.basis_ready = 1;
+  return TPCG_OK;
+}
+
+}  // namespace tpcg

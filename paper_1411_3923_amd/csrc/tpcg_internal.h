@@ -1,0 +1,215 @@
+// Internal declarations of the tpcg library: geometry, handle state, device
+// helpers and the kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "tpcg.h"
+
+namespace tpcg {
+
+constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxParts = 512;       // reduction partials per system and vector kernel
+constexpr int kMaxSys = 4;           // systems solved together
+constexpr int kMaxK = 16;            // coarse vectors per subdomain
+constexpr int kMaxSub = 16;          // eigensolver subspace width
+constexpr int kMaxNb = 96;           // largest block of the block-tridiagonal kernels
+
+// Structured-mesh and partition sizes. Everything is derived from the problem.
+struct Geometry {
+  int dim;
+  int nelx, nely, nelz;              // elements per axis (nelz = 1 in 2D)
+  int nnx, nny, nnz;                 // nodes per axis (nnz = 1 in 2D)
+  int64_t nnodes, ndof, nel;
+  int s;                             // subdomain edge in elements
+  int gx, gy, gz;                    // subdomains per axis (gz = 1 in 2D)
+  int nsub;
+  int bn;                            // nodes per box edge (s + 1)
+  int nbox;                          // nodes per subdomain box
+  int nloc;                          // DOFs per subdomain box
+  int nb, nblk;                      // local block-tridiagonal: block size, block count
+  int k;                             // coarse vectors per subdomain
+  int caxis;                         // coarse blocks run along this subdomain axis
+  int nbc, nblkc;                    // coarse block size, block count
+  int nt;                            // coarse dimension nsub * k
+  int ebn;                           // nodes per extended box edge (s + 3)
+  int nebox;                         // nodes per extended box
+  int ndpe;                          // DOFs per element (8 or 24)
+};
+
+// Coarse index of (subdomain j, mode m): block-major along `caxis`.
+__host__ __device__ inline int coarse_index(const Geometry& g, int jx, int jy, int jz, int m) {
+  int blk, w;
+  if (g.caxis == 0) { blk = jx; w = jy + g.gy * jz; }
+  else if (g.caxis == 1) { blk = jy; w = jx + g.gx * jz; }
+  else { blk = jz; w = jx + g.gx * jy; }
+  return blk * g.nbc + w * g.k + m;
+}
+
+struct Handle {
+  tpcg_problem prob;
+  Geometry g;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int sticky = 0;
+  int mixed = 0;
+
+  // problem data
+  uint8_t* fixed = nullptr;          // [ndof]
+  double* K0 = nullptr;              // [ndpe * ndpe]
+
+  // preconditioner state
+  int basis_ready = 0;
+  int nsys_built = 0;
+  int msub = 0;                      // eigensolver subspace width
+  double* phi = nullptr;             // [nsub][nloc][k]
+  float* phi32 = nullptr;            // same, FP32 (mixed)
+  double* lam = nullptr;             // [nsub][msub] Ritz values
+  double* eres = nullptr;            // [nsub][msub] residual norms
+  void* lfac = nullptr;              // [nsys][nsub][nblk][2][nb][nb], double or float
+  double* cfac = nullptr;            // [nsys][nblkc][2][nbc][nbc]
+
+  // workspace
+  double* r = nullptr;               // [nsys_max][ndof]
+  double* z = nullptr;
+  double* p = nullptr;
+  double* q = nullptr;
+  void* zloc = nullptr;              // [nsys][nsub][nloc], double or float
+  double* yc = nullptr;              // [nsys][nt]
+  double* xc = nullptr;              // [nsys][nt]
+  double* parts = nullptr;           // reduction partials, see kParts* offsets
+  int* istate = nullptr;             // per-system integer state, see kSt*
+  int* hpoll = nullptr;              // pinned host [2][kMaxSys]
+  int* dflag = nullptr;              // device error flags [4]
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+// Partial-sum slots, each [kMaxSys][kMaxParts] doubles.
+enum {
+  kPartPQ = 0,
+  kPartRR0 = 1,     // parity buffers for r.r
+  kPartRR1 = 2,
+  kPartRZ0 = 3,     // parity buffers for r.z
+  kPartRZ1 = 4,
+  kPartRZO = 5,     // r_new . z_old (flexible beta)
+  kPartFF = 6,      // ||P f||^2
+  kPartAux = 7,
+  kNumPartSlots = 8
+};
+
+// Per-system integer state [kNumState][kMaxSys].
+enum { kStLastIt = 0, kStBreak = 1, kStPoll = 2, kNumState = 3 };
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the 256 threads of a workgroup; every thread gets the same value.
+// `sh` needs 4 doubles of LDS. Fixed reduction tree: deterministic.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Sum of n partials in a fixed order (identical in every workgroup).
+__device__ inline double sum_parts(const double* __restrict__ p, int n, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) v += p[i];
+  return block_sum(v, sh);
+}
+
+__device__ inline double simp_modulus(double rho, double E0, double Emin, double penal) {
+  double rp = (penal == 3.0) ? rho * rho * rho : pow(rho, penal);
+  return Emin + (E0 - Emin) * rp;
+}
+
+// Convergence gate of a batched PCG kernel. A system keeps running while
+// its recursive residual r.r (partials in slot rr_slot) exceeds tol2 * ||Pf||^2,
+// no breakdown was flagged and the iteration index is below maxit. Every
+// workgroup re-sums the same partials in the same order, so all agree.
+struct Gate {
+  const double* parts;
+  const int* istate;
+  int np;          // partials per system
+  int rr_slot;     // kPartRR0 or kPartRR1
+  int it;          // iteration index the gated work belongs to
+  int maxit;
+  double tol2;
+  int enabled;     // 0: always run
+};
+
+__device__ inline bool gate_running(const Gate& gt, int sys, double* sh) {
+  if (!gt.enabled) return true;
+  if (gt.it >= gt.maxit) return false;
+  if (gt.istate[kStBreak * kMaxSys + sys]) return false;
+  const double rr = sum_parts(gt.parts + ((size_t)gt.rr_slot * kMaxSys + sys) * kMaxParts, gt.np, sh);
+  const double ff = sum_parts(gt.parts + ((size_t)kPartFF * kMaxSys + sys) * kMaxParts, gt.np, sh);
+  return rr > gt.tol2 * ff;   // false for NaN as well
+}
+
+inline int parts_for(int64_t work) {
+  int64_t b = (work + kThreads - 1) / kThreads;
+  return (int)(b < 1 ? 1 : (b > kMaxParts ? kMaxParts : b));
+}
+
+__host__ __device__ inline double* part_slot(double* parts, int slot, int sys) {
+  return parts + ((size_t)slot * kMaxSys + sys) * kMaxParts;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files). All node-parallel kernels use
+// parts_for(nnodes) workgroups per system, so their partials line up.
+// ---------------------------------------------------------------------------
+
+// matvec.hip: y = P K(rho) P x; optional partials of x.y into slot `dot_slot` (-1: none)
+void launch_apply_K(const Handle& h, const double* rho, const double* x, double* y, int nsys,
+                    int dot_slot, const Gate& gate, hipStream_t st);
+
+// vectors.hip
+void launch_residual_init(const Handle& h, const double* f, double* u, const double* q, int nsys,
+                          hipStream_t st);
+void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hipStream_t st);
+void launch_update_p(const Handle& h, int nsys, const Gate& gate, int flexible, int first,
+                     hipStream_t st);
+void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st);
+// true residual of P(f - q) (q must hold K u) and out[sys] = {iters, status, relres, true_relres}
+void launch_summary(const Handle& h, const double* f, int nsys, const Gate& gate,
+                    double* out /*dev [nsys][4]*/, hipStream_t st);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
+
+// precond.hip: z = M^-1 r, gated; partials of r.z into rz_slot (and r.z_old into kPartRZO)
+void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
+                    int rz_slot, int rz_keep_slot, int flexible, hipStream_t st);
+
+// setup.hip
+int build_preconditioner(Handle& h, const double* rho, int nsys, int rep);
+
+// density.hip
+void launch_filter_project(const Handle& h, const double* rho, double rmin, double beta,
+                           const double* eta, int nsys, double* rho_tilde, double* rho_phys,
+                           hipStream_t st);
+void launch_filter_project_adjoint(const Handle& h, const double* rho_tilde, double rmin,
+                                   double beta, const double* eta, int nsys, const double* g,
+                                   double* out, hipStream_t st);
+void launch_compliance_sens(const Handle& h, const double* rho, const double* u, const double* f,
+                            int nsys, double* c, double* dc, hipStream_t st);
+
+// element.cpp
+void element_stiffness(int dim, double nu, double* K0 /* [ndpe*ndpe] */);
+
+}  // namespace tpcg

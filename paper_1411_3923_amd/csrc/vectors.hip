@@ -1,0 +1,217 @@
+// Batched PCG vector kernels with fused, deterministic reductions.
+//
+// Each kernel sweeps all DOFs of a system with parts_for(nnodes) workgroups,
+// one node per thread per step, and writes one partial sum per workgroup.
+// Scalars (alpha, beta, convergence) are recomputed by every consumer from
+// those partials in a fixed order, so no workgroup ever waits for another and
+// all of them agree bit for bit. Systems that have converged are masked.
+#include "tpcg_internal.h"
+
+namespace tpcg {
+
+namespace {
+
+// r = P (f - q), u <- P u; partials of r.r (slot RR0) and (Pf).(Pf) (slot FF).
+__global__ __launch_bounds__(kThreads) void k_residual_init(
+    Geometry g, const double* __restrict__ f, double* __restrict__ u,
+    const double* __restrict__ q, double* __restrict__ r, const uint8_t* __restrict__ fixed,
+    double* __restrict__ parts, int* __restrict__ istate) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.y;
+  const int d = g.dim;
+  const size_t off = (size_t)sys * g.ndof;
+  double arr = 0.0, aff = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
+       n += (int64_t)gridDim.x * kThreads) {
+    for (int c = 0; c < d; ++c) {
+      const size_t i = off + d * n + c;
+      const bool fx = fixed[d * n + c];
+      const double fi = fx ? 0.0 : f[i];
+      const double ri = fx ? 0.0 : fi - q[i];
+      r[i] = ri;
+      if (fx) u[i] = 0.0;
+      arr += ri * ri;
+      aff += fi * fi;
+    }
+  }
+  const double srr = block_sum(arr, sh);
+  const double sff = block_sum(aff, sh);
+  if (threadIdx.x == 0) {
+    part_slot(parts, kPartRR0, sys)[blockIdx.x] = srr;
+    part_slot(parts, kPartFF, sys)[blockIdx.x] = sff;
+    if (blockIdx.x == 0) {
+      istate[kStLastIt * kMaxSys + sys] = 0;
+      istate[kStBreak * kMaxSys + sys] = 0;
+    }
+  }
+}
+
+// Iteration `it`: alpha = (r.z)/(p.q); u += alpha p; r -= alpha q; partials of
+// the new r.r into the other parity slot. Breakdown (p.q <= 0 or not finite)
+// stops the system.
+__global__ __launch_bounds__(kThreads) void k_update_xr(
+    Geometry g, double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
+    const double* __restrict__ q, double* __restrict__ parts, int* __restrict__ istate,
+    Gate gate) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.y;
+  const int slot_old = gate.rr_slot;
+  const int slot_new = slot_old == kPartRR0 ? kPartRR1 : kPartRR0;
+  const int rz_slot = slot_old == kPartRR0 ? kPartRZ0 : kPartRZ1;
+  bool run = gate_running(gate, sys, sh);
+  double alpha = 0.0;
+  if (run) {
+    const double pq = sum_parts(part_slot(parts, kPartPQ, sys), gate.np, sh);
+    const double rz = sum_parts(part_slot(parts, rz_slot, sys), gate.np, sh);
+    alpha = rz / pq;
+    if (!(pq > 0.0) || !isfinite(alpha)) {
+      run = false;
+      if (blockIdx.x == 0 && threadIdx.x == 0) istate[kStBreak * kMaxSys + sys] = 1;
+    }
+  }
+  if (!run) {
+    if (threadIdx.x == 0)
+      part_slot(parts, slot_new, sys)[blockIdx.x] = part_slot(parts, slot_old, sys)[blockIdx.x];
+    return;
+  }
+  const int d = g.dim;
+  const size_t off = (size_t)sys * g.ndof;
+  double arr = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
+       n += (int64_t)gridDim.x * kThreads) {
+    for (int c = 0; c < d; ++c) {
+      const size_t i = off + d * n + c;
+      u[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      arr += ri * ri;
+    }
+  }
+  const double s = block_sum(arr, sh);
+  if (threadIdx.x == 0) {
+    part_slot(parts, slot_new, sys)[blockIdx.x] = s;
+    if (blockIdx.x == 0) istate[kStLastIt * kMaxSys + sys] = gate.it + 1;
+  }
+}
+
+// p = z + beta p after the preconditioner of iteration `it`; the gate refers
+// to the residual after that iteration's update. first != 0: p = z.
+// beta = (r.z_new)/(r.z_old), or the flexible (Polak-Ribiere) form
+// (r.z_new - r.z_prev)/(r.z_old) when the preconditioner is not exactly
+// symmetric (FP32 inner solves).
+__global__ __launch_bounds__(kThreads) void k_update_p(
+    Geometry g, double* __restrict__ p, const double* __restrict__ z,
+    double* __restrict__ parts, int* __restrict__ istate, Gate gate, int flexible, int first) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.y;
+  if (!gate_running(gate, sys, sh)) return;
+  double beta = 0.0;
+  if (!first) {
+    // the preconditioner of iteration it wrote r.z into the slot of parity it+1
+    const int new_slot = gate.rr_slot == kPartRR0 ? kPartRZ0 : kPartRZ1;
+    const int old_slot = new_slot == kPartRZ0 ? kPartRZ1 : kPartRZ0;
+    const double rzn = sum_parts(part_slot(parts, new_slot, sys), gate.np, sh);
+    const double rzo = sum_parts(part_slot(parts, old_slot, sys), gate.np, sh);
+    double num = rzn;
+    if (flexible) num -= sum_parts(part_slot(parts, kPartRZO, sys), gate.np, sh);
+    beta = num / rzo;
+    if (!(rzn > 0.0) || !isfinite(beta)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) istate[kStBreak * kMaxSys + sys] = 1;
+      return;
+    }
+  }
+  const size_t off = (size_t)sys * g.ndof;
+  const int64_t nv = g.nnodes * g.dim;
+  // DOF-contiguous sweep: the node partition of the other kernels is not
+  // needed here because nothing is reduced
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
+       i += (int64_t)gridDim.x * kThreads)
+    p[off + i] = z[off + i] + beta * p[off + i];
+}
+
+__global__ void k_poll(Gate gate, int* __restrict__ istate) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.x;
+  const bool run = gate_running(gate, sys, sh);
+  if (threadIdx.x == 0) istate[kStPoll * kMaxSys + sys] = run ? 1 : 0;
+}
+
+// partials of ||P (f - q)||^2 into slot Aux
+__global__ __launch_bounds__(kThreads) void k_true_residual(
+    Geometry g, const double* __restrict__ f, const double* __restrict__ q,
+    const uint8_t* __restrict__ fixed, double* __restrict__ parts) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.y;
+  const size_t off = (size_t)sys * g.ndof;
+  double a = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
+       n += (int64_t)gridDim.x * kThreads) {
+    for (int c = 0; c < g.dim; ++c) {
+      const size_t i = g.dim * n + c;
+      const double v = fixed[i] ? 0.0 : f[off + i] - q[off + i];
+      a += v * v;
+    }
+  }
+  const double s = block_sum(a, sh);
+  if (threadIdx.x == 0) part_slot(parts, kPartAux, sys)[blockIdx.x] = s;
+}
+
+// out[sys] = {iterations, status, relres, true_relres}
+__global__ void k_finalize(Gate gate, const double* __restrict__ parts,
+                           const int* __restrict__ istate, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int sys = blockIdx.x;
+  const double rr = sum_parts(part_slot(const_cast<double*>(parts), gate.rr_slot, sys), gate.np, sh);
+  const double ff = sum_parts(part_slot(const_cast<double*>(parts), kPartFF, sys), gate.np, sh);
+  const double tr = sum_parts(part_slot(const_cast<double*>(parts), kPartAux, sys), gate.np, sh);
+  if (threadIdx.x == 0) {
+    const int brk = istate[kStBreak * kMaxSys + sys];
+    double status = TPCG_OK;
+    if (brk) status = TPCG_EBREAKDOWN;
+    else if (!(rr <= gate.tol2 * ff)) status = TPCG_ENOCONV;
+    out[4 * sys + 0] = istate[kStLastIt * kMaxSys + sys];
+    out[4 * sys + 1] = status;
+    out[4 * sys + 2] = ff > 0.0 ? sqrt(rr / ff) : 0.0;
+    out[4 * sys + 3] = ff > 0.0 ? sqrt(tr / ff) : 0.0;
+  }
+}
+
+}  // namespace
+
+void launch_residual_init(const Handle& h, const double* f, double* u, const double* q, int nsys,
+                          hipStream_t st) {
+  dim3 grid(parts_for(h.g.nnodes), nsys);
+  hipLaunchKernelGGL(k_residual_init, grid, dim3(kThreads), 0, st, h.g, f, u, q, h.r, h.fixed,
+                     h.parts, h.istate);
+}
+
+void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hipStream_t st) {
+  dim3 grid(parts_for(h.g.nnodes), nsys);
+  hipLaunchKernelGGL(k_update_xr, grid, dim3(kThreads), 0, st, h.g, u, h.r, h.p, h.q, h.parts,
+                     h.istate, gate);
+}
+
+void launch_update_p(const Handle& h, int nsys, const Gate& gate, int flexible, int first,
+                     hipStream_t st) {
+  dim3 grid(parts_for(h.g.nnodes), nsys);
+  hipLaunchKernelGGL(k_update_p, grid, dim3(kThreads), 0, st, h.g, h.p, h.z, h.parts, h.istate,
+                     gate, flexible, first);
+}
+
+void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_poll, dim3(nsys), dim3(kThreads), 0, st, gate, h.istate);
+}
+
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st) {
+  hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+}
+
+// True residual and the per-system summary; q must already hold K u.
+void launch_summary(const Handle& h, const double* f, int nsys, const Gate& gate, double* out,
+                    hipStream_t st) {
+  dim3 grid(parts_for(h.g.nnodes), nsys);
+  hipLaunchKernelGGL(k_true_residual, grid, dim3(kThreads), 0, st, h.g, f, h.q, h.fixed, h.parts);
+  hipLaunchKernelGGL(k_finalize, dim3(nsys), dim3(kThreads), 0, st, gate, h.parts, h.istate, out);
+}
+
+}  // namespace tpcg

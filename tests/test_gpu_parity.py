@@ -1,0 +1,226 @@
+"""GPU parity tests: every entry point of the C-ABI against the FP64 oracle on
+the same seeded inputs (small meshes spanning several subdomains)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import density, fem, schwarz
+from paper_1411_3923_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1411_3923_amd as T  # noqa: E402
+from tests.gpu_common import dev, handle, host, rel  # noqa: E402
+
+
+def c1():
+    return W.mbb_64x32()
+
+
+def small_cantilever(nelx=128, nely=64, sub=16, k=6):
+    return W.cantilever2d(nelx, nely, sub, k)
+
+
+def small_3d():
+    p = W.cantilever3d(12, 6, 6, sub=3, k=6)
+    return p
+
+
+@pytest.mark.parametrize("which", ["c1", "cantilever", "h8"])
+def test_apply_K_matches_assembled_operator(which):
+    p = {"c1": c1, "cantilever": small_cantilever, "h8": small_3d}[which]()
+    rng = np.random.default_rng(11)
+    rho = rng.uniform(0.0, 1.0, p.n_el)
+    x = rng.standard_normal(p.n_dof)
+    fixed = W.fixed_mask(p)
+    K = fem.assemble(p, fem.simp_modulus(rho, p.E0, p.Emin, p.penal))
+    free = (fixed == 0).astype(float)
+    want = free * (K @ (free * x))
+    h = handle(p, nsys=1)
+    y = dev(np.zeros(p.n_dof))
+    h.apply_K(dev(rho), dev(x), y)
+    got = host(y)
+    assert rel(got, want) < 1e-13
+    assert np.all(got[fixed == 1] == 0.0)
+
+
+def test_filter_projection_and_adjoint():
+    p = small_cantilever()
+    rho = W.design_field(p)
+    etas = (0.3, 0.5, 0.7)
+    rt_o, rb_o = density.filter_project(p, rho, 2.0, 8.0, etas)
+    h = handle(p)
+    rt = dev(np.zeros(p.n_el))
+    rb = dev(np.zeros((3, p.n_el)))
+    h.filter_project(dev(rho), 2.0, 8.0, etas, rt, rb)
+    np.testing.assert_allclose(host(rt), rt_o, rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(host(rb), rb_o, rtol=1e-13, atol=1e-14)
+    g = np.random.default_rng(2).standard_normal((3, p.n_el))
+    adj_o = density.filter_project_adjoint(p, rt_o, 2.0, 8.0, etas, g)
+    out = dev(np.zeros((3, p.n_el)))
+    h.filter_project_adjoint(dev(rt_o), 2.0, 8.0, etas, dev(g), out)
+    np.testing.assert_allclose(host(out), adj_o, rtol=1e-12, atol=1e-13)
+
+
+def test_compliance_and_sensitivity():
+    p = small_cantilever()
+    rng = np.random.default_rng(5)
+    rho = rng.uniform(0.1, 1.0, (3, p.n_el))
+    u = rng.standard_normal((3, p.n_dof))
+    u[:, W.fixed_mask(p) == 1] = 0.0
+    f = np.stack([W.load_vector(p)] * 3)
+    h = handle(p)
+    c = dev(np.zeros(3))
+    dc = dev(np.zeros((3, p.n_el)))
+    h.compliance_and_sensitivity(dev(rho), dev(u), dev(f), c, dc)
+    for s in range(3):
+        assert host(c)[s] == pytest.approx(fem.compliance(f[s], u[s]), rel=1e-13, abs=1e-14)
+        np.testing.assert_allclose(host(dc)[s], fem.sensitivity(p, rho[s], u[s]), rtol=1e-12,
+                                   atol=1e-12)
+
+
+def _eig_compare(p, rho):
+    h = handle(p, nsys=1)
+    h.build_coarse_basis(dev(rho[None, :]), rep=0)
+    phi, lam, res = h.export_coarse_basis()
+    phi = host(phi)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    fixed = W.fixed_mask(p)
+    worst_lam, worst_angle = 0.0, 0.0
+    for j in range(p.n_sub):
+        lo, psi, dofs = schwarz.local_eigenpairs(p, E, fixed, j, p.k + 1)
+        # GPU local order: node x fastest, then component; free DOFs only in the oracle
+        nodes = schwarz.subdomain_nodes(p, j)
+        alld = (p.dim * nodes[:, None] + np.arange(p.dim)[None, :]).ravel()
+        free = fixed[alld] == 0
+        g = phi[j][free]
+        # only compare spans when the cut is clean
+        gap = (lo[p.k] - lo[p.k - 1]) / max(lo[p.k], 1e-300)
+        scale = np.maximum(np.abs(lo[:p.k]), 1e-6 * max(lo[p.k - 1], 1e-12))
+        worst_lam = max(worst_lam, float(np.max(np.abs(lam[j] - lo[:p.k]) / scale)))
+        if gap > 0.05:
+            chi = schwarz.partition_of_unity(p)[dofs // p.dim]
+            A = psi[:, :p.k] * chi[:, None]
+            qa, _ = np.linalg.qr(A)
+            qb, _ = np.linalg.qr(g)
+            s = np.linalg.svd(qa.T @ qb, compute_uv=False)
+            worst_angle = max(worst_angle, float(np.sqrt(max(0.0, 1.0 - s.min() ** 2))))
+    return worst_lam, worst_angle, res
+
+
+def test_eigenbasis_matches_dense_eigensolver_c1():
+    p = c1()
+    rho = W.design_field(p)
+    wl, wa, res = _eig_compare(p, rho)
+    assert wl < 1e-7, wl
+    assert wa < 1e-6, wa
+    assert np.max(res) < 1e-6
+
+
+def test_preconditioner_matches_oracle_c1():
+    p = c1()
+    rho = W.design_field(p)
+    fixed = W.fixed_mask(p)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    K = fem.assemble(p, E)
+    Phi, _ = schwarz.coarse_basis(p, E, fixed, p.k)
+    M = schwarz.TwoLevelSchwarz(p, K, fixed, Phi)
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(p.n_dof)
+    r[fixed == 1] = 0.0
+    want = M.apply(r)
+    h = handle(p, nsys=1)
+    h.build_coarse_basis(dev(rho[None, :]), rep=0)
+    z = dev(np.zeros(p.n_dof))
+    h.apply_precond(dev(r), z)
+    assert rel(host(z), want) < 1e-7
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED])
+def test_pcg_solve_c1_matches_direct(precision):
+    p = c1()
+    rho = W.design_field(p)
+    f = W.load_vector(p)
+    u_o = fem.solve(p, rho)
+    c_o = fem.compliance(f, u_o)
+    h = handle(p, precision=precision, nsys=1)
+    h.build_coarse_basis(dev(rho[None, :]), rep=0)
+    u = dev(np.zeros(p.n_dof))
+    info = h.pcg_solve(dev(rho[None, :]), dev(f[None, :]), u, rtol=1e-12, maxit=2000)
+    assert info[0]["status"] == 0, info
+    uu = host(u)
+    tol = 1e-8 if precision == T.FP64 else 1e-6
+    assert rel(uu, u_o) < tol
+    assert abs(fem.compliance(f, uu) - c_o) / c_o < tol
+    # iteration count of the same method in the oracle, at the bench tolerance
+    if precision == T.FP64:
+        _, it_o, _ = schwarz.solve_pcg(p, [rho], rho, f, W.fixed_mask(p), rtol=1e-8)[0]
+        u2 = dev(np.zeros(p.n_dof))
+        info2 = h.pcg_solve(dev(rho[None, :]), dev(f[None, :]), u2, rtol=1e-8, maxit=2000)
+        assert abs(info2[0]["iters"] - it_o) <= 2, (info2, it_o)
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED])
+def test_three_realisations_cantilever(precision):
+    p = small_cantilever()
+    rho = W.design_field(p)
+    etas = p.etas
+    h = handle(p, precision=precision)
+    rt = dev(np.zeros(p.n_el))
+    rb = dev(np.zeros((3, p.n_el)))
+    h.filter_project(dev(rho), p.rmin, p.beta, etas, rt, rb)
+    h.build_coarse_basis(rb, rep=0)
+    f = W.load_vector(p)
+    F = dev(np.stack([f] * 3))
+    u = dev(np.zeros((3, p.n_dof)))
+    info = h.pcg_solve(rb, F, u, rtol=1e-12, maxit=3000)
+    assert all(i["status"] == 0 for i in info), info
+    _, rb_o = density.filter_project(p, rho, p.rmin, p.beta, etas)
+    uu = host(u)
+    c = dev(np.zeros(3))
+    dc = dev(np.zeros((3, p.n_el)))
+    h.compliance_and_sensitivity(rb, u, F, c, dc)
+    tol = 1e-8 if precision == T.FP64 else 1e-6
+    for s in range(3):
+        u_o = fem.solve(p, rb_o[s])
+        c_o = fem.compliance(f, u_o)
+        assert rel(uu[s], u_o) < tol
+        assert abs(host(c)[s] - c_o) / c_o < tol
+        dc_o = fem.sensitivity(p, rb_o[s], u_o)
+        assert rel(host(dc)[s], dc_o) < tol
+
+
+def test_batch_result_equals_single_system_bitwise():
+    # the per-system reductions do not depend on the other systems in a launch
+    p = small_cantilever()
+    rho = W.design_field(p)
+    _, rb_o = density.filter_project(p, rho, p.rmin, p.beta, p.etas)
+    f = W.load_vector(p)
+    h3 = handle(p)
+    h3.build_coarse_basis(dev(rb_o), rep=0)
+    u3 = dev(np.zeros((3, p.n_dof)))
+    h3.pcg_solve(dev(rb_o), dev(np.stack([f] * 3)), u3, rtol=1e-8)
+    h1 = handle(p, nsys=1)
+    u1 = dev(np.zeros(p.n_dof))
+    # same basis source (system 0) and the same factors for system 0
+    h1.build_coarse_basis(dev(rb_o[:1]), rep=0)
+    h1.pcg_solve(dev(rb_o[:1]), dev(f[None, :]), u1, rtol=1e-8)
+    assert np.array_equal(host(u3)[0], host(u1))
+
+
+def test_error_paths():
+    p = c1()
+    h = handle(p, nsys=1)
+    z = dev(np.zeros(p.n_dof))
+    with pytest.raises(T.TpcgError) as e:
+        h.apply_precond(z, z)
+    assert e.value.code == -6
+    rho = dev(W.design_field(p)[None, :])
+    h.build_coarse_basis(rho)
+    info = h.pcg_solve(rho, dev(W.load_vector(p)[None, :]), z, rtol=1e-12, maxit=1)
+    assert info[0]["status"] == 1 and info[0]["iters"] == 1
