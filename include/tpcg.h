@@ -192,6 +192,19 @@ int tpcg_export_coarse_basis(tpcg_handle* h, double* phi, double* lambda, double
  * out[7] coarse block size, out[8] coarse block count. */
 int tpcg_query(const tpcg_handle* h, int64_t* out9);
 
+/*
+ * Measurement support. With profiling on, tpcg_pcg_solve records HIP events
+ * around every launch of its batched block-solve kernel (the local subdomain
+ * and coarse triangular solves of M^-1) on the handle's stream and
+ * accumulates, over the launches in which at least one system was still
+ * iterating: out3[0] the number of launches, out3[1] their summed duration
+ * in milliseconds, out3[2] their summed algorithmic bytes (band Cholesky
+ * factors read twice, right-hand sides read and results written once).
+ * tpcg_set_profiling resets the accumulators.
+ */
+int tpcg_set_profiling(tpcg_handle* h, int32_t on);
+int tpcg_profile_block_solves(const tpcg_handle* h, double* out3);
+
 const char* tpcg_last_error(const tpcg_handle* h);
 void tpcg_destroy(tpcg_handle* h);
 

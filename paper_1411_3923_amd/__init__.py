@@ -50,7 +50,8 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_apply_K", "tpcg_apply_precond", "tpcg_pcg_solve",
            "tpcg_compliance_and_sensitivity", "tpcg_filter_project",
            "tpcg_filter_project_adjoint", "tpcg_export_coarse_basis", "tpcg_query",
-           "tpcg_last_error", "tpcg_destroy"]
+           "tpcg_set_profiling", "tpcg_profile_block_solves", "tpcg_last_error",
+           "tpcg_destroy"]
 
 
 def load_library(path: str | None = None):
@@ -75,6 +76,8 @@ def load_library(path: str | None = None):
     lib.tpcg_filter_project_adjoint.argtypes = [P, P, D, D, ctypes.POINTER(D), I32, P, P]
     lib.tpcg_export_coarse_basis.argtypes = [P, P, P, P]
     lib.tpcg_query.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
+    lib.tpcg_set_profiling.argtypes = [P, I32]
+    lib.tpcg_profile_block_solves.argtypes = [P, ctypes.POINTER(D)]
     lib.tpcg_last_error.argtypes = [P]
     lib.tpcg_last_error.restype = ctypes.c_char_p
     lib.tpcg_destroy.argtypes = [P]
@@ -212,6 +215,14 @@ class Handle:
             _ptr(dc_drho_phys, torch.float64, nsys * self.n_el),
             _ptr(dc_drho, torch.float64, nsys * self.n_el)))
         return dc_drho
+
+    def set_profiling(self, on=True):
+        self._check(self.lib.tpcg_set_profiling(self.h, 1 if on else 0))
+
+    def profile_block_solves(self):
+        out = (ctypes.c_double * 3)()
+        self._check(self.lib.tpcg_profile_block_solves(self.h, out))
+        return dict(launches=int(out[0]), ms=out[1], bytes=out[2])
 
     def export_coarse_basis(self):
         import numpy as np

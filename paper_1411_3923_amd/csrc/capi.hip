@@ -132,6 +132,8 @@ void release(Handle* h) {
     if (e) hipEventDestroy(e);
   if (h->t0) hipEventDestroy(h->t0);
   if (h->t1) hipEventDestroy(h->t1);
+  for (auto& e : h->prof_ev)
+    if (e) hipEventDestroy(e);
 }
 
 int check_hip(Handle* h, const char* where) {
@@ -142,6 +144,28 @@ int check_hip(Handle* h, const char* where) {
     return TPCG_EHIP;
   }
   return TPCG_OK;
+}
+
+// Minimum bytes one system's share of a block-solve launch must move: a band
+// Cholesky factor read twice (forward and backward) for every subdomain and
+// for the coarse matrix, the right-hand sides read once and the results
+// written once. The half-bandwidth of a subdomain matrix in box order is
+// dim * (bn^(dim-1) + ... + bn + 1) + dim - 1; that of the coarse matrix in
+// block order is nbc + 2k - 1.
+double band_bytes(int64_t n, int64_t w, int elem) {
+  const int64_t full = n * (w + 1) - (w * (w + 1)) / 2;   // rows shorter near the top
+  return (double)full * elem;
+}
+
+double block_solve_bytes(const Geometry& g, int elem) {
+  int64_t w = 1;
+  for (int a = 1; a < g.dim; ++a) w = w * g.bn + 1;
+  w = g.dim * w + g.dim - 1;
+  const double local = g.nsub * (2.0 * band_bytes(g.nloc, std::min<int64_t>(w, g.nloc - 1), elem) +
+                                 (double)g.nloc * (8 + elem));
+  const int64_t wc = std::min<int64_t>(g.nbc + 2 * g.k - 1, g.nt - 1);
+  const double coarse = 2.0 * band_bytes(g.nt, wc, 8) + 16.0 * g.nt;
+  return local + coarse;
 }
 
 Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int enabled) {
@@ -289,7 +313,7 @@ int tpcg_apply_precond(tpcg_handle* hh, const double* r, double* z, int32_t nsys
   if (!r || !z) return fail(hh, TPCG_EINVAL, "NULL array");
   if (nsys != h->nsys_built) return fail(hh, TPCG_EINVAL, "nsys differs from the build");
   Gate nog = make_gate(h, kPartRR0, 0, 1, 0.0, 0);
-  launch_precond(*h, r, z, nsys, nog, kPartAux, kPartAux, 0, h->stream);
+  launch_precond(*h, r, z, nsys, nog, kPartAux, -2, 0, h->stream);
   return check_hip(h, "tpcg_apply_precond");
 }
 
@@ -314,7 +338,8 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   nog.enabled = 0;
   launch_apply_K(*h, rho_phys, u, h->q, nsys, -1, nog, st);
   launch_residual_init(*h, f, u, h->q, nsys, st);
-  launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, kPartRZ0, flexible, st);
+  h->prof_n = 0;
+  launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, -1, flexible, st);
   launch_update_p(*h, nsys, g0, flexible, 1, st);
   int it = 0;
   int chunk = 0;
@@ -328,7 +353,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
       Gate gn = make_gate(h, rr_next, it + 1, maxit, tol2, 1);
       launch_apply_K(*h, rho_phys, h->p, h->q, nsys, kPartPQ, gi, st);
       launch_update_xr(*h, u, nsys, gi, st);
-      launch_precond(*h, h->r, h->z, nsys, gn, rz_next, rz_next, flexible, st);
+      launch_precond(*h, h->r, h->z, nsys, gn, rz_next, it, flexible, st);
       launch_update_p(*h, nsys, gn, flexible, 0, st);
     }
     const int slot = chunk & 1;
@@ -371,6 +396,22 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     const int st_s = info[s].status;
     if (st_s < 0 && (worst >= 0 || st_s < worst)) worst = st_s;
     else if (worst == TPCG_OK && st_s > 0) worst = st_s;
+  }
+  if (h->prof_on) {
+    // attribute each timed block-solve launch its algorithmic bytes: only the
+    // systems still running at that iteration did work
+    const Geometry& g = h->g;
+    const double per_sys = block_solve_bytes(g, h->mixed ? 4 : 8);
+    for (int i = 0; i < h->prof_n; ++i) {
+      int running = 0;
+      for (int s = 0; s < nsys; ++s) running += info[s].iters >= h->prof_it[i] + 2;
+      if (!running) continue;
+      float lms = 0.0f;
+      hipEventElapsedTime(&lms, h->prof_ev[2 * i], h->prof_ev[2 * i + 1]);
+      h->prof_ms += lms;
+      h->prof_bytes += running * per_sys;
+      h->prof_launches += 1;
+    }
   }
   if (worst == TPCG_EBREAKDOWN) h->err = "PCG breakdown (p^T K p <= 0, r^T z <= 0 or NaN)";
   else if (worst == TPCG_ENOCONV) h->err = "maxit reached before rtol";
@@ -442,6 +483,25 @@ int tpcg_query(const tpcg_handle* hh, int64_t* out) {
   const Geometry& g = h->g;
   int64_t v[9] = {g.ndof, g.nel, g.nsub, g.nloc, g.k, g.nb, g.nblk, g.nbc, g.nblkc};
   std::memcpy(out, v, sizeof(v));
+  return TPCG_OK;
+}
+
+int tpcg_set_profiling(tpcg_handle* hh, int32_t on) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  h->prof_on = on ? 1 : 0;
+  h->prof_ms = 0.0;
+  h->prof_bytes = 0.0;
+  h->prof_launches = 0;
+  return TPCG_OK;
+}
+
+int tpcg_profile_block_solves(const tpcg_handle* hh, double* out3) {
+  const Handle* h = H(hh);
+  if (!h || !out3) return TPCG_EINVAL;
+  out3[0] = (double)h->prof_launches;
+  out3[1] = h->prof_ms;
+  out3[2] = h->prof_bytes;
   return TPCG_OK;
 }
 

@@ -175,25 +175,39 @@ void solves_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipSt
 }  // namespace
 
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
-                    int rz_slot, int rz_keep_slot, int flexible, hipStream_t st) {
-  (void)rz_keep_slot;
+                    int rz_slot, int prof_it, int flexible, hipStream_t st) {
   const Geometry& g = h.g;
+  const bool prof = h.prof_on && prof_it >= -1;
+  if (prof && (size_t)(2 * h.prof_n + 2) > h.prof_ev.size()) {
+    const size_t old = h.prof_ev.size();
+    h.prof_ev.resize(old + 512, nullptr);
+    h.prof_it.resize(h.prof_ev.size() / 2, 0);
+    for (size_t i = old; i < h.prof_ev.size(); ++i) hipEventCreate(&h.prof_ev[i]);
+  }
+  auto mark = [&](int which) {
+    if (prof) hipEventRecord(h.prof_ev[2 * h.prof_n + which], st);
+  };
   dim3 egrid(parts_for(g.nnodes), nsys);
   if (h.mixed) {
     hipLaunchKernelGGL(k_restrict<float>, dim3(g.nsub), dim3(kThreads), 0, st, g, h.phi32, r,
                        h.yc, nsys, gate);
+    mark(0);
     solves_launch<float>(h, r, nsys, gate, st);
+    mark(1);
     hipLaunchKernelGGL((k_extend<float, float>), egrid, dim3(kThreads), 0, st, g, r, z,
                        reinterpret_cast<const float*>(h.zloc), h.phi32, h.xc, h.fixed, h.parts,
                        rz_slot, flexible, gate);
   } else {
     hipLaunchKernelGGL(k_restrict<double>, dim3(g.nsub), dim3(kThreads), 0, st, g, h.phi, r,
                        h.yc, nsys, gate);
+    mark(0);
     solves_launch<double>(h, r, nsys, gate, st);
+    mark(1);
     hipLaunchKernelGGL((k_extend<double, double>), egrid, dim3(kThreads), 0, st, g, r, z,
                        reinterpret_cast<const double*>(h.zloc), h.phi, h.xc, h.fixed, h.parts,
                        rz_slot, flexible, gate);
   }
+  if (prof) h.prof_it[h.prof_n++] = prof_it;
 }
 
 }  // namespace tpcg

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "tpcg.h"
 
@@ -87,6 +88,14 @@ struct Handle {
   int* dflag = nullptr;              // device error flags [4]
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t t0 = nullptr, t1 = nullptr;
+
+  // optional event timing of the block-solve launches inside pcg_solve
+  int prof_on = 0;
+  int prof_n = 0;                    // launches recorded in the current solve
+  std::vector<hipEvent_t> prof_ev;   // [2 * capacity]
+  std::vector<int> prof_it;          // PCG iteration of each recorded launch (-1: initial)
+  double prof_ms = 0.0, prof_bytes = 0.0;
+  int64_t prof_launches = 0;
 };
 
 // Partial-sum slots, each [kMaxSys][kMaxParts] doubles.
@@ -193,8 +202,9 @@ void launch_summary(const Handle& h, const double* f, int nsys, const Gate& gate
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 
 // precond.hip: z = M^-1 r, gated; partials of r.z into rz_slot (and r.z_old into kPartRZO)
+// prof_it >= -1 records events around the block-solve launch when profiling is on
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
-                    int rz_slot, int rz_keep_slot, int flexible, hipStream_t st);
+                    int rz_slot, int prof_it, int flexible, hipStream_t st);
 
 // setup.hip
 int build_preconditioner(Handle& h, const double* rho, int nsys, int rep);
