@@ -2,12 +2,20 @@
 // workgroup per matrix.
 //
 // A symmetric positive definite block-tridiagonal matrix with nblk diagonal
-// blocks of size nb factors as A = L L^T with L block lower bidiagonal. The
-// factor is stored per block row b as two dense nb x nb row-major matrices:
-//   slot 0: D_b = L_bb^-1      (lower triangular; zeros above the diagonal)
-//   slot 1: B_b = L_{b,b-1}    (B_0 unused)
-// so that L y = r reads y_b = D_b (r_b - B_b y_{b-1}) and L^T x = y reads
-// x_b = D_b^T (y_b - B_{b+1}^T x_{b+1}): every step is a dense product.
+// blocks of size nb factors as A = L L^T with L block lower bidiagonal:
+// L_bb lower triangular, B_b = L_{b,b-1}. If A has half-bandwidth w, B_{b+1}
+// vanishes left of the band: B_{b+1}[r][c] = 0 for c < r - (w - nb), so it is
+// an upper triangle plus pe = w - nb + 1 diagonals on and below the main one.
+//
+// Packed storage, one record of `bstride` elements per block row b:
+//   Sq_b [nb][nb]: lower triangle (c <= r) = D_b = L_bb^-1,
+//                  strict upper triangle (c > r) = B_{b+1}   (zero for the last b)
+//   Bd_b [nb][pe]: Bd_b[r][t] = B_{b+1}[r][r - t]            (zero outside)
+// That is exactly the band of L (plus the triangles of the inverted diagonal
+// blocks, which replace the triangles of L_bb one for one). Then
+//   L y = r:    y_b = D_b (r_b - B_b y_{b-1})       uses Sq_{b-1} (upper) and Sq_b (lower)
+//   L^T x = y:  x_b = D_b^T (y_b - B_{b+1}^T x_{b+1})  uses Sq_b only
+// and every pass reads each record once.
 //
 // Subdomain stiffness matrices in box order (node x fastest, then y, then z)
 // are block tridiagonal with one node row (2D) or node layer (3D) per block.
@@ -17,202 +25,242 @@
 
 namespace tpcg {
 
-// odd leading dimension: conflict-free LDS columns and rows
+// 16-byte register vector (a native vector type, so that arrays of it stay in
+// registers)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct BtriShape {
+  int nb, nblk, pe, bstride;
+};
+
+inline BtriShape btri_shape(int nb, int nblk, int w) {
+  BtriShape s;
+  s.nb = nb;
+  s.nblk = nblk;
+  s.pe = w - nb + 1 > 0 ? w - nb + 1 : 0;
+  if (s.pe > nb) s.pe = nb;
+  const int e = nb * nb + nb * s.pe;
+  s.bstride = (e + 3) & ~3;   // 16-byte records for both FP64 and FP32
+  return s;
+}
+
+// odd leading dimension: conflict-free LDS columns and rows (factorisation)
 __host__ __device__ inline int lds_ld(int nb) { return nb | 1; }
 
-// Partial products of y = M v (trans = false) or y = M^T v (trans = true) for
-// M in LDS (nb x nb, leading dimension ld). Thread t handles row (or column)
-// t % nb over the chunk t / nb of the summation index and writes its partial
-// to red[chunk * nb + row]. The caller sums the chunks after a barrier.
 template <typename T>
-__device__ inline void lds_gemv_parts(const T* M, int ld, int nb, const T* v, T* red, bool trans) {
+__host__ __device__ constexpr int stage_regs_for(int nb, int pe) {
+  return ((((nb * nb + nb * pe + 3) & ~3) * (int)sizeof(T)) / 16 + kThreads - 1) / kThreads;
+}
+
+// staging register counts the kernels are instantiated for
+inline int stage_bucket(int need) {
+  const int b[] = {2, 5, 10, 16, 24, 36};
+  for (int v : b)
+    if (need <= v) return v;
+  return -1;
+}
+
+__host__ __device__ inline BtriShape local_shape(const Geometry& g) {
+  return {g.nb, g.nblk, g.pe, g.bstride};
+}
+__host__ __device__ inline BtriShape coarse_shape(const Geometry& g) {
+  return {g.nbc, g.nblkc, g.pec, g.bstridec};
+}
+
+// factor.hip
+template <typename T>
+void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
+                   hipStream_t st);
+void launch_solve_multi(const double* fac, const BtriShape& sh, int nmat, int m, const double* X,
+                        double* Y, hipStream_t st);
+// dense symmetric inverse [nmat][n][n] of packed factors (n = nb * nblk)
+void launch_inverse(const double* fac, const BtriShape& sh, int nmat, double* Xinv,
+                    hipStream_t st);
+
+// LDS element count of btri_solve for shape s and NR right-hand sides
+__host__ __device__ inline size_t btri_solve_lds_elems(const BtriShape& s, int nr) {
+  return (size_t)s.bstride + 2 * (size_t)s.nb * nr + (size_t)kThreads * nr;
+}
+
+// Partial sums of one of the four triangular products for all nr columns of
+// v ([nb][nr] row-major) into red[q][i][r]: thread t owns output row (or
+// column) i = t % nb over the chunk q = t / nb of the summation index.
+//   MODE 0: y = lower(M) v            MODE 2: y = lower(M)^T v
+//   MODE 1: y = (upper(M) + band) v   MODE 3: y = (upper(M) + band)^T v
+// upper(M) is the strict upper triangle; band[i][t] multiplies v[i - t].
+template <typename T, int NR, int MODE>
+__device__ inline void tri_parts(const T* __restrict__ M, int ld, const T* __restrict__ E, int pe,
+                                 int nb, const T* __restrict__ v, int nr, T* __restrict__ red) {
   const int t = threadIdx.x;
   const int Q = kThreads / nb;
   const int L = (nb + Q - 1) / Q;
   const int i = t % nb, q = t / nb;
-  if (q < Q) {
-    const int c0 = q * L;
-    const int c1 = min(nb, c0 + L);
-    T acc = 0;
-    if (!trans) {
-      for (int c = c0; c < c1; ++c) acc += M[i * ld + c] * v[c];
-    } else {
-      for (int c = c0; c < c1; ++c) acc += M[c * ld + i] * v[c];
-    }
-    red[q * nb + i] = acc;
+  if (q >= Q) return;
+  T acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = 0;
+  const int c0 = q * L, c1 = min(nb, c0 + L);
+  int lo, hi;
+  if (MODE == 0) { lo = c0; hi = min(c1, i + 1); }
+  else if (MODE == 1) { lo = max(c0, i + 1); hi = c1; }
+  else if (MODE == 2) { lo = max(c0, i); hi = c1; }
+  else { lo = c0; hi = min(c1, i); }
+  for (int c = lo; c < hi; ++c) {
+    const T a = (MODE < 2) ? M[i * ld + c] : M[c * ld + i];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r < nr) acc[r] += a * v[c * nr + r];
   }
+  if (q == 0) {
+    if (MODE == 1) {
+      for (int tt = 0; tt < pe && i - tt >= 0; ++tt) {
+        const T a = E[i * pe + tt];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) acc[r] += a * v[(i - tt) * nr + r];
+      }
+    } else if (MODE == 3) {
+      for (int tt = 0; tt < pe && i + tt < nb; ++tt) {
+        const T a = E[(i + tt) * pe + tt];
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          if (r < nr) acc[r] += a * v[(i + tt) * nr + r];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+    if (r < nr) red[((size_t)q * nb + i) * nr + r] = acc[r];
 }
 
 template <typename T>
-__device__ inline T lds_gemv_sum(const T* red, int nb, int i) {
+__device__ inline T red_sum(const T* red, int nb, int nr, int i, int r) {
   const int Q = kThreads / nb;
   T s = 0;
-  for (int q = 0; q < Q; ++q) s += red[q * nb + i];
+  for (int q = 0; q < Q; ++q) s += red[((size_t)q * nb + i) * nr + r];
   return s;
 }
 
-// Register staging of one nb x nb matrix (nb even) read with 16-byte loads.
-template <typename T, int MAXV>
-struct MatStage {
-  uint4 v[MAXV];
-
-  __device__ inline void load(const T* src, int nv) {
-    const uint4* s = reinterpret_cast<const uint4*>(src);
-#pragma unroll
-    for (int k = 0; k < MAXV; ++k) {
-      const int idx = threadIdx.x + k * kThreads;
-      if (idx < nv) v[k] = s[idx];
-    }
-  }
-
-  __device__ inline void store(T* M, int ld, int nb, int nv) {
-    constexpr int PER = 16 / sizeof(T);
-    // element flat index f = PER * (t + 256 k): advance row/col incrementally
-    const int step = PER * kThreads;
-    const int dq = step / nb, dr = step - dq * nb;
-    int f0 = PER * threadIdx.x;
-    int row = f0 / nb, col = f0 - row * nb;
-#pragma unroll
-    for (int k = 0; k < MAXV; ++k) {
-      const int idx = threadIdx.x + k * kThreads;
-      if (idx < nv) {
-        const T* e = reinterpret_cast<const T*>(&v[k]);
-        int rr = row, cc = col;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          M[rr * ld + cc] = e[u];
-          if (++cc == nb) { cc = 0; ++rr; }
-        }
-      }
-      col += dr;
-      row += dq;
-      if (col >= nb) { col -= nb; ++row; }
-    }
-  }
-};
-
-template <typename T>
-constexpr int stage_regs() { return sizeof(T) == 8 ? 18 : 9; }   // nb <= 96
-
-// LDS bytes of btri_solve for block size nb
-template <typename T>
-inline size_t btri_solve_lds(int nb) {
-  return sizeof(T) * ((size_t)nb * lds_ld(nb) + 2 * (size_t)nb + kThreads);
-}
-
-// Solve (L L^T) x = r for one block-tridiagonal factor `fac`
-// ([nblk][2][nb][nb], T). rhs(b, i) returns element i of block b of r;
-// out(b, i) is a T array slot that receives y (forward) and then x. The
-// same thread reads back what it wrote, so no fence is needed.
-template <typename T, typename Rhs, typename Out>
-__device__ void btri_solve(const T* __restrict__ fac, int nb, int nblk, Rhs rhs, Out out,
+// Solve (L L^T) X = R for one packed factor `fac` ([nblk][bstride] of T) and
+// nr <= NR right-hand sides. rhs(b, i, r) returns R's element (row i of block
+// b, column r); out(b, i, r) is a T slot receiving Y (forward) and then X.
+// Each vector element is handled by one fixed thread in both passes, so the
+// reads of Y in the backward pass see that thread's own forward writes.
+template <typename T, int NR, int MAXV, typename Rhs, typename Out>
+__device__ void btri_solve(const T* __restrict__ fac, const BtriShape sh, int nr, Rhs rhs, Out out,
                            unsigned char* smem) {
-  const int ld = lds_ld(nb);
+  const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
+  const int ld = nb;                              // LDS holds the record as stored
   T* M = reinterpret_cast<T*>(smem);
-  T* va = M + (size_t)nb * ld;
-  T* vb = va + nb;
-  T* red = vb + nb;
-  const int nv = nb * nb * (int)sizeof(T) / 16;
-  const size_t msz = (size_t)nb * nb;
+  T* E = M + (size_t)nb * nb;
+  T* va = M + sh.bstride;
+  T* vb = va + (size_t)nb * nr;
+  T* red = vb + (size_t)nb * nr;
+  const int nv = sh.bstride * (int)sizeof(T) / 16;
   const int t = threadIdx.x;
-  // step s -> matrix: forward D0, B1, D1, ..., B_{n-1}, D_{n-1};
-  // backward B_{n-1}, D_{n-2}, B_{n-2}, ..., B_1, D_0
-  const int nf = 2 * nblk - 1;
-  const int S = nf + 2 * (nblk - 1);
-  auto mat = [&](int s) -> const T* {
-    int b, slot;
-    if (s < nf) { b = (s + 1) / 2; slot = (s & 1) ? 1 : 0; }
-    else {
-      const int u = s - nf;
-      if ((u & 1) == 0) { b = nblk - 1 - u / 2; slot = 1; }
-      else { b = nblk - 2 - u / 2; slot = 0; }
-    }
-    return fac + ((size_t)b * 2 + slot) * msz;
-  };
-  // vector needed in va at step s: forward D0 / B_b take r_b; backward
-  // B_{b+1} takes y_b (b = nblk - 2 - u/2); the rest take none (-1)
-  auto vec_kind = [&](int s, int& b) -> int {
-    if (s < nf) {
-      if (s == 0) { b = 0; return 0; }
-      if (s & 1) { b = (s + 1) / 2; return 0; }
-      return -1;
-    }
-    const int u = s - nf;
-    if ((u & 1) == 0) { b = nblk - 2 - u / 2; return 1; }
-    return -1;
-  };
-  MatStage<T, stage_regs<T>()> stage;
-  T vreg = 0;
-  {
-    stage.load(mat(0), nv);
-    int b;
-    if (t < nb && vec_kind(0, b) == 0) vreg = (T)rhs(b, t);
+  const int nvec = nb * nr;                       // vector elements per block
+  constexpr int VR = (kMaxNb * NR + kThreads - 1) / kThreads;
+  u32x4 stg[MAXV];                                // register staging of the next record
+  T vreg[VR];
+  auto rec = [&](int b) { return fac + (size_t)b * sh.bstride; };
+#define TPCG_STAGE_LOAD(b_)                                                   \
+  {                                                                           \
+    const u32x4* s_ = reinterpret_cast<const u32x4*>(rec(b_));                \
+    _Pragma("unroll") for (int k_ = 0; k_ < MAXV; ++k_) {                     \
+      const int idx_ = t + k_ * kThreads;                                     \
+      if (idx_ < nv) stg[k_] = s_[idx_];                                      \
+    }                                                                         \
   }
-  for (int s = 0; s < S; ++s) {
-    __syncthreads();
-    stage.store(M, ld, nb, nv);
-    int b = 0;
-    const int kind = vec_kind(s, b);
-    if (t < nb && kind >= 0) va[t] = vreg;
-    if (s + 1 < S) {
-      stage.load(mat(s + 1), nv);
-      int b1 = 0;
-      const int k1 = vec_kind(s + 1, b1);
-      if (t < nb) {
-        if (k1 == 0) vreg = (T)rhs(b1, t);
-        else if (k1 == 1) vreg = out(b1, t);
-      }
+#define TPCG_STAGE_STORE()                                                    \
+  {                                                                           \
+    u32x4* d_ = reinterpret_cast<u32x4*>(M);                                  \
+    _Pragma("unroll") for (int k_ = 0; k_ < MAXV; ++k_) {                     \
+      const int idx_ = t + k_ * kThreads;                                     \
+      if (idx_ < nv) d_[idx_] = stg[k_];                                      \
+    }                                                                         \
+  }
+  auto vload_rhs = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int e = t + u * kThreads;
+      if (e < nvec) vreg[u] = (T)rhs(b, e / nr, e % nr);
     }
-    __syncthreads();
-    if (s < nf) {
-      const int bb = (s + 1) / 2;
-      if (s & 1) {
-        // t_b = r_b - B_b y_{b-1}
-        lds_gemv_parts(M, ld, nb, vb, red, false);
-        __syncthreads();
-        if (t < nb) va[t] = va[t] - lds_gemv_sum(red, nb, t);
-      } else {
-        // y_b = D_b t_b
-        lds_gemv_parts(M, ld, nb, va, red, false);
-        __syncthreads();
-        if (t < nb) {
-          const T y = lds_gemv_sum(red, nb, t);
-          vb[t] = y;
-          out(bb, t) = y;
-        }
-        if (bb == nblk - 1) {
-          // x_{n-1} = D_{n-1}^T y_{n-1}
-          __syncthreads();
-          lds_gemv_parts(M, ld, nb, vb, red, true);
-          __syncthreads();
-          if (t < nb) {
-            const T x = lds_gemv_sum(red, nb, t);
-            vb[t] = x;
-            out(bb, t) = x;
-          }
-        }
-      }
-    } else {
-      const int u = s - nf;
-      if ((u & 1) == 0) {
-        // s_b = y_b - B_{b+1}^T x_{b+1}
-        lds_gemv_parts(M, ld, nb, vb, red, true);
-        __syncthreads();
-        if (t < nb) va[t] = va[t] - lds_gemv_sum(red, nb, t);
-      } else {
-        // x_b = D_b^T s_b
-        const int bb = nblk - 2 - u / 2;
-        lds_gemv_parts(M, ld, nb, va, red, true);
-        __syncthreads();
-        if (t < nb) {
-          const T x = lds_gemv_sum(red, nb, t);
-          vb[t] = x;
-          out(bb, t) = x;
-        }
-      }
+  };
+  auto vload_out = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int e = t + u * kThreads;
+      if (e < nvec) vreg[u] = out(b, e / nr, e % nr);
     }
+  };
+  auto vstore = [&](T* dst) {
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int e = t + u * kThreads;
+      if (e < nvec) dst[e] = vreg[u];
+    }
+  };
+  // combine the chunk partials into dst (minus: dst = base - sum), and
+  // optionally write the result to `out` for block b
+  auto combine = [&](T* dst, const T* base, bool minus, int b, bool write) {
+    for (int e = t; e < nvec; e += kThreads) {
+      const int i = e / nr, r = e - (e / nr) * nr;
+      const T s = red_sum(red, nb, nr, i, r);
+      const T v = minus ? base[e] - s : s;
+      dst[e] = v;
+      if (write) out(b, i, r) = v;
+    }
+  };
+
+  // ---- forward: y_b = D_b (r_b - B_b y_{b-1}) ----
+  TPCG_STAGE_LOAD(0);
+  vload_rhs(0);
+  TPCG_STAGE_STORE();
+  vstore(va);
+  if (nblk > 1) { TPCG_STAGE_LOAD(1); vload_rhs(1); }
+  __syncthreads();
+  tri_parts<T, NR, 0>(M, ld, E, pe, nb, va, nr, red);
+  __syncthreads();
+  combine(vb, nullptr, false, 0, true);
+  for (int b = 1; b < nblk; ++b) {
+    __syncthreads();
+    vstore(va);                                        // r_b
+    __syncthreads();
+    tri_parts<T, NR, 1>(M, ld, E, pe, nb, vb, nr, red);   // B_b from record b-1
+    __syncthreads();
+    combine(va, va, true, b, false);
+    __syncthreads();
+    TPCG_STAGE_STORE();           // record b
+    if (b + 1 < nblk) { TPCG_STAGE_LOAD(b + 1); vload_rhs(b + 1); }
+    else if (nblk > 1) { TPCG_STAGE_LOAD(nblk - 2); }
+    __syncthreads();
+    tri_parts<T, NR, 0>(M, ld, E, pe, nb, va, nr, red);
+    __syncthreads();
+    combine(vb, nullptr, false, b, true);
+  }
+  // ---- backward: x_b = D_b^T (y_b - B_{b+1}^T x_{b+1}) ----
+  __syncthreads();
+  tri_parts<T, NR, 2>(M, ld, E, pe, nb, vb, nr, red);
+  __syncthreads();
+  combine(vb, nullptr, false, nblk - 1, true);
+  if (nblk > 1) vload_out(nblk - 2);
+  for (int b = nblk - 2; b >= 0; --b) {
+    __syncthreads();
+    TPCG_STAGE_STORE();           // record b
+    vstore(va);                                        // y_b
+    if (b >= 1) { TPCG_STAGE_LOAD(b - 1); vload_out(b - 1); }
+    __syncthreads();
+    tri_parts<T, NR, 3>(M, ld, E, pe, nb, vb, nr, red);   // B_{b+1}^T from record b
+    __syncthreads();
+    combine(va, va, true, b, false);
+    __syncthreads();
+    tri_parts<T, NR, 2>(M, ld, E, pe, nb, va, nr, red);
+    __syncthreads();
+    combine(vb, nullptr, false, b, true);
   }
   __syncthreads();
+#undef TPCG_STAGE_LOAD
+#undef TPCG_STAGE_STORE
 }
 
 }  // namespace tpcg

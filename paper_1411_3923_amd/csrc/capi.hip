@@ -70,6 +70,18 @@ std::string make_geometry(const tpcg_problem& pr, Geometry& g) {
   g.nblkc = cnt[g.caxis];
   g.nbc = g.k * (g.nsub / g.nblkc);
   g.nt = g.nsub * g.k;
+  // packed factor records: B_{b+1} reaches pe diagonals below its main one
+  {
+    int64_t w = 1;
+    for (int a = 1; a < d; ++a) w = w * g.bn + 1;
+    w = d * w + d - 1;                       // half-bandwidth of a subdomain matrix
+    g.pe = (int)std::min<int64_t>(std::max<int64_t>(w - g.nb + 1, 0), g.nb);
+    g.bstride = (g.nb * g.nb + g.nb * g.pe + 3) & ~3;
+    int dw = 1;                              // coarse neighbours' distance in block rows
+    if (d == 3) dw = 1 + (g.caxis == 0 ? g.gy : g.gx);
+    g.pec = std::min(g.nbc, (dw + 1) * g.k);
+    g.bstridec = (g.nbc * g.nbc + g.nbc * g.pec + 3) & ~3;
+  }
   g.ebn = g.s + 3;
   g.nebox = d == 3 ? g.ebn * g.ebn * g.ebn : g.ebn * g.ebn;
   g.ndpe = d == 3 ? 24 : 8;
@@ -83,6 +95,9 @@ std::string precond_limits(const Geometry& g) {
     return "subdomain node rows/layers give blocks larger than 96 or of odd size";
   if (g.nbc > kMaxNb || (g.nbc & 1))
     return "coarse blocks are larger than 96 or of odd size";
+  if (stage_bucket(stage_regs_for<double>(g.nb, g.pe)) < 0 ||
+      stage_bucket(stage_regs_for<double>(g.nbc, g.pec)) < 0)
+    return "factor records too long for the staged solve kernels";
   return "";
 }
 
@@ -93,23 +108,27 @@ struct Sizes {
 Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   const int mixed = pr.precision == TPCG_MIXED;
   const int msub = std::min(kMaxSub, g.k + (pr.eig_extra > 0 ? pr.eig_extra : g.k));
-  const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
-  const size_t cfsz = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+  const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;          // packed local factors
+  const size_t crec = (size_t)g.nblkc * g.bstridec;                // packed coarse factor
+  const size_t asm_local = (size_t)g.nsub * g.nblk * 2 * g.nb * g.nb;
+  const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   const size_t ts = mixed ? 4 : 8;
   size_t p = 0;
   p += g.ndof + sizeof(double) * g.ndpe * g.ndpe;
   p += sizeof(double) * (size_t)g.nsub * g.nloc * g.k * (mixed ? 1.5 : 1.0);
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
-  p += ts * nsys * g.nsub * fsz;
-  p += sizeof(double) * nsys * cfsz;
+  p += ts * nsys * rec;
+  p += sizeof(double) * nsys * crec;
+  if (g.nt <= kDenseCoarse) p += sizeof(double) * nsys * (size_t)g.nt * g.nt;
   p += 4 * sizeof(double) * nsys * g.ndof;
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
   p += sizeof(double) * kNumPartSlots * kMaxSys * kMaxParts + 4096;
-  size_t eig = sizeof(double) * ((size_t)g.nsub * fsz + (size_t)g.nsub * g.nloc * (1 + 2 * msub));
-  size_t coarse = sizeof(double) * (size_t)g.nsub * g.nebox * g.dim * g.k;
-  size_t local = mixed ? sizeof(double) * g.nsub * fsz : 0;
-  return {p, std::max(eig, std::max(coarse, local))};
+  // transients of the build: one system's assembled blocks at a time, the
+  // Neumann factor and the subspace, the coarse work arrays
+  size_t eig = sizeof(double) * (asm_local + rec + (size_t)g.nsub * g.nloc * (1 + 2 * msub));
+  size_t coarse = sizeof(double) * ((size_t)g.nsub * g.nebox * g.dim * g.k + nsys * asm_coarse);
+  return {p, std::max(eig, std::max(coarse, sizeof(double) * asm_local))};
 }
 
 template <typename T>
@@ -122,7 +141,7 @@ int alloc(T*& p, size_t n) {
 
 void release(Handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phi32, h->lam, h->eres, h->lfac, h->cfac,
+  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phi32, h->lam, h->eres, h->lfac, h->cfac, h->cinv,
                   h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts, h->istate,
                   h->dflag};
   for (void* p : ptrs)
@@ -134,6 +153,9 @@ void release(Handle* h) {
   if (h->t1) hipEventDestroy(h->t1);
   for (auto& e : h->prof_ev)
     if (e) hipEventDestroy(e);
+  if (h->fork) hipEventDestroy(h->fork);
+  if (h->join) hipEventDestroy(h->join);
+  if (h->side) hipStreamDestroy(h->side);
 }
 
 int check_hip(Handle* h, const char* where) {
@@ -146,26 +168,22 @@ int check_hip(Handle* h, const char* where) {
   return TPCG_OK;
 }
 
-// Minimum bytes one system's share of a block-solve launch must move: a band
-// Cholesky factor read twice (forward and backward) for every subdomain and
-// for the coarse matrix, the right-hand sides read once and the results
-// written once. The half-bandwidth of a subdomain matrix in box order is
-// dim * (bn^(dim-1) + ... + bn + 1) + dim - 1; that of the coarse matrix in
-// block order is nbc + 2k - 1.
+// Minimum bytes one system's share of a local-solve launch must move: the band
+// Cholesky factor of every subdomain read twice (forward and backward), the
+// right-hand sides read once (FP64) and the results written once. The
+// half-bandwidth of a subdomain matrix in box order is
+// dim * (bn^(dim-1) + ... + bn + 1) + dim - 1.
 double band_bytes(int64_t n, int64_t w, int elem) {
   const int64_t full = n * (w + 1) - (w * (w + 1)) / 2;   // rows shorter near the top
   return (double)full * elem;
 }
 
-double block_solve_bytes(const Geometry& g, int elem) {
+double local_solve_bytes(const Geometry& g, int elem) {
   int64_t w = 1;
   for (int a = 1; a < g.dim; ++a) w = w * g.bn + 1;
   w = g.dim * w + g.dim - 1;
-  const double local = g.nsub * (2.0 * band_bytes(g.nloc, std::min<int64_t>(w, g.nloc - 1), elem) +
-                                 (double)g.nloc * (8 + elem));
-  const int64_t wc = std::min<int64_t>(g.nbc + 2 * g.k - 1, g.nt - 1);
-  const double coarse = 2.0 * band_bytes(g.nt, wc, 8) + 16.0 * g.nt;
-  return local + coarse;
+  return g.nsub * (2.0 * band_bytes(g.nloc, std::min<int64_t>(w, g.nloc - 1), elem) +
+                   (double)g.nloc * (8 + elem));
 }
 
 Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int enabled) {
@@ -228,7 +246,10 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
   if (hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), 2 * kMaxSys * sizeof(int)) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreate(&h->t0) != hipSuccess || hipEventCreate(&h->t1) != hipSuccess) {
+      hipEventCreate(&h->t0) != hipSuccess || hipEventCreate(&h->t1) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess) {
     release(h);
     delete h;
     return TPCG_EHIP;
@@ -271,8 +292,8 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
   if (!h->phi) {
     // preconditioner storage for nsys_max systems, allocated on first build
     const int ns = h->prob.nsys_max;
-    const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
-    const size_t cfsz = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+    const size_t fsz = (size_t)g.nblk * g.bstride;
+    const size_t cfsz = (size_t)g.nblkc * g.bstridec;
     const size_t ts = h->mixed ? 4 : 8;
     int e = TPCG_OK;
     e |= alloc(h->phi, (size_t)g.nsub * g.nloc * g.k);
@@ -283,6 +304,7 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     e |= alloc(lf, ts * ns * g.nsub * fsz);
     h->lfac = lf;
     e |= alloc(h->cfac, ns * cfsz);
+    if (g.nt <= kDenseCoarse) e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
     unsigned char* zl = nullptr;
     e |= alloc(zl, ts * ns * (size_t)g.nsub * g.nloc);
     h->zloc = zl;
@@ -401,7 +423,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     // attribute each timed block-solve launch its algorithmic bytes: only the
     // systems still running at that iteration did work
     const Geometry& g = h->g;
-    const double per_sys = block_solve_bytes(g, h->mixed ? 4 : 8);
+    const double per_sys = local_solve_bytes(g, h->mixed ? 4 : 8);
     for (int i = 0; i < h->prof_n; ++i) {
       int running = 0;
       for (int s = 0; s < nsys; ++s) running += info[s].iters >= h->prof_it[i] + 2;

@@ -1,12 +1,11 @@
 // Two-level additive Schwarz preconditioner application (Sec. 2.4.2 with the
 // additive form; coarse space of Sec. 2.4):
 //   z = sum_j R_j^T A_j^-1 R_j r + Phi K_c^-1 Phi^T r
-// in three launches:
+// in four launches:
 //   1. restriction y_c = Phi^T r            (one workgroup per subdomain)
-//   2. block-tridiagonal solves: A_j^-1 R_j r for every (system, subdomain)
-//      and K_c^-1 y_c for every system, in one grid (coarse workgroups first,
-//      so the long sequential coarse solves start early)
-//   3. extension z(n) = sum_{j owns n} (A_j^-1 R_j r)(n) + Phi(n) x_c, with the
+//   2. local solves A_j^-1 R_j r for every (system, subdomain)   } concurrent:
+//   3. coarse solves K_c^-1 y_c, one workgroup per system        } forked stream
+//   4. extension z(n) = sum_{j owns n} (A_j^-1 R_j r)(n) + Phi(n) x_c, with the
 //      fused partial sums of r.z (and r.z_old for the flexible beta).
 #include "btri.h"
 
@@ -63,41 +62,65 @@ __global__ __launch_bounds__(kThreads) void k_restrict(Geometry g, const P* __re
   }
 }
 
-// grid.x = nsys (coarse) + nsys * nsub (local). Local factors in T.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_block_solves(
-    Geometry g, const double* __restrict__ r, const T* __restrict__ lfac, T* __restrict__ zloc,
-    const double* __restrict__ cfac, const double* __restrict__ yc, double* __restrict__ xc,
-    int nsys, Gate gate) {
+// one workgroup per (system, subdomain); factors and results in T
+template <typename T, int MAXV>
+__global__ __launch_bounds__(kThreads) void k_local_solves(Geometry g, const double* __restrict__ r,
+                                                          const T* __restrict__ lfac,
+                                                          T* __restrict__ zloc, Gate gate) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sh[4];
-  const int b = blockIdx.x;
-  if (b < nsys) {
-    const int sys = b;
-    if (!gate_running(gate, sys, sh)) return;
-    const double* fac = cfac + (size_t)sys * g.nblkc * 2 * g.nbc * g.nbc;
-    const double* ys = yc + (size_t)sys * g.nt;
-    double* xs = xc + (size_t)sys * g.nt;
-    const int nbc = g.nbc;
-    btri_solve<double>(
-        fac, nbc, g.nblkc, [&](int bb, int i) { return ys[bb * nbc + i]; },
-        [&](int bb, int i) -> double& { return xs[bb * nbc + i]; }, smem);
-    return;
-  }
-  const int idx = b - nsys;
-  const int sys = idx / g.nsub;
-  const int j = idx - sys * g.nsub;
+  const int sys = blockIdx.x / g.nsub;
+  const int j = blockIdx.x - sys * g.nsub;
   if (!gate_running(gate, sys, sh)) return;
   int jx, jy, jz;
   sub_coords(g, j, jx, jy, jz);
-  const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
-  const T* fac = lfac + ((size_t)sys * g.nsub + j) * fsz;
+  const BtriShape shp = local_shape(g);
+  const T* fac = lfac + ((size_t)sys * g.nsub + j) * g.nblk * g.bstride;
   const double* rs = r + (size_t)sys * g.ndof;
   T* zs = zloc + ((size_t)sys * g.nsub + j) * g.nloc;
   const int nb = g.nb;
-  btri_solve<T>(
-      fac, nb, g.nblk, [&](int bb, int i) { return rs[box_dof(g, jx, jy, jz, bb * nb + i)]; },
-      [&](int bb, int i) -> T& { return zs[bb * nb + i]; }, smem);
+  btri_solve<T, 1, MAXV>(
+      fac, shp, 1, [&](int b, int i, int) { return rs[box_dof(g, jx, jy, jz, b * nb + i)]; },
+      [&](int b, int i, int) -> T& { return zs[b * nb + i]; }, smem);
+}
+
+// one workgroup per system
+template <int MAXV>
+__global__ __launch_bounds__(kThreads) void k_coarse_solve(Geometry g, const double* __restrict__ cfac,
+                                                          const double* __restrict__ yc,
+                                                          double* __restrict__ xc, Gate gate) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sh[4];
+  const int sys = blockIdx.x;
+  if (!gate_running(gate, sys, sh)) return;
+  const BtriShape shp = coarse_shape(g);
+  const double* fac = cfac + (size_t)sys * g.nblkc * g.bstridec;
+  const double* ys = yc + (size_t)sys * g.nt;
+  double* xs = xc + (size_t)sys * g.nt;
+  const int nbc = g.nbc;
+  btri_solve<double, 1, MAXV>(
+      fac, shp, 1, [&](int b, int i, int) { return ys[b * nbc + i]; },
+      [&](int b, int i, int) -> double& { return xs[b * nbc + i]; }, smem);
+}
+
+// x_c = K_c^-1 y_c with the dense inverse: one wave per row, four rows per
+// workgroup; grid.x = nsys * ceil(nt / 4)
+__global__ __launch_bounds__(kThreads) void k_coarse_gemv(Geometry g, const double* __restrict__ cinv,
+                                                         const double* __restrict__ yc,
+                                                         double* __restrict__ xc, Gate gate) {
+  __shared__ double sh[4];
+  const int per_sys = (g.nt + 3) / 4;
+  const int sys = blockIdx.x / per_sys;
+  if (!gate_running(gate, sys, sh)) return;
+  const int row = (blockIdx.x - sys * per_sys) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= g.nt) return;
+  const double* a = cinv + ((size_t)sys * g.nt + row) * g.nt;
+  const double* y = yc + (size_t)sys * g.nt;
+  double s = 0.0;
+  for (int c = lane; c < g.nt; c += 64) s += a[c] * y[c];
+  s = wave_sum(s);
+  if (lane == 0) xc[(size_t)sys * g.nt + row] = s;
 }
 
 template <typename T, typename P>
@@ -155,21 +178,61 @@ __global__ __launch_bounds__(kThreads) void k_extend(
   }
 }
 
-template <typename T>
-void solves_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
-  const Geometry& g = h.g;
-  const size_t lds = std::max(btri_solve_lds<T>(g.nb), btri_solve_lds<double>(g.nbc));
-  static bool attr_set[2] = {false, false};
-  if (!attr_set[sizeof(T) == 8]) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_block_solves<T>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipGetLastError();   // an unsupported size must not leave a stale error behind
-    attr_set[sizeof(T) == 8] = true;
+template <typename K>
+void set_lds_once(K kernel, bool& done) {
+  if (done) return;
+  hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipGetLastError();   // an unsupported size must not leave a stale error behind
+  done = true;
+}
+
+#define TPCG_LOCAL_CASE(V)                                                                  \
+  case V: {                                                                                 \
+    static bool done = false;                                                               \
+    set_lds_once(&k_local_solves<T, V>, done);                                              \
+    hipLaunchKernelGGL((k_local_solves<T, V>), dim3(nsys * g.nsub), dim3(kThreads), lds, st, \
+                       g, r, reinterpret_cast<const T*>(h.lfac), reinterpret_cast<T*>(h.zloc), \
+                       gate);                                                               \
+    break;                                                                                  \
   }
-  dim3 grid(nsys + nsys * g.nsub);
-  hipLaunchKernelGGL(k_block_solves<T>, grid, dim3(kThreads), lds, st, g, r,
-                     reinterpret_cast<const T*>(h.lfac), reinterpret_cast<T*>(h.zloc), h.cfac,
-                     h.yc, h.xc, nsys, gate);
+
+template <typename T>
+void local_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
+  const Geometry& g = h.g;
+  const size_t lds = sizeof(T) * btri_solve_lds_elems(local_shape(g), 1);
+  switch (stage_bucket(stage_regs_for<T>(g.nb, g.pe))) {
+    TPCG_LOCAL_CASE(2)
+    TPCG_LOCAL_CASE(5)
+    TPCG_LOCAL_CASE(10)
+    TPCG_LOCAL_CASE(16)
+    TPCG_LOCAL_CASE(24)
+    TPCG_LOCAL_CASE(36)
+    default: break;
+  }
+}
+
+#define TPCG_COARSE_CASE(V)                                                                 \
+  case V: {                                                                                 \
+    static bool done = false;                                                               \
+    set_lds_once(&k_coarse_solve<V>, done);                                                 \
+    hipLaunchKernelGGL(k_coarse_solve<V>, dim3(nsys), dim3(kThreads), lds, st, g, h.cfac,   \
+                       h.yc, h.xc, gate);                                                   \
+    break;                                                                                  \
+  }
+
+void coarse_launch(Handle& h, int nsys, const Gate& gate, hipStream_t st) {
+  const Geometry& g = h.g;
+  const size_t lds = sizeof(double) * btri_solve_lds_elems(coarse_shape(g), 1);
+  switch (stage_bucket(stage_regs_for<double>(g.nbc, g.pec))) {
+    TPCG_COARSE_CASE(2)
+    TPCG_COARSE_CASE(5)
+    TPCG_COARSE_CASE(10)
+    TPCG_COARSE_CASE(16)
+    TPCG_COARSE_CASE(24)
+    TPCG_COARSE_CASE(36)
+    default: break;
+  }
 }
 
 }  // namespace
@@ -188,25 +251,34 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
     if (prof) hipEventRecord(h.prof_ev[2 * h.prof_n + which], st);
   };
   dim3 egrid(parts_for(g.nnodes), nsys);
-  if (h.mixed) {
+  if (h.mixed)
     hipLaunchKernelGGL(k_restrict<float>, dim3(g.nsub), dim3(kThreads), 0, st, g, h.phi32, r,
                        h.yc, nsys, gate);
-    mark(0);
-    solves_launch<float>(h, r, nsys, gate, st);
-    mark(1);
+  else
+    hipLaunchKernelGGL(k_restrict<double>, dim3(g.nsub), dim3(kThreads), 0, st, g, h.phi, r,
+                       h.yc, nsys, gate);
+  // the coarse solves run beside the local ones on the side stream
+  hipEventRecord(h.fork, st);
+  hipStreamWaitEvent(h.side, h.fork, 0);
+  if (h.cinv)
+    hipLaunchKernelGGL(k_coarse_gemv, dim3(nsys * ((g.nt + 3) / 4)), dim3(kThreads), 0, h.side, g,
+                       h.cinv, h.yc, h.xc, gate);
+  else
+    coarse_launch(h, nsys, gate, h.side);
+  hipEventRecord(h.join, h.side);
+  mark(0);
+  if (h.mixed) local_launch<float>(h, r, nsys, gate, st);
+  else local_launch<double>(h, r, nsys, gate, st);
+  mark(1);
+  hipStreamWaitEvent(st, h.join, 0);
+  if (h.mixed)
     hipLaunchKernelGGL((k_extend<float, float>), egrid, dim3(kThreads), 0, st, g, r, z,
                        reinterpret_cast<const float*>(h.zloc), h.phi32, h.xc, h.fixed, h.parts,
                        rz_slot, flexible, gate);
-  } else {
-    hipLaunchKernelGGL(k_restrict<double>, dim3(g.nsub), dim3(kThreads), 0, st, g, h.phi, r,
-                       h.yc, nsys, gate);
-    mark(0);
-    solves_launch<double>(h, r, nsys, gate, st);
-    mark(1);
+  else
     hipLaunchKernelGGL((k_extend<double, double>), egrid, dim3(kThreads), 0, st, g, r, z,
                        reinterpret_cast<const double*>(h.zloc), h.phi, h.xc, h.fixed, h.parts,
                        rz_slot, flexible, gate);
-  }
   if (prof) h.prof_it[h.prof_n++] = prof_it;
 }
 

@@ -138,99 +138,6 @@ __global__ __launch_bounds__(kThreads) void k_assemble(Geometry g, const double*
 // In-place block-tridiagonal Cholesky (FP64), one workgroup per matrix:
 // A_bb <- D_b = L_bb^-1, A_{b,b-1} <- B_b = L_{b,b-1}. flag[0] |= 1 on a
 // non-positive pivot (the pivot is then replaced by 1 to keep going).
-__global__ __launch_bounds__(kThreads) void k_btri_factor(double* __restrict__ fac, int nb, int nblk,
-                                                         int* __restrict__ flag) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int ld = lds_ld(nb);
-  double* buf0 = reinterpret_cast<double*>(smem);
-  double* buf1 = buf0 + (size_t)nb * ld;
-  const size_t msz = (size_t)nb * nb;
-  double* F = fac + (size_t)blockIdx.x * nblk * 2 * msz;
-  const int t = threadIdx.x;
-  double* Xa = buf0;   // receives A_bb, then L_bb
-  double* Yb = buf1;   // holds B_b from the previous step
-  for (int b = 0; b < nblk; ++b) {
-    double* Ab = F + (size_t)b * 2 * msz;
-    for (int e = t; e < nb * nb; e += kThreads) Xa[(e / nb) * ld + e % nb] = Ab[e];
-    __syncthreads();
-    if (b > 0) {
-      // A_bb -= B_b B_b^T (lower triangle)
-      for (int e = t; e < nb * nb; e += kThreads) {
-        const int i = e / nb, jj = e - (e / nb) * nb;
-        if (jj <= i) {
-          double s = 0.0;
-          for (int c = 0; c < nb; ++c) s += Yb[i * ld + c] * Yb[jj * ld + c];
-          Xa[i * ld + jj] -= s;
-        }
-      }
-      __syncthreads();
-    }
-    // right-looking Cholesky of Xa (lower)
-    for (int c = 0; c < nb; ++c) {
-      if (t == 0) {
-        double piv = Xa[c * ld + c];
-        if (!(piv > 0.0)) {
-          flag[0] = 1;
-          piv = 1.0;
-        }
-        Xa[c * ld + c] = sqrt(piv);
-      }
-      __syncthreads();
-      const double dcc = Xa[c * ld + c];
-      for (int i = c + 1 + t; i < nb; i += kThreads) Xa[i * ld + c] /= dcc;
-      __syncthreads();
-      const int n2 = nb - c - 1;
-      for (int e = t; e < n2 * n2; e += kThreads) {
-        const int i = c + 1 + e / n2, jj = c + 1 + e % n2;
-        if (jj <= i) Xa[i * ld + jj] -= Xa[i * ld + c] * Xa[jj * ld + c];
-      }
-      __syncthreads();
-    }
-    // D_b = L_bb^-1 into Yb (B_b is no longer needed), column by column
-    if (t < nb) {
-      const int jj = t;
-      for (int i = 0; i < nb; ++i) {
-        double v;
-        if (i < jj) v = 0.0;
-        else if (i == jj) v = 1.0 / Xa[i * ld + i];
-        else {
-          double s = 0.0;
-          for (int c = jj; c < i; ++c) s += Xa[i * ld + c] * Yb[c * ld + jj];
-          v = -s / Xa[i * ld + i];
-        }
-        Yb[i * ld + jj] = v;
-      }
-    }
-    __syncthreads();
-    for (int e = t; e < nb * nb; e += kThreads) Ab[e] = Yb[(e / nb) * ld + e % nb];
-    if (b + 1 < nblk) {
-      // B_{b+1} = A_{b+1,b} D_b^T, in place row by row (thread i owns row i)
-      double* An = F + ((size_t)(b + 1) * 2 + 1) * msz;
-      for (int e = t; e < nb * nb; e += kThreads) Xa[(e / nb) * ld + e % nb] = An[e];
-      __syncthreads();
-      if (t < nb) {
-        const int i = t;
-        for (int jj = nb - 1; jj >= 0; --jj) {
-          double s = 0.0;
-          for (int c = 0; c <= jj; ++c) s += Xa[i * ld + c] * Yb[jj * ld + c];
-          Xa[i * ld + jj] = s;
-        }
-      }
-      __syncthreads();
-      for (int e = t; e < nb * nb; e += kThreads) An[e] = Xa[(e / nb) * ld + e % nb];
-      // B_{b+1} stays in Xa for the next update; Yb becomes the next receiver
-      double* tmp = Xa;
-      Xa = Yb;
-      Yb = tmp;
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Subspace iteration for the local eigenproblems
-// ---------------------------------------------------------------------------
-
 __device__ inline double hash_uniform(uint64_t a) {
   // splitmix64 finaliser, mapped to [-1, 1)
   a += 0x9E3779B97F4A7C15ull;
@@ -300,92 +207,6 @@ __global__ __launch_bounds__(kThreads) void k_eig_orth(Geometry g, double* __res
 }
 
 // Y = (L L^T)^-1 X for every subdomain, m right-hand sides (FP64).
-__global__ __launch_bounds__(kThreads) void k_btri_solve_multi(const double* __restrict__ fac,
-                                                              int nb, int nblk, int m,
-                                                              const double* __restrict__ X,
-                                                              double* __restrict__ Y) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int ld = lds_ld(nb);
-  double* M = reinterpret_cast<double*>(smem);
-  double* va = M + (size_t)nb * ld;
-  double* vb = va + (size_t)nb * m;
-  double* red = vb + (size_t)nb * m;
-  const size_t msz = (size_t)nb * nb;
-  const size_t n = (size_t)nb * nblk;
-  const double* F = fac + (size_t)blockIdx.x * nblk * 2 * msz;
-  const double* Xj = X + (size_t)blockIdx.x * n * m;
-  double* Yj = Y + (size_t)blockIdx.x * n * m;
-  const int t = threadIdx.x;
-  const int Q = kThreads / nb;
-  const int L = (nb + Q - 1) / Q;
-  const int i = t % nb, q = t / nb;
-  auto load = [&](const double* src) {
-    for (int e = t; e < nb * nb; e += kThreads) M[(e / nb) * ld + e % nb] = src[e];
-  };
-  // parts of M v (or M^T v) for all m columns of v, then the fixed-order sum
-  auto gemv = [&](const double* v, bool trans) {
-    if (q < Q) {
-      double acc[kMaxSub];
-      for (int r = 0; r < kMaxSub; ++r) acc[r] = 0.0;
-      const int c0 = q * L, c1 = min(nb, c0 + L);
-      for (int c = c0; c < c1; ++c) {
-        const double a = trans ? M[c * ld + i] : M[i * ld + c];
-        for (int r = 0; r < m; ++r) acc[r] += a * v[c * m + r];
-      }
-      for (int r = 0; r < m; ++r) red[((size_t)q * nb + i) * m + r] = acc[r];
-    }
-    __syncthreads();
-  };
-  auto sum = [&](int e) {
-    const int ii = e / m, r = e - (e / m) * m;
-    double s = 0.0;
-    for (int qq = 0; qq < Q; ++qq) s += red[((size_t)qq * nb + ii) * m + r];
-    return s;
-  };
-  // forward: y_b = D_b (x_b - B_b y_{b-1})
-  for (int b = 0; b < nblk; ++b) {
-    __syncthreads();
-    for (int e = t; e < nb * m; e += kThreads) va[e] = Xj[(size_t)b * nb * m + e];
-    if (b > 0) {
-      load(F + ((size_t)b * 2 + 1) * msz);
-      __syncthreads();
-      gemv(vb, false);
-      for (int e = t; e < nb * m; e += kThreads) va[e] -= sum(e);
-    }
-    __syncthreads();
-    load(F + (size_t)b * 2 * msz);
-    __syncthreads();
-    gemv(va, false);
-    for (int e = t; e < nb * m; e += kThreads) {
-      const double y = sum(e);
-      vb[e] = y;
-      Yj[(size_t)b * nb * m + e] = y;
-    }
-  }
-  // backward: x_b = D_b^T (y_b - B_{b+1}^T x_{b+1})
-  for (int b = nblk - 1; b >= 0; --b) {
-    __syncthreads();
-    for (int e = t; e < nb * m; e += kThreads) va[e] = Yj[(size_t)b * nb * m + e];
-    if (b < nblk - 1) {
-      load(F + ((size_t)(b + 1) * 2 + 1) * msz);
-      __syncthreads();
-      gemv(vb, true);
-      for (int e = t; e < nb * m; e += kThreads) va[e] -= sum(e);
-    }
-    __syncthreads();
-    load(F + (size_t)b * 2 * msz);
-    __syncthreads();
-    gemv(va, true);
-    for (int e = t; e < nb * m; e += kThreads) {
-      const double x = sum(e);
-      vb[e] = x;
-      Yj[(size_t)b * nb * m + e] = x;
-    }
-  }
-}
-
-// Y = S X with S = D^-1/2 K^N D^-1/2 applied element by element over the
-// cell's own elements (supported DOFs excluded).
 __global__ __launch_bounds__(kThreads) void k_neumann_apply(Geometry g, const double* __restrict__ rho,
                                                            const double* __restrict__ K0,
                                                            const double* __restrict__ dis,
@@ -672,6 +493,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse_assemble(Geometry g, const 
   }
 }
 
+
 __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads)
@@ -686,19 +508,6 @@ T* dalloc(size_t n, int& err) {
   return reinterpret_cast<T*>(p);
 }
 
-void factor(Handle& h, double* fac, int nmat, int nb, int nblk) {
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_btri_factor),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipGetLastError();   // an unsupported size must not leave a stale error behind
-    attr = true;
-  }
-  const size_t lds = 2 * sizeof(double) * (size_t)nb * lds_ld(nb);
-  hipLaunchKernelGGL(k_btri_factor, dim3(nmat), dim3(kThreads), lds, h.stream, fac, nb, nblk,
-                     h.dflag);
-}
-
 }  // namespace
 
 int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
@@ -706,43 +515,36 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   hipStream_t st = h.stream;
   const tpcg_problem& pr = h.prob;
   int err = TPCG_OK;
-  const size_t fsz = (size_t)g.nblk * 2 * g.nb * g.nb;
-  const size_t cfsz = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+  const BtriShape lsh = local_shape(g), csh = coarse_shape(g);
+  const size_t asm_local = (size_t)g.nsub * g.nblk * 2 * g.nb * g.nb;
+  const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+  const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;
   const int m = h.msub;
-  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 40;
+  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 16;
   MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
 
   hipMemsetAsync(h.dflag, 0, 4 * sizeof(int), st);
+  double* A = dalloc<double>(asm_local, err);
+  if (err) { h.err = "out of device memory for the local matrices"; return err; }
 
   // --- 1-3: spectral basis from system `rep` ---
-  double* nfac = dalloc<double>(g.nsub * fsz, err);
+  double* nfac = dalloc<double>(rec, err);
   double* dis = dalloc<double>((size_t)g.nsub * g.nloc, err);
   double* X = dalloc<double>((size_t)g.nsub * g.nloc * m, err);
   double* Y = dalloc<double>((size_t)g.nsub * g.nloc * m, err);
   if (err) {
-    hipFree(nfac); hipFree(dis); hipFree(X); hipFree(Y);
+    hipFree(A); hipFree(nfac); hipFree(dis); hipFree(X); hipFree(Y);
     h.err = "out of device memory for the eigensolver";
     return err;
   }
   const double* rrep = rho + (size_t)rep * g.nel;
   hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g, rrep,
-                     h.fixed, h.K0, nfac, dis, mp, 1);
-  factor(h, nfac, g.nsub, g.nb, g.nblk);
+                     h.fixed, h.K0, A, dis, mp, 1);
+  launch_factor<double>(A, nfac, g.nsub, lsh, h.dflag, st);
   hipLaunchKernelGGL(k_eig_init, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
   hipLaunchKernelGGL(k_eig_orth, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_btri_solve_multi),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipGetLastError();   // an unsupported size must not leave a stale error behind
-    attr = true;
-  }
-  const int Qm = kThreads / g.nb;
-  const size_t slds = sizeof(double) * ((size_t)g.nb * lds_ld(g.nb) + 2 * (size_t)g.nb * m +
-                                        (size_t)Qm * g.nb * m);
   for (int it = 0; it < iters; ++it) {
-    hipLaunchKernelGGL(k_btri_solve_multi, dim3(g.nsub), dim3(kThreads), slds, st, nfac, g.nb,
-                       g.nblk, m, X, Y);
+    launch_solve_multi(nfac, lsh, g.nsub, m, X, Y, st);
     hipLaunchKernelGGL(k_eig_orth, dim3(g.nsub), dim3(kThreads), 0, st, g, Y, dis, m);
     std::swap(X, Y);
   }
@@ -759,42 +561,39 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
 
   // --- 4: coarse matrices and factors, per system ---
   double* W = dalloc<double>((size_t)g.nsub * g.nebox * g.dim * g.k, err);
-  if (err) { h.err = "out of device memory for the coarse operator"; return err; }
-  hipMemsetAsync(h.cfac, 0, sizeof(double) * cfsz * nsys, st);
+  double* Ac = dalloc<double>(asm_coarse * nsys, err);
+  if (err) {
+    hipFree(A); hipFree(W); hipFree(Ac);
+    h.err = "out of device memory for the coarse operator";
+    return err;
+  }
+  hipMemsetAsync(Ac, 0, sizeof(double) * asm_coarse * nsys, st);
   const int nnb = g.dim == 3 ? 27 : 9;
   for (int sys = 0; sys < nsys; ++sys) {
     const double* rs = rho + (size_t)sys * g.nel;
     hipLaunchKernelGGL(k_coarse_W, dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0, h.fixed,
                        h.phi, W, mp);
     hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi, W,
-                       h.cfac + sys * cfsz);
+                       Ac + sys * asm_coarse);
   }
-  factor(h, h.cfac, nsys, g.nbc, g.nblkc);
+  launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
+  if (h.cinv) launch_inverse(h.cfac, csh, nsys, h.cinv, st);
   hipStreamSynchronize(st);
   hipFree(W);
+  hipFree(Ac);
 
-  // --- 5: local Dirichlet factors (FP64; demoted to FP32 in mixed mode one
-  // system at a time) ---
-  if (!h.mixed) {
-    double* lf = reinterpret_cast<double*>(h.lfac);
-    hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, nsys), dim3(kThreads), 0, st, g, rho,
-                       h.fixed, h.K0, lf, nullptr, mp, 0);
-    factor(h, lf, nsys * g.nsub, g.nb, g.nblk);
-  } else {
-    double* lf = dalloc<double>(g.nsub * fsz, err);
-    if (err) { h.err = "out of device memory for the local factors"; return err; }
-    for (int sys = 0; sys < nsys; ++sys) {
-      hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g,
-                         rho + (size_t)sys * g.nel, h.fixed, h.K0, lf, nullptr, mp, 0);
-      factor(h, lf, g.nsub, g.nb, g.nblk);
-      hipLaunchKernelGGL(k_to_float, dim3(4096), dim3(kThreads), 0, st, lf,
-                         reinterpret_cast<float*>(h.lfac) + (size_t)sys * g.nsub * fsz,
-                         (int64_t)g.nsub * fsz);
-    }
-    hipStreamSynchronize(st);
-    hipFree(lf);
+  // --- 5: local Dirichlet factors, one system at a time (FP32 records in mixed mode) ---
+  for (int sys = 0; sys < nsys; ++sys) {
+    hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g,
+                       rho + (size_t)sys * g.nel, h.fixed, h.K0, A, nullptr, mp, 0);
+    if (h.mixed)
+      launch_factor<float>(A, reinterpret_cast<float*>(h.lfac) + sys * rec, g.nsub, lsh, h.dflag, st);
+    else
+      launch_factor<double>(A, reinterpret_cast<double*>(h.lfac) + sys * rec, g.nsub, lsh, h.dflag,
+                            st);
   }
   hipStreamSynchronize(st);
+  hipFree(A);
 
   int flag[4] = {0, 0, 0, 0};
   hipMemcpy(flag, h.dflag, sizeof(flag), hipMemcpyDeviceToHost);

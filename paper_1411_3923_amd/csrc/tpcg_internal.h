@@ -19,6 +19,7 @@ constexpr int kMaxSys = 4;           // systems solved together
 constexpr int kMaxK = 16;            // coarse vectors per subdomain
 constexpr int kMaxSub = 16;          // eigensolver subspace width
 constexpr int kMaxNb = 96;           // largest block of the block-tridiagonal kernels
+constexpr int kDenseCoarse = 12288;  // coarse dimensions up to this keep a dense K_c^-1
 
 // Structured-mesh and partition sizes. Everything is derived from the problem.
 struct Geometry {
@@ -35,7 +36,9 @@ struct Geometry {
   int nb, nblk;                      // local block-tridiagonal: block size, block count
   int k;                             // coarse vectors per subdomain
   int caxis;                         // coarse blocks run along this subdomain axis
+  int pe, bstride;                   // local packed factor: band diagonals of B, record length
   int nbc, nblkc;                    // coarse block size, block count
+  int pec, bstridec;                 // coarse packed factor
   int nt;                            // coarse dimension nsub * k
   int ebn;                           // nodes per extended box edge (s + 3)
   int nebox;                         // nodes per extended box
@@ -71,8 +74,11 @@ struct Handle {
   float* phi32 = nullptr;            // same, FP32 (mixed)
   double* lam = nullptr;             // [nsub][msub] Ritz values
   double* eres = nullptr;            // [nsub][msub] residual norms
-  void* lfac = nullptr;              // [nsys][nsub][nblk][2][nb][nb], double or float
-  double* cfac = nullptr;            // [nsys][nblkc][2][nbc][nbc]
+  void* lfac = nullptr;              // packed [nsys][nsub][nblk][bstride], double or float
+  double* cfac = nullptr;            // packed [nsys][nblkc][bstridec]
+  double* cinv = nullptr;            // dense K_c^-1 [nsys][nt][nt] when nt <= kDenseCoarse
+  hipStream_t side = nullptr;        // second stream for the coarse solve (forked per apply)
+  hipEvent_t fork = nullptr, join = nullptr;
 
   // workspace
   double* r = nullptr;               // [nsys_max][ndof]
