@@ -263,4 +263,162 @@ __device__ void btri_solve(const T* __restrict__ fac, const BtriShape sh, int nr
 #undef TPCG_STAGE_STORE
 }
 
+// ---------------------------------------------------------------------------
+// The same solve for up to 16 right-hand sides in FP64 on the matrix cores:
+// every product of a record with a block of the right-hand sides is a set of
+// 16 x 16 output tiles (v_mfma_f64_16x16x4f64; A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i % 4), register i / 4),
+// one row tile per wave. The triangular masks and the band are applied when
+// the A operand is fetched.
+// ---------------------------------------------------------------------------
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+template <int MODE>
+__device__ inline double rec_elem(const double* M, const double* E, int nb, int pe, int r, int c) {
+  if (r >= nb || c >= nb) return 0.0;
+  if (MODE == 0) return c <= r ? M[r * nb + c] : 0.0;
+  if (MODE == 1) return c > r ? M[r * nb + c] : (r - c < pe ? E[r * pe + (r - c)] : 0.0);
+  if (MODE == 2) return r <= c ? M[c * nb + r] : 0.0;
+  return r > c ? M[c * nb + r] : (c - r < pe ? E[c * pe + (c - r)] : 0.0);
+}
+
+// dst = op(M) v  (or base - op(M) v); v, dst, base are [npad][16] in LDS
+template <int MODE>
+__device__ inline void rec_gemm16(const double* M, const double* E, int nb, int pe, int npad,
+                                  const double* v, double* dst, const double* base) {
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int li = l & 15, lq = l >> 4;
+  for (int I = wv; 16 * I < npad; I += 4) {
+    int k0 = 0, k1 = npad;
+    if (MODE == 0) k1 = min(npad, 16 * I + 16);
+    if (MODE == 1) k0 = max(0, (16 * I - pe + 1) & ~3);
+    if (MODE == 2) k0 = 16 * I;
+    if (MODE == 3) k1 = min(npad, (16 * I + 15 + pe + 3) & ~3);
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k = k0; k < k1; k += 4) {
+      const double a = rec_elem<MODE>(M, E, nb, pe, 16 * I + li, k + lq);
+      const double b = v[(k + lq) * 16 + li];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 16 * I + 4 * q + lq;
+      dst[r * 16 + li] = base ? base[r * 16 + li] - acc[q] : acc[q];
+    }
+  }
+}
+
+__host__ __device__ inline size_t btri_solve16_lds_elems(const BtriShape& s) {
+  const int npad = (s.nb + 15) & ~15;
+  return (size_t)s.bstride + 2 * (size_t)npad * 16;
+}
+
+template <int MAXV, typename Rhs, typename Out>
+__device__ void btri_solve16(const double* __restrict__ fac, const BtriShape sh, int nr, Rhs rhs,
+                             Out out, unsigned char* smem) {
+  const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
+  const int npad = (nb + 15) & ~15;
+  double* M = reinterpret_cast<double*>(smem);
+  double* E = M + (size_t)nb * nb;
+  double* va = M + sh.bstride;
+  double* vb = va + (size_t)npad * 16;
+  const int nv = sh.bstride * (int)sizeof(double) / 16;
+  const int t = threadIdx.x;
+  const int nvec = npad * 16;
+  constexpr int VR = ((kMaxNb + 15) / 16 * 16 * 16 + kThreads - 1) / kThreads;
+  u32x4 stg[MAXV];
+  double vreg[VR];
+  auto rec = [&](int b) { return fac + (size_t)b * sh.bstride; };
+  auto stage_load = [&](int b) {
+    const u32x4* s = reinterpret_cast<const u32x4*>(rec(b));
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const int idx = t + k * kThreads;
+      if (idx < nv) stg[k] = s[idx];
+    }
+  };
+  auto stage_store = [&]() {
+    u32x4* d = reinterpret_cast<u32x4*>(M);
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const int idx = t + k * kThreads;
+      if (idx < nv) d[idx] = stg[k];
+    }
+  };
+  auto vload_rhs = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int e = t + u * kThreads;
+      const int i = e >> 4, r = e & 15;
+      if (e < nvec) vreg[u] = (i < nb && r < nr) ? rhs(b, i, r) : 0.0;
+    }
+  };
+  auto vload_out = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int e = t + u * kThreads;
+      const int i = e >> 4, r = e & 15;
+      if (e < nvec) vreg[u] = (i < nb && r < nr) ? out(b, i, r) : 0.0;
+    }
+  };
+  auto vstore = [&](double* dst) {
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int e = t + u * kThreads;
+      if (e < nvec) dst[e] = vreg[u];
+    }
+  };
+  auto write_out = [&](const double* src, int b) {
+    for (int e = t; e < nvec; e += kThreads) {
+      const int i = e >> 4, r = e & 15;
+      if (i < nb && r < nr) out(b, i, r) = src[e];
+    }
+  };
+  // forward
+  stage_load(0);
+  vload_rhs(0);
+  stage_store();
+  vstore(va);
+  if (nblk > 1) { stage_load(1); vload_rhs(1); }
+  __syncthreads();
+  rec_gemm16<0>(M, E, nb, pe, npad, va, vb, nullptr);
+  __syncthreads();
+  write_out(vb, 0);
+  for (int b = 1; b < nblk; ++b) {
+    vstore(va);                                   // r_b (va last read before the barrier)
+    __syncthreads();
+    rec_gemm16<1>(M, E, nb, pe, npad, vb, va, va);   // t_b = r_b - B_b y_{b-1}
+    __syncthreads();
+    stage_store();                                // record b
+    if (b + 1 < nblk) { stage_load(b + 1); vload_rhs(b + 1); }
+    else if (nblk > 1) { stage_load(nblk - 2); }
+    __syncthreads();
+    rec_gemm16<0>(M, E, nb, pe, npad, va, vb, nullptr);
+    __syncthreads();
+    write_out(vb, b);
+  }
+  // backward
+  rec_gemm16<2>(M, E, nb, pe, npad, vb, va, nullptr);   // x_{n-1}
+  __syncthreads();
+  write_out(va, nblk - 1);
+  {
+    // move x_{n-1} into vb
+    for (int e = t; e < nvec; e += kThreads) vb[e] = va[e];
+  }
+  if (nblk > 1) vload_out(nblk - 2);
+  for (int b = nblk - 2; b >= 0; --b) {
+    __syncthreads();
+    stage_store();                                // record b
+    vstore(va);                                   // y_b
+    if (b >= 1) { stage_load(b - 1); vload_out(b - 1); }
+    __syncthreads();
+    rec_gemm16<3>(M, E, nb, pe, npad, vb, va, va);   // s_b = y_b - B_{b+1}^T x_{b+1}
+    __syncthreads();
+    rec_gemm16<2>(M, E, nb, pe, npad, va, vb, nullptr);   // x_b = D_b^T s_b
+    __syncthreads();
+    write_out(vb, b);
+  }
+  __syncthreads();
+}
+
 }  // namespace tpcg

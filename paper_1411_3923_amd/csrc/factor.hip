@@ -116,6 +116,261 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   }
 }
 
+// ---------------------------------------------------------------------------
+// MFMA variant (FP64 matrix cores, v_mfma_f64_16x16x4f64) for blocks of up to
+// kMfmaNb rows. Lane layout of the instruction: A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, result D[i][j] in lane j + 16 (i % 4), register i / 4.
+// The O(nb^3) parts run as 16 x 16 tiles on the matrix cores: the update
+// A_bb -= B_b B_b^T, the trailing updates of a blocked Cholesky (16-column
+// panels), the off-diagonal tiles of the blocked triangular inverse and
+// B_{b+1} = A_{b+1,b} D_b^T. Rows and columns past nb read as zero.
+// ---------------------------------------------------------------------------
+constexpr int kMfmaNb = 76;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline double lget(const double* M, int ld, int nb, int r, int c) {
+  return (r < nb && c < nb) ? M[r * ld + c] : 0.0;
+}
+
+// acc += A[ra.., k] * Bm[rb.., k]^T over k in [k0, k1) (k0 multiple of 4)
+__device__ inline d4 mfma_nt(const double* A, const double* Bm, int ld, int nb, int ra, int rb,
+                             int k0, int k1, d4 acc) {
+  const int l = threadIdx.x & 63;
+  const int li = l & 15, lk = l >> 4;
+  for (int k = k0; k < k1; k += 4) {
+    const double a = lget(A, ld, nb, ra + li, k + lk);
+    const double b = lget(Bm, ld, nb, rb + li, k + lk);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// acc += A[ra.., k] * Bm[k, cb..] over k in [k0, k1) (Bm read row-major, not transposed)
+__device__ inline d4 mfma_nn(const double* A, int lda, const double* Bm, int ldb, int nb, int ra,
+                             int cb, int k0, int k1, d4 acc) {
+  const int l = threadIdx.x & 63;
+  const int li = l & 15, lk = l >> 4;
+  for (int k = k0; k < k1; k += 4) {
+    const double a = lget(A, lda, nb, ra + li, k + lk);
+    const double b = lget(Bm, ldb, nb, k + lk, cb + li);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// value of v in lane `lane` (uniform index) for every lane
+__device__ inline double bcast_lane(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_btri_factor_mfma(const double* __restrict__ A,
+                                                              T* __restrict__ out, BtriShape sh,
+                                                              int* __restrict__ flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
+  const int ld = lds_ld(nb);
+  const int NT = (nb + 15) / 16;
+  double* X = reinterpret_cast<double*>(smem);   // A_bb -> L_bb
+  double* Y = X + (size_t)nb * ld;                // B_b, then A_{b+1,b} -> B_{b+1}
+  double* D = Y + (size_t)nb * ld;                // D_b = L_bb^-1
+  double* tmp = D + (size_t)nb * ld;              // 16 x 16 per wave
+  const size_t msz = (size_t)nb * nb;
+  const double* F = A + (size_t)blockIdx.x * nblk * 2 * msz;
+  T* O = out + (size_t)blockIdx.x * nblk * sh.bstride;
+  const int t = threadIdx.x;
+  const int wv = t >> 6, l = t & 63;
+  const int li = l & 15, lq = l >> 4;
+  double* tw = tmp + wv * 256;
+  auto load = [&](double* dst, const double* src) {
+    for (int r = t / 16; r < nb; r += kThreads / 16)
+      for (int c = t % 16; c < nb; c += 16) dst[r * ld + c] = src[(size_t)r * nb + c];
+  };
+  load(X, F);
+  for (int b = 0; b < nblk; ++b) {
+    __syncthreads();
+    if (b > 0) {
+      // A_bb -= B_b B_b^T on the lower tiles
+      int tile = 0;
+      for (int I = 0; I < NT; ++I)
+        for (int J = 0; J <= I; ++J, ++tile) {
+          if ((tile & 3) != wv) continue;
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+          acc = mfma_nt(Y, Y, ld, nb, 16 * I, 16 * J, 0, (nb + 3) & ~3, acc);
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
+            if (r < nb && c < nb) X[r * ld + c] -= acc[v];
+          }
+        }
+      __syncthreads();
+    }
+    // blocked Cholesky: panel p of 16 columns factored by wave 0, then MFMA
+    // trailing update of the tiles to its right
+    for (int p = 0; p < NT; ++p) {
+      const int c0 = 16 * p, c1 = min(nb, c0 + 16);
+      if (wv == 0) {
+        // the panel (rows c0.., 16 columns) in registers: lane l holds rows
+        // c0 + l and c0 + l + 64; column entries move between lanes by readlane
+        const int w = c1 - c0;
+        double x[2][16];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int r = c0 + l + 64 * s;
+#pragma unroll
+          for (int cc = 0; cc < 16; ++cc) x[s][cc] = (r < nb && cc < w) ? X[r * ld + c0 + cc] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c < w) {
+            double piv = bcast_lane(x[0][c], c);      // row c0 + c lives in lane c
+            if (!(piv > 0.0)) {
+              if (l == 0) flag[0] = 1;
+              piv = 1.0;
+            }
+            const double dcc = sqrt(piv);
+            const double inv = 1.0 / dcc;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+              const int rr = l + 64 * s;
+              if (rr == c) x[s][c] = dcc;
+              else if (rr > c) x[s][c] *= inv;
+            }
+#pragma unroll
+            for (int cc = c + 1; cc < 16; ++cc) {
+              if (cc < w) {
+                const double lcc = bcast_lane(x[0][c], cc);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                  if (l + 64 * s >= cc) x[s][cc] -= x[s][c] * lcc;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int r = c0 + l + 64 * s;
+#pragma unroll
+          for (int cc = 0; cc < 16; ++cc)
+            if (r < nb && cc < w) X[r * ld + c0 + cc] = x[s][cc];
+        }
+      }
+      __syncthreads();
+      int tile = 0;
+      for (int I = p + 1; I < NT; ++I)
+        for (int J = p + 1; J <= I; ++J, ++tile) {
+          if ((tile & 3) != wv) continue;
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+          acc = mfma_nt(X, X, ld, nb, 16 * I, 16 * J, c0, c0 + 16, acc);
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
+            if (r < nb && c < nb) X[r * ld + c] -= acc[v];
+          }
+        }
+      __syncthreads();
+    }
+    // D = L^-1: diagonal tiles by forward substitution (lanes 0..15 of a wave
+    // own one column each), then the off-diagonal tiles by distance from the
+    // diagonal: D_IJ = -D_II sum_{K=J}^{I-1} L_IK D_KJ
+    for (int I = wv; I < NT; I += 4) {
+      if (li == l) {
+        // lane li solves L_II y = e_li with y in registers
+        const int j = 16 * I + li;
+        double y[16];
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) {
+          const int r = 16 * I + ii;
+          double s = (ii == li) ? 1.0 : 0.0;
+#pragma unroll
+          for (int c = 0; c < ii; ++c) s -= lget(X, ld, nb, r, 16 * I + c) * y[c];
+          y[ii] = r < nb ? s / X[r * ld + r] : 0.0;
+        }
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) {
+          const int r = 16 * I + ii;
+          if (r < nb && j < nb) D[r * ld + j] = y[ii];
+        }
+      }
+    }
+    // zero the strict upper triangle of D (off-diagonal tiles above)
+    for (int r = t / 16; r < nb; r += kThreads / 16)
+      for (int c = t % 16; c < nb; c += 16)
+        if (c / 16 > r / 16) D[r * ld + c] = 0.0;
+    __syncthreads();
+    for (int dist = 1; dist < NT; ++dist) {
+      for (int J = wv; J + dist < NT; J += 4) {
+        const int I = J + dist;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mfma_nn(X, ld, D, ld, nb, 16 * I, 16 * J, 16 * J, 16 * I, acc);
+        for (int v = 0; v < 4; ++v) tw[(4 * v + lq) * 16 + li] = acc[v];
+        wave_sync();
+        d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+        {
+          // acc2 = D_II * tw
+          for (int k = 0; k < 16; k += 4) {
+            const double a = lget(D, ld, nb, 16 * I + li, 16 * I + k + lq);
+            const double bb = tw[(k + lq) * 16 + li];
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc2, 0, 0, 0);
+          }
+        }
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
+          if (r < nb && c < nb) D[r * ld + c] = -acc2[v];
+        }
+        wave_sync();
+      }
+      __syncthreads();
+    }
+    const bool last = b + 1 == nblk;
+    if (!last) {
+      // B_{b+1} = A_{b+1,b} D^T; wave w owns row tiles I = w, w + 4, ...
+      load(Y, F + ((size_t)(b + 1) * 2 + 1) * msz);
+      __syncthreads();
+      constexpr int kMaxTiles = (kMfmaNb + 15) / 16;
+      for (int I = wv; I < NT; I += 4) {
+        d4 acc[kMaxTiles];
+#pragma unroll
+        for (int J = 0; J < kMaxTiles; ++J) {
+          acc[J] = d4{0.0, 0.0, 0.0, 0.0};
+          if (J < NT)
+            acc[J] = mfma_nt(Y, D, ld, nb, 16 * I, 16 * J, 0, min((nb + 3) & ~3, 16 * J + 16),
+                             acc[J]);
+        }
+        wave_sync();
+#pragma unroll
+        for (int J = 0; J < kMaxTiles; ++J)
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
+            if (J < NT && r < nb && c < nb) Y[r * ld + c] = acc[J][v];
+          }
+      }
+      __syncthreads();
+    }
+    // record b: lower(D_b) | strict upper(B_{b+1}) | band of B_{b+1}
+    T* R = O + (size_t)b * sh.bstride;
+    for (int e = t; e < nb * nb; e += kThreads) {
+      const int r = e / nb, c = e - (e / nb) * nb;
+      const double v = c <= r ? D[r * ld + c] : (last ? 0.0 : Y[r * ld + c]);
+      R[e] = (T)v;
+    }
+    for (int e = t; e < nb * pe; e += kThreads) {
+      const int r = e / pe, tt = e - (e / pe) * pe;
+      const double v = (last || r - tt < 0) ? 0.0 : Y[r * ld + r - tt];
+      R[nb * nb + e] = (T)v;
+    }
+    for (int e = nb * nb + nb * pe + t; e < sh.bstride; e += kThreads) R[e] = (T)0;
+    if (!last) load(X, F + (size_t)(b + 1) * 2 * msz);
+  }
+}
+
 // Y = (L L^T)^-1 X for every matrix, m <= kMaxSub right-hand sides, FP64,
 // X and Y [nmat][n][m] row-major (n = nb * nblk).
 template <int MAXV>
@@ -129,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_solve_multi(const double* __r
   const double* Xj = X + (size_t)blockIdx.x * n * m;
   double* Yj = Y + (size_t)blockIdx.x * n * m;
   const int nb = sh.nb;
-  btri_solve<double, kMaxSub, MAXV>(
+  btri_solve16<MAXV>(
       F, sh, m, [&](int b, int i, int r) { return Xj[((size_t)b * nb + i) * m + r]; },
       [&](int b, int i, int r) -> double& { return Yj[((size_t)b * nb + i) * m + r]; }, smem);
 }
@@ -148,7 +403,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_inverse(const double* __restr
   const double* F = fac + (size_t)mat * sh.nblk * sh.bstride;
   double* Xm = Xinv + (size_t)mat * n * n;
   const int nb = sh.nb;
-  btri_solve<double, kMaxSub, MAXV>(
+  btri_solve16<MAXV>(
       F, sh, nr, [&](int b, int i, int r) { return (b * nb + i == c0 + r) ? 1.0 : 0.0; },
       [&](int b, int i, int r) -> double& { return Xm[(size_t)(b * nb + i) * n + c0 + r]; },
       smem);
@@ -167,9 +422,19 @@ template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
                    hipStream_t st) {
   static bool attr = false;
-  if (!attr) { set_lds(&k_btri_factor<T>); attr = true; }
-  const size_t lds = 2 * sizeof(double) * (size_t)sh.nb * lds_ld(sh.nb);
-  hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag);
+  if (!attr) {
+    set_lds(&k_btri_factor<T>);
+    set_lds(&k_btri_factor_mfma<T>);
+    attr = true;
+  }
+  if (sh.nb <= kMfmaNb) {
+    const size_t lds = sizeof(double) * (3 * (size_t)sh.nb * lds_ld(sh.nb) + 4 * 256);
+    hipLaunchKernelGGL(k_btri_factor_mfma<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh,
+                       flag);
+  } else {
+    const size_t lds = 2 * sizeof(double) * (size_t)sh.nb * lds_ld(sh.nb);
+    hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag);
+  }
 }
 
 template void launch_factor<double>(const double*, double*, int, const BtriShape&, int*, hipStream_t);
@@ -186,7 +451,7 @@ template void launch_factor<float>(const double*, float*, int, const BtriShape&,
 
 void launch_solve_multi(const double* fac, const BtriShape& sh, int nmat, int m, const double* X,
                         double* Y, hipStream_t st) {
-  const size_t lds = sizeof(double) * btri_solve_lds_elems(sh, m);
+  const size_t lds = sizeof(double) * btri_solve16_lds_elems(sh);
   switch (stage_bucket(stage_regs_for<double>(sh.nb, sh.pe))) {
     TPCG_MULTI_CASE(2)
     TPCG_MULTI_CASE(5)
@@ -211,7 +476,7 @@ void launch_inverse(const double* fac, const BtriShape& sh, int nmat, double* Xi
                     hipStream_t st) {
   const int n = sh.nb * sh.nblk;
   const int chunks = (n + kMaxSub - 1) / kMaxSub;
-  const size_t lds = sizeof(double) * btri_solve_lds_elems(sh, kMaxSub);
+  const size_t lds = sizeof(double) * btri_solve16_lds_elems(sh);
   switch (stage_bucket(stage_regs_for<double>(sh.nb, sh.pe))) {
     TPCG_INV_CASE(2)
     TPCG_INV_CASE(5)

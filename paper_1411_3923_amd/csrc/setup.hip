@@ -159,6 +159,90 @@ __global__ __launch_bounds__(kThreads) void k_eig_init(Geometry g, double* __res
   }
 }
 
+// Orthonormalise the columns of X[j] (nloc x m, row-major, m <= 16) in place
+// by Cholesky QR applied twice: G = X^T X (on the matrix cores:
+// v_mfma_f64_16x16x4f64 with both operands read from X, four waves over
+// interleaved row chunks, partial tiles summed in LDS), G + s I = R^T R with a
+// tiny shift s = 1e-14 trace(G) that keeps the factorisation defined when X is
+// ill-conditioned, then X <- X R^-1. The second pass restores orthogonality to
+// working accuracy. Supported DOFs are zeroed first.
+typedef double dv4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __restrict__ X,
+                                                        const double* __restrict__ dis, int m) {
+  __shared__ double part[4][256];
+  __shared__ double R[16 * 16];
+  __shared__ double G[16 * 16];
+  __shared__ double U[16 * 16];
+  const int j = blockIdx.x;
+  double* Xj = X + (size_t)j * g.nloc * m;
+  const double* dj = dis + (size_t)j * g.nloc;
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63, li = l & 15, lq = l >> 4;
+  for (int r = t; r < g.nloc; r += kThreads)
+    if (dj[r] == 0.0)
+      for (int c = 0; c < m; ++c) Xj[(size_t)r * m + c] = 0.0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    // G = X^T X: wave wv takes the 4-row chunks k = 4 (wv + 4 i)
+    dv4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 4 * wv; k < g.nloc; k += 16) {
+      const int row = k + lq;
+      const double v = (row < g.nloc && li < m) ? Xj[(size_t)row * m + li] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+    for (int q = 0; q < 4; ++q) part[wv][(4 * q + lq) * 16 + li] = acc[q];
+    __syncthreads();
+    if (t == 0) {
+      double tr = 0.0;
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b)
+          G[a * 16 + b] = (part[0][a * 16 + b] + part[1][a * 16 + b]) +
+                          (part[2][a * 16 + b] + part[3][a * 16 + b]);
+      for (int a = 0; a < m; ++a) tr += G[a * 16 + a];
+      const double shift = 1e-14 * tr;
+      // upper Cholesky G + shift I = R^T R, then R^-1 (upper) into R
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) U[a * 16 + b] = 0.0;
+      for (int a = 0; a < m; ++a) {
+        double s = G[a * 16 + a] + shift;
+        for (int c = 0; c < a; ++c) s -= U[c * 16 + a] * U[c * 16 + a];
+        const double d = s > 0.0 ? sqrt(s) : 1.0;
+        U[a * 16 + a] = d;
+        for (int b = a + 1; b < m; ++b) {
+          double v = G[a * 16 + b];
+          for (int c = 0; c < a; ++c) v -= U[c * 16 + a] * U[c * 16 + b];
+          U[a * 16 + b] = v / d;
+        }
+      }
+      for (int a = 0; a < 16 * 16; ++a) R[a] = 0.0;
+      for (int b = 0; b < m; ++b) {          // column b of U^-1 by back substitution
+        for (int a = b; a >= 0; --a) {
+          double v = a == b ? 1.0 : 0.0;
+          for (int c = a + 1; c <= b; ++c) v -= U[a * 16 + c] * R[c * 16 + b];
+          R[a * 16 + b] = v / U[a * 16 + a];
+        }
+      }
+    }
+    __syncthreads();
+    // X <- X R^-1 row by row
+    for (int r = t; r < g.nloc; r += kThreads) {
+      double x[kMaxSub];
+#pragma unroll
+      for (int c = 0; c < kMaxSub; ++c) x[c] = c < m ? Xj[(size_t)r * m + c] : 0.0;
+#pragma unroll
+      for (int b = 0; b < kMaxSub; ++b) {
+        if (b < m) {
+          double v = 0.0;
+#pragma unroll
+          for (int a = 0; a <= b; ++a) v += x[a] * R[a * 16 + b];
+          Xj[(size_t)r * m + b] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Classical Gram-Schmidt applied twice, column by column, on X[j] (nloc x m,
 // row-major) in place; supported DOFs are zeroed first.
 __global__ __launch_bounds__(kThreads) void k_eig_orth(Geometry g, double* __restrict__ X,
@@ -542,10 +626,10 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
                      h.fixed, h.K0, A, dis, mp, 1);
   launch_factor<double>(A, nfac, g.nsub, lsh, h.dflag, st);
   hipLaunchKernelGGL(k_eig_init, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
-  hipLaunchKernelGGL(k_eig_orth, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
+  hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
   for (int it = 0; it < iters; ++it) {
     launch_solve_multi(nfac, lsh, g.nsub, m, X, Y, st);
-    hipLaunchKernelGGL(k_eig_orth, dim3(g.nsub), dim3(kThreads), 0, st, g, Y, dis, m);
+    hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, Y, dis, m);
     std::swap(X, Y);
   }
   hipLaunchKernelGGL(k_neumann_apply, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis, X,
