@@ -1,131 +1,26 @@
 // Batched block-tridiagonal Cholesky factorisation into the packed record
-// format of btri.h, and the multi-right-hand-side solve used by the
-// subspace iteration of the local eigenproblems.
+// format of btri.h (one workgroup per matrix), the multi-right-hand-side
+// solve used by the subspace iteration of the local eigenproblems, and the
+// dense inverse of a packed factor.
+//
+// The O(nb^3) work runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+// Lane layout of the instruction: A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k, result D[i][j] in lane j + 16 (i % 4), register i / 4. Per block row:
+//   A_bb -= B_b B_b^T                         16 x 16 tiles on MFMA
+//   A_bb = L_bb L_bb^T                        16-column panels: the panel in
+//                                             registers (readlane broadcasts),
+//                                             trailing tiles on MFMA
+//   D_b = L_bb^-1 in place                    diagonal tiles by substitution in
+//                                             registers, off-diagonal tiles
+//                                             D_IJ = -D_II sum_K L_IK D_KJ on MFMA
+//   B_{b+1} = A_{b+1,b} D_b^T in place        MFMA, each wave owns its row tiles
+// Rows and columns past nb read as zero. Two nb x nb LDS buffers suffice, so
+// blocks of up to 96 fit.
 #include "btri.h"
 
 namespace tpcg {
 
 namespace {
-
-// One workgroup per matrix. Input: assembled blocks A[b][0] = A_bb,
-// A[b][1] = A_{b,b-1} (FP64, row-major nb x nb). Output: packed records in T.
-// flag[0] = 1 on a non-positive pivot (replaced by 1 so that the
-// factorisation completes and the caller can report it).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restrict__ A,
-                                                         T* __restrict__ out, BtriShape sh,
-                                                         int* __restrict__ flag) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
-  const int ld = lds_ld(nb);
-  double* buf0 = reinterpret_cast<double*>(smem);
-  double* buf1 = buf0 + (size_t)nb * ld;
-  const size_t msz = (size_t)nb * nb;
-  const double* F = A + (size_t)blockIdx.x * nblk * 2 * msz;
-  T* O = out + (size_t)blockIdx.x * nblk * sh.bstride;
-  const int t = threadIdx.x;
-  const int ti = t >> 4, tj = t & 15;     // 16 x 16 thread tile
-  double* Xa = buf0;                       // receives A_bb, then L_bb, then A_{b+1,b} -> B_{b+1}
-  double* Yb = buf1;                       // B_b of the previous step, then D_b
-  for (int b = 0; b < nblk; ++b) {
-    const double* Ab = F + (size_t)b * 2 * msz;
-    for (int e = t; e < nb * nb; e += kThreads) Xa[(e / nb) * ld + e % nb] = Ab[e];
-    __syncthreads();
-    if (b > 0) {
-      // A_bb -= B_b B_b^T on the lower triangle
-      for (int i = ti; i < nb; i += 16)
-        for (int jj = tj; jj <= i; jj += 16) {
-          double s = 0.0;
-          for (int c = 0; c < nb; ++c) s += Yb[i * ld + c] * Yb[jj * ld + c];
-          Xa[i * ld + jj] -= s;
-        }
-      __syncthreads();
-    }
-    // right-looking Cholesky of Xa (lower)
-    for (int c = 0; c < nb; ++c) {
-      if (t == 0) {
-        double piv = Xa[c * ld + c];
-        if (!(piv > 0.0)) {
-          flag[0] = 1;
-          piv = 1.0;
-        }
-        Xa[c * ld + c] = sqrt(piv);
-      }
-      __syncthreads();
-      const double inv = 1.0 / Xa[c * ld + c];
-      for (int i = c + 1 + t; i < nb; i += kThreads) Xa[i * ld + c] *= inv;
-      __syncthreads();
-      for (int i = c + 1 + ti; i < nb; i += 16) {
-        const double lic = Xa[i * ld + c];
-        for (int jj = c + 1 + tj; jj <= i; jj += 16) Xa[i * ld + jj] -= lic * Xa[jj * ld + c];
-      }
-      __syncthreads();
-    }
-    // D_b = L_bb^-1 into Yb, one column per thread (forward substitution)
-    if (t < nb) {
-      const int jj = t;
-      for (int i = 0; i < nb; ++i) {
-        double v;
-        if (i < jj) v = 0.0;
-        else if (i == jj) v = 1.0 / Xa[i * ld + i];
-        else {
-          double s = 0.0;
-          for (int c = jj; c < i; ++c) s += Xa[i * ld + c] * Yb[c * ld + jj];
-          v = -s / Xa[i * ld + i];
-        }
-        Yb[i * ld + jj] = v;
-      }
-    }
-    __syncthreads();
-    const bool last = b + 1 == nblk;
-    if (!last) {
-      // B_{b+1} = A_{b+1,b} D_b^T in place, thread i owns row i (right to left)
-      const double* An = F + ((size_t)(b + 1) * 2 + 1) * msz;
-      for (int e = t; e < nb * nb; e += kThreads) Xa[(e / nb) * ld + e % nb] = An[e];
-      __syncthreads();
-      if (t < nb) {
-        const int i = t;
-        for (int jj = nb - 1; jj >= 0; --jj) {
-          double s = 0.0;
-          for (int c = 0; c <= jj; ++c) s += Xa[i * ld + c] * Yb[jj * ld + c];
-          Xa[i * ld + jj] = s;
-        }
-      }
-      __syncthreads();
-    }
-    // record b: lower(D_b) | strict upper(B_{b+1}) | band of B_{b+1}
-    T* R = O + (size_t)b * sh.bstride;
-    for (int e = t; e < nb * nb; e += kThreads) {
-      const int r = e / nb, c = e - (e / nb) * nb;
-      const double v = c <= r ? Yb[r * ld + c] : (last ? 0.0 : Xa[r * ld + c]);
-      R[e] = (T)v;
-    }
-    for (int e = t; e < nb * pe; e += kThreads) {
-      const int r = e / pe, tt = e - (e / pe) * pe;
-      const double v = (last || r - tt < 0) ? 0.0 : Xa[r * ld + r - tt];
-      R[nb * nb + e] = (T)v;
-    }
-    for (int e = nb * nb + nb * pe + t; e < sh.bstride; e += kThreads) R[e] = (T)0;
-    __syncthreads();
-    if (!last) {
-      // B_{b+1} stays in Xa for the next update; Yb receives the next block
-      double* tmp = Xa;
-      Xa = Yb;
-      Yb = tmp;
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// MFMA variant (FP64 matrix cores, v_mfma_f64_16x16x4f64) for blocks of up to
-// kMfmaNb rows. Lane layout of the instruction: A[i][k] in lane i + 16k,
-// B[k][j] in lane j + 16k, result D[i][j] in lane j + 16 (i % 4), register i / 4.
-// The O(nb^3) parts run as 16 x 16 tiles on the matrix cores: the update
-// A_bb -= B_b B_b^T, the trailing updates of a blocked Cholesky (16-column
-// panels), the off-diagonal tiles of the blocked triangular inverse and
-// B_{b+1} = A_{b+1,b} D_b^T. Rows and columns past nb read as zero.
-// ---------------------------------------------------------------------------
-constexpr int kMfmaNb = 76;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -146,14 +41,14 @@ __device__ inline d4 mfma_nt(const double* A, const double* Bm, int ld, int nb, 
   return acc;
 }
 
-// acc += A[ra.., k] * Bm[k, cb..] over k in [k0, k1) (Bm read row-major, not transposed)
-__device__ inline d4 mfma_nn(const double* A, int lda, const double* Bm, int ldb, int nb, int ra,
-                             int cb, int k0, int k1, d4 acc) {
+// acc += A[ra.., k] * Bm[k, cb..] over k in [k0, k1) (Bm not transposed)
+__device__ inline d4 mfma_nn(const double* A, const double* Bm, int ld, int nb, int ra, int cb,
+                             int k0, int k1, d4 acc) {
   const int l = threadIdx.x & 63;
   const int li = l & 15, lk = l >> 4;
   for (int k = k0; k < k1; k += 4) {
-    const double a = lget(A, lda, nb, ra + li, k + lk);
-    const double b = lget(Bm, ldb, nb, k + lk, cb + li);
+    const double a = lget(A, ld, nb, ra + li, k + lk);
+    const double b = lget(Bm, ld, nb, k + lk, cb + li);
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
   return acc;
@@ -167,23 +62,29 @@ __device__ inline double bcast_lane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// orders the LDS traffic of one wave
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
+constexpr int kMaxTiles = (kMaxNb + 15) / 16;
+
+// One workgroup per matrix. Input: assembled blocks A[b][0] = A_bb,
+// A[b][1] = A_{b,b-1} (FP64, row-major nb x nb). Output: packed records in T.
+// flag[0] = 1 on a non-positive pivot (replaced by 1 so that the
+// factorisation completes and the caller can report it).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_btri_factor_mfma(const double* __restrict__ A,
-                                                              T* __restrict__ out, BtriShape sh,
-                                                              int* __restrict__ flag) {
+__global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restrict__ A,
+                                                         T* __restrict__ out, BtriShape sh,
+                                                         int* __restrict__ flag) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
   const int ld = lds_ld(nb);
   const int NT = (nb + 15) / 16;
-  double* X = reinterpret_cast<double*>(smem);   // A_bb -> L_bb
+  double* X = reinterpret_cast<double*>(smem);   // A_bb -> L_bb -> D_b
   double* Y = X + (size_t)nb * ld;                // B_b, then A_{b+1,b} -> B_{b+1}
-  double* D = Y + (size_t)nb * ld;                // D_b = L_bb^-1
-  double* tmp = D + (size_t)nb * ld;              // 16 x 16 per wave
+  double* tmp = Y + (size_t)nb * ld;              // 16 x 16 per wave
   const size_t msz = (size_t)nb * nb;
   const double* F = A + (size_t)blockIdx.x * nblk * 2 * msz;
   T* O = out + (size_t)blockIdx.x * nblk * sh.bstride;
@@ -213,15 +114,13 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor_mfma(const double* __r
         }
       __syncthreads();
     }
-    // blocked Cholesky: panel p of 16 columns factored by wave 0, then MFMA
-    // trailing update of the tiles to its right
+    // blocked Cholesky: panel p (16 columns) in the registers of wave 0,
+    // then the trailing tiles on MFMA
     for (int p = 0; p < NT; ++p) {
       const int c0 = 16 * p, c1 = min(nb, c0 + 16);
       if (wv == 0) {
-        // the panel (rows c0.., 16 columns) in registers: lane l holds rows
-        // c0 + l and c0 + l + 64; column entries move between lanes by readlane
         const int w = c1 - c0;
-        double x[2][16];
+        double x[2][16];   // lane l holds panel rows c0 + l and c0 + l + 64
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           const int r = c0 + l + 64 * s;
@@ -277,12 +176,11 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor_mfma(const double* __r
         }
       __syncthreads();
     }
-    // D = L^-1: diagonal tiles by forward substitution (lanes 0..15 of a wave
-    // own one column each), then the off-diagonal tiles by distance from the
-    // diagonal: D_IJ = -D_II sum_{K=J}^{I-1} L_IK D_KJ
+    // D = L^-1 in place. Diagonal tiles first: lane li of a wave solves
+    // L_II y = e_li in registers (all its reads precede its writes, and the
+    // lanes of a wave move in lockstep)
     for (int I = wv; I < NT; I += 4) {
       if (li == l) {
-        // lane li solves L_II y = e_li with y in registers
         const int j = 16 * I + li;
         double y[16];
 #pragma unroll
@@ -291,57 +189,55 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor_mfma(const double* __r
           double s = (ii == li) ? 1.0 : 0.0;
 #pragma unroll
           for (int c = 0; c < ii; ++c) s -= lget(X, ld, nb, r, 16 * I + c) * y[c];
-          y[ii] = r < nb ? s / X[r * ld + r] : 0.0;
+          y[ii] = r < nb ? s / lget(X, ld, nb, r, r) : 0.0;
         }
+        wave_sync();
 #pragma unroll
         for (int ii = 0; ii < 16; ++ii) {
           const int r = 16 * I + ii;
-          if (r < nb && j < nb) D[r * ld + j] = y[ii];
+          if (r < nb && j < nb) X[r * ld + j] = y[ii];
         }
       }
     }
-    // zero the strict upper triangle of D (off-diagonal tiles above)
-    for (int r = t / 16; r < nb; r += kThreads / 16)
-      for (int c = t % 16; c < nb; c += 16)
-        if (c / 16 > r / 16) D[r * ld + c] = 0.0;
     __syncthreads();
-    for (int dist = 1; dist < NT; ++dist) {
-      for (int J = wv; J + dist < NT; J += 4) {
-        const int I = J + dist;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
-        acc = mfma_nn(X, ld, D, ld, nb, 16 * I, 16 * J, 16 * J, 16 * I, acc);
-        for (int v = 0; v < 4; ++v) tw[(4 * v + lq) * 16 + li] = acc[v];
-        wave_sync();
-        d4 acc2 = {0.0, 0.0, 0.0, 0.0};
-        {
-          // acc2 = D_II * tw
+    // off-diagonal tiles, columns left to right and rows top-down within a
+    // column (column J still needs the L tiles right of it):
+    // D_IJ = -D_II sum_{K=J}^{I-1} L_IK D_KJ
+    if (wv == 0) {
+      for (int J = 0; J + 1 < NT; ++J)
+        for (int I = J + 1; I < NT; ++I) {
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+          acc = mfma_nn(X, X, ld, nb, 16 * I, 16 * J, 16 * J, 16 * I, acc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) tw[(4 * v + lq) * 16 + li] = acc[v];
+          wave_sync();
+          d4 acc2 = {0.0, 0.0, 0.0, 0.0};
           for (int k = 0; k < 16; k += 4) {
-            const double a = lget(D, ld, nb, 16 * I + li, 16 * I + k + lq);
+            const double a = lget(X, ld, nb, 16 * I + li, 16 * I + k + lq);
             const double bb = tw[(k + lq) * 16 + li];
             acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc2, 0, 0, 0);
           }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
+            if (r < nb && c < nb) X[r * ld + c] = -acc2[v];
+          }
+          wave_sync();
         }
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
-          if (r < nb && c < nb) D[r * ld + c] = -acc2[v];
-        }
-        wave_sync();
-      }
-      __syncthreads();
     }
+    __syncthreads();
     const bool last = b + 1 == nblk;
     if (!last) {
       // B_{b+1} = A_{b+1,b} D^T; wave w owns row tiles I = w, w + 4, ...
       load(Y, F + ((size_t)(b + 1) * 2 + 1) * msz);
       __syncthreads();
-      constexpr int kMaxTiles = (kMfmaNb + 15) / 16;
       for (int I = wv; I < NT; I += 4) {
         d4 acc[kMaxTiles];
 #pragma unroll
         for (int J = 0; J < kMaxTiles; ++J) {
           acc[J] = d4{0.0, 0.0, 0.0, 0.0};
-          if (J < NT)
-            acc[J] = mfma_nt(Y, D, ld, nb, 16 * I, 16 * J, 0, min((nb + 3) & ~3, 16 * J + 16),
+          if (J < NT)   // D row 16J + j is zero right of column 16J + j
+            acc[J] = mfma_nt(Y, X, ld, nb, 16 * I, 16 * J, 0, min((nb + 3) & ~3, 16 * J + 16),
                              acc[J]);
         }
         wave_sync();
@@ -358,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor_mfma(const double* __r
     T* R = O + (size_t)b * sh.bstride;
     for (int e = t; e < nb * nb; e += kThreads) {
       const int r = e / nb, c = e - (e / nb) * nb;
-      const double v = c <= r ? D[r * ld + c] : (last ? 0.0 : Y[r * ld + c]);
+      const double v = c <= r ? X[r * ld + c] : (last ? 0.0 : Y[r * ld + c]);
       R[e] = (T)v;
     }
     for (int e = t; e < nb * pe; e += kThreads) {
@@ -367,7 +263,10 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor_mfma(const double* __r
       R[nb * nb + e] = (T)v;
     }
     for (int e = nb * nb + nb * pe + t; e < sh.bstride; e += kThreads) R[e] = (T)0;
-    if (!last) load(X, F + (size_t)(b + 1) * 2 * msz);
+    if (!last) {
+      __syncthreads();
+      load(X, F + (size_t)(b + 1) * 2 * msz);
+    }
   }
 }
 
@@ -422,19 +321,9 @@ template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
                    hipStream_t st) {
   static bool attr = false;
-  if (!attr) {
-    set_lds(&k_btri_factor<T>);
-    set_lds(&k_btri_factor_mfma<T>);
-    attr = true;
-  }
-  if (sh.nb <= kMfmaNb) {
-    const size_t lds = sizeof(double) * (3 * (size_t)sh.nb * lds_ld(sh.nb) + 4 * 256);
-    hipLaunchKernelGGL(k_btri_factor_mfma<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh,
-                       flag);
-  } else {
-    const size_t lds = 2 * sizeof(double) * (size_t)sh.nb * lds_ld(sh.nb);
-    hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag);
-  }
+  if (!attr) { set_lds(&k_btri_factor<T>); attr = true; }
+  const size_t lds = sizeof(double) * (2 * (size_t)sh.nb * lds_ld(sh.nb) + 4 * 256);
+  hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag);
 }
 
 template void launch_factor<double>(const double*, double*, int, const BtriShape&, int*, hipStream_t);
