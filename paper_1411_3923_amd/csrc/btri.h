@@ -67,10 +67,56 @@ __host__ __device__ inline BtriShape coarse_shape(const Geometry& g) {
   return {g.nbc, g.nblkc, g.pec, g.bstridec};
 }
 
+// ---------------------------------------------------------------------------
+// Tiled factor storage for the single-right-hand-side subdomain solves.
+//
+// Since B_{b+1} = A_{b+1,b} L_bb^-T = A_{b+1,b} D_b^T, the two passes can be
+// written with D_b and the stiffness coupling between node layers alone:
+//   L y = r:    y_b = D_b (r_b - A_{b,b-1} (D_{b-1}^T y_{b-1}))
+//   L^T x = y:  x_b = D_b^T (y_b - D_b (A_{b+1,b}^T x_{b+1}))
+// The coupling A_{b+1,b} is the element stiffness of the element layer
+// between the two node layers and is applied matrix-free, so a record holds
+// only the lower triangle of D_b: the 4 x 4 tiles (I, J), I >= J, of the
+// block padded to 4 nt rows, tile index tau = I (I + 1) / 2 + J, element
+// e = 4 row + col inside a tile. Storage is thread-major in 16-byte vectors:
+// element e of tile tau sits at ((e / per) nl + tau) per + e % per, with
+// per = 16 / sizeof(T), so thread tau reads its tile with 16 / per coalesced
+// loads. Entries past nb and above the diagonal are zero.
+// ---------------------------------------------------------------------------
+struct TileShape {
+  int nb, nt, nl, tstride;   // block size, tile rows, lower tiles, elements per record
+};
+
+__host__ __device__ inline TileShape tile_shape(int nb) {
+  TileShape s;
+  s.nb = nb;
+  s.nt = (nb + 3) / 4;
+  s.nl = s.nt * (s.nt + 1) / 2;
+  s.tstride = 16 * s.nl;
+  return s;
+}
+
+// tau -> (I, J) with tau = I (I + 1) / 2 + J, 0 <= J <= I
+__host__ __device__ inline void tile_rc(int tau, int& I, int& J) {
+  int i = (int)((sqrtf(8.0f * (float)tau + 1.0f) - 1.0f) * 0.5f);
+  while (i * (i + 1) / 2 > tau) --i;
+  while ((i + 1) * (i + 2) / 2 <= tau) ++i;
+  I = i;
+  J = tau - i * (i + 1) / 2;
+}
+
+template <typename T>
+__host__ __device__ inline size_t tile_offset(int nl, int tau, int e) {
+  constexpr int per = 16 / (int)sizeof(T);
+  return ((size_t)(e / per) * nl + tau) * per + e % per;
+}
+
 // factor.hip
+// Packed records (tiles == false) or tiled records of D_b only (tiles == true,
+// record stride tile_shape(nb).tstride).
 template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
-                   hipStream_t st);
+                   hipStream_t st, bool tiles = false);
 void launch_solve_multi(const double* fac, const BtriShape& sh, int nmat, int m, const double* X,
                         double* Y, hipStream_t st);
 // dense symmetric inverse [nmat][n][n] of packed factors (n = nb * nblk)

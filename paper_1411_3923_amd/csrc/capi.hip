@@ -108,7 +108,8 @@ struct Sizes {
 Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   const int mixed = pr.precision == TPCG_MIXED;
   const int msub = std::min(kMaxSub, g.k + (pr.eig_extra > 0 ? pr.eig_extra : g.k));
-  const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;          // packed local factors
+  const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;          // packed Neumann factors
+  const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;   // tiled local factors
   const size_t crec = (size_t)g.nblkc * g.bstridec;                // packed coarse factor
   const size_t asm_local = (size_t)g.nsub * g.nblk * 2 * g.nb * g.nb;
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
@@ -117,7 +118,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += g.ndof + sizeof(double) * g.ndpe * g.ndpe;
   p += sizeof(double) * (size_t)g.nsub * g.nloc * g.k * (mixed ? 1.5 : 1.0);
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
-  p += ts * nsys * rec;
+  p += ts * nsys * (trec + (size_t)g.nel);
   p += sizeof(double) * nsys * crec;
   if (g.nt <= kDenseCoarse) p += sizeof(double) * nsys * (size_t)g.nt * g.nt;
   p += 4 * sizeof(double) * nsys * g.ndof;
@@ -141,9 +142,9 @@ int alloc(T*& p, size_t n) {
 
 void release(Handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phi32, h->lam, h->eres, h->lfac, h->cfac, h->cinv,
-                  h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts, h->istate,
-                  h->dflag};
+  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phi32, h->lam, h->eres, h->lfac, h->emod,
+                  h->cfac, h->cinv, h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts,
+                  h->istate, h->dflag};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);
@@ -168,22 +169,18 @@ int check_hip(Handle* h, const char* where) {
   return TPCG_OK;
 }
 
-// Minimum bytes one system's share of a local-solve launch must move: the band
-// Cholesky factor of every subdomain read twice (forward and backward), the
-// right-hand sides read once (FP64) and the results written once. The
-// half-bandwidth of a subdomain matrix in box order is
-// dim * (bn^(dim-1) + ... + bn + 1) + dim - 1.
-double band_bytes(int64_t n, int64_t w, int elem) {
-  const int64_t full = n * (w + 1) - (w * (w + 1)) / 2;   // rows shorter near the top
-  return (double)full * elem;
-}
-
+// Minimum bytes one system's share of a local-solve launch must move, per
+// subdomain: the lower triangles of the inverted diagonal factor blocks D_b
+// (read in the forward and the backward pass; the last block once), the
+// moduli of the inner element layers, the right-hand side (FP64) and the
+// support flags read once, the forward result written and read back and the
+// solution written.
 double local_solve_bytes(const Geometry& g, int elem) {
-  int64_t w = 1;
-  for (int a = 1; a < g.dim; ++a) w = w * g.bn + 1;
-  w = g.dim * w + g.dim - 1;
-  return g.nsub * (2.0 * band_bytes(g.nloc, std::min<int64_t>(w, g.nloc - 1), elem) +
-                   (double)g.nloc * (8 + elem));
+  const double tri = 0.5 * g.nb * (g.nb + 1.0);
+  const double sw = g.dim == 3 ? (g.bn + 1.0) * (g.bn + 1.0) : g.bn + 1.0;
+  const double per = (2.0 * g.nblk - 1.0) * tri * elem + (g.nblk - 1.0) * sw * elem +
+                     (double)g.nloc * (8.0 + 1.0 + 3.0 * elem);
+  return g.nsub * per;
 }
 
 Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int enabled) {
@@ -292,7 +289,7 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
   if (!h->phi) {
     // preconditioner storage for nsys_max systems, allocated on first build
     const int ns = h->prob.nsys_max;
-    const size_t fsz = (size_t)g.nblk * g.bstride;
+    const size_t fsz = (size_t)g.nblk * tile_shape(g.nb).tstride;
     const size_t cfsz = (size_t)g.nblkc * g.bstridec;
     const size_t ts = h->mixed ? 4 : 8;
     int e = TPCG_OK;
@@ -303,6 +300,9 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     unsigned char* lf = nullptr;
     e |= alloc(lf, ts * ns * g.nsub * fsz);
     h->lfac = lf;
+    unsigned char* em = nullptr;
+    e |= alloc(em, ts * ns * (size_t)g.nel);
+    h->emod = em;
     e |= alloc(h->cfac, ns * cfsz);
     if (g.nt <= kDenseCoarse) e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
     unsigned char* zl = nullptr;

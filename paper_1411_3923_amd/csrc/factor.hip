@@ -77,7 +77,7 @@ constexpr int kMaxTiles = (kMaxNb + 15) / 16;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restrict__ A,
                                                          T* __restrict__ out, BtriShape sh,
-                                                         int* __restrict__ flag) {
+                                                         int* __restrict__ flag, int tiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
   const int ld = lds_ld(nb);
@@ -87,7 +87,9 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   double* tmp = Y + (size_t)nb * ld;              // 16 x 16 per wave
   const size_t msz = (size_t)nb * nb;
   const double* F = A + (size_t)blockIdx.x * nblk * 2 * msz;
-  T* O = out + (size_t)blockIdx.x * nblk * sh.bstride;
+  const TileShape tsh = tile_shape(nb);
+  const int rstride = tiles ? tsh.tstride : sh.bstride;
+  T* O = out + (size_t)blockIdx.x * nblk * rstride;
   const int t = threadIdx.x;
   const int wv = t >> 6, l = t & 63;
   const int li = l & 15, lq = l >> 4;
@@ -250,8 +252,26 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
       }
       __syncthreads();
     }
+    T* R = O + (size_t)b * rstride;
+    if (tiles) {
+      // record b: the lower tiles of D_b, thread-major
+      constexpr int per = 16 / (int)sizeof(T);
+      for (int o = t; o < tsh.tstride; o += kThreads) {
+        const int q = o / per, w = o - (o / per) * per;
+        const int v = q / tsh.nl, tau = q - (q / tsh.nl) * tsh.nl;
+        const int e = v * per + w;
+        int I, J;
+        tile_rc(tau, I, J);
+        const int r = 4 * I + e / 4, c = 4 * J + (e & 3);
+        R[o] = (T)((r < nb && c <= r) ? X[r * ld + c] : 0.0);
+      }
+      if (!last) {
+        __syncthreads();
+        load(X, F + (size_t)(b + 1) * 2 * msz);
+      }
+      continue;
+    }
     // record b: lower(D_b) | strict upper(B_{b+1}) | band of B_{b+1}
-    T* R = O + (size_t)b * sh.bstride;
     for (int e = t; e < nb * nb; e += kThreads) {
       const int r = e / nb, c = e - (e / nb) * nb;
       const double v = c <= r ? X[r * ld + c] : (last ? 0.0 : Y[r * ld + c]);
@@ -319,15 +339,18 @@ void set_lds(K kernel) {
 
 template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
-                   hipStream_t st) {
+                   hipStream_t st, bool tiles) {
   static bool attr = false;
   if (!attr) { set_lds(&k_btri_factor<T>); attr = true; }
   const size_t lds = sizeof(double) * (2 * (size_t)sh.nb * lds_ld(sh.nb) + 4 * 256);
-  hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag);
+  hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag,
+                     tiles ? 1 : 0);
 }
 
-template void launch_factor<double>(const double*, double*, int, const BtriShape&, int*, hipStream_t);
-template void launch_factor<float>(const double*, float*, int, const BtriShape&, int*, hipStream_t);
+template void launch_factor<double>(const double*, double*, int, const BtriShape&, int*,
+                                    hipStream_t, bool);
+template void launch_factor<float>(const double*, float*, int, const BtriShape&, int*,
+                                   hipStream_t, bool);
 
 #define TPCG_MULTI_CASE(V)                                                                  \
   case V: {                                                                                 \

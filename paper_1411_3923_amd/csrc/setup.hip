@@ -22,11 +22,6 @@ namespace {
 
 constexpr double kFixedDiag = 1.0e3;   // decoupled supported DOFs of S_j sit far above its spectrum
 
-__device__ inline int corner_of(int dx, int dy, int dz) {
-  // counter-clockwise in the x-y plane, bottom face first
-  return (dy ? (dx ? 2 : 3) : (dx ? 1 : 0)) + 4 * dz;
-}
-
 struct NodeRef {
   int gx, gy, gz, c;
   int64_t dof;
@@ -135,9 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_assemble(Geometry g, const double*
   }
 }
 
-// In-place block-tridiagonal Cholesky (FP64), one workgroup per matrix:
-// A_bb <- D_b = L_bb^-1, A_{b,b-1} <- B_b = L_{b,b-1}. flag[0] |= 1 on a
-// non-positive pivot (the pivot is then replaced by 1 to keep going).
+// Deterministic start vectors of the subspace iteration.
 __device__ inline double hash_uniform(uint64_t a) {
   // splitmix64 finaliser, mapped to [-1, 1)
   a += 0x9E3779B97F4A7C15ull;
@@ -578,6 +571,15 @@ __global__ __launch_bounds__(kThreads) void k_coarse_assemble(Geometry g, const 
 }
 
 
+// moduli E_e of the systems the local factors are built from
+template <typename T>
+__global__ void k_moduli(const double* __restrict__ rho, T* __restrict__ out, int64_t n,
+                         double E0, double Emin, double penal) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    out[i] = (T)simp_modulus(rho[i], E0, Emin, penal);
+}
+
 __global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads)
@@ -666,16 +668,26 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   hipFree(W);
   hipFree(Ac);
 
-  // --- 5: local Dirichlet factors, one system at a time (FP32 records in mixed mode) ---
+  // --- 5: local Dirichlet factors, one system at a time, as tiled D_b records
+  //        (FP32 in mixed mode), and the moduli their layer couplings use ---
+  const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;
+  const int64_t nm = (int64_t)nsys * g.nel;
   for (int sys = 0; sys < nsys; ++sys) {
     hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g,
                        rho + (size_t)sys * g.nel, h.fixed, h.K0, A, nullptr, mp, 0);
     if (h.mixed)
-      launch_factor<float>(A, reinterpret_cast<float*>(h.lfac) + sys * rec, g.nsub, lsh, h.dflag, st);
+      launch_factor<float>(A, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh, h.dflag,
+                           st, true);
     else
-      launch_factor<double>(A, reinterpret_cast<double*>(h.lfac) + sys * rec, g.nsub, lsh, h.dflag,
-                            st);
+      launch_factor<double>(A, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub, lsh,
+                            h.dflag, st, true);
   }
+  if (h.mixed)
+    hipLaunchKernelGGL(k_moduli<float>, dim3(1024), dim3(kThreads), 0, st, rho,
+                       reinterpret_cast<float*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
+  else
+    hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, st, rho,
+                       reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
   hipStreamSynchronize(st);
   hipFree(A);
 

@@ -74,7 +74,8 @@ struct Handle {
   float* phi32 = nullptr;            // same, FP32 (mixed)
   double* lam = nullptr;             // [nsub][msub] Ritz values
   double* eres = nullptr;            // [nsub][msub] residual norms
-  void* lfac = nullptr;              // packed [nsys][nsub][nblk][bstride], double or float
+  void* lfac = nullptr;              // tiled D_b [nsys][nsub][nblk][tstride], double or float
+  void* emod = nullptr;              // moduli the local factors were built from [nsys][nel], same type
   double* cfac = nullptr;            // packed [nsys][nblkc][bstridec]
   double* cinv = nullptr;            // dense K_c^-1 [nsys][nt][nt] when nt <= kDenseCoarse
   hipStream_t side = nullptr;        // second stream for the coarse solve (forked per apply)
@@ -146,6 +147,12 @@ __device__ inline double sum_parts(const double* __restrict__ p, int n, double* 
   double v = 0.0;
   for (int i = threadIdx.x; i < n; i += kThreads) v += p[i];
   return block_sum(v, sh);
+}
+
+// element-local node of the corner at offset (dx, dy, dz) from the element's
+// first node: counter-clockwise in the x-y plane, bottom face first
+__host__ __device__ inline int corner_of(int dx, int dy, int dz) {
+  return (dy ? (dx ? 2 : 3) : (dx ? 1 : 0)) + 4 * dz;
 }
 
 __device__ inline double simp_modulus(double rho, double E0, double Emin, double penal) {
