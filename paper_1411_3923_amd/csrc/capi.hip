@@ -116,7 +116,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   const size_t ts = mixed ? 4 : 8;
   size_t p = 0;
   p += g.ndof + sizeof(double) * g.ndpe * g.ndpe;
-  p += sizeof(double) * (size_t)g.nsub * g.nloc * g.k * (mixed ? 1.5 : 1.0);
+  p += (sizeof(double) + ts) * (size_t)g.nsub * g.nloc * g.k;
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
   p += ts * nsys * (trec + (size_t)g.nel);
   p += sizeof(double) * nsys * crec;
@@ -142,7 +142,7 @@ int alloc(T*& p, size_t n) {
 
 void release(Handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phi32, h->lam, h->eres, h->lfac, h->emod,
+  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phim, h->lam, h->eres, h->lfac, h->emod,
                   h->cfac, h->cinv, h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts,
                   h->istate, h->dflag};
   for (void* p : ptrs)
@@ -294,7 +294,9 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     const size_t ts = h->mixed ? 4 : 8;
     int e = TPCG_OK;
     e |= alloc(h->phi, (size_t)g.nsub * g.nloc * g.k);
-    if (h->mixed) e |= alloc(h->phi32, (size_t)g.nsub * g.nloc * g.k);
+    unsigned char* pm = nullptr;
+    e |= alloc(pm, ts * (size_t)g.nsub * g.nloc * g.k);
+    h->phim = pm;
     e |= alloc(h->lam, (size_t)g.nsub * h->msub);
     e |= alloc(h->eres, (size_t)g.nsub * h->msub);
     unsigned char* lf = nullptr;
@@ -360,6 +362,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   nog.enabled = 0;
   launch_apply_K(*h, rho_phys, u, h->q, nsys, -1, nog, st);
   launch_residual_init(*h, f, u, h->q, nsys, st);
+  launch_gate(*h, nsys, g0, st);
   h->prof_n = 0;
   launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, -1, flexible, st);
   launch_update_p(*h, nsys, g0, flexible, 1, st);
@@ -375,6 +378,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
       Gate gn = make_gate(h, rr_next, it + 1, maxit, tol2, 1);
       launch_apply_K(*h, rho_phys, h->p, h->q, nsys, kPartPQ, gi, st);
       launch_update_xr(*h, u, nsys, gi, st);
+      launch_gate(*h, nsys, gn, st);
       launch_precond(*h, h->r, h->z, nsys, gn, rz_next, it, flexible, st);
       launch_update_p(*h, nsys, gn, flexible, 0, st);
     }

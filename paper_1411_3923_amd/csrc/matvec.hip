@@ -18,7 +18,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_q4(
   __shared__ double K0s[64];
   __shared__ double sh[4];
   const int sys = blockIdx.y;
-  if (!gate_running(gate, sys, sh)) return;
+  if (!gate_running(gate, sys)) return;
   if (threadIdx.x < 64) K0s[threadIdx.x] = K0[threadIdx.x];
   __syncthreads();
   const double* xs = x + (size_t)sys * g.ndof;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kThreads) void k_apply_h8(
   __shared__ double K0s[576];
   __shared__ double sh[4];
   const int sys = blockIdx.y;
-  if (!gate_running(gate, sys, sh)) return;
+  if (!gate_running(gate, sys)) return;
   for (int i = threadIdx.x; i < 576; i += kThreads) K0s[i] = K0[i];
   __syncthreads();
   const double* xs = x + (size_t)sys * g.ndof;

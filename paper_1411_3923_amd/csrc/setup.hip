@@ -580,10 +580,17 @@ __global__ void k_moduli(const double* __restrict__ rho, T* __restrict__ out, in
     out[i] = (T)simp_modulus(rho[i], E0, Emin, penal);
 }
 
-__global__ void k_to_float(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+// mode-major copy of Phi for the iteration kernels: out[j][m][l] = phi[j][l][m]
+template <typename T>
+__global__ void k_phi_modes(Geometry g, const double* __restrict__ phi, T* __restrict__ out) {
+  const int64_t n = (int64_t)g.nsub * g.nloc * g.k;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads)
-    b[i] = (float)a[i];
+       i += (int64_t)gridDim.x * kThreads) {
+    const int64_t j = i / ((int64_t)g.k * g.nloc);
+    const int rem = (int)(i - j * g.k * g.nloc);
+    const int m = rem / g.nloc, l = rem - (rem / g.nloc) * g.nloc;
+    out[i] = (T)phi[((size_t)j * g.nloc + l) * g.k + m];
+  }
 }
 
 template <typename T>
@@ -638,10 +645,12 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
                      Y, m, mp);
   hipLaunchKernelGGL(k_eig_rr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, Y, dis, m, h.lam,
                      h.eres, h.phi);
-  if (h.mixed) {
-    const int64_t n = (int64_t)g.nsub * g.nloc * g.k;
-    hipLaunchKernelGGL(k_to_float, dim3(1024), dim3(kThreads), 0, st, h.phi, h.phi32, n);
-  }
+  if (h.mixed)
+    hipLaunchKernelGGL(k_phi_modes<float>, dim3(1024), dim3(kThreads), 0, st, g, h.phi,
+                       reinterpret_cast<float*>(h.phim));
+  else
+    hipLaunchKernelGGL(k_phi_modes<double>, dim3(1024), dim3(kThreads), 0, st, g, h.phi,
+                       reinterpret_cast<double*>(h.phim));
   hipStreamSynchronize(st);
   hipFree(nfac); hipFree(X); hipFree(Y); hipFree(dis);
 

@@ -54,6 +54,25 @@ __host__ __device__ inline int coarse_index(const Geometry& g, int jx, int jy, i
   return blk * g.nbc + w * g.k + m;
 }
 
+// global DOF of local DOF l (box order) of subdomain (jx, jy, jz)
+__device__ inline int64_t box_dof(const Geometry& g, int jx, int jy, int jz, int l) {
+  const int d = g.dim;
+  const int ln = l / d, c = l - ln * d;
+  const int lx = ln % g.bn;
+  const int rest = ln / g.bn;
+  const int ly = rest % g.bn;
+  const int lz = rest / g.bn;
+  const int64_t n = (int64_t)(g.s * jx + lx) +
+                    (int64_t)g.nnx * ((g.s * jy + ly) + (int64_t)g.nny * (g.s * jz + lz));
+  return d * n + c;
+}
+
+__host__ __device__ inline void sub_coords(const Geometry& g, int j, int& jx, int& jy, int& jz) {
+  jx = j % g.gx;
+  jy = (j / g.gx) % g.gy;
+  jz = j / (g.gx * g.gy);
+}
+
 struct Handle {
   tpcg_problem prob;
   Geometry g;
@@ -71,7 +90,7 @@ struct Handle {
   int nsys_built = 0;
   int msub = 0;                      // eigensolver subspace width
   double* phi = nullptr;             // [nsub][nloc][k]
-  float* phi32 = nullptr;            // same, FP32 (mixed)
+  void* phim = nullptr;              // mode-major copy [nsub][k][nloc], double (FP32 when mixed)
   double* lam = nullptr;             // [nsub][msub] Ritz values
   double* eres = nullptr;            // [nsub][msub] residual norms
   void* lfac = nullptr;              // tiled D_b [nsys][nsub][nblk][tstride], double or float
@@ -119,7 +138,7 @@ enum {
 };
 
 // Per-system integer state [kNumState][kMaxSys].
-enum { kStLastIt = 0, kStBreak = 1, kStPoll = 2, kNumState = 3 };
+enum { kStLastIt = 0, kStBreak = 1, kStPoll = 2, kStRun = 3, kNumState = 4 };
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -131,21 +150,27 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum over the 256 threads of a workgroup; every thread gets the same value.
-// `sh` needs 4 doubles of LDS. Fixed reduction tree: deterministic.
+// Sum over the threads of a workgroup (blockDim.x a multiple of 64, at most
+// 256); every thread gets the same value. `sh` needs 4 doubles of LDS. Fixed
+// reduction tree: deterministic.
 __device__ inline double block_sum(double v, double* sh) {
   v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) sh[w] = v;
   __syncthreads();
-  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  double s = sh[0];
+  if (nw == 4) s = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  else
+    for (int i = 1; i < nw; ++i) s += sh[i];
+  return s;
 }
 
-// Sum of n partials in a fixed order (identical in every workgroup).
+// Sum of n partials in a fixed order (identical in every workgroup of a
+// launch).
 __device__ inline double sum_parts(const double* __restrict__ p, int n, double* sh) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += kThreads) v += p[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += p[i];
   return block_sum(v, sh);
 }
 
@@ -162,8 +187,9 @@ __device__ inline double simp_modulus(double rho, double E0, double Emin, double
 
 // Convergence gate of a batched PCG kernel. A system keeps running while
 // its recursive residual r.r (partials in slot rr_slot) exceeds tol2 * ||Pf||^2,
-// no breakdown was flagged and the iteration index is below maxit. Every
-// workgroup re-sums the same partials in the same order, so all agree.
+// no breakdown was flagged and the iteration index is below maxit. The
+// residual test is taken once per iteration by k_gate (launch_gate), which
+// stores it in the kStRun state; the kernels read that flag.
 struct Gate {
   const double* parts;
   const int* istate;
@@ -175,13 +201,11 @@ struct Gate {
   int enabled;     // 0: always run
 };
 
-__device__ inline bool gate_running(const Gate& gt, int sys, double* sh) {
+__device__ inline bool gate_running(const Gate& gt, int sys) {
   if (!gt.enabled) return true;
   if (gt.it >= gt.maxit) return false;
   if (gt.istate[kStBreak * kMaxSys + sys]) return false;
-  const double rr = sum_parts(gt.parts + ((size_t)gt.rr_slot * kMaxSys + sys) * kMaxParts, gt.np, sh);
-  const double ff = sum_parts(gt.parts + ((size_t)kPartFF * kMaxSys + sys) * kMaxParts, gt.np, sh);
-  return rr > gt.tol2 * ff;   // false for NaN as well
+  return gt.istate[kStRun * kMaxSys + sys] != 0;
 }
 
 inline int parts_for(int64_t work) {
@@ -209,6 +233,8 @@ void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hi
 void launch_update_p(const Handle& h, int nsys, const Gate& gate, int flexible, int first,
                      hipStream_t st);
 void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st);
+// residual test of gate.rr_slot into the kStRun flags
+void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st);
 // true residual of P(f - q) (q must hold K u) and out[sys] = {iters, status, relres, true_relres}
 void launch_summary(const Handle& h, const double* f, int nsys, const Gate& gate,
                     double* out /*dev [nsys][4]*/, hipStream_t st);
@@ -218,6 +244,9 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 // prof_it >= -1 records events around the block-solve launch when profiling is on
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
                     int rz_slot, int prof_it, int flexible, hipStream_t st);
+
+// local.hip: zloc = A_j^-1 R_j r for every running (system, subdomain)
+void launch_local_solves(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st);
 
 // setup.hip
 int build_preconditioner(Handle& h, const double* rho, int nsys, int rep);

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(
   const int slot_old = gate.rr_slot;
   const int slot_new = slot_old == kPartRR0 ? kPartRR1 : kPartRR0;
   const int rz_slot = slot_old == kPartRR0 ? kPartRZ0 : kPartRZ1;
-  bool run = gate_running(gate, sys, sh);
+  bool run = gate_running(gate, sys);
   double alpha = 0.0;
   if (run) {
     const double pq = sum_parts(part_slot(parts, kPartPQ, sys), gate.np, sh);
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_update_p(
     double* __restrict__ parts, int* __restrict__ istate, Gate gate, int flexible, int first) {
   __shared__ double sh[4];
   const int sys = blockIdx.y;
-  if (!gate_running(gate, sys, sh)) return;
+  if (!gate_running(gate, sys)) return;
   double beta = 0.0;
   if (!first) {
     // the preconditioner of iteration it wrote r.z into the slot of parity it+1
@@ -129,10 +129,19 @@ __global__ __launch_bounds__(kThreads) void k_update_p(
     p[off + i] = z[off + i] + beta * p[off + i];
 }
 
-__global__ void k_poll(Gate gate, int* __restrict__ istate) {
+// the residual test of the gate, once per iteration: kStRun = r.r > tol2 ||Pf||^2
+__global__ __launch_bounds__(kThreads) void k_gate(Gate gate, int* __restrict__ istate) {
   __shared__ double sh[4];
   const int sys = blockIdx.x;
-  const bool run = gate_running(gate, sys, sh);
+  double* parts = const_cast<double*>(gate.parts);
+  const double rr = sum_parts(part_slot(parts, gate.rr_slot, sys), gate.np, sh);
+  const double ff = sum_parts(part_slot(parts, kPartFF, sys), gate.np, sh);
+  if (threadIdx.x == 0) istate[kStRun * kMaxSys + sys] = rr > gate.tol2 * ff ? 1 : 0;
+}
+
+__global__ void k_poll(Gate gate, int* __restrict__ istate) {
+  const int sys = blockIdx.x;
+  const bool run = gate_running(gate, sys);
   if (threadIdx.x == 0) istate[kStPoll * kMaxSys + sys] = run ? 1 : 0;
 }
 
@@ -196,6 +205,10 @@ void launch_update_p(const Handle& h, int nsys, const Gate& gate, int flexible, 
   dim3 grid(parts_for(h.g.nnodes), nsys);
   hipLaunchKernelGGL(k_update_p, grid, dim3(kThreads), 0, st, h.g, h.p, h.z, h.parts, h.istate,
                      gate, flexible, first);
+}
+
+void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_gate, dim3(nsys), dim3(kThreads), 0, st, gate, h.istate);
 }
 
 void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
