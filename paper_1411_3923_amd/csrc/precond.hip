@@ -14,15 +14,18 @@ namespace tpcg {
 
 namespace {
 
+constexpr int kSubThreads = 1024;   // restriction: one 16-wave workgroup per subdomain
+constexpr int kAddChunk = 256;      // coarse addition: box DOFs per workgroup
+
 // One workgroup per subdomain, all running systems together (Phi, mode-major,
 // read once); KM >= k bounds the accumulators.
 template <typename P, int KM>
-__global__ __launch_bounds__(kThreads) void k_restrict(Geometry g, const P* __restrict__ phim,
-                                                       const double* __restrict__ r,
-                                                       double* __restrict__ yc, int nsys,
-                                                       Gate gate) {
-  __shared__ double sh[4];
-  __shared__ double red[4][kMaxSys * KM];
+__global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* __restrict__ phim,
+                                                          const double* __restrict__ r,
+                                                          double* __restrict__ yc, int nsys,
+                                                          Gate gate) {
+  constexpr int NW = kSubThreads / 64;
+  __shared__ double red[NW][kMaxSys * KM];
   unsigned run = 0;
   for (int sys = 0; sys < nsys; ++sys)
     if (gate_running(gate, sys)) run |= 1u << sys;
@@ -37,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_restrict(Geometry g, const P* __re
   for (int q = 0; q < kMaxSys; ++q)
 #pragma unroll
     for (int m = 0; m < KM; ++m) acc[q][m] = 0.0;
-  for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+  for (int l = threadIdx.x; l < g.nloc; l += kSubThreads) {
     const int64_t dof = box_dof(g, jx, jy, jz, l);
     double rv[kMaxSys];
 #pragma unroll
@@ -60,12 +63,14 @@ __global__ __launch_bounds__(kThreads) void k_restrict(Geometry g, const P* __re
         if ((threadIdx.x & 63) == 0) red[w][q * KM + m] = v;
       }
   __syncthreads();
-  for (int i = threadIdx.x; i < nsys * k; i += kThreads) {
+  for (int i = threadIdx.x; i < nsys * k; i += kSubThreads) {
     const int q = i / k, m = i - (i / k) * k;
     if (!((run >> q) & 1u)) continue;
     const int e = q * KM + m;
-    yc[(size_t)q * g.nt + coarse_index(g, jx, jy, jz, m)] =
-        (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+    double s = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < NW; ++w2) s += red[w2][e];
+    yc[(size_t)q * g.nt + coarse_index(g, jx, jy, jz, m)] = s;
   }
 }
 
@@ -106,19 +111,22 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemv(Geometry g, const doub
   if (lane == 0) xc[(size_t)sys * g.nt + row] = s;
 }
 
-// zloc_j += Phi_j x_c,j in place for every running system: one workgroup per
-// subdomain, Phi (mode-major, [nsub][k][nloc]) read once for all systems,
-// every access contiguous.
+// zloc_j += Phi_j x_c,j in place for every running system: workgroup
+// (j, chunk) updates kAddChunk box DOFs of subdomain j, one per thread; Phi
+// (mode-major, [nsub][k][nloc]) read once for all systems, every access
+// contiguous.
 template <typename T, typename P, int KM>
-__global__ __launch_bounds__(kThreads) void k_coarse_add(Geometry g, T* __restrict__ zloc,
-                                                         const P* __restrict__ phim,
-                                                         const double* __restrict__ xc, int nsys,
-                                                         Gate gate) {
+__global__ __launch_bounds__(kAddChunk) void k_coarse_add(Geometry g, T* __restrict__ zloc,
+                                                          const P* __restrict__ phim,
+                                                          const double* __restrict__ xc, int nsys,
+                                                          Gate gate) {
   unsigned run = 0;
   for (int sys = 0; sys < nsys; ++sys)
     if (gate_running(gate, sys)) run |= 1u << sys;
   if (!run) return;
   const int j = blockIdx.x;
+  const int l = blockIdx.y * kAddChunk + threadIdx.x;
+  if (l >= g.nloc) return;
   int jx, jy, jz;
   sub_coords(g, j, jx, jy, jz);
   const int k = g.k;
@@ -132,24 +140,22 @@ __global__ __launch_bounds__(kThreads) void k_coarse_add(Geometry g, T* __restri
   const P* ph = phim + (size_t)j * k * g.nloc;
   const size_t zstride = (size_t)g.nsub * g.nloc;
   T* zj = zloc + (size_t)j * g.nloc;
-  for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
-    double a[kMaxSys];
+  double a[kMaxSys];
 #pragma unroll
-    for (int q = 0; q < kMaxSys; ++q) a[q] = 0.0;
+  for (int q = 0; q < kMaxSys; ++q) a[q] = 0.0;
 #pragma unroll
-    for (int m = 0; m < KM; ++m)
-      if (m < k) {
-        const double p = (double)ph[(size_t)m * g.nloc + l];
+  for (int m = 0; m < KM; ++m)
+    if (m < k) {
+      const double p = (double)ph[(size_t)m * g.nloc + l];
 #pragma unroll
-        for (int q = 0; q < kMaxSys; ++q) a[q] += p * xv[q][m];
-      }
+      for (int q = 0; q < kMaxSys; ++q) a[q] += p * xv[q][m];
+    }
 #pragma unroll
-    for (int q = 0; q < kMaxSys; ++q)
-      if ((run >> q) & 1u) {
-        T* zq = zj + q * zstride + l;
-        *zq = (T)((double)*zq + a[q]);
-      }
-  }
+  for (int q = 0; q < kMaxSys; ++q)
+    if ((run >> q) & 1u) {
+      T* zq = zj + q * zstride + l;
+      *zq = (T)((double)*zq + a[q]);
+    }
 }
 
 // z(n) = P sum_{j owns n} zloc_j(n) for every running system, with the fused
@@ -252,6 +258,37 @@ void coarse_launch(Handle& h, int nsys, const Gate& gate, hipStream_t st) {
   }
 }
 
+// Phi^T r for every running system (T: precision of the iteration copy of Phi)
+template <typename T>
+void restrict_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
+  const Geometry& g = h.g;
+  const T* pm = reinterpret_cast<const T*>(h.phim);
+  if (g.k <= 8)
+    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(g.nsub), dim3(kSubThreads), 0, st, g, pm, r, h.yc,
+                       nsys, gate);
+  else
+    hipLaunchKernelGGL((k_restrict<T, kMaxK>), dim3(g.nsub), dim3(kSubThreads), 0, st, g, pm, r,
+                       h.yc, nsys, gate);
+}
+
+// zloc += Phi x_c, then z = P sum_j R_j^T zloc_j with the r.z partials
+template <typename T>
+void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& gate, int rz_slot,
+                   int flexible, hipStream_t st) {
+  const Geometry& g = h.g;
+  const T* pm = reinterpret_cast<const T*>(h.phim);
+  T* zl = reinterpret_cast<T*>(h.zloc);
+  const dim3 agrid(g.nsub, (g.nloc + kAddChunk - 1) / kAddChunk);
+  if (g.k <= 8)
+    hipLaunchKernelGGL((k_coarse_add<T, T, 8>), agrid, dim3(kAddChunk), 0, st, g, zl, pm, h.xc,
+                       nsys, gate);
+  else
+    hipLaunchKernelGGL((k_coarse_add<T, T, kMaxK>), agrid, dim3(kAddChunk), 0, st, g, zl, pm,
+                       h.xc, nsys, gate);
+  hipLaunchKernelGGL(k_extend<T>, dim3(parts_for(g.nnodes)), dim3(kThreads), 0, st, g, r, z, zl,
+                     h.fixed, h.parts, rz_slot, flexible, nsys, gate);
+}
+
 }  // namespace
 
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
@@ -267,23 +304,8 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   auto mark = [&](int which) {
     if (prof) hipEventRecord(h.prof_ev[2 * h.prof_n + which], st);
   };
-  const float* pm32 = reinterpret_cast<const float*>(h.phim);
-  const double* pm64 = reinterpret_cast<const double*>(h.phim);
-  if (h.mixed) {
-    if (g.k <= 8)
-      hipLaunchKernelGGL((k_restrict<float, 8>), dim3(g.nsub), dim3(kThreads), 0, st, g, pm32, r,
-                         h.yc, nsys, gate);
-    else
-      hipLaunchKernelGGL((k_restrict<float, kMaxK>), dim3(g.nsub), dim3(kThreads), 0, st, g,
-                         pm32, r, h.yc, nsys, gate);
-  } else {
-    if (g.k <= 8)
-      hipLaunchKernelGGL((k_restrict<double, 8>), dim3(g.nsub), dim3(kThreads), 0, st, g, pm64,
-                         r, h.yc, nsys, gate);
-    else
-      hipLaunchKernelGGL((k_restrict<double, kMaxK>), dim3(g.nsub), dim3(kThreads), 0, st, g,
-                         pm64, r, h.yc, nsys, gate);
-  }
+  if (h.mixed) restrict_launch<float>(h, r, nsys, gate, st);
+  else restrict_launch<double>(h, r, nsys, gate, st);
   // the coarse solves run beside the local ones on the side stream
   hipEventRecord(h.fork, st);
   hipStreamWaitEvent(h.side, h.fork, 0);
@@ -297,28 +319,8 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   launch_local_solves(h, r, nsys, gate, st);
   mark(1);
   hipStreamWaitEvent(st, h.join, 0);
-  const dim3 egrid(parts_for(g.nnodes));
-  if (h.mixed) {
-    float* zl = reinterpret_cast<float*>(h.zloc);
-    if (g.k <= 8)
-      hipLaunchKernelGGL((k_coarse_add<float, float, 8>), dim3(g.nsub), dim3(kThreads), 0, st, g,
-                         zl, pm32, h.xc, nsys, gate);
-    else
-      hipLaunchKernelGGL((k_coarse_add<float, float, kMaxK>), dim3(g.nsub), dim3(kThreads), 0, st,
-                         g, zl, pm32, h.xc, nsys, gate);
-    hipLaunchKernelGGL(k_extend<float>, egrid, dim3(kThreads), 0, st, g, r, z, zl, h.fixed,
-                       h.parts, rz_slot, flexible, nsys, gate);
-  } else {
-    double* zl = reinterpret_cast<double*>(h.zloc);
-    if (g.k <= 8)
-      hipLaunchKernelGGL((k_coarse_add<double, double, 8>), dim3(g.nsub), dim3(kThreads), 0, st,
-                         g, zl, pm64, h.xc, nsys, gate);
-    else
-      hipLaunchKernelGGL((k_coarse_add<double, double, kMaxK>), dim3(g.nsub), dim3(kThreads), 0,
-                         st, g, zl, pm64, h.xc, nsys, gate);
-    hipLaunchKernelGGL(k_extend<double>, egrid, dim3(kThreads), 0, st, g, r, z, zl, h.fixed,
-                       h.parts, rz_slot, flexible, nsys, gate);
-  }
+  if (h.mixed) extend_launch<float>(h, r, z, nsys, gate, rz_slot, flexible, st);
+  else extend_launch<double>(h, r, z, nsys, gate, rz_slot, flexible, st);
   if (prof) h.prof_it[h.prof_n++] = prof_it;
 }
 

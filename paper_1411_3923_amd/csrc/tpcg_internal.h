@@ -14,7 +14,7 @@
 namespace tpcg {
 
 constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
-constexpr int kMaxParts = 512;       // reduction partials per system and vector kernel
+constexpr int kMaxParts = 2048;      // reduction partials per system and vector kernel
 constexpr int kMaxSys = 4;           // systems solved together
 constexpr int kMaxK = 16;            // coarse vectors per subdomain
 constexpr int kMaxSub = 16;          // eigensolver subspace width
@@ -222,7 +222,9 @@ __host__ __device__ inline double* part_slot(double* parts, int slot, int sys) {
 // parts_for(nnodes) workgroups per system, so their partials line up.
 // ---------------------------------------------------------------------------
 
-// matvec.hip: y = P K(rho) P x; optional partials of x.y into slot `dot_slot` (-1: none)
+// matvec.hip: y = P K(rho) P x; optional partials of x.y into slot `dot_slot` (-1: none),
+// apply_parts(g) of them per system
+int apply_parts(const Geometry& g);
 void launch_apply_K(const Handle& h, const double* rho, const double* x, double* y, int nsys,
                     int dot_slot, const Gate& gate, hipStream_t st);
 

@@ -46,13 +46,14 @@ __global__ __launch_bounds__(kThreads) void k_residual_init(
   }
 }
 
-// Iteration `it`: alpha = (r.z)/(p.q); u += alpha p; r -= alpha q; partials of
+// Iteration `it`: alpha = (r.z)/(p.q) (np_pq partials of p.q from the
+// operator launch); u += alpha p; r -= alpha q; partials of
 // the new r.r into the other parity slot. Breakdown (p.q <= 0 or not finite)
 // stops the system.
 __global__ __launch_bounds__(kThreads) void k_update_xr(
     Geometry g, double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ q, double* __restrict__ parts, int* __restrict__ istate,
-    Gate gate) {
+    Gate gate, int np_pq) {
   __shared__ double sh[4];
   const int sys = blockIdx.y;
   const int slot_old = gate.rr_slot;
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(
   bool run = gate_running(gate, sys);
   double alpha = 0.0;
   if (run) {
-    const double pq = sum_parts(part_slot(parts, kPartPQ, sys), gate.np, sh);
+    const double pq = sum_parts(part_slot(parts, kPartPQ, sys), np_pq, sh);
     const double rz = sum_parts(part_slot(parts, rz_slot, sys), gate.np, sh);
     alpha = rz / pq;
     if (!(pq > 0.0) || !isfinite(alpha)) {
@@ -197,7 +198,7 @@ void launch_residual_init(const Handle& h, const double* f, double* u, const dou
 void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hipStream_t st) {
   dim3 grid(parts_for(h.g.nnodes), nsys);
   hipLaunchKernelGGL(k_update_xr, grid, dim3(kThreads), 0, st, h.g, u, h.r, h.p, h.q, h.parts,
-                     h.istate, gate);
+                     h.istate, gate, apply_parts(h.g));
 }
 
 void launch_update_p(const Handle& h, int nsys, const Gate& gate, int flexible, int first,
