@@ -144,7 +144,7 @@ void release(Handle* h) {
   if (!h) return;
   void* ptrs[] = {h->fixed, h->K0, h->phi, h->phim, h->lam, h->eres, h->lfac, h->emod,
                   h->cfac, h->cinv, h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts,
-                  h->istate, h->dflag};
+                  h->istate, h->dflag, h->build_ws};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);

@@ -1,7 +1,7 @@
-// Batched block-tridiagonal Cholesky factorisation into the packed record
-// format of btri.h (one workgroup per matrix), the multi-right-hand-side
-// solve used by the subspace iteration of the local eigenproblems, and the
-// dense inverse of a packed factor.
+// Batched block-tridiagonal Cholesky factorisation into the packed or the
+// tiled record format of btri.h (one workgroup per matrix), the
+// multi-right-hand-side solve used by the subspace iteration of the local
+// eigenproblems, and the dense inverse of a packed factor.
 //
 // The O(nb^3) work runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
 // Lane layout of the instruction: A[i][k] in lane i + 16k, B[k][j] in lane
@@ -12,7 +12,8 @@
 //                                             trailing tiles on MFMA
 //   D_b = L_bb^-1 in place                    diagonal tiles by substitution in
 //                                             registers, off-diagonal tiles
-//                                             D_IJ = -D_II sum_K L_IK D_KJ on MFMA
+//                                             D_IJ = -D_II sum_K L_IK D_KJ on MFMA,
+//                                             one tile column per wave
 //   B_{b+1} = A_{b+1,b} D_b^T in place        MFMA, each wave owns its row tiles
 // Rows and columns past nb read as zero. Two nb x nb LDS buffers suffice, so
 // blocks of up to 96 fit.
@@ -41,18 +42,6 @@ __device__ inline d4 mfma_nt(const double* A, const double* Bm, int ld, int nb, 
   return acc;
 }
 
-// acc += A[ra.., k] * Bm[k, cb..] over k in [k0, k1) (Bm not transposed)
-__device__ inline d4 mfma_nn(const double* A, const double* Bm, int ld, int nb, int ra, int cb,
-                             int k0, int k1, d4 acc) {
-  const int l = threadIdx.x & 63;
-  const int li = l & 15, lk = l >> 4;
-  for (int k = k0; k < k1; k += 4) {
-    const double a = lget(A, ld, nb, ra + li, k + lk);
-    const double b = lget(Bm, ld, nb, k + lk, cb + li);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-  return acc;
-}
 
 // value of v in lane `lane` (uniform index) for every lane
 __device__ inline double bcast_lane(double v, int lane) {
@@ -202,30 +191,41 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
       }
     }
     __syncthreads();
-    // off-diagonal tiles, columns left to right and rows top-down within a
-    // column (column J still needs the L tiles right of it):
-    // D_IJ = -D_II sum_{K=J}^{I-1} L_IK D_KJ
-    if (wv == 0) {
-      for (int J = 0; J + 1 < NT; ++J)
-        for (int I = J + 1; I < NT; ++I) {
-          d4 acc = {0.0, 0.0, 0.0, 0.0};
-          acc = mfma_nn(X, X, ld, nb, 16 * I, 16 * J, 16 * J, 16 * I, acc);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) tw[(4 * v + lq) * 16 + li] = acc[v];
-          wave_sync();
-          d4 acc2 = {0.0, 0.0, 0.0, 0.0};
-          for (int k = 0; k < 16; k += 4) {
-            const double a = lget(X, ld, nb, 16 * I + li, 16 * I + k + lq);
-            const double bb = tw[(k + lq) * 16 + li];
-            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc2, 0, 0, 0);
-          }
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
-            if (r < nb && c < nb) X[r * ld + c] = -acc2[v];
-          }
-          wave_sync();
+    // off-diagonal tiles, rows top-down within a column:
+    // D_IJ = -D_II sum_{K=J}^{I-1} L_IK D_KJ. The columns are independent, so
+    // wave w sweeps J = w, w + 4, ...; the new tiles go to Y (free until the
+    // next coupling block is loaded), which leaves in X the L tiles that the
+    // other columns still read, and are copied back once all columns are done.
+    for (int J = wv; J + 1 < NT; J += 4)
+      for (int I = J + 1; I < NT; ++I) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 16 * J; k < 16 * I; k += 4) {
+          const int kr = k + lq;   // row of D_KJ: the diagonal tile lives in X, the others in Y
+          const double a = lget(X, ld, nb, 16 * I + li, kr);
+          const double bb = kr < 16 * J + 16 ? lget(X, ld, nb, kr, 16 * J + li)
+                                             : lget(Y, ld, nb, kr, 16 * J + li);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
         }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tw[(4 * v + lq) * 16 + li] = acc[v];
+        wave_sync();
+        d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < 16; k += 4) {
+          const double a = lget(X, ld, nb, 16 * I + li, 16 * I + k + lq);
+          const double bb = tw[(k + lq) * 16 + li];
+          acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc2, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
+          if (r < nb && c < nb) Y[r * ld + c] = -acc2[v];
+        }
+        wave_sync();
+      }
+    __syncthreads();
+    for (int e = t; e < nb * nb; e += kThreads) {
+      const int r = e / nb, c = e - (e / nb) * nb;
+      if ((r >> 4) > (c >> 4)) X[r * ld + c] = Y[r * ld + c];
     }
     __syncthreads();
     const bool last = b + 1 == nblk;

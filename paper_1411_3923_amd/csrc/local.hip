@@ -65,48 +65,90 @@ struct Vec16<float> {
   typedef float type __attribute__((ext_vector_type(4)));
 };
 
-// LDS elements (of T) of k_local_solves; nloc bytes of support flags follow
-size_t local_solve_lds_elems(const Geometry& g) {
+// LDS of one chain in elements of T: tile partials [nt][np], three vectors of
+// np, the element-layer moduli [nblk - 1][sw]; nloc bytes of support flags
+// per chain follow all chains, K0 precedes them.
+__host__ __device__ inline size_t chain_lds_elems(const Geometry& g) {
   const TileShape ts = tile_shape(g.nb);
   const int np = 4 * ts.nt;
   const int sw = g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1;
-  return (size_t)ts.nt * np + 3 * (size_t)np + (size_t)g.ndpe * g.ndpe +
-         (size_t)(g.nblk - 1) * sw;
+  return (size_t)ts.nt * np + 3 * (size_t)np + (size_t)(g.nblk - 1) * sw;
 }
 
-// Thread tau < nl holds tile tau (and tau + 256 when TPT = 2) of the current
-// record; thread o < nb owns DOF o of the current node layer. The block steps
-// run 0, 1, ..., nblk - 1 (forward, the last one also giving x_{nblk-1}) and
-// then nblk - 2, ..., 0 (backward). zloc receives the forward intermediate y
-// and then the solution, in box order.
-template <typename T, int TPT>
+size_t local_solve_lds_bytes(const Geometry& g, int ch, size_t elem) {
+  return elem * ((size_t)g.ndpe * g.ndpe + ch * chain_lds_elems(g)) +
+         ch * (((size_t)g.nloc + 15) & ~(size_t)15);
+}
+
+// CH independent chains (system, subdomain) per workgroup, advanced in
+// lockstep so that they share the barriers and keep CH records in flight.
+// Thread tau < nl holds tile tau (and tau + 256 when TPT = 2) of each chain's
+// current record; thread o < nb owns DOF o of each chain's current node
+// layer. The block steps run 0, 1, ..., nblk - 1 (forward, the last one also
+// giving x_{nblk-1}) and then nblk - 2, ..., 0 (backward). zloc receives the
+// forward intermediate y and then the solution, in box order.
+template <typename T, int TPT, int CH>
 __global__ __launch_bounds__(kThreads) void k_local_solves(
     Geometry g, const double* __restrict__ r, const T* __restrict__ lfac,
     const T* __restrict__ emod, const uint8_t* __restrict__ fixed, const double* __restrict__ K0,
-    T* __restrict__ zloc, Gate gate) {
+    T* __restrict__ zloc, int nchains, Gate gate) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int sys = blockIdx.x / g.nsub;
-  const int j = blockIdx.x - sys * g.nsub;
-  if (!gate_running(gate, sys)) return;
-  int jx, jy, jz;
-  sub_coords(g, j, jx, jy, jz);
   const int d = g.dim, nb = g.nb, nblk = g.nblk, bn = g.bn, nd = g.ndpe;
   const TileShape ts = tile_shape(nb);
-  const int nt = ts.nt, np = 4 * nt, nl = ts.nl;
+  const int nt = ts.nt, np = 4 * ts.nt, nl = ts.nl;
   const int sw = d == 3 ? (bn + 1) * (bn + 1) : bn + 1;
-  T* red = reinterpret_cast<T*>(smem);          // [nt][np] tile partials
-  T* va = red + (size_t)nt * np;                // t_b (forward) / w_b (backward)
-  T* vb = va + np;                              // y_b (forward) / v_b (backward)
-  T* vc = vb + np;                              // masked s_b (forward) / masked x_{b+1} (backward)
-  T* K0s = vc + np;
-  T* strip = K0s + nd * nd;                     // [nblk - 1][sw] element-layer moduli
-  uint8_t* fx = reinterpret_cast<uint8_t*>(strip + (size_t)(nblk - 1) * sw);
   const int t = threadIdx.x;
-  const bool own = t < nb;
-  const double* rs = r + (size_t)sys * g.ndof;
-  const T* es = emod + (size_t)sys * g.nel;
-  T* zs = zloc + ((size_t)sys * g.nsub + j) * g.nloc;
-  const T* F = lfac + ((size_t)sys * g.nsub + j) * nblk * ts.tstride;
+  // DOF o of chain c's node layer belongs to thread c * (kThreads / CH) + o,
+  // so the chains' row phases run on different waves
+  int o[CH];
+  bool ow[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    o[c] = t - c * (kThreads / CH);
+    ow[c] = o[c] >= 0 && o[c] < nb;
+  }
+
+  // chains of this workgroup; a chain whose system has stopped only follows
+  // the barriers
+  bool run[CH];
+  int jx[CH], jy[CH], jz[CH];
+  const double* rs[CH];
+  const T* es[CH];
+  const T* F[CH];
+  T* zs[CH];
+  bool any = false;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int id = blockIdx.x * CH + c;
+    const int sys = id / g.nsub, j = id - (id / g.nsub) * g.nsub;
+    run[c] = id < nchains && gate_running(gate, sys);
+    any |= run[c];
+    sub_coords(g, j, jx[c], jy[c], jz[c]);
+    rs[c] = r + (size_t)sys * g.ndof;
+    es[c] = emod + (size_t)sys * g.nel;
+    zs[c] = zloc + (size_t)id * g.nloc;
+    F[c] = lfac + (size_t)id * nblk * ts.tstride;
+  }
+  if (!any) return;
+
+  const size_t cl = chain_lds_elems(g);
+  T* K0s = reinterpret_cast<T*>(smem);
+  T* red[CH];   // [nt][np] tile partials
+  T* va[CH];   // t_b (forward) / w_b (backward)
+  T* vb[CH];   // y_b (forward) / v_b (backward)
+  T* vc[CH];   // masked s_b (forward) / masked x_{b+1} (backward)
+  T* strip[CH];
+  uint8_t* fx[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    red[c] = K0s + nd * nd + c * cl;
+    va[c] = red[c] + (size_t)nt * np;
+    vb[c] = va[c] + np;
+    vc[c] = vb[c] + np;
+    strip[c] = vc[c] + np;
+    fx[c] = reinterpret_cast<uint8_t*>(K0s + nd * nd + CH * cl) +
+            c * (((size_t)g.nloc + 15) & ~(size_t)15);
+  }
 
   typedef typename Vec16<T>::type V;
   typedef T Tiles[TPT][16];
@@ -120,8 +162,9 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
     tJ[u] = 0;
     if (tau[u] < nl) tile_rc(tau[u], tI[u], tJ[u]);
   }
-  auto load_tiles = [&](Tiles& tl, int b) {
-    const V* src = reinterpret_cast<const V*>(F + (size_t)b * ts.tstride);
+  Tiles tl[CH];
+  auto load_tiles = [&](int c, int b) {
+    const V* src = reinterpret_cast<const V*>(F[c] + (size_t)b * ts.tstride);
 #pragma unroll
     for (int u = 0; u < TPT; ++u)
       if (tau[u] < nl) {
@@ -129,130 +172,150 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
         for (int v = 0; v < nvl; ++v) {
           const V q = src[(size_t)v * nl + tau[u]];
 #pragma unroll
-          for (int w = 0; w < per; ++w) tl[u][v * per + w] = q[w];
+          for (int w = 0; w < per; ++w) tl[c][u][v * per + w] = q[w];
         }
       }
   };
   // red[J][4I + i] = (D_IJ x_J)[i]
-  auto prod_n = [&](const Tiles& tl, const T* x) {
+  auto prod_n = [&](int c, const T* x) {
 #pragma unroll
     for (int u = 0; u < TPT; ++u)
       if (tau[u] < nl) {
         const T* xv = x + 4 * tJ[u];
         const T x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
-        T* o = red + (size_t)tJ[u] * np + 4 * tI[u];
+        T* o = red[c] + (size_t)tJ[u] * np + 4 * tI[u];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          o[i] = tl[u][4 * i] * x0 + tl[u][4 * i + 1] * x1 + tl[u][4 * i + 2] * x2 +
-                 tl[u][4 * i + 3] * x3;
+          o[i] = tl[c][u][4 * i] * x0 + tl[c][u][4 * i + 1] * x1 + tl[c][u][4 * i + 2] * x2 +
+                 tl[c][u][4 * i + 3] * x3;
       }
   };
-  // red[I][4J + c] = (D_IJ^T x_I)[c]
-  auto prod_t = [&](const Tiles& tl, const T* x) {
+  // red[I][4J + k] = (D_IJ^T x_I)[k]
+  auto prod_t = [&](int c, const T* x) {
 #pragma unroll
     for (int u = 0; u < TPT; ++u)
       if (tau[u] < nl) {
         const T* xv = x + 4 * tI[u];
         const T x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
-        T* o = red + (size_t)tI[u] * np + 4 * tJ[u];
+        T* o = red[c] + (size_t)tI[u] * np + 4 * tJ[u];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-          o[c] = tl[u][c] * x0 + tl[u][4 + c] * x1 + tl[u][8 + c] * x2 + tl[u][12 + c] * x3;
+        for (int k = 0; k < 4; ++k)
+          o[k] = tl[c][u][k] * x0 + tl[c][u][4 + k] * x1 + tl[c][u][8 + k] * x2 +
+                 tl[c][u][12 + k] * x3;
       }
   };
-  auto sum_n = [&](int o) {
+  auto sum_n = [&](int c, int o) {
     T s = 0;
-    for (int J = 0; J <= o / 4; ++J) s += red[(size_t)J * np + o];
+    for (int J = 0; J <= o / 4; ++J) s += red[c][(size_t)J * np + o];
     return s;
   };
-  auto sum_t = [&](int o) {
+  auto sum_t = [&](int c, int o) {
     T s = 0;
-    for (int I = o / 4; I < nt; ++I) s += red[(size_t)I * np + o];
+    for (int I = o / 4; I < nt; ++I) s += red[c][(size_t)I * np + o];
     return s;
   };
-  auto rhs = [&](int b) { return (T)rs[box_dof(g, jx, jy, jz, b * nb + t)]; };
+  auto rhs = [&](int c, int b) {
+    return (T)rs[c][box_dof(g, jx[c], jy[c], jz[c], b * nb + o[c])];
+  };
 
+  // set-up: first records, K0, layer moduli, support flags, zeroed padding
+  T rn[CH], yb[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    rn[c] = 0;
+    yb[c] = 0;
+    if (run[c]) {
+      if (ow[c]) rn[c] = rhs(c, 0);
+      load_tiles(c, 0);
+    }
+  }
+  for (int i = t; i < nd * nd; i += kThreads) K0s[i] = (T)K0[i];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    if (!run[c]) continue;
+    for (int i = t; i < (nblk - 1) * sw; i += kThreads) {
+      const int b = i / sw, q = i - (i / sw) * sw;
+      const int qx = q % (bn + 1), qy = q / (bn + 1);
+      const int ex = g.s * jx[c] - 1 + qx;
+      const int ey = d == 3 ? g.s * jy[c] - 1 + qy : g.s * jy[c] + b;
+      const int ez = d == 3 ? g.s * jz[c] + b : 0;
+      const bool in = ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely;
+      strip[c][i] = in ? es[c][ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)] : (T)0;
+    }
+    for (int l = t; l < g.nloc; l += kThreads) fx[c][l] = fixed[box_dof(g, jx[c], jy[c], jz[c], l)];
+    for (int i = t; i < 3 * np; i += kThreads) va[c][i] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    if (!run[c] || !ow[c]) continue;
+    va[c][o[c]] = rn[c];                            // t_0 = r_0
+    if (nblk > 1) rn[c] = rhs(c, 1);
+  }
+  __syncthreads();
+
+  // Block steps k = 0 .. nsteps - 1: forward block b = k, then backward
+  // block b = 2 nblk - 2 - k. Entering a step, va holds t_b (forward) or
+  // w_b = A_{b+1,b}^T x_{b+1} (backward) and tl holds D_b.
   const int nsteps = 2 * nblk - 1;
-  T rn = 0, yb = 0;
-  Tiles tl;
-  auto step = [&](int k) {
-    if (k < nblk) {
-      // forward: y_b = D_b t_b, s_b = D_b^T y_b, t_{b+1} = r_{b+1} - A_{b+1,b} s_b
-      const int b = k;
-      prod_n(tl, va);
-      __syncthreads();
-      if (own) {
-        const T y = sum_n(t);
-        vb[t] = y;
-        zs[b * nb + t] = y;
+  for (int k = 0; k < nsteps; ++k) {
+    const bool fwd = k < nblk;
+    const int b = fwd ? k : 2 * nblk - 2 - k;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (run[c]) prod_n(c, va[c]);              // D_b t_b  or  D_b w_b
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (!run[c] || !ow[c]) continue;
+      const T sn = sum_n(c, o[c]);
+      if (fwd) {
+        vb[c][o[c]] = sn;                           // y_b
+        zs[c][b * nb + o[c]] = sn;
+      } else {
+        vb[c][o[c]] = yb[c] - sn;                   // v_b = y_b - D_b w_b
       }
-      __syncthreads();
-      prod_t(tl, vb);                            // for the last block this is x_{nblk-1}
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (!run[c]) continue;
+      prod_t(c, vb[c]);                          // s_b = D_b^T y_b  or  x_b = D_b^T v_b
       // the record has been used twice: request the next one
-      if (k + 1 < nsteps) load_tiles(tl, k + 1 < nblk ? k + 1 : 2 * nblk - 3 - k);
-      __syncthreads();
-      if (own) {
-        const T s = sum_t(t);
-        vc[t] = fx[b * nb + t] ? (T)0 : s;
-        if (b + 1 == nblk) zs[b * nb + t] = s;
-      }
-      __syncthreads();
-      if (b + 1 < nblk) {
-        if (own) {
-          const bool f = fx[(b + 1) * nb + t];
-          va[t] = f ? rn : rn - layer_coupling(d, bn, K0s, strip + (size_t)b * sw, vc, t, true);
-          if (b + 2 < nblk) rn = rhs(b + 2);
+      if (k + 1 < nsteps) load_tiles(c, k + 1 < nblk ? k + 1 : 2 * nblk - 3 - k);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (!run[c] || !ow[c]) continue;
+      const T st = sum_t(c, o[c]);
+      vc[c][o[c]] = fx[c][b * nb + o[c]] ? (T)0 : st;
+      if (!fwd || b + 1 == nblk) zs[c][b * nb + o[c]] = st;   // x_b (x_{nblk-1} = s_{nblk-1})
+    }
+    __syncthreads();
+    if (k + 1 < nsteps) {
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        if (!run[c] || !ow[c]) continue;
+        if (k + 1 < nblk) {
+          // t_{b+1} = r_{b+1} - A_{b+1,b} s_b
+          const bool f = fx[c][(b + 1) * nb + o[c]];
+          va[c][o[c]] = f ? rn[c]
+                       : rn[c] - layer_coupling(d, bn, K0s, strip[c] + (size_t)b * sw, vc[c],
+                                                o[c], true);
+          if (b + 2 < nblk) rn[c] = rhs(c, b + 2);
+        } else {
+          // w_e = A_{e+1,e}^T x_{e+1} for the next backward block e
+          const int e = 2 * nblk - 3 - k;
+          va[c][o[c]] = fx[c][e * nb + o[c]]
+                         ? (T)0
+                         : layer_coupling(d, bn, K0s, strip[c] + (size_t)e * sw, vc[c], o[c], false);
+          yb[c] = zs[c][e * nb + o[c]];             // y_e from the forward pass
         }
-        __syncthreads();
-      } else if (own && nblk > 1) {
-        yb = zs[(nblk - 2) * nb + t];
-      }
-    } else {
-      // backward: w_b = A_{b+1,b}^T x_{b+1}, v_b = y_b - D_b w_b, x_b = D_b^T v_b
-      const int b = 2 * nblk - 2 - k;
-      if (own)
-        va[t] = fx[b * nb + t] ? (T)0
-                               : layer_coupling(d, bn, K0s, strip + (size_t)b * sw, vc, t, false);
-      __syncthreads();
-      prod_n(tl, va);
-      __syncthreads();
-      if (own) {
-        vb[t] = yb - sum_n(t);
-        if (b >= 1) yb = zs[(b - 1) * nb + t];
-      }
-      __syncthreads();
-      prod_t(tl, vb);
-      if (k + 1 < nsteps) load_tiles(tl, 2 * nblk - 3 - k);
-      __syncthreads();
-      if (own) {
-        const T x = sum_t(t);
-        zs[b * nb + t] = x;
-        vc[t] = fx[b * nb + t] ? (T)0 : x;
       }
       __syncthreads();
     }
-  };
-
-  // set-up: first record, K0, layer moduli, support flags, zeroed padding
-  if (own) rn = rhs(0);
-  load_tiles(tl, 0);
-  for (int i = t; i < nd * nd; i += kThreads) K0s[i] = (T)K0[i];
-  for (int i = t; i < (nblk - 1) * sw; i += kThreads) {
-    const int b = i / sw, q = i - (i / sw) * sw;
-    const int qx = q % (bn + 1), qy = q / (bn + 1);
-    const int ex = g.s * jx - 1 + qx;
-    const int ey = d == 3 ? g.s * jy - 1 + qy : g.s * jy + b;
-    const int ez = d == 3 ? g.s * jz + b : 0;
-    const bool in = ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely;
-    strip[i] = in ? es[ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)] : (T)0;
   }
-  for (int l = t; l < g.nloc; l += kThreads) fx[l] = fixed[box_dof(g, jx, jy, jz, l)];
-  for (int i = t; i < 3 * np; i += kThreads) va[i] = 0;
-  __syncthreads();
-  if (own) va[t] = rn;                           // t_0 = r_0
-  if (own && nblk > 1) rn = rhs(1);
-  __syncthreads();
-  for (int k = 0; k < nsteps; ++k) step(k);
 }
 
 template <typename K>
@@ -264,25 +327,23 @@ void allow_lds(K kernel, bool& done) {
   done = true;
 }
 
+template <typename T, int TPT, int CH>
+void local_launch_as(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
+  const Geometry& g = h.g;
+  const int nchains = nsys * g.nsub;
+  static bool done = false;
+  allow_lds(&k_local_solves<T, TPT, CH>, done);
+  hipLaunchKernelGGL((k_local_solves<T, TPT, CH>), dim3((nchains + CH - 1) / CH), dim3(kThreads),
+                     local_solve_lds_bytes(g, CH, sizeof(T)), st, g, r,
+                     reinterpret_cast<const T*>(h.lfac), reinterpret_cast<const T*>(h.emod),
+                     h.fixed, h.K0, reinterpret_cast<T*>(h.zloc), nchains, gate);
+}
+
 template <typename T>
 void local_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
-  const Geometry& g = h.g;
-  const size_t lds = sizeof(T) * local_solve_lds_elems(g) + (size_t)g.nloc;
-  const T* fac = reinterpret_cast<const T*>(h.lfac);
-  const T* em = reinterpret_cast<const T*>(h.emod);
-  T* zl = reinterpret_cast<T*>(h.zloc);
-  const dim3 grid(nsys * g.nsub);
-  if (tile_shape(g.nb).nl <= kThreads) {
-    static bool done = false;
-    allow_lds(&k_local_solves<T, 1>, done);
-    hipLaunchKernelGGL((k_local_solves<T, 1>), grid, dim3(kThreads), lds, st, g, r, fac, em,
-                       h.fixed, h.K0, zl, gate);
-  } else {
-    static bool done = false;
-    allow_lds(&k_local_solves<T, 2>, done);
-    hipLaunchKernelGGL((k_local_solves<T, 2>), grid, dim3(kThreads), lds, st, g, r, fac, em,
-                       h.fixed, h.K0, zl, gate);
-  }
+  // two chains per workgroup where one tile per thread suffices
+  if (tile_shape(h.g.nb).nl <= kThreads) local_launch_as<T, 1, 2>(h, r, nsys, gate, st);
+  else local_launch_as<T, 2, 1>(h, r, nsys, gate, st);
 }
 
 }  // namespace

@@ -616,20 +616,27 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const int iters = pr.eig_iters > 0 ? pr.eig_iters : 16;
   MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
 
+  // work arrays of the build, kept by the handle from one build to the next:
+  // the assembled blocks, then either the eigensolver's arrays (Neumann
+  // factor, scaling, two subspace blocks) or the coarse assembly's
+  const size_t nsl = (size_t)g.nsub * g.nloc;
+  const size_t wsz = (size_t)g.nsub * g.nebox * g.dim * g.k;
+  const size_t need =
+      asm_local + std::max(rec + nsl * (1 + 2 * (size_t)m), wsz + asm_coarse * pr.nsys_max);
+  if (h.build_elems < need) {
+    if (h.build_ws) hipFree(h.build_ws);
+    h.build_ws = dalloc<double>(need, err);
+    h.build_elems = h.build_ws ? need : 0;
+    if (err) { h.err = "out of device memory for the preconditioner build"; return err; }
+  }
   hipMemsetAsync(h.dflag, 0, 4 * sizeof(int), st);
-  double* A = dalloc<double>(asm_local, err);
-  if (err) { h.err = "out of device memory for the local matrices"; return err; }
+  double* A = h.build_ws;
 
   // --- 1-3: spectral basis from system `rep` ---
-  double* nfac = dalloc<double>(rec, err);
-  double* dis = dalloc<double>((size_t)g.nsub * g.nloc, err);
-  double* X = dalloc<double>((size_t)g.nsub * g.nloc * m, err);
-  double* Y = dalloc<double>((size_t)g.nsub * g.nloc * m, err);
-  if (err) {
-    hipFree(A); hipFree(nfac); hipFree(dis); hipFree(X); hipFree(Y);
-    h.err = "out of device memory for the eigensolver";
-    return err;
-  }
+  double* nfac = A + asm_local;
+  double* dis = nfac + rec;
+  double* X = dis + nsl;
+  double* Y = X + nsl * m;
   const double* rrep = rho + (size_t)rep * g.nel;
   hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g, rrep,
                      h.fixed, h.K0, A, dis, mp, 1);
@@ -651,17 +658,10 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   else
     hipLaunchKernelGGL(k_phi_modes<double>, dim3(1024), dim3(kThreads), 0, st, g, h.phi,
                        reinterpret_cast<double*>(h.phim));
-  hipStreamSynchronize(st);
-  hipFree(nfac); hipFree(X); hipFree(Y); hipFree(dis);
 
   // --- 4: coarse matrices and factors, per system ---
-  double* W = dalloc<double>((size_t)g.nsub * g.nebox * g.dim * g.k, err);
-  double* Ac = dalloc<double>(asm_coarse * nsys, err);
-  if (err) {
-    hipFree(A); hipFree(W); hipFree(Ac);
-    h.err = "out of device memory for the coarse operator";
-    return err;
-  }
+  double* W = A + asm_local;
+  double* Ac = W + wsz;
   hipMemsetAsync(Ac, 0, sizeof(double) * asm_coarse * nsys, st);
   const int nnb = g.dim == 3 ? 27 : 9;
   for (int sys = 0; sys < nsys; ++sys) {
@@ -673,9 +673,6 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   }
   launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
   if (h.cinv) launch_inverse(h.cfac, csh, nsys, h.cinv, st);
-  hipStreamSynchronize(st);
-  hipFree(W);
-  hipFree(Ac);
 
   // --- 5: local Dirichlet factors, one system at a time, as tiled D_b records
   //        (FP32 in mixed mode), and the moduli their layer couplings use ---
@@ -698,7 +695,6 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, st, rho,
                        reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
   hipStreamSynchronize(st);
-  hipFree(A);
 
   int flag[4] = {0, 0, 0, 0};
   hipMemcpy(flag, h.dflag, sizeof(flag), hipMemcpyDeviceToHost);

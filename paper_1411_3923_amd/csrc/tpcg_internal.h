@@ -97,6 +97,8 @@ struct Handle {
   void* emod = nullptr;              // moduli the local factors were built from [nsys][nel], same type
   double* cfac = nullptr;            // packed [nsys][nblkc][bstridec]
   double* cinv = nullptr;            // dense K_c^-1 [nsys][nt][nt] when nt <= kDenseCoarse
+  double* build_ws = nullptr;        // work arrays of the preconditioner build
+  size_t build_elems = 0;
   hipStream_t side = nullptr;        // second stream for the coarse solve (forked per apply)
   hipEvent_t fork = nullptr, join = nullptr;
 
