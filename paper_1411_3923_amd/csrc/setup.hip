@@ -3,13 +3,15 @@
 //      supports kept) of the representative system, scaled to
 //      S_j = D^-1/2 K_j^N D^-1/2 with D = diag(K_j^N), and factored shifted.
 //   2. The k smallest eigenpairs of S_j by shift-invert block subspace
-//      iteration (classical Gram-Schmidt twice) and a final Rayleigh-Ritz
-//      step; psi = D^-1/2 x solves K_j^N psi = lambda D psi.
+//      iteration (Cholesky QR applied twice) and a final Rayleigh-Ritz step;
+//      psi = D^-1/2 x solves K_j^N psi = lambda D psi.
 //   3. Phi_j = chi_j psi_j with chi_j(n) = 1 / (subdomains containing n).
 //   4. Per system: W_j = K Phi_j on the cell grown by one node layer, the
-//      Galerkin blocks Phi_l^T W_j of K_c = Phi^T K Phi, and the coarse factor.
+//      Galerkin blocks Phi_l^T W_j of K_c = Phi^T K Phi, the coarse factor and,
+//      for moderate coarse dimensions, the dense K_c^-1.
 //   5. Per system: local Dirichlet matrices A_j (principal submatrices of
-//      the supported K on the closed-cell DOFs) and their factors.
+//      the supported K on the closed-cell DOFs) and their factors, on the
+//      second stream, concurrently with 1-4.
 // All factors are block-tridiagonal Cholesky factors (see btri.h).
 #include <algorithm>
 #include <vector>
@@ -613,16 +615,18 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;
   const int m = h.msub;
-  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 16;
+  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 10;
   MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
 
   // work arrays of the build, kept by the handle from one build to the next:
-  // the assembled blocks, then either the eigensolver's arrays (Neumann
-  // factor, scaling, two subspace blocks) or the coarse assembly's
+  // the Neumann blocks, then either the eigensolver's arrays (Neumann factor,
+  // scaling, two subspace blocks) or the coarse assembly's; apart, the
+  // Dirichlet blocks of the local factors, which are built on the second
+  // stream while the eigensolver and the coarse operator run on the first
   const size_t nsl = (size_t)g.nsub * g.nloc;
   const size_t wsz = (size_t)g.nsub * g.nebox * g.dim * g.k;
-  const size_t need =
-      asm_local + std::max(rec + nsl * (1 + 2 * (size_t)m), wsz + asm_coarse * pr.nsys_max);
+  const size_t need = 2 * asm_local + std::max(rec + nsl * (1 + 2 * (size_t)m),
+                                               wsz + asm_coarse * pr.nsys_max);
   if (h.build_elems < need) {
     if (h.build_ws) hipFree(h.build_ws);
     h.build_ws = dalloc<double>(need, err);
@@ -631,6 +635,35 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   }
   hipMemsetAsync(h.dflag, 0, 4 * sizeof(int), st);
   double* A = h.build_ws;
+  double* Aloc = h.build_ws + need - asm_local;
+  hipEventRecord(h.fork, st);
+  hipStreamWaitEvent(h.side, h.fork, 0);
+
+  // --- 5 (second stream): local Dirichlet factors, one system at a time, as
+  //     tiled D_b records (FP32 in mixed mode), and the moduli their layer
+  //     couplings use ---
+  {
+    hipStream_t s2 = h.side;
+    const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;
+    const int64_t nm = (int64_t)nsys * g.nel;
+    for (int sys = 0; sys < nsys; ++sys) {
+      hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, s2, g,
+                         rho + (size_t)sys * g.nel, h.fixed, h.K0, Aloc, nullptr, mp, 0);
+      if (h.mixed)
+        launch_factor<float>(Aloc, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh,
+                             h.dflag, s2, true);
+      else
+        launch_factor<double>(Aloc, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub, lsh,
+                              h.dflag, s2, true);
+    }
+    if (h.mixed)
+      hipLaunchKernelGGL(k_moduli<float>, dim3(1024), dim3(kThreads), 0, s2, rho,
+                         reinterpret_cast<float*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
+    else
+      hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho,
+                         reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
+    hipEventRecord(h.join, s2);
+  }
 
   // --- 1-3: spectral basis from system `rep` ---
   double* nfac = A + asm_local;
@@ -674,26 +707,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
   if (h.cinv) launch_inverse(h.cfac, csh, nsys, h.cinv, st);
 
-  // --- 5: local Dirichlet factors, one system at a time, as tiled D_b records
-  //        (FP32 in mixed mode), and the moduli their layer couplings use ---
-  const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;
-  const int64_t nm = (int64_t)nsys * g.nel;
-  for (int sys = 0; sys < nsys; ++sys) {
-    hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g,
-                       rho + (size_t)sys * g.nel, h.fixed, h.K0, A, nullptr, mp, 0);
-    if (h.mixed)
-      launch_factor<float>(A, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh, h.dflag,
-                           st, true);
-    else
-      launch_factor<double>(A, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub, lsh,
-                            h.dflag, st, true);
-  }
-  if (h.mixed)
-    hipLaunchKernelGGL(k_moduli<float>, dim3(1024), dim3(kThreads), 0, st, rho,
-                       reinterpret_cast<float*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
-  else
-    hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, st, rho,
-                       reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
+  hipStreamWaitEvent(st, h.join, 0);
   hipStreamSynchronize(st);
 
   int flag[4] = {0, 0, 0, 0};
