@@ -111,12 +111,29 @@ __host__ __device__ inline size_t tile_offset(int nl, int tau, int e) {
   return ((size_t)(e / per) * nl + tau) * per + e % per;
 }
 
+// Input of a factorisation that computes the subdomain matrices itself from
+// the element moduli (rho != nullptr): matrix j of the batch is the Dirichlet
+// matrix of subdomain j (principal submatrix of the supported stiffness
+// matrix on its closed-cell DOFs), or with neumann != 0 the cell-only
+// stiffness matrix S = D^-1/2 K^N D^-1/2 + shift I (D = diag K^N, supported
+// DOFs decoupled with diagonal fixed_diag + shift), D^-1/2 stored to dis.
+struct StencilIn {
+  Geometry g;
+  const double* rho;
+  const uint8_t* fixed;
+  const double* K0;
+  double E0, Emin, penal, shift, fixed_diag;
+  int neumann;
+  double* dis;
+};
+
 // factor.hip
 // Packed records (tiles == false) or tiled records of D_b only (tiles == true,
-// record stride tile_shape(nb).tstride).
+// record stride tile_shape(nb).tstride); the blocks come from A, or from the
+// stencil input when si.rho is set (A is then not read).
 template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
-                   hipStream_t st, bool tiles = false);
+                   hipStream_t st, bool tiles = false, const StencilIn* si = nullptr);
 void launch_solve_multi(const double* fac, const BtriShape& sh, int nmat, int m, const double* X,
                         double* Y, hipStream_t st);
 // dense symmetric inverse [nmat][n][n] of packed factors (n = nb * nblk)

@@ -111,7 +111,6 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;          // packed Neumann factors
   const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;   // tiled local factors
   const size_t crec = (size_t)g.nblkc * g.bstridec;                // packed coarse factor
-  const size_t asm_local = (size_t)g.nsub * g.nblk * 2 * g.nb * g.nb;
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   const size_t ts = mixed ? 4 : 8;
   size_t p = 0;
@@ -125,11 +124,12 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
   p += sizeof(double) * kNumPartSlots * kMaxSys * kMaxParts + 4096;
-  // transients of the build: one system's assembled blocks at a time, the
-  // Neumann factor and the subspace, the coarse work arrays
-  size_t eig = sizeof(double) * (asm_local + rec + (size_t)g.nsub * g.nloc * (1 + 2 * msub));
-  size_t coarse = sizeof(double) * ((size_t)g.nsub * g.nebox * g.dim * g.k + nsys * asm_coarse);
-  return {p, std::max(eig, std::max(coarse, sizeof(double) * asm_local))};
+  // work arrays of the build (kept by the handle): the Neumann factor and the
+  // subspace, or the coarse assembly's arrays
+  size_t eig = sizeof(double) * (rec + (size_t)g.nsub * g.nloc * (1 + 2 * msub));
+  size_t coarse =
+      sizeof(double) * ((size_t)g.nsub * g.nebox * g.dim * g.k + pr.nsys_max * asm_coarse);
+  return {p, std::max(eig, coarse)};
 }
 
 template <typename T>

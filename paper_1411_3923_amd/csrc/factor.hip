@@ -59,14 +59,90 @@ __device__ inline void wave_sync() {
 
 constexpr int kMaxTiles = (kMaxNb + 15) / 16;
 
+// LDS (doubles) of the stencil input: two element layers of moduli, K0 and
+// the Neumann diagonals of two node layers
+__host__ __device__ inline int layer_width(const Geometry& g) {
+  return g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1;
+}
+__host__ __device__ inline size_t stencil_lds_elems(const Geometry& g) {
+  return 2 * (size_t)layer_width(g) + (size_t)g.ndpe * g.ndpe + 2 * (size_t)g.nb;
+}
+
+// Box-local coordinates of local DOF l: x, y (3D), layer (the block axis), component.
+struct BoxNode {
+  int x, y, lay, c;
+};
+__device__ inline BoxNode box_node(const Geometry& g, int l) {
+  const int ln = l / g.dim;
+  BoxNode n;
+  n.c = l - ln * g.dim;
+  n.x = ln % g.bn;
+  if (g.dim == 3) {
+    n.y = (ln / g.bn) % g.bn;
+    n.lay = ln / (g.bn * g.bn);
+  } else {
+    n.y = 0;
+    n.lay = ln / g.bn;
+  }
+  return n;
+}
+
+// Moduli of element layers L0 and L0 + 1 (layer L lies between node layers L
+// and L + 1; -1 and nblk - 1 are outside the box) into Es, zero outside the
+// mesh and, for the Neumann matrices, outside the cell.
+__device__ void stage_layers(const StencilIn& si, int jx, int jy, int jz, int L0, double* Es) {
+  const Geometry& g = si.g;
+  const int d = g.dim, ew = layer_width(g), s = g.s;
+  for (int i = threadIdx.x; i < 2 * ew; i += kThreads) {
+    const int L = L0 + i / ew, q = i - (i / ew) * ew;
+    const int qx = q % (g.bn + 1), qy = q / (g.bn + 1);
+    const int ex = s * jx - 1 + qx;
+    const int ey = d == 3 ? s * jy - 1 + qy : s * jy + L;
+    const int ez = d == 3 ? s * jz + L : 0;
+    bool in = ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely && ez >= 0 && ez < g.nelz;
+    if (si.neumann)
+      in = in && ex >= s * jx && ex < s * jx + s && ey >= s * jy && ey < s * jy + s &&
+           (d == 2 || (ez >= s * jz && ez < s * jz + s));
+    Es[i] = in ? simp_modulus(si.rho[ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)], si.E0,
+                              si.Emin, si.penal)
+               : 0.0;
+  }
+}
+
+// Stiffness entry K(lr, lc) over the staged element layers (the node layers
+// of lr and lc differ by at most one and are covered by L0, L0 + 1).
+__device__ double stencil_entry(const Geometry& g, int lr, int lc, int L0, const double* Es,
+                                const double* K0s) {
+  const BoxNode a = box_node(g, lr), b = box_node(g, lc);
+  if (abs(a.x - b.x) > 1 || abs(a.y - b.y) > 1 || abs(a.lay - b.lay) > 1) return 0.0;
+  const int d = g.dim, nd = g.ndpe, ew = layer_width(g);
+  const int y0 = d == 3 ? max(a.y, b.y) - 1 : 0, y1 = d == 3 ? min(a.y, b.y) : 0;
+  double v = 0.0;
+  for (int L = max(a.lay, b.lay) - 1; L <= min(a.lay, b.lay); ++L)
+    for (int ey = y0; ey <= y1; ++ey)
+      for (int ex = max(a.x, b.x) - 1; ex <= min(a.x, b.x); ++ex) {
+        const double E = Es[(L - L0) * ew + (ex + 1) + (d == 3 ? (g.bn + 1) * (ey + 1) : 0)];
+        const int ar = d == 3 ? corner_of(a.x - ex, a.y - ey, a.lay - L)
+                              : corner_of(a.x - ex, a.lay - L, 0);
+        const int ac = d == 3 ? corner_of(b.x - ex, b.y - ey, b.lay - L)
+                              : corner_of(b.x - ex, b.lay - L, 0);
+        v += E * K0s[(d * ar + a.c) * nd + d * ac + b.c];
+      }
+  return v;
+}
+
 // One workgroup per matrix. Input: assembled blocks A[b][0] = A_bb,
-// A[b][1] = A_{b,b-1} (FP64, row-major nb x nb). Output: packed records in T.
-// flag[0] = 1 on a non-positive pivot (replaced by 1 so that the
-// factorisation completes and the caller can report it).
+// A[b][1] = A_{b,b-1} (FP64, row-major nb x nb), or, when si.rho is set, the
+// subdomain stiffness matrix of subdomain blockIdx.x computed block by block
+// from the element moduli (the Dirichlet matrix, or the scaled shifted
+// Neumann matrix with D^-1/2 written to si.dis). Output: packed or tiled
+// records in T. flag[0] = 1 on a non-positive pivot (replaced by 1 so that
+// the factorisation completes and the caller can report it).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restrict__ A,
                                                          T* __restrict__ out, BtriShape sh,
-                                                         int* __restrict__ flag, int tiles) {
+                                                         int* __restrict__ flag, int tiles,
+                                                         StencilIn si) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
   const int ld = lds_ld(nb);
@@ -83,11 +159,58 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   const int wv = t >> 6, l = t & 63;
   const int li = l & 15, lq = l >> 4;
   double* tw = tmp + wv * 256;
+  // stencil input: staged moduli, K0 and the Neumann diagonals of the last
+  // two node layers (by parity)
+  const bool sten = si.rho != nullptr;
+  double* Es = tmp + 4 * 256;
+  double* K0s = Es + 2 * (sten ? layer_width(si.g) : 0);
+  double* dl = K0s + (sten ? si.g.ndpe * si.g.ndpe : 0);
+  int jx = 0, jy = 0, jz = 0;
+  if (sten) {
+    sub_coords(si.g, blockIdx.x, jx, jy, jz);
+    for (int i = t; i < si.g.ndpe * si.g.ndpe; i += kThreads) K0s[i] = si.K0[i];
+  }
+  // Neumann diagonal of node layer L (needs the layers L - 1 and L staged
+  // at L0), D^-1/2 to si.dis
+  auto diag_layer = [&](int L, int L0) {
+    for (int i = t; i < nb; i += kThreads) {
+      const int lr = L * nb + i;
+      const bool fx = si.fixed[box_dof(si.g, jx, jy, jz, lr)];
+      const double dd = stencil_entry(si.g, lr, lr, L0, Es, K0s);
+      dl[(L & 1) * nb + i] = dd;
+      if (si.dis) si.dis[(size_t)blockIdx.x * si.g.nloc + lr] = fx ? 0.0 : 1.0 / sqrt(dd);
+    }
+  };
+  // block (Lr, Lc) of the subdomain matrix from the staged layers
+  auto fill = [&](double* dst, int Lr, int Lc, int L0) {
+    for (int r = t / 16; r < nb; r += kThreads / 16)
+      for (int c = t % 16; c < nb; c += 16) {
+        const int lr = Lr * nb + r, lc = Lc * nb + c;
+        double v;
+        if (si.fixed[box_dof(si.g, jx, jy, jz, lr)] || si.fixed[box_dof(si.g, jx, jy, jz, lc)]) {
+          v = lr == lc ? (si.neumann ? si.fixed_diag + si.shift : 1.0) : 0.0;
+        } else {
+          v = stencil_entry(si.g, lr, lc, L0, Es, K0s);
+          if (si.neumann)
+            v = v / sqrt(dl[(Lr & 1) * nb + r] * dl[(Lc & 1) * nb + c]) +
+                (lr == lc ? si.shift : 0.0);
+        }
+        dst[r * ld + c] = v;
+      }
+  };
   auto load = [&](double* dst, const double* src) {
     for (int r = t / 16; r < nb; r += kThreads / 16)
       for (int c = t % 16; c < nb; c += 16) dst[r * ld + c] = src[(size_t)r * nb + c];
   };
-  load(X, F);
+  if (sten) {
+    stage_layers(si, jx, jy, jz, -1, Es);
+    __syncthreads();
+    if (si.neumann) diag_layer(0, -1);
+    __syncthreads();
+    fill(X, 0, 0, -1);
+  } else {
+    load(X, F);
+  }
   for (int b = 0; b < nblk; ++b) {
     __syncthreads();
     if (b > 0) {
@@ -231,7 +354,16 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
     const bool last = b + 1 == nblk;
     if (!last) {
       // B_{b+1} = A_{b+1,b} D^T; wave w owns row tiles I = w, w + 4, ...
-      load(Y, F + ((size_t)(b + 1) * 2 + 1) * msz);
+      if (sten) {
+        // element layers b and b + 1 serve A_{b+1,b} now and A_{b+1,b+1} below
+        stage_layers(si, jx, jy, jz, b, Es);
+        __syncthreads();
+        if (si.neumann) diag_layer(b + 1, b);
+        __syncthreads();
+        fill(Y, b + 1, b, b);
+      } else {
+        load(Y, F + ((size_t)(b + 1) * 2 + 1) * msz);
+      }
       __syncthreads();
       for (int I = wv; I < NT; I += 4) {
         d4 acc[kMaxTiles];
@@ -267,7 +399,8 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
       }
       if (!last) {
         __syncthreads();
-        load(X, F + (size_t)(b + 1) * 2 * msz);
+        if (sten) fill(X, b + 1, b + 1, b);
+        else load(X, F + (size_t)(b + 1) * 2 * msz);
       }
       continue;
     }
@@ -285,7 +418,8 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
     for (int e = nb * nb + nb * pe + t; e < sh.bstride; e += kThreads) R[e] = (T)0;
     if (!last) {
       __syncthreads();
-      load(X, F + (size_t)(b + 1) * 2 * msz);
+      if (sten) fill(X, b + 1, b + 1, b);
+      else load(X, F + (size_t)(b + 1) * 2 * msz);
     }
   }
 }
@@ -339,18 +473,21 @@ void set_lds(K kernel) {
 
 template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
-                   hipStream_t st, bool tiles) {
+                   hipStream_t st, bool tiles, const StencilIn* si) {
   static bool attr = false;
   if (!attr) { set_lds(&k_btri_factor<T>); attr = true; }
-  const size_t lds = sizeof(double) * (2 * (size_t)sh.nb * lds_ld(sh.nb) + 4 * 256);
+  StencilIn s{};
+  if (si) s = *si;
+  const size_t lds = sizeof(double) * (2 * (size_t)sh.nb * lds_ld(sh.nb) + 4 * 256 +
+                                       (si ? stencil_lds_elems(si->g) : 0));
   hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag,
-                     tiles ? 1 : 0);
+                     tiles ? 1 : 0, s);
 }
 
 template void launch_factor<double>(const double*, double*, int, const BtriShape&, int*,
-                                    hipStream_t, bool);
+                                    hipStream_t, bool, const StencilIn*);
 template void launch_factor<float>(const double*, float*, int, const BtriShape&, int*,
-                                   hipStream_t, bool);
+                                   hipStream_t, bool, const StencilIn*);
 
 #define TPCG_MULTI_CASE(V)                                                                  \
   case V: {                                                                                 \

@@ -24,113 +24,9 @@ namespace {
 
 constexpr double kFixedDiag = 1.0e3;   // decoupled supported DOFs of S_j sit far above its spectrum
 
-struct NodeRef {
-  int gx, gy, gz, c;
-  int64_t dof;
-};
-
-__device__ inline NodeRef local_node(const Geometry& g, int jx, int jy, int jz, int l) {
-  const int d = g.dim;
-  const int ln = l / d;
-  NodeRef n;
-  n.c = l - ln * d;
-  const int lx = ln % g.bn, rest = ln / g.bn;
-  n.gx = g.s * jx + lx;
-  n.gy = g.s * jy + rest % g.bn;
-  n.gz = g.s * jz + rest / g.bn;
-  n.dof = (int64_t)d * (n.gx + (int64_t)g.nnx * (n.gy + (int64_t)g.nny * n.gz)) + n.c;
-  return n;
-}
-
-// Sum over the elements that contain both nodes of E_e K0[a_r d + c_r][a_c d + c_c].
-// cell_only restricts to the elements of subdomain (jx, jy, jz).
-__device__ double pair_stiffness(const Geometry& g, const NodeRef& a, const NodeRef& b,
-                                 const double* __restrict__ rho, const double* __restrict__ K0,
-                                 double E0, double Emin, double penal, bool cell_only, int jx,
-                                 int jy, int jz) {
-  if (abs(a.gx - b.gx) > 1 || abs(a.gy - b.gy) > 1 || abs(a.gz - b.gz) > 1) return 0.0;
-  const int d = g.dim;
-  int xl = max(a.gx, b.gx) - 1, xh = min(a.gx, b.gx);
-  int yl = max(a.gy, b.gy) - 1, yh = min(a.gy, b.gy);
-  int zl = 0, zh = 0;
-  if (d == 3) { zl = max(a.gz, b.gz) - 1; zh = min(a.gz, b.gz); }
-  xl = max(xl, 0); yl = max(yl, 0); zl = max(zl, 0);
-  xh = min(xh, g.nelx - 1); yh = min(yh, g.nely - 1);
-  if (d == 3) zh = min(zh, g.nelz - 1);
-  if (cell_only) {
-    xl = max(xl, g.s * jx); xh = min(xh, g.s * jx + g.s - 1);
-    yl = max(yl, g.s * jy); yh = min(yh, g.s * jy + g.s - 1);
-    if (d == 3) { zl = max(zl, g.s * jz); zh = min(zh, g.s * jz + g.s - 1); }
-  }
-  const int nd = g.ndpe;
-  double v = 0.0;
-  for (int ez = zl; ez <= zh; ++ez)
-    for (int ey = yl; ey <= yh; ++ey)
-      for (int ex = xl; ex <= xh; ++ex) {
-        const int64_t e = ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez);
-        const double E = simp_modulus(rho[e], E0, Emin, penal);
-        const int ar = corner_of(a.gx - ex, a.gy - ey, d == 3 ? a.gz - ez : 0);
-        const int ac = corner_of(b.gx - ex, b.gy - ey, d == 3 ? b.gz - ez : 0);
-        v += E * K0[(d * ar + a.c) * nd + d * ac + b.c];
-      }
-  return v;
-}
-
 struct MatParams {
   double E0, Emin, penal, shift;
 };
-
-// Fill block-tridiagonal storage. kind 0: Dirichlet A_j of every system in
-// grid.y; kind 1: scaled shifted Neumann S_j + shift I of one system, and
-// dis[j][l] = D_l^-1/2 (0 on supported DOFs). grid.x = nsub * nblk.
-__global__ __launch_bounds__(kThreads) void k_assemble(Geometry g, const double* __restrict__ rho,
-                                                      const uint8_t* __restrict__ fixed,
-                                                      const double* __restrict__ K0,
-                                                      double* __restrict__ out, double* __restrict__ dis,
-                                                      MatParams mp, int kind) {
-  const int j = blockIdx.x / g.nblk;
-  const int b = blockIdx.x - j * g.nblk;
-  const int sys = blockIdx.y;
-  int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
-  const double* rs = rho + (size_t)sys * g.nel;
-  const int nb = g.nb;
-  const size_t msz = (size_t)nb * nb;
-  double* blk = out + (((size_t)sys * g.nsub + j) * g.nblk + b) * 2 * msz;
-  const bool neu = kind == 1;
-  for (int e = threadIdx.x; e < 2 * nb * nb; e += kThreads) {
-    const int slot = e / (nb * nb);
-    const int rc = e - slot * nb * nb;
-    const int r = rc / nb, c = rc - (rc / nb) * nb;
-    double v = 0.0;
-    if (!(slot == 1 && b == 0)) {
-      const int lr = b * nb + r;
-      const int lc = (b - slot) * nb + c;
-      const NodeRef A = local_node(g, jx, jy, jz, lr);
-      const NodeRef B = local_node(g, jx, jy, jz, lc);
-      if (fixed[A.dof] || fixed[B.dof]) {
-        v = (lr == lc) ? (neu ? kFixedDiag + mp.shift : 1.0) : 0.0;
-      } else {
-        v = pair_stiffness(g, A, B, rs, K0, mp.E0, mp.Emin, mp.penal, neu, jx, jy, jz);
-        if (neu) {
-          const double da = pair_stiffness(g, A, A, rs, K0, mp.E0, mp.Emin, mp.penal, true, jx, jy, jz);
-          const double db = pair_stiffness(g, B, B, rs, K0, mp.E0, mp.Emin, mp.penal, true, jx, jy, jz);
-          v = v / sqrt(da * db) + (lr == lc ? mp.shift : 0.0);
-        }
-      }
-    }
-    blk[slot * msz + (size_t)r * nb + c] = v;
-  }
-  if (neu && dis) {
-    for (int i = threadIdx.x; i < nb; i += kThreads) {
-      const int l = b * nb + i;
-      const NodeRef A = local_node(g, jx, jy, jz, l);
-      double v = 0.0;
-      if (!fixed[A.dof])
-        v = 1.0 / sqrt(pair_stiffness(g, A, A, rs, K0, mp.E0, mp.Emin, mp.penal, true, jx, jy, jz));
-      dis[(size_t)j * g.nloc + l] = v;
-    }
-  }
-}
 
 // Deterministic start vectors of the subspace iteration.
 __device__ inline double hash_uniform(uint64_t a) {
@@ -611,7 +507,6 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const tpcg_problem& pr = h.prob;
   int err = TPCG_OK;
   const BtriShape lsh = local_shape(g), csh = coarse_shape(g);
-  const size_t asm_local = (size_t)g.nsub * g.nblk * 2 * g.nb * g.nb;
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;
   const int m = h.msub;
@@ -619,14 +514,12 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
 
   // work arrays of the build, kept by the handle from one build to the next:
-  // the Neumann blocks, then either the eigensolver's arrays (Neumann factor,
-  // scaling, two subspace blocks) or the coarse assembly's; apart, the
-  // Dirichlet blocks of the local factors, which are built on the second
-  // stream while the eigensolver and the coarse operator run on the first
+  // the eigensolver's (Neumann factor, scaling, two subspace blocks), then the
+  // coarse assembly's. The factorisations compute their matrices block by
+  // block from the element moduli, so no assembled matrix is stored.
   const size_t nsl = (size_t)g.nsub * g.nloc;
   const size_t wsz = (size_t)g.nsub * g.nebox * g.dim * g.k;
-  const size_t need = 2 * asm_local + std::max(rec + nsl * (1 + 2 * (size_t)m),
-                                               wsz + asm_coarse * pr.nsys_max);
+  const size_t need = std::max(rec + nsl * (1 + 2 * (size_t)m), wsz + asm_coarse * pr.nsys_max);
   if (h.build_elems < need) {
     if (h.build_ws) hipFree(h.build_ws);
     h.build_ws = dalloc<double>(need, err);
@@ -634,8 +527,15 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     if (err) { h.err = "out of device memory for the preconditioner build"; return err; }
   }
   hipMemsetAsync(h.dflag, 0, 4 * sizeof(int), st);
-  double* A = h.build_ws;
-  double* Aloc = h.build_ws + need - asm_local;
+  StencilIn si{};
+  si.g = g;
+  si.fixed = h.fixed;
+  si.K0 = h.K0;
+  si.E0 = pr.E0;
+  si.Emin = pr.Emin;
+  si.penal = pr.penal;
+  si.shift = mp.shift;
+  si.fixed_diag = kFixedDiag;
   hipEventRecord(h.fork, st);
   hipStreamWaitEvent(h.side, h.fork, 0);
 
@@ -647,14 +547,16 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;
     const int64_t nm = (int64_t)nsys * g.nel;
     for (int sys = 0; sys < nsys; ++sys) {
-      hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, s2, g,
-                         rho + (size_t)sys * g.nel, h.fixed, h.K0, Aloc, nullptr, mp, 0);
+      StencilIn sd = si;
+      sd.rho = rho + (size_t)sys * g.nel;
+      sd.neumann = 0;
+      sd.dis = nullptr;
       if (h.mixed)
-        launch_factor<float>(Aloc, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh,
-                             h.dflag, s2, true);
+        launch_factor<float>(nullptr, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh,
+                             h.dflag, s2, true, &sd);
       else
-        launch_factor<double>(Aloc, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub, lsh,
-                              h.dflag, s2, true);
+        launch_factor<double>(nullptr, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub,
+                              lsh, h.dflag, s2, true, &sd);
     }
     if (h.mixed)
       hipLaunchKernelGGL(k_moduli<float>, dim3(1024), dim3(kThreads), 0, s2, rho,
@@ -666,14 +568,18 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   }
 
   // --- 1-3: spectral basis from system `rep` ---
-  double* nfac = A + asm_local;
+  double* nfac = h.build_ws;
   double* dis = nfac + rec;
   double* X = dis + nsl;
   double* Y = X + nsl * m;
   const double* rrep = rho + (size_t)rep * g.nel;
-  hipLaunchKernelGGL(k_assemble, dim3(g.nsub * g.nblk, 1), dim3(kThreads), 0, st, g, rrep,
-                     h.fixed, h.K0, A, dis, mp, 1);
-  launch_factor<double>(A, nfac, g.nsub, lsh, h.dflag, st);
+  {
+    StencilIn sn = si;
+    sn.rho = rrep;
+    sn.neumann = 1;
+    sn.dis = dis;
+    launch_factor<double>(nullptr, nfac, g.nsub, lsh, h.dflag, st, false, &sn);
+  }
   hipLaunchKernelGGL(k_eig_init, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
   hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
   for (int it = 0; it < iters; ++it) {
@@ -693,7 +599,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
                        reinterpret_cast<double*>(h.phim));
 
   // --- 4: coarse matrices and factors, per system ---
-  double* W = A + asm_local;
+  double* W = h.build_ws;
   double* Ac = W + wsz;
   hipMemsetAsync(Ac, 0, sizeof(double) * asm_coarse * nsys, st);
   const int nnb = g.dim == 3 ? 27 : 9;

@@ -41,9 +41,9 @@ def test_workspace_sizing_and_validation_on_host():
     ok = T.make_problem(2, (1024, 512), 32, 6, 3)
     n = lib.tpcg_workspace_bytes(ctypes.byref(ok), 3)
     # at least the tiled FP64 local factors (3 systems x 512 subdomains x 33
-    # blocks x 153 lower 4x4 tiles of D_b) and the set-up's assembled blocks
-    # (512 x 33 x 2 x 66^2 doubles)
-    assert n > 3 * 512 * 33 * 153 * 16 * 8 + 512 * 33 * 2 * 66 * 66 * 8
+    # blocks x 153 lower 4x4 tiles of D_b) and the packed Neumann factors of
+    # the eigensolver (512 x 33 records of 66 x (66 + 4) doubles)
+    assert n > 3 * 512 * 33 * 153 * 16 * 8 + 512 * 33 * 66 * 70 * 8
     bad = T.make_problem(2, (100, 50), 32, 6, 3)      # not a multiple of the subdomain size
     assert lib.tpcg_workspace_bytes(ctypes.byref(bad), 3) == 0
     mixed = T.make_problem(2, (1024, 512), 32, 6, 3, precision=T.MIXED)

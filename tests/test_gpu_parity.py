@@ -84,8 +84,14 @@ def test_compliance_and_sensitivity():
                                    atol=1e-12)
 
 
+# Subspace iteration approaches the dense eigenpairs geometrically; the
+# comparisons against the exact eigenvectors run it well past the production
+# default (10 sweeps), whose quality is judged by the PCG iteration counts.
+CONVERGED_SWEEPS = 40
+
+
 def _eig_compare(p, rho):
-    h = handle(p, nsys=1)
+    h = handle(p, nsys=1, eig_iters=CONVERGED_SWEEPS)
     h.build_coarse_basis(dev(rho[None, :]), rep=0)
     phi, lam, res = h.export_coarse_basis()
     phi = host(phi)
@@ -134,7 +140,7 @@ def test_preconditioner_matches_oracle_c1():
     r = rng.standard_normal(p.n_dof)
     r[fixed == 1] = 0.0
     want = M.apply(r)
-    h = handle(p, nsys=1)
+    h = handle(p, nsys=1, eig_iters=CONVERGED_SWEEPS)
     h.build_coarse_basis(dev(rho[None, :]), rep=0)
     z = dev(np.zeros(p.n_dof))
     h.apply_precond(dev(r), z)
