@@ -126,7 +126,7 @@ def cpu_baseline(args):
         threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    p = W.cantilever2d(256, 64, 32, 6)
+    p = W.cantilever2d(512, 128, 32, 6)
     rho = W.design_field(p)
     fixed, f = W.fixed_mask(p), W.load_vector(p)
     t0 = time.perf_counter()
@@ -140,10 +140,92 @@ def cpu_baseline(args):
     return {"value": work / (t1 - t0), "unit": "DOF-iters/s", "cores": int(threads),
             "kind": "oracle",
             "sample": (f"one full step (filter+projection, spectral basis, 3-realisation PCG to "
-                       f"{args.rtol:g}, sensitivities, chain rule) on a 256x64-element section of "
-                       f"the cantilever workload (16 subdomains of 32x32, k=6; "
+                       f"{args.rtol:g}, sensitivities, chain rule) on a 512x128-element section of "
+                       f"the cantilever workload (64 subdomains of 32x32, k=6; "
                        f"{p.n_dof} DOFs/system); {t1 - t0:.1f} s, iterations "
                        f"{[r[1] for r in res]}")}
+
+
+def short_name(name):
+    """Kernel name without namespace, template arguments or parameter list."""
+    base = name.split("(")[0]
+    base = base.split("<")[0]
+    return base.split("::")[-1].replace("void ", "")
+
+
+def summarize_trace(stats_csv, command, out, title, bench_json=None):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel summary."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# Kernel trace: {title}", "", "Command (on one MI355X, from the repository root):",
+             "", "    " + command, "",
+             "| kernel | calls | total ms | avg us | min us | max us |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| {short_name(r['Name'])} | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    if bench_json:
+        b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        rl = b["roofline"]
+        lines += ["", f"The bench line of the same run timed {rl['kernel']} with HIP events on its "
+                  f"stream: {rl['launches']} launches with work, {rl['avg_launch_ms'] * 1e3:.1f} us "
+                  f"per launch, {rl['algorithmic_bytes_per_launch'] / 1e9:.3f} GB algorithmic "
+                  f"bytes per launch, {rl['achieved']:.0f} GB/s. The trace average above also "
+                  f"counts the near-empty launches after the systems converge."]
+        trace_csv = os.path.join(os.path.dirname(stats_csv), "run_kernel_trace.csv")
+        if os.path.exists(trace_csv):
+            key = rl["kernel"].split("<")[0]
+            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                 for r in csv.DictReader(open(trace_csv)) if key in r["Kernel_Name"]]
+            busy = [x for x in d if x > 20.0][-rl["launches"]:]
+            lines += ["", f"In the trace, the last {len(busy)} launches of {key} that do work "
+                      f"(the timed steps) average {sum(busy) / len(busy):.1f} us."]
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def summarize_traffic(fetch_csv, write_csv, command, out_json, out_md, kernel="k_local_solves<double>"):
+    """HBM bytes per launch of the roofline kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch). Each counter is scaled by
+    what it reads for the first device-to-device copy of the run, a copy of
+    COPY_BYTES bytes in each direction."""
+    import csv
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        copy = next(r for r in rows if "copyBuffer" in r["Kernel_Name"])
+        kib_copy = float(copy["Counter_Value"])
+        assert kib_copy * 1024 > COPY_BYTES / 4, "calibration copy not found"
+        key = kernel.rstrip(">")          # template arguments beyond the element type vary
+        vals = [float(r["Counter_Value"]) for r in rows if key in r["Kernel_Name"]]
+        return COPY_BYTES / (kib_copy * 1024), vals
+
+    ff, fv = load(fetch_csv, "FETCH_SIZE")
+    wf, wv = load(write_csv, "WRITE_SIZE")
+    # launches with work, as the bench counts them: once every system has
+    # converged a launch only reads the gate flags
+    busy = [i for i, v in enumerate(fv) if v * 1024 * ff > 1e6]
+    fv = [fv[i] for i in busy]
+    wv = [wv[i] for i in busy if i < len(wv)]
+    fetch = sum(fv) / len(fv) * 1024 * ff
+    write = sum(wv) / len(wv) * 1024 * wf
+    res = {"kernel": kernel, "kernel_hash": kernel_hash(), "kernel_sources": KERNEL_SOURCES,
+           "bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
+           "write_bytes_per_launch": write, "fetch_scale": ff, "write_scale": wf,
+           "launches": len(fv), "command": command}
+    json.dump(res, open(out_json, "w"), indent=1)
+    lines = [f"# HBM traffic of {kernel}: 1024x512 cantilever, 3 realisations, FP64", "",
+             "Commands (on one MI355X, from the repository root):", ""]
+    lines += ["    " + c for c in command.split(" ;; ")]
+    lines += ["", f"The first copy in each run moves {COPY_BYTES} bytes. FETCH_SIZE reads it as "
+              f"{COPY_BYTES / ff / 1024:.0f} KiB (scale {ff:.3f}), WRITE_SIZE as "
+              f"{COPY_BYTES / wf / 1024:.0f} KiB (scale {wf:.3f}).", "",
+              "| per launch (mean over the run's launches) | bytes |", "|---|---:|",
+              f"| scaled FETCH_SIZE | {fetch:.4g} |", f"| scaled WRITE_SIZE | {write:.4g} |",
+              f"| traffic | {fetch + write:.4g} |", "",
+              f"{len(fv)} launches with work. Kernel sources hash {res['kernel_hash']}."]
+    open(out_md, "w").write("\n".join(lines) + "\n")
 
 
 def main():
@@ -159,7 +241,22 @@ def main():
     ap.add_argument("--eig-extra", type=int, default=0, help="guard vectors (0: library default)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device, the reference kernel for HBM counters")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
+                    help="write a profile summary of a rocprofv3 --stats run and exit (no GPU)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic of the roofline kernel from two --pmc runs and exit")
+    ap.add_argument("--command", default="", help="command recorded in a summary")
+    ap.add_argument("--title", default="1024x512 cantilever, 3 realisations, FP64")
+    ap.add_argument("--bench-json", default=None, help="bench line of the traced run")
+    ap.add_argument("--out", default=None, help="summary file")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.command, args.out, args.title, args.bench_json)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.command, TRAFFIC_FILE,
+                          TRAFFIC_FILE.replace(".json", ".md"))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve of one "
               "system does not span GPUs in this build", file=sys.stderr)
