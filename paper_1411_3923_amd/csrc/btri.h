@@ -117,6 +117,13 @@ __host__ __device__ inline size_t tile_offset(int nl, int tau, int e) {
 // matrix on its closed-cell DOFs), or with neumann != 0 the cell-only
 // stiffness matrix S = D^-1/2 K^N D^-1/2 + shift I (D = diag K^N, supported
 // DOFs decoupled with diagonal fixed_diag + shift), D^-1/2 stored to dis.
+// With twist set (Dirichlet matrices, tiled records only) the factorisation
+// is the twisted one of the subdomain solves: the block rows above the
+// middle block mid = nblk / 2 are eliminated downwards, those below it
+// upwards, and block mid takes both Schur terms, so that
+//   A = M M^T,  M_bb = L_bb,  M_{b,b-1} = A_{b,b-1} D_{b-1}^T (b <= mid),
+//               M_{b,b+1} = A_{b,b+1} D_{b+1}^T (b >= mid);
+// twist is scratch of nb (nb + 1) / 2 doubles per matrix.
 struct StencilIn {
   Geometry g;
   const double* rho;
@@ -125,6 +132,7 @@ struct StencilIn {
   double E0, Emin, penal, shift, fixed_diag;
   int neumann;
   double* dis;
+  double* twist;
 };
 
 // factor.hip

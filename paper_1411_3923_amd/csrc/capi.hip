@@ -93,6 +93,8 @@ std::string make_geometry(const tpcg_problem& pr, Geometry& g) {
 std::string precond_limits(const Geometry& g) {
   if (g.nb > kMaxNb || (g.nb & 1))
     return "subdomain node rows/layers give blocks larger than 96 or of odd size";
+  if ((g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1) > 64)
+    return "element layers wider than one wave";
   if (g.nbc > kMaxNb || (g.nbc & 1))
     return "coarse blocks are larger than 96 or of odd size";
   if (stage_bucket(stage_regs_for<double>(g.nb, g.pe)) < 0 ||
@@ -118,6 +120,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += (sizeof(double) + ts) * (size_t)g.nsub * g.nloc * g.k;
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
   p += ts * nsys * (trec + (size_t)g.nel);
+  p += sizeof(double) * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
   p += sizeof(double) * nsys * crec;
   if (g.nt <= kDenseCoarse) p += sizeof(double) * nsys * (size_t)g.nt * g.nt;
   p += 4 * sizeof(double) * nsys * g.ndof;
@@ -143,7 +146,7 @@ int alloc(T*& p, size_t n) {
 void release(Handle* h) {
   if (!h) return;
   void* ptrs[] = {h->fixed, h->K0, h->phi, h->phim, h->lam, h->eres, h->lfac, h->emod,
-                  h->cfac, h->cinv, h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts,
+                  h->twist, h->cfac, h->cinv, h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts,
                   h->istate, h->dflag, h->build_ws};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -171,14 +174,17 @@ int check_hip(Handle* h, const char* where) {
 
 // Minimum bytes one system's share of a local-solve launch must move, per
 // subdomain: the lower triangles of the inverted diagonal factor blocks D_b
-// (read in the forward and the backward pass; the last block once), the
-// moduli of the inner element layers, the right-hand side (FP64) and the
-// support flags read once, the forward result written and read back and the
-// solution written.
+// (read in the forward and the backward pass of the twisted solve: the
+// middle block once, the lower half's innermost block once), the moduli of
+// the inner element layers, the right-hand side (FP64) and the support flags
+// read once, the forward result written and read back and the solution
+// written.
 double local_solve_bytes(const Geometry& g, int elem) {
   const double tri = 0.5 * g.nb * (g.nb + 1.0);
   const double sw = g.dim == 3 ? (g.bn + 1.0) * (g.bn + 1.0) : g.bn + 1.0;
-  const double per = (2.0 * g.nblk - 1.0) * tri * elem + (g.nblk - 1.0) * sw * elem +
+  const int mid = g.nblk / 2, nbot = g.nblk - 1 - mid;
+  const double reads = 2.0 * mid + 1.0 + (nbot > 0 ? 2.0 * nbot - 1.0 : 0.0);
+  const double per = reads * tri * elem + (g.nblk - 1.0) * sw * elem +
                      (double)g.nloc * (8.0 + 1.0 + 3.0 * elem);
   return g.nsub * per;
 }
@@ -305,6 +311,7 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     unsigned char* em = nullptr;
     e |= alloc(em, ts * ns * (size_t)g.nel);
     h->emod = em;
+    e |= alloc(h->twist, (size_t)g.nsub * g.nb * (g.nb + 1) / 2);
     e |= alloc(h->cfac, ns * cfsz);
     if (g.nt <= kDenseCoarse) e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
     unsigned char* zl = nullptr;

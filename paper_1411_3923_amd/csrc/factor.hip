@@ -202,18 +202,31 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
     for (int r = t / 16; r < nb; r += kThreads / 16)
       for (int c = t % 16; c < nb; c += 16) dst[r * ld + c] = src[(size_t)r * nb + c];
   };
+  // Twisted order (stencil input with si.twist set): the node layers below
+  // the middle block mid = nblk / 2 are eliminated upwards from the last one
+  // (blocks nblk - 1, ..., mid + 1, records at their own index), their Schur
+  // term for block mid is parked in si.twist, then the layers 0, ..., mid
+  // are eliminated downwards and block mid receives both terms.
+  const bool twist = sten && si.twist != nullptr;
+  const int mid = nblk / 2;
+  const int nbot = twist ? nblk - 1 - mid : 0;
+  double* TS = twist ? si.twist + (size_t)blockIdx.x * ((size_t)nb * (nb + 1) / 2) : nullptr;
   if (sten) {
-    stage_layers(si, jx, jy, jz, -1, Es);
+    // block B needs the element layers B - 1 and B
+    const int b0 = nbot > 0 ? nblk - 1 : 0;
+    stage_layers(si, jx, jy, jz, b0 - 1, Es);
     __syncthreads();
     if (si.neumann) diag_layer(0, -1);
     __syncthreads();
-    fill(X, 0, 0, -1);
+    fill(X, b0, b0, b0 - 1);
   } else {
     load(X, F);
   }
-  for (int b = 0; b < nblk; ++b) {
+  for (int step = 0; step < nblk; ++step) {
+    const bool bot = step < nbot;
+    const int b = bot ? nblk - 1 - step : step - nbot;
     __syncthreads();
-    if (b > 0) {
+    if (step != 0 && step != nbot) {
       // A_bb -= B_b B_b^T on the lower tiles
       int tile = 0;
       for (int I = 0; I < NT; ++I)
@@ -226,6 +239,14 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
             if (r < nb && c < nb) X[r * ld + c] -= acc[v];
           }
         }
+      __syncthreads();
+    }
+    if (nbot > 0 && !bot && b == mid) {
+      // the middle block also takes the Schur term of the lower half
+      for (int e = t; e < nb * nb; e += kThreads) {
+        const int r = e / nb, c = e - (e / nb) * nb;
+        if (c <= r) X[r * ld + c] += TS[(size_t)r * (r + 1) / 2 + c];
+      }
       __syncthreads();
     }
     // blocked Cholesky: panel p (16 columns) in the registers of wave 0,
@@ -351,16 +372,21 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
       if ((r >> 4) > (c >> 4)) X[r * ld + c] = Y[r * ld + c];
     }
     __syncthreads();
-    const bool last = b + 1 == nblk;
+    const bool last = step + 1 == nblk;
+    const bool last_bot = bot && step + 1 == nbot;
+    // next block row nr and the staged element layers L0, L0 + 1: downwards
+    // (b, b + 1) serve A_{b+1,b} now and A_{b+1,b+1} below; upwards
+    // (b - 2, b - 1) serve A_{b-1,b} and A_{b-1,b-1}
+    const int nr = bot ? (last_bot ? mid : b - 1) : b + 1;
+    const int L0 = bot ? b - 2 : b;
     if (!last) {
-      // B_{b+1} = A_{b+1,b} D^T; wave w owns row tiles I = w, w + 4, ...
+      // B = A_{nr,b} D^T; wave w owns row tiles I = w, w + 4, ...
       if (sten) {
-        // element layers b and b + 1 serve A_{b+1,b} now and A_{b+1,b+1} below
-        stage_layers(si, jx, jy, jz, b, Es);
+        stage_layers(si, jx, jy, jz, L0, Es);
         __syncthreads();
         if (si.neumann) diag_layer(b + 1, b);
         __syncthreads();
-        fill(Y, b + 1, b, b);
+        fill(Y, nr, b, L0);
       } else {
         load(Y, F + ((size_t)(b + 1) * 2 + 1) * msz);
       }
@@ -399,8 +425,29 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
       }
       if (!last) {
         __syncthreads();
-        if (sten) fill(X, b + 1, b + 1, b);
-        else load(X, F + (size_t)(b + 1) * 2 * msz);
+        if (last_bot) {
+          // Schur term -B B^T of the lower half for block mid, lower triangle
+          int tile = 0;
+          for (int I = 0; I < NT; ++I)
+            for (int J = 0; J <= I; ++J, ++tile) {
+              if ((tile & 3) != wv) continue;
+              d4 acc = {0.0, 0.0, 0.0, 0.0};
+              acc = mfma_nt(Y, Y, ld, nb, 16 * I, 16 * J, 0, (nb + 3) & ~3, acc);
+              for (int v = 0; v < 4; ++v) {
+                const int r = 16 * I + 4 * v + lq, c = 16 * J + li;
+                if (r < nb && c <= r) TS[(size_t)r * (r + 1) / 2 + c] = -acc[v];
+              }
+            }
+          __syncthreads();
+          // then the upper half starts at block 0
+          stage_layers(si, jx, jy, jz, -1, Es);
+          __syncthreads();
+          fill(X, 0, 0, -1);
+        } else if (sten) {
+          fill(X, nr, nr, L0);
+        } else {
+          load(X, F + (size_t)(b + 1) * 2 * msz);
+        }
       }
       continue;
     }

@@ -3,16 +3,28 @@
 // supported stiffness matrix on the subdomain's closed-cell DOFs), one
 // workgroup per (system, subdomain).
 //
-// The factor of A_j is kept as the tiled inverted diagonal blocks D_b of its
-// block-tridiagonal Cholesky factor (btri.h); the off-diagonal factor blocks
-// are never stored: B_{b+1} = A_{b+1,b} D_b^T, and A_{b+1,b} is applied
-// matrix-free from the moduli of the element layer between node layers b and
-// b + 1 and the element matrix K0 (Sec. 2.2). Per block the workgroup forms
-// D_b v and D_b^T v from register tiles, 4 x 4 per thread, with the partial
-// sums of each row combined in LDS by the thread owning that row, in a fixed
-// order. Each record is requested as soon as the previous one has been used
-// for both products of its block; the other workgroups on the compute unit
-// cover the latency.
+// A_j is factored in twisted form (btri.h): A_j = M M^T, the diagonal blocks
+// of M kept as the tiled inverses D_b, the off-diagonal blocks never stored,
+// since M_{b,b-1} = A_{b,b-1} D_{b-1}^T above the middle block mid = nblk / 2
+// and M_{b,b+1} = A_{b,b+1} D_{b+1}^T below it. A_{b,b+-1} is the stiffness
+// of one element layer, applied matrix-free from its moduli and the element
+// matrix K0 (Sec. 2.2). Both triangular solves then run from the two ends
+// towards the middle and back, as two chains of half the length:
+//   M y = r    y_b = D_b (r_b - A_{b,b-1} s_{b-1}),  s_b = D_b^T y_b,   b = 0 .. mid - 1
+//              y_b = D_b (r_b - A_{b,b+1} s_{b+1}),  s_b = D_b^T y_b,   b = nblk - 1 .. mid + 1
+//              y_mid = D_mid (r_mid - A_{mid,mid-1} s_{mid-1} - A_{mid,mid+1} s_{mid+1})
+//   M^T x = y  x_mid = D_mid^T y_mid
+//              x_b = D_b^T (y_b - D_b A_{b,b+1} x_{b+1}),   b = mid - 1 .. 0
+//              x_b = D_b^T (y_b - D_b A_{b,b-1} x_{b-1}),   b = mid + 1 .. nblk - 1
+// (s and x enter the couplings with supported DOFs zeroed.)
+//
+// The two chains advance in lockstep and share the barriers. Per block the
+// workgroup forms D_b v and D_b^T v from register tiles, 4 x 4 per thread
+// (thread tau holds tile tau of both chains' current records), with the
+// partial sums of each row combined in LDS by the thread owning that row, in
+// a fixed order. Each record is requested as soon as the previous one has
+// been used for both products of its block; the other workgroups on the
+// compute unit cover the latency.
 #include "btri.h"
 
 namespace tpcg {
@@ -20,10 +32,11 @@ namespace tpcg {
 namespace {
 
 // (A_{b+1,b} v)[o] for a DOF o of node layer b + 1 (top = true, v on layer b)
-// or (A_{b+1,b}^T v)[o] for a DOF o of layer b (top = false, v on layer
-// b + 1): the stiffness of the element layer between the two node layers,
-// E[] its moduli indexed (ex + 1) + (bn + 1) (ey + 1) over box-local element
-// coordinates, zero outside the mesh. Supported DOFs are masked by the caller.
+// or (A_{b+1,b}^T v)[o] = (A_{b,b+1} v)[o] for a DOF o of layer b (top =
+// false, v on layer b + 1): the stiffness of the element layer between the
+// two node layers, E[] its moduli indexed (ex + 1) + (bn + 1) (ey + 1) over
+// box-local element coordinates, zero outside the mesh. Supported DOFs are
+// masked by the caller.
 template <typename T>
 __device__ inline T layer_coupling(int d, int bn, const T* __restrict__ K0s,
                                    const T* __restrict__ E, const T* __restrict__ v, int o,
@@ -65,41 +78,53 @@ struct Vec16<float> {
   typedef float type __attribute__((ext_vector_type(4)));
 };
 
-// LDS of one chain in elements of T: tile partials [nt][np], three vectors of
-// np, the element-layer moduli [nblk - 1][sw]; nloc bytes of support flags
-// per chain follow all chains, K0 precedes them.
+__host__ __device__ inline int strip_width(const Geometry& g) {
+  return g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1;
+}
+
+// LDS in elements of T: K0 [nd][nd]; per chain the tile partials [nt][np]
+// and the vectors a, b, c [np]; the two exchanged vectors [np] (the lower
+// chain's coupling into block mid, and x_mid); the element-layer moduli
+// [nblk - 1][sw]; then nloc bytes of support flags.
 __host__ __device__ inline size_t chain_lds_elems(const Geometry& g) {
   const TileShape ts = tile_shape(g.nb);
-  const int np = 4 * ts.nt;
-  const int sw = g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1;
-  return (size_t)ts.nt * np + 3 * (size_t)np + (size_t)(g.nblk - 1) * sw;
+  return (size_t)ts.nt * 4 * ts.nt + 3 * (size_t)4 * ts.nt;
+}
+__host__ __device__ inline size_t local_elems(const Geometry& g) {
+  return (size_t)g.ndpe * g.ndpe + 2 * chain_lds_elems(g) + 8 * (size_t)tile_shape(g.nb).nt +
+         (size_t)(g.nblk - 1) * strip_width(g);
 }
 
-size_t local_solve_lds_bytes(const Geometry& g, int ch, size_t elem) {
-  return elem * ((size_t)g.ndpe * g.ndpe + ch * chain_lds_elems(g)) +
-         ch * (((size_t)g.nloc + 15) & ~(size_t)15);
+size_t local_solve_lds_bytes(const Geometry& g, size_t elem) {
+  return ((local_elems(g) * elem + 15) & ~(size_t)15) + (((size_t)g.nloc + 15) & ~(size_t)15);
 }
 
-// CH independent chains (system, subdomain) per workgroup, advanced in
-// lockstep so that they share the barriers and keep CH records in flight.
-// Thread tau < nl holds tile tau (and tau + 256 when TPT = 2) of each chain's
-// current record; thread o < nb owns DOF o of each chain's current node
-// layer. The block steps run 0, 1, ..., nblk - 1 (forward, the last one also
-// giving x_{nblk-1}) and then nblk - 2, ..., 0 (backward). zloc receives the
-// forward intermediate y and then the solution, in box order.
-template <typename T, int TPT, int CH>
+// Steps K = 0 .. 2 mid: the upper chain (c = 0) runs blocks 0 .. mid - 1
+// (forward), mid (K = mid), mid - 1 .. 0 (backward); the lower chain (c = 1)
+// runs blocks nblk - 1 .. mid + 1 (K < nbot) and mid + 1 .. nblk - 1
+// (K = mid + 1 ..) and idles otherwise. Thread tau < nl holds tile tau (and
+// tau + 256 when TPT = 2) of both chains' records; DOF o of chain c's node
+// layer belongs to thread 128 c + o. zloc receives y and then x, in box
+// order.
+template <typename T, int TPT>
 __global__ __launch_bounds__(kThreads) void k_local_solves(
     Geometry g, const double* __restrict__ r, const T* __restrict__ lfac,
     const T* __restrict__ emod, const uint8_t* __restrict__ fixed, const double* __restrict__ K0,
     T* __restrict__ zloc, int nchains, Gate gate) {
   extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int CH = 2;
+  const int id = blockIdx.x;
+  if (id >= nchains) return;
+  const int sys = id / g.nsub, j = id - (id / g.nsub) * g.nsub;
+  if (!gate_running(gate, sys)) return;   // uniform over the workgroup
+
   const int d = g.dim, nb = g.nb, nblk = g.nblk, bn = g.bn, nd = g.ndpe;
   const TileShape ts = tile_shape(nb);
   const int nt = ts.nt, np = 4 * ts.nt, nl = ts.nl;
-  const int sw = d == 3 ? (bn + 1) * (bn + 1) : bn + 1;
+  const int sw = strip_width(g);
+  const int mid = nblk / 2, nbot = nblk - 1 - mid;
   const int t = threadIdx.x;
-  // DOF o of chain c's node layer belongs to thread c * (kThreads / CH) + o,
-  // so the chains' row phases run on different waves
+  // the row phases of the two chains run on different waves
   int o[CH];
   bool ow[CH];
 #pragma unroll
@@ -107,48 +132,30 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
     o[c] = t - c * (kThreads / CH);
     ow[c] = o[c] >= 0 && o[c] < nb;
   }
-
-  // chains of this workgroup; a chain whose system has stopped only follows
-  // the barriers
-  bool run[CH];
-  int jx[CH], jy[CH], jz[CH];
-  const double* rs[CH];
-  const T* es[CH];
-  const T* F[CH];
-  T* zs[CH];
-  bool any = false;
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const int id = blockIdx.x * CH + c;
-    const int sys = id / g.nsub, j = id - (id / g.nsub) * g.nsub;
-    run[c] = id < nchains && gate_running(gate, sys);
-    any |= run[c];
-    sub_coords(g, j, jx[c], jy[c], jz[c]);
-    rs[c] = r + (size_t)sys * g.ndof;
-    es[c] = emod + (size_t)sys * g.nel;
-    zs[c] = zloc + (size_t)id * g.nloc;
-    F[c] = lfac + (size_t)id * nblk * ts.tstride;
-  }
-  if (!any) return;
+  int jx, jy, jz;
+  sub_coords(g, j, jx, jy, jz);
+  const double* rs = r + (size_t)sys * g.ndof;
+  const T* es = emod + (size_t)sys * g.nel;
+  T* zs = zloc + (size_t)id * g.nloc;
+  const T* F = lfac + (size_t)id * nblk * ts.tstride;
 
   const size_t cl = chain_lds_elems(g);
   T* K0s = reinterpret_cast<T*>(smem);
   T* red[CH];   // [nt][np] tile partials
-  T* va[CH];   // t_b (forward) / w_b (backward)
-  T* vb[CH];   // y_b (forward) / v_b (backward)
-  T* vc[CH];   // masked s_b (forward) / masked x_{b+1} (backward)
-  T* strip[CH];
-  uint8_t* fx[CH];
+  T* va[CH];    // t_b (forward) / w_b (backward)
+  T* vb[CH];    // y_b (forward) / v_b (backward)
+  T* vc[CH];    // masked s_b (forward) / masked x_b (backward)
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     red[c] = K0s + nd * nd + c * cl;
     va[c] = red[c] + (size_t)nt * np;
     vb[c] = va[c] + np;
     vc[c] = vb[c] + np;
-    strip[c] = vc[c] + np;
-    fx[c] = reinterpret_cast<uint8_t*>(K0s + nd * nd + CH * cl) +
-            c * (((size_t)g.nloc + 15) & ~(size_t)15);
   }
+  T* cm = K0s + nd * nd + CH * cl;   // A_{mid,mid+1} s_{mid+1} from the lower chain
+  T* xm = cm + np;                   // masked x_mid for the lower chain
+  T* strip = xm + np;                // moduli of element layer L at strip + L sw
+  uint8_t* fx = smem + ((local_elems(g) * sizeof(T) + 15) & ~(size_t)15);
 
   typedef typename Vec16<T>::type V;
   typedef T Tiles[TPT][16];
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
   }
   Tiles tl[CH];
   auto load_tiles = [&](int c, int b) {
-    const V* src = reinterpret_cast<const V*>(F[c] + (size_t)b * ts.tstride);
+    const V* src = reinterpret_cast<const V*>(F + (size_t)b * ts.tstride);
 #pragma unroll
     for (int u = 0; u < TPT; ++u)
       if (tau[u] < nl) {
@@ -183,11 +190,11 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
       if (tau[u] < nl) {
         const T* xv = x + 4 * tJ[u];
         const T x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
-        T* o = red[c] + (size_t)tJ[u] * np + 4 * tI[u];
+        T* out = red[c] + (size_t)tJ[u] * np + 4 * tI[u];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          o[i] = tl[c][u][4 * i] * x0 + tl[c][u][4 * i + 1] * x1 + tl[c][u][4 * i + 2] * x2 +
-                 tl[c][u][4 * i + 3] * x3;
+          out[i] = tl[c][u][4 * i] * x0 + tl[c][u][4 * i + 1] * x1 + tl[c][u][4 * i + 2] * x2 +
+                   tl[c][u][4 * i + 3] * x3;
       }
   };
   // red[I][4J + k] = (D_IJ^T x_I)[k]
@@ -197,123 +204,157 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
       if (tau[u] < nl) {
         const T* xv = x + 4 * tI[u];
         const T x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
-        T* o = red[c] + (size_t)tI[u] * np + 4 * tJ[u];
+        T* out = red[c] + (size_t)tI[u] * np + 4 * tJ[u];
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          o[k] = tl[c][u][k] * x0 + tl[c][u][4 + k] * x1 + tl[c][u][8 + k] * x2 +
-                 tl[c][u][12 + k] * x3;
+          out[k] = tl[c][u][k] * x0 + tl[c][u][4 + k] * x1 + tl[c][u][8 + k] * x2 +
+                   tl[c][u][12 + k] * x3;
       }
   };
-  auto sum_n = [&](int c, int o) {
+  auto sum_n = [&](int c, int oo) {
     T s = 0;
-    for (int J = 0; J <= o / 4; ++J) s += red[c][(size_t)J * np + o];
+    for (int J = 0; J <= oo / 4; ++J) s += red[c][(size_t)J * np + oo];
     return s;
   };
-  auto sum_t = [&](int c, int o) {
+  auto sum_t = [&](int c, int oo) {
     T s = 0;
-    for (int I = o / 4; I < nt; ++I) s += red[c][(size_t)I * np + o];
+    for (int I = oo / 4; I < nt; ++I) s += red[c][(size_t)I * np + oo];
     return s;
   };
-  auto rhs = [&](int c, int b) {
-    return (T)rs[c][box_dof(g, jx[c], jy[c], jz[c], b * nb + o[c])];
+  auto rhs = [&](int b, int oo) { return (T)rs[box_dof(g, jx, jy, jz, b * nb + oo)]; };
+  auto coupling = [&](int L, const T* v, int oo, bool top) {
+    return layer_coupling(d, bn, K0s, strip + (size_t)L * sw, v, oo, top);
   };
 
-  // set-up: first records, K0, layer moduli, support flags, zeroed padding
+  // set-up: first records, K0, layer moduli, support flags, zeroed vectors,
+  // first right-hand sides
+  const bool lower_runs = nbot > 0;
   T rn[CH], yb[CH];
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     rn[c] = 0;
     yb[c] = 0;
-    if (run[c]) {
-      if (ow[c]) rn[c] = rhs(c, 0);
-      load_tiles(c, 0);
-    }
+    if (c == 0 || lower_runs) load_tiles(c, c == 0 ? 0 : nblk - 1);
   }
   for (int i = t; i < nd * nd; i += kThreads) K0s[i] = (T)K0[i];
-#pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    if (!run[c]) continue;
-    for (int i = t; i < (nblk - 1) * sw; i += kThreads) {
-      const int b = i / sw, q = i - (i / sw) * sw;
-      const int qx = q % (bn + 1), qy = q / (bn + 1);
-      const int ex = g.s * jx[c] - 1 + qx;
-      const int ey = d == 3 ? g.s * jy[c] - 1 + qy : g.s * jy[c] + b;
-      const int ez = d == 3 ? g.s * jz[c] + b : 0;
-      const bool in = ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely;
-      strip[c][i] = in ? es[c][ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)] : (T)0;
-    }
-    for (int l = t; l < g.nloc; l += kThreads) fx[c][l] = fixed[box_dof(g, jx[c], jy[c], jz[c], l)];
-    for (int i = t; i < 3 * np; i += kThreads) va[c][i] = 0;
+  for (int i = t; i < (nblk - 1) * sw; i += kThreads) {
+    const int L = i / sw, q = i - (i / sw) * sw;
+    const int qx = q % (bn + 1), qy = q / (bn + 1);
+    const int ex = g.s * jx - 1 + qx;
+    const int ey = d == 3 ? g.s * jy - 1 + qy : g.s * jy + L;
+    const int ez = d == 3 ? g.s * jz + L : 0;
+    const bool in = ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely;
+    strip[i] = in ? es[ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)] : (T)0;
   }
+  for (int l = t; l < g.nloc; l += kThreads) fx[l] = fixed[box_dof(g, jx, jy, jz, l)];
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+    for (int i = t; i < 3 * np; i += kThreads) va[c][i] = 0;   // va, vb, vc
+  for (int i = t; i < 2 * np; i += kThreads) cm[i] = 0;        // cm, xm
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
-    if (!run[c] || !ow[c]) continue;
-    va[c][o[c]] = rn[c];                            // t_0 = r_0
-    if (nblk > 1) rn[c] = rhs(c, 1);
+    if (!ow[c] || (c == 1 && !lower_runs)) continue;
+    const int b0 = c == 0 ? 0 : nblk - 1, b1 = c == 0 ? 1 : nblk - 2;
+    va[c][o[c]] = rhs(b0, o[c]);              // t_b0 = r_b0
+    if (c == 0 ? b1 <= mid : b1 >= mid + 1) rn[c] = rhs(b1, o[c]);
   }
-  __syncthreads();
 
-  // Block steps k = 0 .. nsteps - 1: forward block b = k, then backward
-  // block b = 2 nblk - 2 - k. Entering a step, va holds t_b (forward) or
-  // w_b = A_{b+1,b}^T x_{b+1} (backward) and tl holds D_b.
-  const int nsteps = 2 * nblk - 1;
-  for (int k = 0; k < nsteps; ++k) {
-    const bool fwd = k < nblk;
-    const int b = fwd ? k : 2 * nblk - 2 - k;
-#pragma unroll
-    for (int c = 0; c < CH; ++c)
-      if (run[c]) prod_n(c, va[c]);              // D_b t_b  or  D_b w_b
+  for (int K = 0; K <= 2 * mid; ++K) {
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      if (!run[c] || !ow[c]) continue;
-      const T sn = sum_n(c, o[c]);
-      if (fwd) {
-        vb[c][o[c]] = sn;                           // y_b
-        zs[c][b * nb + o[c]] = sn;
-      } else {
-        vb[c][o[c]] = yb[c] - sn;                   // v_b = y_b - D_b w_b
-      }
+    if (K == mid && lower_runs) {
+      // t_mid -= A_{mid,mid+1} s_{mid+1}, from the lower chain
+      if (ow[0] && !fx[mid * nb + o[0]]) va[0][o[0]] -= cm[o[0]];
+      __syncthreads();
     }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      if (!run[c]) continue;
-      prod_t(c, vb[c]);                          // s_b = D_b^T y_b  or  x_b = D_b^T v_b
-      // the record has been used twice: request the next one
-      if (k + 1 < nsteps) load_tiles(c, k + 1 < nblk ? k + 1 : 2 * nblk - 3 - k);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      if (!run[c] || !ow[c]) continue;
-      const T st = sum_t(c, o[c]);
-      vc[c][o[c]] = fx[c][b * nb + o[c]] ? (T)0 : st;
-      if (!fwd || b + 1 == nblk) zs[c][b * nb + o[c]] = st;   // x_b (x_{nblk-1} = s_{nblk-1})
-    }
-    __syncthreads();
-    if (k + 1 < nsteps) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        if (!run[c] || !ow[c]) continue;
-        if (k + 1 < nblk) {
-          // t_{b+1} = r_{b+1} - A_{b+1,b} s_b
-          const bool f = fx[c][(b + 1) * nb + o[c]];
-          va[c][o[c]] = f ? rn[c]
-                       : rn[c] - layer_coupling(d, bn, K0s, strip[c] + (size_t)b * sw, vc[c],
-                                                o[c], true);
-          if (b + 2 < nblk) rn[c] = rhs(c, b + 2);
-        } else {
-          // w_e = A_{e+1,e}^T x_{e+1} for the next backward block e
-          const int e = 2 * nblk - 3 - k;
-          va[c][o[c]] = fx[c][e * nb + o[c]]
-                         ? (T)0
-                         : layer_coupling(d, bn, K0s, strip[c] + (size_t)e * sw, vc[c], o[c], false);
-          yb[c] = zs[c][e * nb + o[c]];             // y_e from the forward pass
-        }
+    if (K == mid + 1 && lower_runs) {
+      // lower chain: w_{mid+1} = A_{mid+1,mid} x_mid, y_{mid+1} from the forward pass
+      if (ow[1]) {
+        va[1][o[1]] = fx[(mid + 1) * nb + o[1]] ? (T)0 : coupling(mid, xm, o[1], true);
+        yb[1] = zs[(mid + 1) * nb + o[1]];
       }
       __syncthreads();
+    }
+    // activity and block of each chain at this step
+    bool act[CH], fwd[CH], middle[CH];
+    int b[CH];
+    act[0] = true;
+    fwd[0] = K < mid;
+    middle[0] = K == mid;
+    b[0] = K <= mid ? K : 2 * mid - K;
+    fwd[1] = K < nbot;
+    middle[1] = false;
+    b[1] = fwd[1] ? nblk - 1 - K : K;
+    act[1] = fwd[1] || (K >= mid + 1 && K <= mid + nbot);
+
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (act[c]) prod_n(c, va[c]);            // D_b t_b  or  D_b w_b
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (!act[c] || !ow[c]) continue;
+      const T sn = sum_n(c, o[c]);
+      if (fwd[c] || middle[c]) {
+        vb[c][o[c]] = sn;                        // y_b
+        zs[b[c] * nb + o[c]] = sn;
+      } else {
+        vb[c][o[c]] = yb[c] - sn;                // v_b = y_b - D_b w_b
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (!act[c]) continue;
+      prod_t(c, vb[c]);                          // s_b = D_b^T y_b  or  x_b = D_b^T v_b
+      // the record has been used twice: request the next one (the lower
+      // chain keeps D_{mid+1} from its last forward step to its first
+      // backward one)
+      int nx;
+      if (c == 0) nx = K < mid ? K + 1 : b[c] - 1;
+      else if (fwd[c]) nx = b[c] - 1 >= mid + 1 ? b[c] - 1 : -1;
+      else nx = b[c] + 1 < nblk ? b[c] + 1 : -1;
+      if (nx >= 0) load_tiles(c, nx);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (!act[c] || !ow[c]) continue;
+      const T st = sum_t(c, o[c]);
+      const T sm = fx[b[c] * nb + o[c]] ? (T)0 : st;
+      vc[c][o[c]] = sm;
+      if (!fwd[c]) zs[b[c] * nb + o[c]] = st;   // x_b
+      if (middle[c]) xm[o[c]] = sm;
+    }
+    __syncthreads();
+    // couplings into the next step of each chain
+    if (act[0] && ow[0]) {
+      const int bc = b[0];
+      if (fwd[0]) {
+        // t_{b+1} = r_{b+1} - A_{b+1,b} s_b
+        va[0][o[0]] = fx[(bc + 1) * nb + o[0]] ? rn[0]
+                                                : rn[0] - coupling(bc, vc[0], o[0], true);
+        if (bc + 2 <= mid) rn[0] = rhs(bc + 2, o[0]);
+      } else if (bc >= 1) {
+        // w_{b-1} = A_{b-1,b} x_b
+        va[0][o[0]] = fx[(bc - 1) * nb + o[0]] ? (T)0 : coupling(bc - 1, vc[0], o[0], false);
+        yb[0] = zs[(bc - 1) * nb + o[0]];
+      }
+    }
+    if (act[1] && ow[1]) {
+      const int bc = b[1];
+      if (fwd[1] && bc == mid + 1) {
+        cm[o[1]] = coupling(mid, vc[1], o[1], false);   // A_{mid,mid+1} s_{mid+1}
+      } else if (fwd[1]) {
+        // t_{b-1} = r_{b-1} - A_{b-1,b} s_b
+        va[1][o[1]] = fx[(bc - 1) * nb + o[1]] ? rn[1]
+                                                : rn[1] - coupling(bc - 1, vc[1], o[1], false);
+        if (bc - 2 >= mid + 1) rn[1] = rhs(bc - 2, o[1]);
+      } else if (bc + 1 < nblk) {
+        // w_{b+1} = A_{b+1,b} x_b
+        va[1][o[1]] = fx[(bc + 1) * nb + o[1]] ? (T)0 : coupling(bc, vc[1], o[1], true);
+        yb[1] = zs[(bc + 1) * nb + o[1]];
+      }
     }
   }
 }
@@ -327,23 +368,23 @@ void allow_lds(K kernel, bool& done) {
   done = true;
 }
 
-template <typename T, int TPT, int CH>
+template <typename T, int TPT>
 void local_launch_as(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
   const Geometry& g = h.g;
   const int nchains = nsys * g.nsub;
   static bool done = false;
-  allow_lds(&k_local_solves<T, TPT, CH>, done);
-  hipLaunchKernelGGL((k_local_solves<T, TPT, CH>), dim3((nchains + CH - 1) / CH), dim3(kThreads),
-                     local_solve_lds_bytes(g, CH, sizeof(T)), st, g, r,
+  allow_lds(&k_local_solves<T, TPT>, done);
+  hipLaunchKernelGGL((k_local_solves<T, TPT>), dim3(nchains), dim3(kThreads),
+                     local_solve_lds_bytes(g, sizeof(T)), st, g, r,
                      reinterpret_cast<const T*>(h.lfac), reinterpret_cast<const T*>(h.emod),
                      h.fixed, h.K0, reinterpret_cast<T*>(h.zloc), nchains, gate);
 }
 
 template <typename T>
 void local_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
-  // two chains per workgroup where one tile per thread suffices
-  if (tile_shape(h.g.nb).nl <= kThreads) local_launch_as<T, 1, 2>(h, r, nsys, gate, st);
-  else local_launch_as<T, 2, 1>(h, r, nsys, gate, st);
+  // one tile per thread where it suffices
+  if (tile_shape(h.g.nb).nl <= kThreads) local_launch_as<T, 1>(h, r, nsys, gate, st);
+  else local_launch_as<T, 2>(h, r, nsys, gate, st);
 }
 
 }  // namespace

@@ -10,7 +10,8 @@
 //      Galerkin blocks Phi_l^T W_j of K_c = Phi^T K Phi, the coarse factor and,
 //      for moderate coarse dimensions, the dense K_c^-1.
 //   5. Per system: local Dirichlet matrices A_j (principal submatrices of
-//      the supported K on the closed-cell DOFs) and their factors, on the
+//      the supported K on the closed-cell DOFs) and their twisted
+//      factors (eliminated from both ends towards the middle block), on the
 //      second stream, concurrently with 1-4.
 // All factors are block-tridiagonal Cholesky factors (see btri.h).
 #include <algorithm>
@@ -551,6 +552,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
       sd.rho = rho + (size_t)sys * g.nel;
       sd.neumann = 0;
       sd.dis = nullptr;
+      sd.twist = h.twist;   // one system at a time on this stream
       if (h.mixed)
         launch_factor<float>(nullptr, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh,
                              h.dflag, s2, true, &sd);
