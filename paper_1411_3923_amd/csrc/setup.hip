@@ -12,7 +12,7 @@
 //   5. Per system: local Dirichlet matrices A_j (principal submatrices of
 //      the supported K on the closed-cell DOFs) and their twisted
 //      factors (eliminated from both ends towards the middle block), on the
-//      second stream, concurrently with 1-4.
+//      second stream, concurrently with 4.
 // All factors are block-tridiagonal Cholesky factors (see btri.h).
 #include <algorithm>
 #include <vector>
@@ -511,7 +511,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;
   const int m = h.msub;
-  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 10;
+  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 8;
   MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
 
   // work arrays of the build, kept by the handle from one build to the next:
@@ -537,38 +537,6 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   si.penal = pr.penal;
   si.shift = mp.shift;
   si.fixed_diag = kFixedDiag;
-  hipEventRecord(h.fork, st);
-  hipStreamWaitEvent(h.side, h.fork, 0);
-
-  // --- 5 (second stream): local Dirichlet factors, one system at a time, as
-  //     tiled D_b records (FP32 in mixed mode), and the moduli their layer
-  //     couplings use ---
-  {
-    hipStream_t s2 = h.side;
-    const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;
-    const int64_t nm = (int64_t)nsys * g.nel;
-    for (int sys = 0; sys < nsys; ++sys) {
-      StencilIn sd = si;
-      sd.rho = rho + (size_t)sys * g.nel;
-      sd.neumann = 0;
-      sd.dis = nullptr;
-      sd.twist = h.twist;   // one system at a time on this stream
-      if (h.mixed)
-        launch_factor<float>(nullptr, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh,
-                             h.dflag, s2, true, &sd);
-      else
-        launch_factor<double>(nullptr, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub,
-                              lsh, h.dflag, s2, true, &sd);
-    }
-    if (h.mixed)
-      hipLaunchKernelGGL(k_moduli<float>, dim3(1024), dim3(kThreads), 0, s2, rho,
-                         reinterpret_cast<float*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
-    else
-      hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho,
-                         reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
-    hipEventRecord(h.join, s2);
-  }
-
   // --- 1-3: spectral basis from system `rep` ---
   double* nfac = h.build_ws;
   double* dis = nfac + rec;
@@ -612,6 +580,40 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi, W,
                        Ac + sys * asm_coarse);
   }
+  hipEventRecord(h.fork, st);
+  hipStreamWaitEvent(h.side, h.fork, 0);
+
+  // --- 5 (second stream, beside the coarse factorisation, which occupies
+  //     only one workgroup per system, and the coarse inverse): local
+  //     Dirichlet factors, one system at a
+  //     time, as tiled D_b records (FP32 in mixed mode), and the moduli their
+  //     layer couplings use ---
+  {
+    hipStream_t s2 = h.side;
+    const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;
+    const int64_t nm = (int64_t)nsys * g.nel;
+    for (int sys = 0; sys < nsys; ++sys) {
+      StencilIn sd = si;
+      sd.rho = rho + (size_t)sys * g.nel;
+      sd.neumann = 0;
+      sd.dis = nullptr;
+      sd.twist = h.twist;   // one system at a time on this stream
+      if (h.mixed)
+        launch_factor<float>(nullptr, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh,
+                             h.dflag, s2, true, &sd);
+      else
+        launch_factor<double>(nullptr, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub,
+                              lsh, h.dflag, s2, true, &sd);
+    }
+    if (h.mixed)
+      hipLaunchKernelGGL(k_moduli<float>, dim3(1024), dim3(kThreads), 0, s2, rho,
+                         reinterpret_cast<float*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
+    else
+      hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho,
+                         reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
+    hipEventRecord(h.join, s2);
+  }
+
   launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
   if (h.cinv) launch_inverse(h.cfac, csh, nsys, h.cinv, st);
 

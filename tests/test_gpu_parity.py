@@ -86,7 +86,7 @@ def test_compliance_and_sensitivity():
 
 # Subspace iteration approaches the dense eigenpairs geometrically; the
 # comparisons against the exact eigenvectors run it well past the production
-# default (10 sweeps), whose quality is judged by the PCG iteration counts.
+# default (8 sweeps), whose quality is judged by the PCG iteration counts.
 CONVERGED_SWEEPS = 40
 
 
