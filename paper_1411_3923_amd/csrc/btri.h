@@ -71,17 +71,20 @@ __host__ __device__ inline BtriShape coarse_shape(const Geometry& g) {
 // Tiled factor storage for the single-right-hand-side subdomain solves.
 //
 // Since B_{b+1} = A_{b+1,b} L_bb^-T = A_{b+1,b} D_b^T, the two passes can be
-// written with D_b and the stiffness coupling between node layers alone:
-//   L y = r:    y_b = D_b (r_b - A_{b,b-1} (D_{b-1}^T y_{b-1}))
-//   L^T x = y:  x_b = D_b^T (y_b - D_b (A_{b+1,b}^T x_{b+1}))
-// The coupling A_{b+1,b} is the element stiffness of the element layer
-// between the two node layers and is applied matrix-free, so a record holds
-// only the lower triangle of D_b: the 4 x 4 tiles (I, J), I >= J, of the
-// block padded to 4 nt rows, tile index tau = I (I + 1) / 2 + J, element
-// e = 4 row + col inside a tile. Storage is thread-major in 16-byte vectors:
-// element e of tile tau sits at ((e / per) nl + tau) per + e % per, with
-// per = 16 / sizeof(T), so thread tau reads its tile with 16 / per coalesced
-// loads. Entries past nb and above the diagonal are zero.
+// written with D_b and the stiffness coupling between node layers alone, and
+// with s_b = D_b^T y_b and C_b = D_b^T D_b (the inverse of the block's Schur
+// complement, symmetric) even with C_b alone:
+//   L y = r:    s_b = C_b (r_b - A_{b,b-1} s_{b-1})
+//   L^T x = y:  x_b = s_b - C_b (A_{b+1,b}^T x_{b+1})
+// one symmetric product per block and pass. The coupling A_{b+1,b} is the
+// element stiffness of the element layer between the two node layers and is
+// applied matrix-free, so a record holds only the lower triangle of C_b: the
+// 4 x 4 tiles (I, J), I >= J, of the block padded to 4 nt rows (diagonal
+// tiles in full), tile index tau = I (I + 1) / 2 + J, element e = 4 row + col
+// inside a tile. Storage is thread-major in 16-byte vectors: element e of
+// tile tau sits at ((e / per) nl + tau) per + e % per, with per =
+// 16 / sizeof(T), so thread tau reads its tile with 16 / per coalesced loads.
+// Entries past nb are zero.
 // ---------------------------------------------------------------------------
 struct TileShape {
   int nb, nt, nl, tstride;   // block size, tile rows, lower tiles, elements per record
@@ -123,7 +126,8 @@ __host__ __device__ inline size_t tile_offset(int nl, int tau, int e) {
 // upwards, and block mid takes both Schur terms, so that
 //   A = M M^T,  M_bb = L_bb,  M_{b,b-1} = A_{b,b-1} D_{b-1}^T (b <= mid),
 //               M_{b,b+1} = A_{b,b+1} D_{b+1}^T (b >= mid);
-// twist is scratch of nb (nb + 1) / 2 doubles per matrix.
+// the records then hold C_b = D_b^T D_b of this factorisation. twist is
+// scratch of nb (nb + 1) / 2 doubles per matrix.
 struct StencilIn {
   Geometry g;
   const double* rho;
@@ -136,7 +140,7 @@ struct StencilIn {
 };
 
 // factor.hip
-// Packed records (tiles == false) or tiled records of D_b only (tiles == true,
+// Packed records (tiles == false) or tiled records of C_b = D_b^T D_b only (tiles == true,
 // record stride tile_shape(nb).tstride); the blocks come from A, or from the
 // stencil input when si.rho is set (A is then not read).
 template <typename T>

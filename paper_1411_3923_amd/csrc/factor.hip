@@ -412,16 +412,30 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
     }
     T* R = O + (size_t)b * rstride;
     if (tiles) {
-      // record b: the lower tiles of D_b, thread-major
-      constexpr int per = 16 / (int)sizeof(T);
-      for (int o = t; o < tsh.tstride; o += kThreads) {
-        const int q = o / per, w = o - (o / per) * per;
-        const int v = q / tsh.nl, tau = q - (q / tsh.nl) * tsh.nl;
-        const int e = v * per + w;
-        int I, J;
-        tile_rc(tau, I, J);
-        const int r = 4 * I + e / 4, c = 4 * J + (e & 3);
-        R[o] = (T)((r < nb && c <= r) ? X[r * ld + c] : 0.0);
+      // record b: the lower 4 x 4 tiles of C_b = D_b^T D_b (the inverse of
+      // the block's Schur complement, symmetric; its diagonal tiles in full),
+      // thread-major. 16 x 16 tiles (P, Q), P >= Q, on MFMA, one per wave in
+      // turn: C_PQ = sum_{K >= P} D_KP^T D_KQ over the lower triangle of D.
+      {
+        auto dget = [&](int r, int c) { return (r < nb && c <= r) ? X[r * ld + c] : 0.0; };
+        int tile = 0;
+        for (int P = 0; P < NT; ++P)
+          for (int Q = 0; Q <= P; ++Q, ++tile) {
+            if ((tile & 3) != wv) continue;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int k = 16 * P; k < 16 * NT; k += 4) {
+              const double a = dget(k + lq, 16 * P + li);   // A[i][kk] = D[k + kk][16 P + i]
+              const double bb = dget(k + lq, 16 * Q + li);  // B[kk][j] = D[k + kk][16 Q + j]
+              acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int r = 16 * P + 4 * v + lq, c = 16 * Q + li;
+              const int I = r >> 2, J = c >> 2;
+              if (I < tsh.nt && J <= I)
+                R[tile_offset<T>(tsh.nl, I * (I + 1) / 2 + J, 4 * (r & 3) + (c & 3))] = (T)acc[v];
+            }
+          }
       }
       if (!last) {
         __syncthreads();

@@ -3,28 +3,29 @@
 // supported stiffness matrix on the subdomain's closed-cell DOFs), one
 // workgroup per (system, subdomain).
 //
-// A_j is factored in twisted form (btri.h): A_j = M M^T, the diagonal blocks
-// of M kept as the tiled inverses D_b, the off-diagonal blocks never stored,
-// since M_{b,b-1} = A_{b,b-1} D_{b-1}^T above the middle block mid = nblk / 2
-// and M_{b,b+1} = A_{b,b+1} D_{b+1}^T below it. A_{b,b+-1} is the stiffness
-// of one element layer, applied matrix-free from its moduli and the element
-// matrix K0 (Sec. 2.2). Both triangular solves then run from the two ends
-// towards the middle and back, as two chains of half the length:
-//   M y = r    y_b = D_b (r_b - A_{b,b-1} s_{b-1}),  s_b = D_b^T y_b,   b = 0 .. mid - 1
-//              y_b = D_b (r_b - A_{b,b+1} s_{b+1}),  s_b = D_b^T y_b,   b = nblk - 1 .. mid + 1
-//              y_mid = D_mid (r_mid - A_{mid,mid-1} s_{mid-1} - A_{mid,mid+1} s_{mid+1})
-//   M^T x = y  x_mid = D_mid^T y_mid
-//              x_b = D_b^T (y_b - D_b A_{b,b+1} x_{b+1}),   b = mid - 1 .. 0
-//              x_b = D_b^T (y_b - D_b A_{b,b-1} x_{b-1}),   b = mid + 1 .. nblk - 1
+// A_j is factored in twisted form (btri.h): A_j = M M^T with M_bb = L_bb,
+// M_{b,b-1} = A_{b,b-1} D_{b-1}^T above the middle block mid = nblk / 2 and
+// M_{b,b+1} = A_{b,b+1} D_{b+1}^T below it (D_b = L_bb^-1). A record holds
+// only C_b = D_b^T D_b, the inverse of the block's Schur complement; the
+// off-diagonal blocks are never stored, since A_{b,b+-1} is the stiffness of
+// one element layer, applied matrix-free from its moduli and the element
+// matrix K0 (Sec. 2.2). With s_b = D_b^T y_b both triangular solves need one
+// symmetric product per block, and they run from the two ends towards the
+// middle and back, as two chains of half the length:
+//   M y = r    s_b = C_b (r_b - A_{b,b-1} s_{b-1}),   b = 0 .. mid - 1
+//              s_b = C_b (r_b - A_{b,b+1} s_{b+1}),   b = nblk - 1 .. mid + 1
+//   M^T x = y  x_mid = C_mid (r_mid - A_{mid,mid-1} s_{mid-1} - A_{mid,mid+1} s_{mid+1})
+//              x_b = s_b - C_b A_{b,b+1} x_{b+1},    b = mid - 1 .. 0
+//              x_b = s_b - C_b A_{b,b-1} x_{b-1},    b = mid + 1 .. nblk - 1
 // (s and x enter the couplings with supported DOFs zeroed.)
 //
-// The two chains advance in lockstep and share the barriers. Per block the
-// workgroup forms D_b v and D_b^T v from register tiles, 4 x 4 per thread
-// (thread tau holds tile tau of both chains' current records), with the
-// partial sums of each row combined in LDS by the thread owning that row, in
-// a fixed order. Each record is requested as soon as the previous one has
-// been used for both products of its block; the other workgroups on the
-// compute unit cover the latency.
+// The two chains advance in lockstep and share the barriers: per block one
+// phase for the product (thread tau holds tile tau of both chains' current
+// records in registers and writes its partial products), one for the row
+// sums (the thread owning a row adds its partials in a fixed order) and one
+// for the couplings into the next block. The next record is requested as
+// soon as the product is formed, and the barriers order LDS traffic only,
+// so the load flies across the two other phases.
 #include "btri.h"
 
 namespace tpcg {
@@ -78,17 +79,19 @@ struct Vec16<float> {
   typedef float type __attribute__((ext_vector_type(4)));
 };
 
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __host__ __device__ inline int strip_width(const Geometry& g) {
   return g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1;
 }
 
 // LDS in elements of T: K0 [nd][nd]; per chain the tile partials [nt][np]
-// and the vectors a, b, c [np]; the two exchanged vectors [np] (the lower
+// and the vectors a, c [np]; the two exchanged vectors [np] (the lower
 // chain's coupling into block mid, and x_mid); the element-layer moduli
 // [nblk - 1][sw]; then nloc bytes of support flags.
 __host__ __device__ inline size_t chain_lds_elems(const Geometry& g) {
   const TileShape ts = tile_shape(g.nb);
-  return (size_t)ts.nt * 4 * ts.nt + 3 * (size_t)4 * ts.nt;
+  return (size_t)ts.nt * 4 * ts.nt + 2 * (size_t)4 * ts.nt;
 }
 __host__ __device__ inline size_t local_elems(const Geometry& g) {
   return (size_t)g.ndpe * g.ndpe + 2 * chain_lds_elems(g) + 8 * (size_t)tile_shape(g.nb).nt +
@@ -104,7 +107,7 @@ size_t local_solve_lds_bytes(const Geometry& g, size_t elem) {
 // runs blocks nblk - 1 .. mid + 1 (K < nbot) and mid + 1 .. nblk - 1
 // (K = mid + 1 ..) and idles otherwise. Thread tau < nl holds tile tau (and
 // tau + 256 when TPT = 2) of both chains' records; DOF o of chain c's node
-// layer belongs to thread 128 c + o. zloc receives y and then x, in box
+// layer belongs to thread 128 c + o. zloc receives s and then x, in box
 // order.
 template <typename T, int TPT>
 __global__ __launch_bounds__(kThreads) void k_local_solves(
@@ -143,14 +146,12 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
   T* K0s = reinterpret_cast<T*>(smem);
   T* red[CH];   // [nt][np] tile partials
   T* va[CH];    // t_b (forward) / w_b (backward)
-  T* vb[CH];    // y_b (forward) / v_b (backward)
   T* vc[CH];    // masked s_b (forward) / masked x_b (backward)
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     red[c] = K0s + nd * nd + c * cl;
     va[c] = red[c] + (size_t)nt * np;
-    vb[c] = va[c] + np;
-    vc[c] = vb[c] + np;
+    vc[c] = va[c] + np;
   }
   T* cm = K0s + nd * nd + CH * cl;   // A_{mid,mid+1} s_{mid+1} from the lower chain
   T* xm = cm + np;                   // masked x_mid for the lower chain
@@ -183,42 +184,36 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
         }
       }
   };
-  // red[J][4I + i] = (D_IJ x_J)[i]
-  auto prod_n = [&](int c, const T* x) {
+  // y = C x for the symmetric C from its lower tiles, as partial products in
+  // disjoint slots: tile (I, J) writes (C_IJ x_J) to red[J][4I + i] and, off
+  // the diagonal, (C_IJ^T x_I) to red[I][4J + k]; row o is then the sum of
+  // red[K][o] over all K (K <= o / 4 from the tiles left of the diagonal,
+  // K > o / 4 from those below it)
+  auto prod_sym = [&](int c, const T* x) {
 #pragma unroll
     for (int u = 0; u < TPT; ++u)
       if (tau[u] < nl) {
-        const T* xv = x + 4 * tJ[u];
-        const T x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
-        T* out = red[c] + (size_t)tJ[u] * np + 4 * tI[u];
+        const T* xj = x + 4 * tJ[u];
+        const T* xi = x + 4 * tI[u];
+        const T j0 = xj[0], j1 = xj[1], j2 = xj[2], j3 = xj[3];
+        const T i0 = xi[0], i1 = xi[1], i2 = xi[2], i3 = xi[3];
+        T* on = red[c] + (size_t)tJ[u] * np + 4 * tI[u];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          out[i] = tl[c][u][4 * i] * x0 + tl[c][u][4 * i + 1] * x1 + tl[c][u][4 * i + 2] * x2 +
-                   tl[c][u][4 * i + 3] * x3;
+          on[i] = tl[c][u][4 * i] * j0 + tl[c][u][4 * i + 1] * j1 + tl[c][u][4 * i + 2] * j2 +
+                  tl[c][u][4 * i + 3] * j3;
+        if (tI[u] != tJ[u]) {
+          T* ot = red[c] + (size_t)tI[u] * np + 4 * tJ[u];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            ot[k] = tl[c][u][k] * i0 + tl[c][u][4 + k] * i1 + tl[c][u][8 + k] * i2 +
+                    tl[c][u][12 + k] * i3;
+        }
       }
   };
-  // red[I][4J + k] = (D_IJ^T x_I)[k]
-  auto prod_t = [&](int c, const T* x) {
-#pragma unroll
-    for (int u = 0; u < TPT; ++u)
-      if (tau[u] < nl) {
-        const T* xv = x + 4 * tI[u];
-        const T x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
-        T* out = red[c] + (size_t)tI[u] * np + 4 * tJ[u];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          out[k] = tl[c][u][k] * x0 + tl[c][u][4 + k] * x1 + tl[c][u][8 + k] * x2 +
-                   tl[c][u][12 + k] * x3;
-      }
-  };
-  auto sum_n = [&](int c, int oo) {
+  auto row_sum = [&](int c, int oo) {
     T s = 0;
-    for (int J = 0; J <= oo / 4; ++J) s += red[c][(size_t)J * np + oo];
-    return s;
-  };
-  auto sum_t = [&](int c, int oo) {
-    T s = 0;
-    for (int I = oo / 4; I < nt; ++I) s += red[c][(size_t)I * np + oo];
+    for (int K = 0; K < nt; ++K) s += red[c][(size_t)K * np + oo];
     return s;
   };
   auto rhs = [&](int b, int oo) { return (T)rs[box_dof(g, jx, jy, jz, b * nb + oo)]; };
@@ -249,9 +244,9 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
   for (int l = t; l < g.nloc; l += kThreads) fx[l] = fixed[box_dof(g, jx, jy, jz, l)];
 #pragma unroll
   for (int c = 0; c < CH; ++c)
-    for (int i = t; i < 3 * np; i += kThreads) va[c][i] = 0;   // va, vb, vc
+    for (int i = t; i < 2 * np; i += kThreads) va[c][i] = 0;   // va, vc
   for (int i = t; i < 2 * np; i += kThreads) cm[i] = 0;        // cm, xm
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int c = 0; c < CH; ++c) {
     if (!ow[c] || (c == 1 && !lower_runs)) continue;
@@ -261,19 +256,19 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
   }
 
   for (int K = 0; K <= 2 * mid; ++K) {
-    __syncthreads();
+    lds_barrier();
     if (K == mid && lower_runs) {
       // t_mid -= A_{mid,mid+1} s_{mid+1}, from the lower chain
       if (ow[0] && !fx[mid * nb + o[0]]) va[0][o[0]] -= cm[o[0]];
-      __syncthreads();
+      lds_barrier();
     }
     if (K == mid + 1 && lower_runs) {
-      // lower chain: w_{mid+1} = A_{mid+1,mid} x_mid, y_{mid+1} from the forward pass
+      // lower chain: w_{mid+1} = A_{mid+1,mid} x_mid, s_{mid+1} from the forward pass
       if (ow[1]) {
         va[1][o[1]] = fx[(mid + 1) * nb + o[1]] ? (T)0 : coupling(mid, xm, o[1], true);
         yb[1] = zs[(mid + 1) * nb + o[1]];
       }
-      __syncthreads();
+      lds_barrier();
     }
     // activity and block of each chain at this step
     bool act[CH], fwd[CH], middle[CH];
@@ -288,45 +283,31 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
     act[1] = fwd[1] || (K >= mid + 1 && K <= mid + nbot);
 
 #pragma unroll
-    for (int c = 0; c < CH; ++c)
-      if (act[c]) prod_n(c, va[c]);            // D_b t_b  or  D_b w_b
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      if (!act[c] || !ow[c]) continue;
-      const T sn = sum_n(c, o[c]);
-      if (fwd[c] || middle[c]) {
-        vb[c][o[c]] = sn;                        // y_b
-        zs[b[c] * nb + o[c]] = sn;
-      } else {
-        vb[c][o[c]] = yb[c] - sn;                // v_b = y_b - D_b w_b
-      }
-    }
-    __syncthreads();
-#pragma unroll
     for (int c = 0; c < CH; ++c) {
       if (!act[c]) continue;
-      prod_t(c, vb[c]);                          // s_b = D_b^T y_b  or  x_b = D_b^T v_b
-      // the record has been used twice: request the next one (the lower
-      // chain keeps D_{mid+1} from its last forward step to its first
-      // backward one)
+      prod_sym(c, va[c]);                        // C_b t_b  or  C_b w_b
+      // the record has served its block: request the next one (the lower
+      // chain keeps its block mid + 1 from its last forward step to its
+      // first backward one)
       int nx;
       if (c == 0) nx = K < mid ? K + 1 : b[c] - 1;
       else if (fwd[c]) nx = b[c] - 1 >= mid + 1 ? b[c] - 1 : -1;
       else nx = b[c] + 1 < nblk ? b[c] + 1 : -1;
       if (nx >= 0) load_tiles(c, nx);
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       if (!act[c] || !ow[c]) continue;
-      const T st = sum_t(c, o[c]);
-      const T sm = fx[b[c] * nb + o[c]] ? (T)0 : st;
+      const T sum = row_sum(c, o[c]);
+      // forward: s_b; middle: x_mid; backward: x_b = s_b - C_b w_b
+      const T val = (fwd[c] || middle[c]) ? sum : yb[c] - sum;
+      zs[b[c] * nb + o[c]] = val;
+      const T sm = fx[b[c] * nb + o[c]] ? (T)0 : val;
       vc[c][o[c]] = sm;
-      if (!fwd[c]) zs[b[c] * nb + o[c]] = st;   // x_b
       if (middle[c]) xm[o[c]] = sm;
     }
-    __syncthreads();
+    lds_barrier();
     // couplings into the next step of each chain
     if (act[0] && ow[0]) {
       const int bc = b[0];
@@ -336,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
                                                 : rn[0] - coupling(bc, vc[0], o[0], true);
         if (bc + 2 <= mid) rn[0] = rhs(bc + 2, o[0]);
       } else if (bc >= 1) {
-        // w_{b-1} = A_{b-1,b} x_b
+        // w_{b-1} = A_{b-1,b} x_b, and s_{b-1} back from the forward pass
         va[0][o[0]] = fx[(bc - 1) * nb + o[0]] ? (T)0 : coupling(bc - 1, vc[0], o[0], false);
         yb[0] = zs[(bc - 1) * nb + o[0]];
       }
@@ -351,7 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
                                                 : rn[1] - coupling(bc - 1, vc[1], o[1], false);
         if (bc - 2 >= mid + 1) rn[1] = rhs(bc - 2, o[1]);
       } else if (bc + 1 < nblk) {
-        // w_{b+1} = A_{b+1,b} x_b
+        // w_{b+1} = A_{b+1,b} x_b, and s_{b+1} back from the forward pass
         va[1][o[1]] = fx[(bc + 1) * nb + o[1]] ? (T)0 : coupling(bc, vc[1], o[1], true);
         yb[1] = zs[(bc + 1) * nb + o[1]];
       }
