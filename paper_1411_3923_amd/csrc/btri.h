@@ -29,6 +29,13 @@ namespace tpcg {
 // registers)
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS
+// operations, then for the other waves. Outstanding global loads and stores
+// keep flying across it (a __syncthreads would drain them as a
+// workgroup-scope fence), so it may only separate threads that exchange data
+// through LDS; a thread may still read back its own global writes.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 struct BtriShape {
   int nb, nblk, pe, bstride;
 };
@@ -137,6 +144,7 @@ struct StencilIn {
   int neumann;
   double* dis;
   double* twist;
+  const double* emod;   // moduli of the system's elements, precomputed (launch_local_factor)
 };
 
 // factor.hip
@@ -146,6 +154,13 @@ struct StencilIn {
 template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
                    hipStream_t st, bool tiles = false, const StencilIn* si = nullptr);
+// Tiled records of C_b of the twisted factorisation of each subdomain's
+// Dirichlet matrix (moduli from si.emod, si.twist optional), one workgroup
+// per subdomain, via the Schur complements (no Cholesky factor).
+// local_factor_fits tells whether it takes geometry g (block size and LDS).
+bool local_factor_fits(const Geometry& g);
+template <typename T>
+void launch_local_factor(const StencilIn& si, T* out, int* flag, hipStream_t st);
 void launch_solve_multi(const double* fac, const BtriShape& sh, int nmat, int m, const double* X,
                         double* Y, hipStream_t st);
 // dense symmetric inverse [nmat][n][n] of packed factors (n = nb * nblk)

@@ -121,6 +121,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
   p += ts * nsys * (trec + (size_t)g.nel);
   p += sizeof(double) * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
+  if (mixed) p += sizeof(double) * (size_t)g.nel;
   p += sizeof(double) * nsys * crec;
   if (g.nt <= kDenseCoarse) p += sizeof(double) * nsys * (size_t)g.nt * g.nt;
   p += 4 * sizeof(double) * nsys * g.ndof;
@@ -145,9 +146,10 @@ int alloc(T*& p, size_t n) {
 
 void release(Handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->fixed, h->K0, h->phi, h->phim, h->lam, h->eres, h->lfac, h->emod,
-                  h->twist, h->cfac, h->cinv, h->r, h->z, h->p, h->q, h->zloc, h->yc, h->xc, h->parts,
-                  h->istate, h->dflag, h->build_ws};
+  void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam,      h->eres, h->lfac,
+                  h->emod,  h->twist, h->emod64, h->cfac, h->cinv, h->r,    h->z,
+                  h->p,     h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
+                  h->dflag, h->build_ws};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);
@@ -312,6 +314,7 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     e |= alloc(em, ts * ns * (size_t)g.nel);
     h->emod = em;
     e |= alloc(h->twist, (size_t)g.nsub * g.nb * (g.nb + 1) / 2);
+    if (h->mixed) e |= alloc(h->emod64, (size_t)g.nel);
     e |= alloc(h->cfac, ns * cfsz);
     if (g.nt <= kDenseCoarse) e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
     unsigned char* zl = nullptr;

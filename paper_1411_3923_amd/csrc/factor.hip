@@ -59,13 +59,15 @@ __device__ inline void wave_sync() {
 
 constexpr int kMaxTiles = (kMaxNb + 15) / 16;
 
-// LDS (doubles) of the stencil input: two element layers of moduli, K0 and
-// the Neumann diagonals of two node layers
+// LDS (doubles) of the stencil input: two element layers of moduli, K0, the
+// Neumann diagonals of two node layers and the support flags of the three
+// node layers those element layers touch
 __host__ __device__ inline int layer_width(const Geometry& g) {
   return g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1;
 }
 __host__ __device__ inline size_t stencil_lds_elems(const Geometry& g) {
-  return 2 * (size_t)layer_width(g) + (size_t)g.ndpe * g.ndpe + 2 * (size_t)g.nb;
+  return 2 * (size_t)layer_width(g) + (size_t)g.ndpe * g.ndpe + 2 * (size_t)g.nb +
+         (3 * (size_t)g.nb + 7) / 8;
 }
 
 // Box-local coordinates of local DOF l: x, y (3D), layer (the block axis), component.
@@ -89,11 +91,19 @@ __device__ inline BoxNode box_node(const Geometry& g, int l) {
 
 // Moduli of element layers L0 and L0 + 1 (layer L lies between node layers L
 // and L + 1; -1 and nblk - 1 are outside the box) into Es, zero outside the
-// mesh and, for the Neumann matrices, outside the cell.
-__device__ void stage_layers(const StencilIn& si, int jx, int jy, int jz, int L0, double* Es) {
+// mesh and, for the Neumann matrices, outside the cell; the support flags of
+// node layers L0, L0 + 1, L0 + 2 into fl. PRE: the moduli are read from
+// si.emod instead of being formed from the densities.
+template <bool PRE = false>
+__device__ void stage_layers(const StencilIn& si, int jx, int jy, int jz, int L0, double* Es,
+                             uint8_t* fl, int tid = threadIdx.x) {
   const Geometry& g = si.g;
   const int d = g.dim, ew = layer_width(g), s = g.s;
-  for (int i = threadIdx.x; i < 2 * ew; i += kThreads) {
+  for (int i = tid; i < 3 * g.nb; i += kThreads) {
+    const int L = L0 + i / g.nb;
+    fl[i] = (L >= 0 && L < g.nblk) ? si.fixed[box_dof(g, jx, jy, jz, L * g.nb + i % g.nb)] : 0;
+  }
+  for (int i = tid; i < 2 * ew; i += kThreads) {
     const int L = L0 + i / ew, q = i - (i / ew) * ew;
     const int qx = q % (g.bn + 1), qy = q / (g.bn + 1);
     const int ex = s * jx - 1 + qx;
@@ -103,9 +113,11 @@ __device__ void stage_layers(const StencilIn& si, int jx, int jy, int jz, int L0
     if (si.neumann)
       in = in && ex >= s * jx && ex < s * jx + s && ey >= s * jy && ey < s * jy + s &&
            (d == 2 || (ez >= s * jz && ez < s * jz + s));
-    Es[i] = in ? simp_modulus(si.rho[ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)], si.E0,
-                              si.Emin, si.penal)
-               : 0.0;
+    const int64_t el = ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez);
+    if (PRE)
+      Es[i] = in ? si.emod[el] : 0.0;
+    else
+      Es[i] = in ? simp_modulus(si.rho[el], si.E0, si.Emin, si.penal) : 0.0;
   }
 }
 
@@ -165,6 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   double* Es = tmp + 4 * 256;
   double* K0s = Es + 2 * (sten ? layer_width(si.g) : 0);
   double* dl = K0s + (sten ? si.g.ndpe * si.g.ndpe : 0);
+  uint8_t* fl = reinterpret_cast<uint8_t*>(dl + (sten ? 2 * nb : 0));   // flags of 3 node layers
   int jx = 0, jy = 0, jz = 0;
   if (sten) {
     sub_coords(si.g, blockIdx.x, jx, jy, jz);
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   auto diag_layer = [&](int L, int L0) {
     for (int i = t; i < nb; i += kThreads) {
       const int lr = L * nb + i;
-      const bool fx = si.fixed[box_dof(si.g, jx, jy, jz, lr)];
+      const bool fx = fl[(L - L0) * nb + i];
       const double dd = stencil_entry(si.g, lr, lr, L0, Es, K0s);
       dl[(L & 1) * nb + i] = dd;
       if (si.dis) si.dis[(size_t)blockIdx.x * si.g.nloc + lr] = fx ? 0.0 : 1.0 / sqrt(dd);
@@ -187,7 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
       for (int c = t % 16; c < nb; c += 16) {
         const int lr = Lr * nb + r, lc = Lc * nb + c;
         double v;
-        if (si.fixed[box_dof(si.g, jx, jy, jz, lr)] || si.fixed[box_dof(si.g, jx, jy, jz, lc)]) {
+        if (fl[(Lr - L0) * nb + r] || fl[(Lc - L0) * nb + c]) {
           v = lr == lc ? (si.neumann ? si.fixed_diag + si.shift : 1.0) : 0.0;
         } else {
           v = stencil_entry(si.g, lr, lc, L0, Es, K0s);
@@ -214,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   if (sten) {
     // block B needs the element layers B - 1 and B
     const int b0 = nbot > 0 ? nblk - 1 : 0;
-    stage_layers(si, jx, jy, jz, b0 - 1, Es);
+    stage_layers(si, jx, jy, jz, b0 - 1, Es, fl);
     __syncthreads();
     if (si.neumann) diag_layer(0, -1);
     __syncthreads();
@@ -382,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
     if (!last) {
       // B = A_{nr,b} D^T; wave w owns row tiles I = w, w + 4, ...
       if (sten) {
-        stage_layers(si, jx, jy, jz, L0, Es);
+        stage_layers(si, jx, jy, jz, L0, Es, fl);
         __syncthreads();
         if (si.neumann) diag_layer(b + 1, b);
         __syncthreads();
@@ -454,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
             }
           __syncthreads();
           // then the upper half starts at block 0
-          stage_layers(si, jx, jy, jz, -1, Es);
+          stage_layers(si, jx, jy, jz, -1, Es, fl);
           __syncthreads();
           fill(X, 0, 0, -1);
         } else if (sten) {
@@ -523,6 +536,294 @@ __global__ __launch_bounds__(kThreads) void k_btri_inverse(const double* __restr
       smem);
 }
 
+// ---------------------------------------------------------------------------
+// Local Dirichlet factors of the subdomain solves, through the Schur
+// complements of the twisted elimination (btri.h):
+//   S_b = A_bb - A_{b,p} C_p A_{p,b},   C_b = S_b^-1,
+// p the previous block of b's half (b - 1 above the middle block, b + 1 below
+// it; none for the first block of a half), and the middle block with both
+// terms. The solves need C_b only, so no Cholesky factor is formed.
+//
+// S_b lives in registers: thread (ti, tj) of an R x C grid owns rows
+// ti + R a (a < SR) and columns tj + C q (q < SC), R = ceil(nb / SR),
+// C = ceil(nb / SC); rows and columns past nb stay exactly zero throughout,
+// so no access needs a bounds test. A_{b,p} and A_bb have at most 3 d
+// entries per row (the nodes next to a node in a layer, all components),
+// stored sparse; the correction is two sparse passes over C_p in LDS
+// (T = C_p A_{p,b}, then A_{b,p} T), and A_bb is scattered into a cleared
+// dense buffer. S_b is inverted in place by Gauss-Jordan elimination, which
+// needs no pivoting on a symmetric positive definite matrix: step k, with
+// pivot p = s_kk, maps s_ij to z_ij - c_i r_j, where z is s with column k
+// replaced by the unit vector e_k, r is row k with r_k = 1, c_i = s_ik / p
+// (i != k) and c_k = 1 - 1 / p. The pivot row and column go through LDS,
+// double buffered so that one barrier per step suffices.
+struct LfShape {
+  int SR, SC;             // register block per thread
+  int R, C, NR, NC, ld;   // thread grid, padded rows and columns, LDS leading dimension
+};
+
+constexpr LfShape lf_shape(int nb, int SR, int SC) {
+  LfShape f{};
+  f.SR = SR;
+  f.SC = SC;
+  f.R = (nb + SR - 1) / SR;
+  f.C = (nb + SC - 1) / SC;
+  f.NR = f.R * SR;
+  f.NC = f.C * SC;
+  f.ld = (f.NR > f.NC ? f.NR : f.NC) | 1;
+  return f;
+}
+
+// the smallest register block whose thread grid fits the workgroup
+constexpr LfShape lf_pick_shape(int nb) {
+  constexpr int blocks[][2] = {{1, 1}, {1, 2}, {2, 2}, {2, 3}, {3, 3},
+                               {3, 4}, {3, 6}, {4, 6}, {6, 6}};
+  for (const auto& b : blocks) {
+    const LfShape f = lf_shape(nb, b[0], b[1]);
+    if (f.R * f.C <= kThreads) return f;
+  }
+  return LfShape{};
+}
+
+__host__ __device__ inline int coupling_nz(const Geometry& g) { return g.dim == 3 ? 27 : 6; }
+
+__host__ __device__ inline size_t local_factor_lds_bytes(const Geometry& g, const LfShape& f) {
+  const size_t np = (size_t)f.ld, nz = coupling_nz(g);
+  const size_t dbl = (size_t)f.NR * f.ld + 2 * np * nz + 4 * np + 2 * (size_t)layer_width(g) +
+                     (size_t)g.ndpe * g.ndpe;
+  return dbl * sizeof(double) + np * nz * sizeof(int) + 3 * (size_t)g.nb;
+}
+
+// NB = g.nb: the block size is a compile-time constant, so that the
+// register block, the thread grid and the LDS offsets are immediates
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void k_local_factor(StencilIn si, T* __restrict__ out,
+                                                          int* __restrict__ flag) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Geometry& g = si.g;
+  constexpr LfShape f = lf_pick_shape(NB);
+  constexpr int SR = f.SR, SC = f.SC, R = f.R, C = f.C, ld = f.ld, nb = NB;
+  static_assert(SR > 0, "block size too large for the local factorisation");
+  const int nblk = g.nblk, d = g.dim, bn = g.bn, nd = g.ndpe, nz = coupling_nz(g);
+  const TileShape tsh = tile_shape(nb);
+  double* Cp = reinterpret_cast<double*>(smem);   // C_p, then T, then A_bb [NR][ld]
+  double* Pv = Cp + (size_t)f.NR * ld;            // A_{b,p} rows, sparse [ld][nz]
+  double* Av = Pv + (size_t)ld * nz;              // A_bb rows, same pattern
+  double* pk = Av + (size_t)ld * nz;              // pivot row and column [parity][2][ld]
+  double* Es = pk + 4 * ld;
+  double* K0s = Es + 2 * layer_width(g);
+  int* Pc = reinterpret_cast<int*>(K0s + nd * nd);   // column of each sparse entry
+  uint8_t* fl = reinterpret_cast<uint8_t*>(Pc + ld * nz);
+  const int t = threadIdx.x;
+  const bool act = t < R * C;   // the rest duplicate thread 0 and write nothing
+  const int ti = act ? t / C : 0, tj = act ? t - (t / C) * C : 0;
+  const int j = blockIdx.x;
+  int jx, jy, jz;
+  sub_coords(g, j, jx, jy, jz);
+  for (int i = t; i < nd * nd; i += kThreads) K0s[i] = si.K0[i];
+  for (int i = t; i < f.NR * ld; i += kThreads) Cp[i] = 0.0;
+  for (int i = t; i < 4 * ld; i += kThreads) pk[i] = 0.0;
+  const int mid = nblk / 2;
+  const int nbot = si.twist ? nblk - 1 - mid : 0;
+  double* TS = si.twist ? si.twist + (size_t)j * ((size_t)nb * (nb + 1) / 2) : nullptr;
+  T* O = out + (size_t)j * nblk * tsh.tstride;
+  double s[SR][SC];
+
+  // owned entries to and from the dense LDS buffer
+  auto store_s = [&]() {
+    if (act)
+#pragma unroll
+      for (int a = 0; a < SR; ++a)
+#pragma unroll
+        for (int q = 0; q < SC; ++q) Cp[(ti + R * a) * ld + tj + C * q] = s[a][q];
+  };
+
+  // s = A_{cur,cur} - A_{cur,p} C_p A_{p,cur} (C_p in Cp) when withA, else
+  // the product alone; element layers cur - 1 and cur are staged
+  auto build = [&](int cur, int p, bool withA) {
+    // an opaque copy of the thread index keeps the compiler from hoisting
+    // the per-thread parts of the staging and sparse rows out of the block
+    // loop, where they would hold registers through the elimination
+    int tq = t;
+    asm volatile("" : "+v"(tq));
+    stage_layers<true>(si, jx, jy, jz, cur - 1, Es, fl, tq);
+    __syncthreads();
+    // sparse rows: row i couples to the nodes next to its node in a layer
+    // (padding rows and outside nodes: column 0, value 0)
+    for (int e = tq; e < ld * nz; e += kThreads) {
+      const int i = e / nz, slot = e - (e / nz) * nz;
+      const int node = i / d, c2 = slot % d, ns = slot / d;
+      const int x = node % bn + ns % 3 - 1;
+      const int y = (d == 3 ? node / bn : 0) + (d == 3 ? ns / 3 - 1 : 0);
+      const bool in = i < nb && x >= 0 && x < bn && y >= 0 && y < (d == 3 ? bn : 1);
+      const int k = in ? d * (x + bn * y) + c2 : 0;
+      double v = 0.0, w = 0.0;
+      if (in && !fl[nb + i]) {
+        if (p >= 0 && !fl[(p - cur + 1) * nb + k])
+          v = stencil_entry(g, cur * nb + i, p * nb + k, cur - 1, Es, K0s);
+        if (withA)   // supported DOFs: decoupled, unit diagonal
+          w = fl[nb + k] ? 0.0 : stencil_entry(g, cur * nb + i, cur * nb + k, cur - 1, Es, K0s);
+      } else if (in && withA && k == i) {
+        w = 1.0;
+      }
+      Pc[e] = k;
+      Pv[e] = v;
+      Av[e] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < SR; ++a)
+#pragma unroll
+      for (int q = 0; q < SC; ++q) s[a][q] = 0.0;
+    if (p >= 0) {
+      // T[k][c] = sum_l C_p[k][l] A_{cur,p}[c][l]
+#pragma unroll 1
+      for (int z = 0; z < nz; ++z) {
+        int l[SC];
+        double pv[SC];
+#pragma unroll
+        for (int q = 0; q < SC; ++q) {
+          l[q] = Pc[(tj + C * q) * nz + z];
+          pv[q] = Pv[(tj + C * q) * nz + z];
+        }
+#pragma unroll
+        for (int a = 0; a < SR; ++a)
+#pragma unroll
+          for (int q = 0; q < SC; ++q) s[a][q] += Cp[(ti + R * a) * ld + l[q]] * pv[q];
+      }
+      lds_barrier();
+      store_s();
+      lds_barrier();
+      // A_{cur,p} T
+#pragma unroll
+      for (int a = 0; a < SR; ++a)
+#pragma unroll
+        for (int q = 0; q < SC; ++q) s[a][q] = 0.0;
+#pragma unroll 1
+      for (int z = 0; z < nz; ++z)
+#pragma unroll
+        for (int a = 0; a < SR; ++a) {
+          const int r = ti + R * a;
+          const double* Tk = Cp + Pc[r * nz + z] * ld + tj;
+          const double pv = Pv[r * nz + z];
+#pragma unroll
+          for (int q = 0; q < SC; ++q) s[a][q] += pv * Tk[C * q];
+        }
+    }
+    if (withA) {
+      // A_{cur,cur} scattered into the cleared buffer (last read above)
+      lds_barrier();
+      for (int e = t; e < f.NR * ld; e += kThreads) Cp[e] = 0.0;
+      lds_barrier();
+      for (int e = t; e < nb * nz; e += kThreads) {
+        const double w = Av[e];   // the nonzeros sit at distinct (row, column) places
+        if (w != 0.0) Cp[(e / nz) * ld + Pc[e]] = w;
+      }
+      lds_barrier();
+#pragma unroll
+      for (int a = 0; a < SR; ++a)
+#pragma unroll
+        for (int q = 0; q < SC; ++q) s[a][q] = Cp[(ti + R * a) * ld + tj + C * q] - s[a][q];
+    }
+  };
+
+  // s <- s^-1 in place by Gauss-Jordan elimination
+  auto invert = [&]() {
+#pragma unroll 1
+    for (int k = 0; k < nb; ++k) {
+      double* rowk = pk + (k & 1) * 2 * ld;
+      double* colk = rowk + ld;
+      const int ka = k / R, kr = k - ka * R, kq = k / C, kc = k - kq * C;
+      if (act && ti == kr) {
+#pragma unroll
+        for (int a = 0; a < SR; ++a)
+          if (a == ka)
+#pragma unroll
+            for (int q = 0; q < SC; ++q) rowk[tj + C * q] = s[a][q];
+      }
+      if (act && tj == kc) {
+#pragma unroll
+        for (int q = 0; q < SC; ++q)
+          if (q == kq) {
+#pragma unroll
+            for (int a = 0; a < SR; ++a) {
+              colk[ti + R * a] = s[a][q];
+              s[a][q] = ti + R * a == k ? 1.0 : 0.0;
+            }
+          }
+        if (ti == kr) rowk[k] = 1.0;
+      }
+      lds_barrier();
+      double pv = colk[k];
+      if (!(pv > 0.0)) {
+        if (t == 0) flag[0] = 1;
+        pv = 1.0;
+      }
+      const double inv = 1.0 / pv;
+      double cr[SR], rc[SC];
+#pragma unroll
+      for (int a = 0; a < SR; ++a) {
+        const int r = ti + R * a;
+        cr[a] = r == k ? 1.0 - inv : colk[r] * inv;
+      }
+#pragma unroll
+      for (int q = 0; q < SC; ++q) rc[q] = rowk[tj + C * q];
+#pragma unroll
+      for (int a = 0; a < SR; ++a)
+#pragma unroll
+        for (int q = 0; q < SC; ++q) s[a][q] = fma(-cr[a], rc[q], s[a][q]);
+    }
+  };
+
+  for (int step = 0; step < nblk; ++step) {
+    const bool bot = step < nbot;
+    const int b = bot ? nblk - 1 - step : step - nbot;
+    const bool first = step == 0 || step == nbot;
+    __syncthreads();
+    build(b, first ? -1 : (bot ? b + 1 : b - 1), true);
+    if (!bot && nbot > 0 && b == mid) {
+      // the lower half's term for the middle block
+#pragma unroll
+      for (int a = 0; a < SR; ++a)
+#pragma unroll
+        for (int q = 0; q < SC; ++q) {
+          const int r = ti + R * a, c = tj + C * q;
+          if (r < nb && c < nb)
+            s[a][q] -= r >= c ? TS[(size_t)r * (r + 1) / 2 + c] : TS[(size_t)c * (c + 1) / 2 + r];
+        }
+    }
+    invert();
+    // C_b to LDS (the next block of the half reads it), then record b from
+    // there in record order: the lower 4 x 4 tiles, diagonal tiles in full
+    lds_barrier();
+    store_s();
+    lds_barrier();
+    T* Rb = O + (size_t)b * tsh.tstride;
+    constexpr int per = 16 / (int)sizeof(T);
+    for (int o = t; o < tsh.tstride; o += kThreads) {
+      const int gq = o / (tsh.nl * per), rem = o - gq * (tsh.nl * per);
+      const int tau = rem / per, e = gq * per + (rem - (rem / per) * per);
+      int I, J;
+      tile_rc(tau, I, J);
+      const int r = 4 * I + (e >> 2), c = 4 * J + (e & 3);
+      Rb[o] = (T)(r < nb && c < nb ? Cp[r * ld + c] : 0.0);
+    }
+    if (bot && step + 1 == nbot) {
+      // A_{mid,b} C_b A_{b,mid} (b = mid + 1) for the middle block
+      __syncthreads();
+      build(mid, b, false);
+      if (act)
+#pragma unroll
+        for (int a = 0; a < SR; ++a)
+#pragma unroll
+          for (int q = 0; q < SC; ++q) {
+            const int r = ti + R * a, c = tj + C * q;
+            if (r < nb && c <= r) TS[(size_t)r * (r + 1) / 2 + c] = s[a][q];
+          }
+    }
+  }
+}
+
 template <typename K>
 void set_lds(K kernel) {
   hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
@@ -544,6 +845,40 @@ void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* 
   hipLaunchKernelGGL(k_btri_factor<T>, dim3(nmat), dim3(kThreads), lds, st, A, out, sh, flag,
                      tiles ? 1 : 0, s);
 }
+
+template <typename T, int NB>
+void local_factor_as(const StencilIn& si, T* out, int* flag, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) { set_lds(&k_local_factor<T, NB>); attr = true; }
+  hipLaunchKernelGGL((k_local_factor<T, NB>), dim3(si.g.nsub), dim3(kThreads),
+                     local_factor_lds_bytes(si.g, lf_pick_shape(NB)), st, si, out, flag);
+}
+
+// block sizes with a compiled local factorisation: d (s + 1)^(d - 1) DOFs per
+// node layer of a subdomain of s cells a side, 2-d s = 4 ... 40, 3-d s = 1 ... 4
+#define TPCG_LF_SIZES(X) X(10) X(18) X(34) X(50) X(66) X(82) X(12) X(27) X(48) X(75)
+
+bool local_factor_fits(const Geometry& g) {
+  bool known = false;
+#define TPCG_LF_KNOWN(n) known = known || g.nb == n;
+  TPCG_LF_SIZES(TPCG_LF_KNOWN)
+#undef TPCG_LF_KNOWN
+  return known && local_factor_lds_bytes(g, lf_pick_shape(g.nb)) <= 160 * 1024;
+}
+
+template <typename T>
+void launch_local_factor(const StencilIn& si, T* out, int* flag, hipStream_t st) {
+  switch (si.g.nb) {
+#define TPCG_LF_CASE(n) \
+  case n: local_factor_as<T, n>(si, out, flag, st); break;
+    TPCG_LF_SIZES(TPCG_LF_CASE)
+#undef TPCG_LF_CASE
+    default: break;   // callers check local_factor_fits first
+  }
+}
+
+template void launch_local_factor<double>(const StencilIn&, double*, int*, hipStream_t);
+template void launch_local_factor<float>(const StencilIn&, float*, int*, hipStream_t);
 
 template void launch_factor<double>(const double*, double*, int, const BtriShape&, int*,
                                     hipStream_t, bool, const StencilIn*);

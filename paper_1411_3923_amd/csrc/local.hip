@@ -79,8 +79,6 @@ struct Vec16<float> {
   typedef float type __attribute__((ext_vector_type(4)));
 };
 
-__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
 __host__ __device__ inline int strip_width(const Geometry& g) {
   return g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1;
 }
