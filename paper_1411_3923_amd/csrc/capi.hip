@@ -239,7 +239,7 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
   e |= alloc(h->z, ns * (size_t)g.ndof);
   e |= alloc(h->p, ns * (size_t)g.ndof);
   e |= alloc(h->q, ns * (size_t)g.ndof);
-  e |= alloc(h->parts, (size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys);
+  e |= alloc(h->parts, kPartsElems);
   e |= alloc(h->istate, (size_t)kNumState * kMaxSys);
   e |= alloc(h->dflag, 4);
   if (e != TPCG_OK) {
@@ -262,9 +262,18 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
   std::vector<double> K0((size_t)g.ndpe * g.ndpe);
   element_stiffness(g.dim, prob->nu, K0.data());
   hipMemcpy(h->K0, K0.data(), sizeof(double) * K0.size(), hipMemcpyHostToDevice);
+  if (g.dim == 2) {
+    std::copy(K0.begin(), K0.end(), h->K0q4);
+    if (!q4_structured(h->K0q4)) {
+      fprintf(stderr, "tpcg_build_partition: Q4 element matrix without the square's structure\n");
+      release(h);
+      delete h;
+      return TPCG_EINVAL;
+    }
+  }
   hipMemcpy(h->fixed, fixed_mask, g.ndof, hipMemcpyHostToDevice);
   hipMemset(h->istate, 0, sizeof(int) * kNumState * kMaxSys);
-  hipMemset(h->parts, 0, sizeof(double) * ((size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys));
+  hipMemset(h->parts, 0, sizeof(double) * kPartsElems);
   if (check_hip(h, "tpcg_build_partition") != TPCG_OK) {
     fprintf(stderr, "%s\n", h->err.c_str());
     release(h);
@@ -375,7 +384,8 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   launch_gate(*h, nsys, g0, st);
   h->prof_n = 0;
   launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, -1, flexible, st);
-  launch_update_p(*h, nsys, g0, flexible, 1, st);
+  launch_beta(*h, nsys, g0, kPartRZ0, flexible, 1, st);
+  launch_update_p(*h, nsys, g0, 1, st);
   int it = 0;
   int chunk = 0;
   bool done = maxit == 0;
@@ -390,7 +400,8 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
       launch_update_xr(*h, u, nsys, gi, st);
       launch_gate(*h, nsys, gn, st);
       launch_precond(*h, h->r, h->z, nsys, gn, rz_next, it, flexible, st);
-      launch_update_p(*h, nsys, gn, flexible, 0, st);
+      launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
+      launch_update_p(*h, nsys, gn, 0, st);
     }
     const int slot = chunk & 1;
     Gate gp = make_gate(h, (it & 1) ? kPartRR1 : kPartRR0, it, maxit, tol2, 1);

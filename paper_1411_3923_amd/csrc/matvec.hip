@@ -6,6 +6,7 @@
 // element's nodal displacements. No atomics; each output is written once.
 // K0 lives in LDS; the SIMP modulus is evaluated in the kernel.
 #include <algorithm>
+#include <cmath>
 
 #include "tpcg_internal.h"
 
@@ -15,91 +16,151 @@ namespace {
 
 // Q4: the mesh is cut into tiles of kTX x kTY nodes. A workgroup stages the
 // tile's halo of P x (one node ring, rows contiguous in memory) and the moduli
-// of the tile's elements in LDS, then each thread forms two nodes' rows of
-// y = P K P x from LDS only, so x and rho are read from HBM about once.
-constexpr int kTX = 64, kTY = 8;
+// of the elements touching the tile in LDS; thread (tx, ty) then forms the
+// rows of y = P K P x for the kRN nodes of column tx, rows kRN ty ..
+// kRN ty + kRN - 1, sliding a 3 x 3 window of nodal values and a 2 x 2
+// window of moduli down the column.
+//
+// The unit-square bilinear element matrix has only eight distinct entries
+// (the square's reflections and its rotation by a right angle map each entry
+// to one of them): K0 = q[kQ4Map], q its first row. q is uniform over the
+// launch and passed by value, so K0 comes from scalar registers and the LDS
+// carries only the nodal values and moduli.
+constexpr int kTX = 64, kRN = 4, kTY = (kThreads / kTX) * kRN;
 constexpr int kHX = kTX + 2, kHY = kTY + 2;   // halo of nodes
 constexpr int kEX = kTX + 1, kEY = kTY + 1;   // elements touching the tile
+
+constexpr int kQ4Map[8][8] = {{0, 1, 2, 3, 4, 5, 6, 7}, {1, 0, 7, 6, 5, 4, 3, 2},
+                              {2, 7, 0, 5, 6, 3, 4, 1}, {3, 6, 5, 0, 7, 2, 1, 4},
+                              {4, 5, 6, 7, 0, 1, 2, 3}, {5, 4, 3, 2, 1, 0, 7, 6},
+                              {6, 3, 4, 1, 2, 7, 0, 5}, {7, 2, 1, 4, 3, 6, 5, 0}};
+
+struct Q4Row {
+  double q[8];
+};
 
 __host__ __device__ inline int q4_tiles(const Geometry& g) {
   return ((g.nnx + kTX - 1) / kTX) * ((g.nny + kTY - 1) / kTY);
 }
 
+// P3: penal == 3, the modulus without pow (whose code would otherwise hold
+// registers through the whole kernel)
+template <bool P3>
 __global__ __launch_bounds__(kThreads) void k_apply_q4(
     Geometry g, const double* __restrict__ rho, const double* __restrict__ x,
-    double* __restrict__ y, const uint8_t* __restrict__ fixed, const double* __restrict__ K0,
-    double E0, double Emin, double penal, double* __restrict__ parts, Gate gate) {
-  __shared__ double K0s[64];
+    double* __restrict__ y, const uint8_t* __restrict__ fixed, Q4Row K, double E0, double Emin,
+    double penal, double* __restrict__ parts, Gate gate) {
+  constexpr int kHN = (kHY * kHX + kThreads - 1) / kThreads;   // staged values per thread
+  constexpr int kEN = (kEY * kEX + kThreads - 1) / kThreads;
   __shared__ double2 xh[kHY * kHX];
   __shared__ double Eh[kEY * kEX];
   __shared__ double sh[4];
   const int sys = blockIdx.y;
   if (!gate_running(gate, sys)) return;
   const int t = threadIdx.x;
-  if (t < 64) K0s[t] = K0[t];
   const double* xs = x + (size_t)sys * g.ndof;
   double* ys = y + (size_t)sys * g.ndof;
   const double* rs = rho + (size_t)sys * g.nel;
   const uint16_t* fx2 = reinterpret_cast<const uint16_t*>(fixed);   // both flags of a node
   const int nnx = g.nnx, nny = g.nny;
   const int ntx = (nnx + kTX - 1) / kTX, ntiles = q4_tiles(g);
-  const int tx = t % kTX, ty = t / kTX;   // kThreads / kTX = 4 rows of threads
+  const int tx = t % kTX, ty = t / kTX;
   double acc = 0.0;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % ntx) * kTX, y0 = (tile / ntx) * kTY;
-    __syncthreads();   // the previous tile's LDS reads are done
-    for (int i = t; i < kHY * kHX; i += kThreads) {
+    // every load of the tile is issued before any is used
+    double2 hv[kHN];
+    uint16_t hf[kHN];
+    double rv[kEN];
+#pragma unroll
+    for (int q = 0; q < kHN; ++q) {
+      const int i = t + q * kThreads;
       const int X = x0 - 1 + i % kHX, Y = y0 - 1 + i / kHX;
-      double2 v = make_double2(0.0, 0.0);
-      if (X >= 0 && X < nnx && Y >= 0 && Y < nny) {
+      hv[q] = make_double2(0.0, 0.0);
+      hf[q] = 0xffffu;
+      if (i < kHY * kHX && X >= 0 && X < nnx && Y >= 0 && Y < nny) {
         const int64_t n = X + (int64_t)nnx * Y;
-        v = *reinterpret_cast<const double2*>(xs + 2 * n);
-        const uint16_t f = fx2[n];
-        if (f & 0x00ffu) v.x = 0.0;
-        if (f & 0xff00u) v.y = 0.0;
+        hv[q] = *reinterpret_cast<const double2*>(xs + 2 * n);
+        hf[q] = fx2[n];
       }
-      xh[i] = v;
     }
-    for (int i = t; i < kEY * kEX; i += kThreads) {
+#pragma unroll
+    for (int q = 0; q < kEN; ++q) {
+      const int i = t + q * kThreads;
       const int ex = x0 - 1 + i % kEX, ey = y0 - 1 + i / kEX;
-      double E = 0.0;
-      if (ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely)
-        E = simp_modulus(rs[ex + (int64_t)g.nelx * ey], E0, Emin, penal);
-      Eh[i] = E;
+      rv[q] = -1.0;   // outside the mesh
+      if (i < kEY * kEX && ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely)
+        rv[q] = rs[ex + (int64_t)g.nelx * ey];
+    }
+    __syncthreads();   // the previous tile's LDS reads are done
+#pragma unroll
+    for (int q = 0; q < kHN; ++q) {
+      const int i = t + q * kThreads;
+      double2 v = hv[q];
+      if (hf[q] & 0x00ffu) v.x = 0.0;
+      if (hf[q] & 0xff00u) v.y = 0.0;
+      if (i < kHY * kHX) xh[i] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < kEN; ++q) {
+      const int i = t + q * kThreads;
+      const double r = rv[q];
+      const double E = r < 0.0 ? 0.0
+                               : (P3 ? Emin + (E0 - Emin) * (r * r * r)
+                                     : simp_modulus(r, E0, Emin, penal));
+      if (i < kEY * kEX) Eh[i] = E;
     }
     __syncthreads();
+    // window rows: halo rows kRN ty + i .. + 2, element rows kRN ty + i .. + 1
+    double2 w[3][3];
+    double e[2][2];
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-      const int lx = tx, ly = ty + 4 * rr;              // tile-local node
-      const int X = x0 + lx, Y = y0 + ly;
-      if (X >= nnx || Y >= nny) continue;
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[r + 1][c] = xh[(kRN * ty + r) * kHX + tx + c];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) e[1][c] = Eh[kRN * ty * kEX + tx + c];
+#pragma unroll
+    for (int i = 0; i < kRN; ++i) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        w[0][c] = w[1][c];
+        w[1][c] = w[2][c];
+        w[2][c] = xh[(kRN * ty + i + 2) * kHX + tx + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        e[0][c] = e[1][c];
+        e[1][c] = Eh[(kRN * ty + i + 1) * kEX + tx + c];
+      }
       double y0v = 0.0, y1v = 0.0;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        // the node is corner a of element (ex, ey); corners counter-clockwise
+        // the node (window row 1, column 1) is corner a of the element whose
+        // corner 0 is window (1 - dy, 1 - dx); corners counter-clockwise
         const int dx = (a == 1) || (a == 2), dy = a >= 2;
-        const double E = Eh[(ly - dy + 1) * kEX + (lx - dx + 1)];
-        const int hx0 = lx - dx + 1, hy0 = ly - dy + 1;  // halo index of the element's corner 0
         double t0 = 0.0, t1 = 0.0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int bx = (b == 1) || (b == 2), by = b >= 2;
-          const double2 u = xh[(hy0 + by) * kHX + hx0 + bx];
-          t0 += K0s[(2 * a) * 8 + 2 * b] * u.x + K0s[(2 * a) * 8 + 2 * b + 1] * u.y;
-          t1 += K0s[(2 * a + 1) * 8 + 2 * b] * u.x + K0s[(2 * a + 1) * 8 + 2 * b + 1] * u.y;
+          const double2 u = w[1 - dy + by][1 - dx + bx];
+          t0 += K.q[kQ4Map[2 * a][2 * b]] * u.x + K.q[kQ4Map[2 * a][2 * b + 1]] * u.y;
+          t1 += K.q[kQ4Map[2 * a + 1][2 * b]] * u.x + K.q[kQ4Map[2 * a + 1][2 * b + 1]] * u.y;
         }
+        const double E = e[1 - dy][1 - dx];
         y0v += E * t0;
         y1v += E * t1;
       }
-      const int64_t n = X + (int64_t)nnx * Y;
-      const uint16_t f = fx2[n];
-      if (f & 0x00ffu) y0v = 0.0;
-      if (f & 0xff00u) y1v = 0.0;
-      *reinterpret_cast<double2*>(ys + 2 * n) = make_double2(y0v, y1v);
-      if (parts) {
-        const double2 xv = xh[(ly + 1) * kHX + lx + 1];   // already P x
-        acc += xv.x * y0v + xv.y * y1v;
+      const int X = x0 + tx, Y = y0 + kRN * ty + i;
+      if (X < nnx && Y < nny) {
+        const int64_t n = X + (int64_t)nnx * Y;
+        const uint16_t f = fx2[n];
+        if (f & 0x00ffu) y0v = 0.0;
+        if (f & 0xff00u) y1v = 0.0;
+        *reinterpret_cast<double2*>(ys + 2 * n) = make_double2(y0v, y1v);
+        if (parts) acc += w[1][1].x * y0v + w[1][1].y * y1v;   // w[1][1]: P x at the node
       }
+      __builtin_amdgcn_sched_barrier(0);   // one node at a time: fewer live registers
     }
   }
   if (parts) {
@@ -171,6 +232,15 @@ __global__ __launch_bounds__(kThreads) void k_apply_h8(
 
 }  // namespace
 
+bool q4_structured(const double* K0) {
+  double mx = 0.0;
+  for (int i = 0; i < 64; ++i) mx = std::max(mx, std::fabs(K0[i]));
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j)
+      if (std::fabs(K0[8 * i + j] - K0[kQ4Map[i][j]]) > 1e-14 * mx) return false;
+  return true;
+}
+
 int apply_parts(const Geometry& g) {
   if (g.dim == 2) return std::min(q4_tiles(g), kMaxParts);
   return parts_for(g.nnodes);
@@ -182,9 +252,16 @@ void launch_apply_K(const Handle& h, const double* rho, const double* x, double*
   dim3 grid(apply_parts(g), nsys);
   double* parts = dot_slot >= 0 ? part_slot(h.parts, dot_slot, 0) : nullptr;
   const tpcg_problem& pr = h.prob;
-  if (g.dim == 2)
-    hipLaunchKernelGGL(k_apply_q4, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, h.K0,
-                       pr.E0, pr.Emin, pr.penal, parts, gate);
+  if (g.dim == 2) {
+    Q4Row q;
+    std::copy(h.K0q4, h.K0q4 + 8, q.q);
+    if (pr.penal == 3.0)
+      hipLaunchKernelGGL(k_apply_q4<true>, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, q,
+                         pr.E0, pr.Emin, pr.penal, parts, gate);
+    else
+      hipLaunchKernelGGL(k_apply_q4<false>, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, q,
+                         pr.E0, pr.Emin, pr.penal, parts, gate);
+  }
   else
     hipLaunchKernelGGL(k_apply_h8, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, h.K0,
                        pr.E0, pr.Emin, pr.penal, parts, gate);

@@ -40,17 +40,29 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
   for (int q = 0; q < kMaxSys; ++q)
 #pragma unroll
     for (int m = 0; m < KM; ++m) acc[q][m] = 0.0;
-  for (int l = threadIdx.x; l < g.nloc; l += kSubThreads) {
-    const int64_t dof = box_dof(g, jx, jy, jz, l);
-    double rv[kMaxSys];
+  // kRU box DOFs per thread at a time, all their loads issued before use
+  // (one with the wide accumulators, which fill the registers)
+  constexpr int kRU = KM <= 8 ? 3 : 1;
+  for (int l0 = threadIdx.x; l0 < g.nloc; l0 += kRU * kSubThreads) {
+    double rv[kRU][kMaxSys];
 #pragma unroll
-    for (int q = 0; q < kMaxSys; ++q) rv[q] = ((run >> q) & 1u) ? r[q * g.ndof + dof] : 0.0;
+    for (int u = 0; u < kRU; ++u) {
+      const int l = l0 + u * kSubThreads;
+      const int64_t dof = l < g.nloc ? box_dof(g, jx, jy, jz, l) : 0;
+#pragma unroll
+      for (int q = 0; q < kMaxSys; ++q)
+        rv[u][q] = (l < g.nloc && ((run >> q) & 1u)) ? r[q * g.ndof + dof] : 0.0;
+    }
 #pragma unroll
     for (int m = 0; m < KM; ++m)
       if (m < k) {
-        const double p = (double)ph[(size_t)m * g.nloc + l];
 #pragma unroll
-        for (int q = 0; q < kMaxSys; ++q) acc[q][m] += p * rv[q];
+        for (int u = 0; u < kRU; ++u) {
+          const int l = l0 + u * kSubThreads;
+          const double p = l < g.nloc ? (double)ph[(size_t)m * g.nloc + l] : 0.0;
+#pragma unroll
+          for (int q = 0; q < kMaxSys; ++q) acc[q][m] += p * rv[u][q];
+        }
       }
   }
   const int w = threadIdx.x >> 6;
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(kAddChunk) void k_coarse_add(Geometry g, T* __restr
 // z(n) = P sum_{j owns n} zloc_j(n) for every running system, with the fused
 // partial sums of r.z (and r.z_old for the flexible beta). zloc already holds
 // the coarse part.
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_extend(
     Geometry g, const double* __restrict__ r, double* __restrict__ z, const T* __restrict__ zloc,
     const uint8_t* __restrict__ fixed, double* __restrict__ parts, int rz_slot, int flexible,
@@ -171,7 +183,8 @@ __global__ __launch_bounds__(kThreads) void k_extend(
   for (int sys = 0; sys < nsys; ++sys)
     if (gate_running(gate, sys)) run |= 1u << sys;
   if (!run) return;
-  const int d = g.dim, s = g.s;
+  constexpr int d = D;
+  const int s = g.s;
   const size_t zstride = (size_t)g.nsub * g.nloc;
   double arz[kMaxSys], arzo[kMaxSys];
 #pragma unroll
@@ -185,21 +198,30 @@ __global__ __launch_bounds__(kThreads) void k_extend(
     const int y0 = iy == 0 ? 0 : (iy - 1) / s, y1 = min(g.gy - 1, iy / s);
     int z0 = 0, z1 = 0;
     if (d == 3) { z0 = iz == 0 ? 0 : (iz - 1) / s; z1 = min(g.gz - 1, iz / s); }
+    // a node lies in at most two subdomains along each axis (overlap of one
+    // cell): all candidate loads are issued, predicated, before any is summed
     double acc[kMaxSys][3];
 #pragma unroll
     for (int q = 0; q < kMaxSys; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
-    for (int jz = z0; jz <= z1; ++jz)
-      for (int jy = y0; jy <= y1; ++jy)
-        for (int jx = x0; jx <= x1; ++jx) {
+#pragma unroll
+    for (int cz = 0; cz < D - 1; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          const int jx = x0 + cx, jy = y0 + cy, jz = z0 + cz;
+          if (jx > x1 || jy > y1 || jz > z1) continue;
           const int j = jx + g.gx * (jy + g.gy * jz);
           const int ln = (ix - s * jx) + g.bn * ((iy - s * jy) + g.bn * (iz - s * jz));
           const T* zj = zloc + (size_t)j * g.nloc + (size_t)d * ln;
 #pragma unroll
           for (int q = 0; q < kMaxSys; ++q)
             if ((run >> q) & 1u)
-              for (int c = 0; c < d; ++c) acc[q][c] += (double)zj[q * zstride + c];
+#pragma unroll
+              for (int c = 0; c < D; ++c) acc[q][c] += (double)zj[q * zstride + c];
         }
-    for (int c = 0; c < d; ++c) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
       const int64_t i = d * n + c;
       const bool f = fixed[i];
 #pragma unroll
@@ -285,8 +307,12 @@ void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& 
   else
     hipLaunchKernelGGL((k_coarse_add<T, T, kMaxK>), agrid, dim3(kAddChunk), 0, st, g, zl, pm,
                        h.xc, nsys, gate);
-  hipLaunchKernelGGL(k_extend<T>, dim3(parts_for(g.nnodes)), dim3(kThreads), 0, st, g, r, z, zl,
-                     h.fixed, h.parts, rz_slot, flexible, nsys, gate);
+  if (g.dim == 2)
+    hipLaunchKernelGGL((k_extend<T, 2>), dim3(parts_for(g.nnodes)), dim3(kThreads), 0, st, g, r, z,
+                       zl, h.fixed, h.parts, rz_slot, flexible, nsys, gate);
+  else
+    hipLaunchKernelGGL((k_extend<T, 3>), dim3(parts_for(g.nnodes)), dim3(kThreads), 0, st, g, r, z,
+                       zl, h.fixed, h.parts, rz_slot, flexible, nsys, gate);
 }
 
 }  // namespace

@@ -84,6 +84,7 @@ struct Handle {
   // problem data
   uint8_t* fixed = nullptr;          // [ndof]
   double* K0 = nullptr;              // [ndpe * ndpe]
+  double K0q4[64] = {};              // host copy of the Q4 element matrix (2-d)
 
   // preconditioner state
   int basis_ready = 0;
@@ -95,8 +96,8 @@ struct Handle {
   double* eres = nullptr;            // [nsub][msub] residual norms
   void* lfac = nullptr;              // tiled D_b [nsys][nsub][nblk][tstride], double or float
   void* emod = nullptr;              // moduli the local factors were built from [nsys][nel], same type
-  double* twist = nullptr;
-  double* emod64 = nullptr;          // FP64 moduli of one system (mixed precision), [nel]           // Schur terms of the lower halves, [nsub][nb (nb + 1) / 2]
+  double* twist = nullptr;           // Schur terms of the lower halves, [nsub][nb (nb + 1) / 2]
+  double* emod64 = nullptr;          // FP64 moduli of one system (mixed precision), [nel]
   double* cfac = nullptr;            // packed [nsys][nblkc][bstridec]
   double* cinv = nullptr;            // dense K_c^-1 [nsys][nt][nt] when nt <= kDenseCoarse
   double* build_ws = nullptr;        // work arrays of the preconditioner build
@@ -140,6 +141,18 @@ enum {
   kPartAux = 7,
   kNumPartSlots = 8
 };
+
+// Per-system scalars of the iteration, [kNumScal][kMaxSys] doubles after the
+// partial slots and the four summary values per system: beta of the latest
+// direction update and r.z of the latest preconditioned residual, each
+// reduced once (k_beta) instead of by every workgroup that needs it.
+enum { kScBeta = 0, kScRZ = 1, kNumScal = 2 };
+constexpr size_t kPartsElems = (size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys +
+                               (size_t)kNumScal * kMaxSys;
+
+__host__ __device__ inline double* scal_slot(double* parts, int which) {
+  return parts + (size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys + which * kMaxSys;
+}
 
 // Per-system integer state [kNumState][kMaxSys].
 enum { kStLastIt = 0, kStBreak = 1, kStPoll = 2, kStRun = 3, kNumState = 4 };
@@ -229,6 +242,9 @@ __host__ __device__ inline double* part_slot(double* parts, int slot, int sys) {
 // matvec.hip: y = P K(rho) P x; optional partials of x.y into slot `dot_slot` (-1: none),
 // apply_parts(g) of them per system
 int apply_parts(const Geometry& g);
+// whether a Q4 element matrix has the eight-value structure of the unit
+// square's element, which the Q4 product relies on
+bool q4_structured(const double* K0);
 void launch_apply_K(const Handle& h, const double* rho, const double* x, double* y, int nsys,
                     int dot_slot, const Gate& gate, hipStream_t st);
 
@@ -236,8 +252,12 @@ void launch_apply_K(const Handle& h, const double* rho, const double* x, double*
 void launch_residual_init(const Handle& h, const double* f, double* u, const double* q, int nsys,
                           hipStream_t st);
 void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hipStream_t st);
-void launch_update_p(const Handle& h, int nsys, const Gate& gate, int flexible, int first,
-                     hipStream_t st);
+// beta and r.z of the preconditioned residual whose r.z partials are in
+// rz_slot (first: beta = 0), into the scalar slots; flags a breakdown
+void launch_beta(const Handle& h, int nsys, const Gate& gate, int rz_slot, int flexible,
+                 int first, hipStream_t st);
+// p = z + beta p with the beta of launch_beta (first: p = z)
+void launch_update_p(const Handle& h, int nsys, const Gate& gate, int first, hipStream_t st);
 void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st);
 // residual test of gate.rr_slot into the kStRun flags
 void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st);

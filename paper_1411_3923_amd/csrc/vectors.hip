@@ -46,10 +46,10 @@ __global__ __launch_bounds__(kThreads) void k_residual_init(
   }
 }
 
-// Iteration `it`: alpha = (r.z)/(p.q) (np_pq partials of p.q from the
-// operator launch); u += alpha p; r -= alpha q; partials of
-// the new r.r into the other parity slot. Breakdown (p.q <= 0 or not finite)
-// stops the system.
+// Iteration `it`: alpha = (r.z)/(p.q) (r.z from the scalar slot, np_pq
+// partials of p.q from the operator launch); u += alpha p; r -= alpha q;
+// partials of the new r.r into the other parity slot. Breakdown (p.q <= 0
+// or not finite) stops the system.
 __global__ __launch_bounds__(kThreads) void k_update_xr(
     Geometry g, double* __restrict__ u, double* __restrict__ r, const double* __restrict__ p,
     const double* __restrict__ q, double* __restrict__ parts, int* __restrict__ istate,
@@ -58,12 +58,11 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(
   const int sys = blockIdx.y;
   const int slot_old = gate.rr_slot;
   const int slot_new = slot_old == kPartRR0 ? kPartRR1 : kPartRR0;
-  const int rz_slot = slot_old == kPartRR0 ? kPartRZ0 : kPartRZ1;
   bool run = gate_running(gate, sys);
   double alpha = 0.0;
   if (run) {
     const double pq = sum_parts(part_slot(parts, kPartPQ, sys), np_pq, sh);
-    const double rz = sum_parts(part_slot(parts, rz_slot, sys), gate.np, sh);
+    const double rz = scal_slot(parts, kScRZ)[sys];
     alpha = rz / pq;
     if (!(pq > 0.0) || !isfinite(alpha)) {
       run = false;
@@ -95,39 +94,49 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(
   }
 }
 
-// p = z + beta p after the preconditioner of iteration `it`; the gate refers
-// to the residual after that iteration's update. first != 0: p = z.
-// beta = (r.z_new)/(r.z_old), or the flexible (Polak-Ribiere) form
-// (r.z_new - r.z_prev)/(r.z_old) when the preconditioner is not exactly
-// symmetric (FP32 inner solves).
-__global__ __launch_bounds__(kThreads) void k_update_p(
-    Geometry g, double* __restrict__ p, const double* __restrict__ z,
-    double* __restrict__ parts, int* __restrict__ istate, Gate gate, int flexible, int first) {
+// One workgroup per system, after the preconditioner of iteration `it` (the
+// gate refers to the residual after that iteration's update): r.z_new from
+// its partials; beta = (r.z_new)/(r.z_old), or the flexible (Polak-Ribiere)
+// form (r.z_new - r.z_prev)/(r.z_old) when the preconditioner is not exactly
+// symmetric (FP32 inner solves); first: beta = 0. r.z_new replaces r.z_old.
+__global__ __launch_bounds__(kThreads) void k_beta(Gate gate, int rz_slot, int flexible, int first,
+                                                   int* __restrict__ istate) {
   __shared__ double sh[4];
-  const int sys = blockIdx.y;
+  const int sys = blockIdx.x;
   if (!gate_running(gate, sys)) return;
+  double* parts = const_cast<double*>(gate.parts);
+  const double rzn = sum_parts(part_slot(parts, rz_slot, sys), gate.np, sh);
   double beta = 0.0;
+  bool brk = false;
   if (!first) {
-    // the preconditioner of iteration it wrote r.z into the slot of parity it+1
-    const int new_slot = gate.rr_slot == kPartRR0 ? kPartRZ0 : kPartRZ1;
-    const int old_slot = new_slot == kPartRZ0 ? kPartRZ1 : kPartRZ0;
-    const double rzn = sum_parts(part_slot(parts, new_slot, sys), gate.np, sh);
-    const double rzo = sum_parts(part_slot(parts, old_slot, sys), gate.np, sh);
     double num = rzn;
     if (flexible) num -= sum_parts(part_slot(parts, kPartRZO, sys), gate.np, sh);
-    beta = num / rzo;
-    if (!(rzn > 0.0) || !isfinite(beta)) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) istate[kStBreak * kMaxSys + sys] = 1;
-      return;
-    }
+    beta = num / scal_slot(parts, kScRZ)[sys];
+    brk = !(rzn > 0.0) || !isfinite(beta);
   }
+  if (threadIdx.x == 0) {
+    if (brk) istate[kStBreak * kMaxSys + sys] = 1;
+    scal_slot(parts, kScBeta)[sys] = beta;
+    scal_slot(parts, kScRZ)[sys] = rzn;
+  }
+}
+
+// p = z + beta p (beta from k_beta; p = z on the first update, when beta = 0
+// and p may hold anything)
+__global__ __launch_bounds__(kThreads) void k_update_p(Geometry g, double* __restrict__ p,
+                                                       const double* __restrict__ z,
+                                                       const double* __restrict__ parts, Gate gate,
+                                                       int first) {
+  const int sys = blockIdx.y;
+  if (!gate_running(gate, sys)) return;
+  const double beta = scal_slot(const_cast<double*>(parts), kScBeta)[sys];
   const size_t off = (size_t)sys * g.ndof;
   const int64_t nv = g.nnodes * g.dim;
-  // DOF-contiguous sweep: the node partition of the other kernels is not
-  // needed here because nothing is reduced
+  // DOF-contiguous sweep: nothing is reduced, so the node partition of the
+  // other kernels is not needed
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
        i += (int64_t)gridDim.x * kThreads)
-    p[off + i] = z[off + i] + beta * p[off + i];
+    p[off + i] = first ? z[off + i] : z[off + i] + beta * p[off + i];
 }
 
 // the residual test of the gate, once per iteration: kStRun = r.r > tol2 ||Pf||^2
@@ -201,11 +210,16 @@ void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hi
                      h.istate, gate, apply_parts(h.g));
 }
 
-void launch_update_p(const Handle& h, int nsys, const Gate& gate, int flexible, int first,
-                     hipStream_t st) {
+void launch_beta(const Handle& h, int nsys, const Gate& gate, int rz_slot, int flexible,
+                 int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_beta, dim3(nsys), dim3(kThreads), 0, st, gate, rz_slot, flexible, first,
+                     h.istate);
+}
+
+void launch_update_p(const Handle& h, int nsys, const Gate& gate, int first, hipStream_t st) {
   dim3 grid(parts_for(h.g.nnodes), nsys);
-  hipLaunchKernelGGL(k_update_p, grid, dim3(kThreads), 0, st, h.g, h.p, h.z, h.parts, h.istate,
-                     gate, flexible, first);
+  hipLaunchKernelGGL(k_update_p, grid, dim3(kThreads), 0, st, h.g, h.p, h.z, h.parts, gate,
+                     first);
 }
 
 void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
