@@ -126,3 +126,16 @@ def test_quadrature_order_does_not_matter():
     # the integrand is at most quadratic per axis, so 2 Gauss points are exact
     np.testing.assert_allclose(fem.q4_K0(NU, npts=2), fem.q4_K0(NU, npts=5), atol=1e-14)
     np.testing.assert_allclose(fem.h8_K0(NU, npts=2), fem.h8_K0(NU, npts=4), atol=1e-14)
+
+
+@pytest.mark.parametrize("nu", [0.17, 0.3, 0.45])
+def test_q4_matrix_takes_eight_values_of_its_first_row(nu):
+    """The square's reflections and quarter turn map every entry of the
+    unit-square Q4 matrix onto an entry of its first row, whose eight entries
+    are distinct: the GPU product keeps only those eight values (in scalar
+    registers) and the library checks the index map on the host."""
+    K = fem.q4_K0(nu)
+    row = K[0]
+    assert len(np.unique(np.round(row, 14))) == 8
+    for v in K.ravel():
+        assert np.min(np.abs(row - v)) < 1e-14
