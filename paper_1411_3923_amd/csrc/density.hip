@@ -110,6 +110,9 @@ __global__ __launch_bounds__(kThreads) void k_filter_project_adjoint(
   }
 }
 
+// D = g.dim as a constant: the element vector is indexed statically and
+// stays in registers
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_sensitivity(Geometry g, const double* __restrict__ rho,
                                                          const double* __restrict__ u,
                                                          const uint8_t* __restrict__ fixed,
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_sensitivity(Geometry g, const doub
                                                          double* __restrict__ dc) {
   __shared__ double K0s[576];
   const int sys = blockIdx.y;
-  const int nd = g.ndpe, d = g.dim;
+  constexpr int d = D, nd = D == 3 ? 24 : 8;
   for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
   __syncthreads();
   const double* us = u + (size_t)sys * g.ndof;
@@ -130,20 +133,28 @@ __global__ __launch_bounds__(kThreads) void k_sensitivity(Geometry g, const doub
     const int64_t n0 = ex + (int64_t)g.nnx * (ey + (int64_t)g.nny * ez);
     const int64_t lay = (int64_t)g.nnx * g.nny;
     int64_t nodes[8] = {n0, n0 + 1, n0 + 1 + g.nnx, n0 + g.nnx, 0, 0, 0, 0};
-    const int na = d == 3 ? 8 : 4;
-    if (d == 3)
+    constexpr int na = D == 3 ? 8 : 4;
+    if (D == 3)
+#pragma unroll
       for (int a = 0; a < 4; ++a) nodes[4 + a] = nodes[a] + lay;
-    double ue[24];
+    double ue[nd];
+#pragma unroll
     for (int a = 0; a < na; ++a)
+#pragma unroll
       for (int c = 0; c < d; ++c) {
         const int64_t dof = d * nodes[a] + c;
         ue[d * a + c] = fixed[dof] ? 0.0 : us[dof];
       }
     double q = 0.0;
+#pragma unroll 1
     for (int a = 0; a < nd; ++a) {
-      double t = 0.0;
-      for (int b = 0; b < nd; ++b) t += K0s[a * nd + b] * ue[b];
-      q += ue[a] * t;
+      double t = 0.0, ua = 0.0;
+#pragma unroll
+      for (int b = 0; b < nd; ++b) {
+        t += K0s[a * nd + b] * ue[b];
+        ua = b == a ? ue[b] : ua;   // ue[a] without a dynamic register index
+      }
+      q += ua * t;
     }
     const double r = rs[e];
     const double rp1 = penal == 3.0 ? r * r : pow(r, penal - 1.0);
@@ -209,8 +220,12 @@ void launch_compliance_sens(const Handle& h, const double* rho, const double* u,
   hipLaunchKernelGGL(k_fu_final, dim3(nsys), dim3(kThreads), 0, st, h.parts, np, c);
   if (dc) {
     const tpcg_problem& pr = h.prob;
-    hipLaunchKernelGGL(k_sensitivity, dim3(elem_blocks(h.g.nel), nsys), dim3(kThreads), 0, st,
-                       h.g, rho, u, h.fixed, h.K0, pr.E0, pr.Emin, pr.penal, dc);
+    if (h.g.dim == 2)
+      hipLaunchKernelGGL(k_sensitivity<2>, dim3(elem_blocks(h.g.nel), nsys), dim3(kThreads), 0, st,
+                         h.g, rho, u, h.fixed, h.K0, pr.E0, pr.Emin, pr.penal, dc);
+    else
+      hipLaunchKernelGGL(k_sensitivity<3>, dim3(elem_blocks(h.g.nel), nsys), dim3(kThreads), 0, st,
+                         h.g, rho, u, h.fixed, h.K0, pr.E0, pr.Emin, pr.penal, dc);
   }
 }
 

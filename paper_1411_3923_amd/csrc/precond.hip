@@ -14,7 +14,7 @@ namespace tpcg {
 
 namespace {
 
-constexpr int kSubThreads = 1024;   // restriction: one 16-wave workgroup per subdomain
+constexpr int kSubThreads = 256;    // restriction: one workgroup per subdomain
 constexpr int kAddChunk = 256;      // coarse addition: box DOFs per workgroup
 
 // One workgroup per subdomain, all running systems together (Phi, mode-major,

@@ -183,6 +183,9 @@ __global__ __launch_bounds__(kThreads) void k_eig_orth(Geometry g, double* __res
 }
 
 // Y = (L L^T)^-1 X for every subdomain, m right-hand sides (FP64).
+// D = g.dim as a constant, so that the accumulators are indexed statically
+// and stay in registers
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_neumann_apply(Geometry g, const double* __restrict__ rho,
                                                            const double* __restrict__ K0,
                                                            const double* __restrict__ dis,
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_neumann_apply(Geometry g, const do
   __shared__ double K0s[576];
   const int j = blockIdx.x;
   const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
-  const int d = g.dim, nd = g.ndpe;
+  constexpr int d = D, nd = D == 3 ? 24 : 8;
   for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
   __syncthreads();
   const double* dj = dis + (size_t)j * g.nloc;
@@ -200,10 +203,12 @@ __global__ __launch_bounds__(kThreads) void k_neumann_apply(Geometry g, const do
   double* Yj = Y + (size_t)j * g.nloc * m;
   for (int ln = threadIdx.x; ln < g.nbox; ln += kThreads) {
     const int lx = ln % g.bn, ly = (ln / g.bn) % g.bn, lz = ln / (g.bn * g.bn);
-    double acc[3][kMaxSub];
-    for (int c = 0; c < 3; ++c)
+    double acc[D][kMaxSub];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
       for (int r = 0; r < kMaxSub; ++r) acc[c][r] = 0.0;
-    const int na = d == 3 ? 8 : 4;
+    constexpr int na = D == 3 ? 8 : 4;
     for (int a = 0; a < na; ++a) {
       const int dx = (a & 3) == 1 || (a & 3) == 2, dy = (a & 3) >= 2, dz = a >= 4;
       const int ex = lx - dx, ey = ly - dy, ez = lz - dz;   // cell-local element
@@ -220,17 +225,25 @@ __global__ __launch_bounds__(kThreads) void k_neumann_apply(Geometry g, const do
           const int l2 = d * lb + cc;
           const double s2 = dj[l2];
           if (s2 == 0.0) continue;
-          for (int c = 0; c < d; ++c) {
+          double xv[kMaxSub];
+#pragma unroll
+          for (int r = 0; r < kMaxSub; ++r) xv[r] = r < m ? Xj[(size_t)l2 * m + r] : 0.0;
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
             const double kv = E * K0s[(d * a + c) * nd + d * bnode + cc] * s2;
-            for (int r = 0; r < m; ++r) acc[c][r] += kv * Xj[(size_t)l2 * m + r];
+#pragma unroll
+            for (int r = 0; r < kMaxSub; ++r) acc[c][r] += kv * xv[r];
           }
         }
       }
     }
-    for (int c = 0; c < d; ++c) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
       const int l = d * ln + c;
       const double s1 = dj[l];
-      for (int r = 0; r < m; ++r) Yj[(size_t)l * m + r] = s1 * acc[c][r];
+#pragma unroll
+      for (int r = 0; r < kMaxSub; ++r)
+        if (r < m) Yj[(size_t)l * m + r] = s1 * acc[c][r];
     }
   }
 }
@@ -359,6 +372,7 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
 
 // W[j][en][c][m] = (K Phi_j) at the node en of the cell grown by one node
 // layer (zero outside the mesh).
+template <int D, int KM>
 __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double* __restrict__ rho,
                                                       const double* __restrict__ K0,
                                                       const uint8_t* __restrict__ fixed,
@@ -367,7 +381,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
   __shared__ double K0s[576];
   const int j = blockIdx.x;
   const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
-  const int d = g.dim, nd = g.ndpe, k = g.k;
+  constexpr int d = D, nd = D == 3 ? 24 : 8;
+  const int k = g.k;
   for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
   __syncthreads();
   const double* ph = phi + (size_t)j * g.nloc * k;
@@ -377,12 +392,14 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
     const int ex_ = en % e, ey_ = (en / e) % e, ez_ = en / (e * e);
     const int nx = g.s * jx - 1 + ex_, ny = g.s * jy - 1 + ey_;
     const int nz = d == 3 ? g.s * jz - 1 + ez_ : 0;
-    double acc[3][kMaxK];
-    for (int c = 0; c < 3; ++c)
-      for (int mm = 0; mm < kMaxK; ++mm) acc[c][mm] = 0.0;
+    double acc[D][KM];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+      for (int mm = 0; mm < KM; ++mm) acc[c][mm] = 0.0;
     const bool in_mesh = nx >= 0 && nx < g.nnx && ny >= 0 && ny < g.nny && nz >= 0 && nz < g.nnz;
     if (in_mesh) {
-      const int na = d == 3 ? 8 : 4;
+      constexpr int na = D == 3 ? 8 : 4;
       for (int a = 0; a < na; ++a) {
         const int dx = (a & 3) == 1 || (a & 3) == 2, dy = (a & 3) >= 2, dz = a >= 4;
         const int elx = nx - dx, ely = ny - dy, elz = nz - dz;
@@ -399,18 +416,25 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
           const int lb = lx + g.bn * (ly + g.bn * lz);
           for (int cc = 0; cc < d; ++cc) {
             const double* pv = ph + ((size_t)d * lb + cc) * k;
-            for (int c = 0; c < d; ++c) {
+            double pvv[KM];
+#pragma unroll
+            for (int mm = 0; mm < KM; ++mm) pvv[mm] = mm < k ? pv[mm] : 0.0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
               const double kv = E * K0s[(d * a + c) * nd + d * bnode + cc];
-              for (int mm = 0; mm < k; ++mm) acc[c][mm] += kv * pv[mm];
+#pragma unroll
+              for (int mm = 0; mm < KM; ++mm) acc[c][mm] += kv * pvv[mm];
             }
           }
         }
       }
     }
-    for (int c = 0; c < d; ++c) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
       const bool fx = in_mesh && fixed[(int64_t)d * (nx + (int64_t)g.nnx * (ny + (int64_t)g.nny * nz)) + c];
-      for (int mm = 0; mm < k; ++mm)
-        Wj[((size_t)en * d + c) * k + mm] = (in_mesh && !fx) ? acc[c][mm] : 0.0;
+#pragma unroll
+      for (int mm = 0; mm < KM; ++mm)
+        if (mm < k) Wj[((size_t)en * d + c) * k + mm] = (in_mesh && !fx) ? acc[c][mm] : 0.0;
     }
   }
 }
@@ -557,8 +581,12 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, Y, dis, m);
     std::swap(X, Y);
   }
-  hipLaunchKernelGGL(k_neumann_apply, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis, X,
-                     Y, m, mp);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_neumann_apply<2>, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis,
+                       X, Y, m, mp);
+  else
+    hipLaunchKernelGGL(k_neumann_apply<3>, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis,
+                       X, Y, m, mp);
   hipLaunchKernelGGL(k_eig_rr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, Y, dis, m, h.lam,
                      h.eres, h.phi);
   if (h.mixed)
@@ -575,8 +603,18 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const int nnb = g.dim == 3 ? 27 : 9;
   for (int sys = 0; sys < nsys; ++sys) {
     const double* rs = rho + (size_t)sys * g.nel;
-    hipLaunchKernelGGL(k_coarse_W, dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0, h.fixed,
-                       h.phi, W, mp);
+    if (g.dim == 2 && g.k <= 8)
+      hipLaunchKernelGGL((k_coarse_W<2, 8>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
+                         h.fixed, h.phi, W, mp);
+    else if (g.dim == 2)
+      hipLaunchKernelGGL((k_coarse_W<2, kMaxK>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
+                         h.fixed, h.phi, W, mp);
+    else if (g.k <= 8)
+      hipLaunchKernelGGL((k_coarse_W<3, 8>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
+                         h.fixed, h.phi, W, mp);
+    else
+      hipLaunchKernelGGL((k_coarse_W<3, kMaxK>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
+                         h.fixed, h.phi, W, mp);
     hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi, W,
                        Ac + sys * asm_coarse);
   }
