@@ -60,6 +60,30 @@ __global__ __launch_bounds__(kThreads) void k_eig_init(Geometry g, double* __res
 // working accuracy. Supported DOFs are zeroed first.
 typedef double dv4 __attribute__((ext_vector_type(4)));
 
+// part[w] = this wave's share of A^T B (16 x 16 tile, row-major, m <= 16
+// columns, rows of A and B with stride m): wave w takes the 4-row chunks
+// 4 (w + 4 i); eight chunks are loaded before their products are formed.
+// Sum part[0..3] for the product.
+__device__ void gram_waves(const double* __restrict__ A, const double* __restrict__ B, int n,
+                           int m, double (*part)[256]) {
+  constexpr int kU = 8;
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63, li = l & 15, lq = l >> 4;
+  dv4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 4 * wv; k0 < n; k0 += 16 * kU) {
+    double va[kU], vb[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int row = k0 + 16 * u + lq;
+      const bool in = row < n && li < m;
+      va[u] = in ? A[(size_t)row * m + li] : 0.0;
+      vb[u] = in ? B[(size_t)row * m + li] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], vb[u], acc, 0, 0, 0);
+  }
+  for (int q = 0; q < 4; ++q) part[wv][(4 * q + lq) * 16 + li] = acc[q];
+}
+
 __global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __restrict__ X,
                                                         const double* __restrict__ dis, int m) {
   __shared__ double part[4][256];
@@ -69,20 +93,13 @@ __global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __r
   const int j = blockIdx.x;
   double* Xj = X + (size_t)j * g.nloc * m;
   const double* dj = dis + (size_t)j * g.nloc;
-  const int t = threadIdx.x, wv = t >> 6, l = t & 63, li = l & 15, lq = l >> 4;
+  const int t = threadIdx.x;
   for (int r = t; r < g.nloc; r += kThreads)
     if (dj[r] == 0.0)
       for (int c = 0; c < m; ++c) Xj[(size_t)r * m + c] = 0.0;
   __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
-    // G = X^T X: wave wv takes the 4-row chunks k = 4 (wv + 4 i)
-    dv4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k = 4 * wv; k < g.nloc; k += 16) {
-      const int row = k + lq;
-      const double v = (row < g.nloc && li < m) ? Xj[(size_t)row * m + li] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
-    }
-    for (int q = 0; q < 4; ++q) part[wv][(4 * q + lq) * 16 + li] = acc[q];
+    gram_waves(Xj, Xj, g.nloc, m, part);   // G = X^T X
     __syncthreads();
     if (t == 0) {
       double tr = 0.0;
@@ -118,6 +135,9 @@ __global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __r
     __syncthreads();
     // X <- X R^-1 row by row
     for (int r = t; r < g.nloc; r += kThreads) {
+      int oz = 0;   // opaque: R is read per row, not held in registers
+      asm volatile("" : "+v"(oz));
+      const double* Rv = R + oz;
       double x[kMaxSub];
 #pragma unroll
       for (int c = 0; c < kMaxSub; ++c) x[c] = c < m ? Xj[(size_t)r * m + c] : 0.0;
@@ -126,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __r
         if (b < m) {
           double v = 0.0;
 #pragma unroll
-          for (int a = 0; a <= b; ++a) v += x[a] * R[a * 16 + b];
+          for (int a = 0; a <= b; ++a) v += x[a] * Rv[a * 16 + b];
           Xj[(size_t)r * m + b] = v;
         }
       }
@@ -262,69 +282,72 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
                                                     double* __restrict__ eres,
                                                     double* __restrict__ phi) {
   __shared__ double sh[4];
+  __shared__ double part[4][256];
   __shared__ double H[kMaxSub * kMaxSub];
   __shared__ double Qm[kMaxSub * kMaxSub];
+  __shared__ double Qo[kMaxSub * kMaxSub];   // Ritz vectors in ascending order, zero-padded
   __shared__ double th[kMaxSub];
   __shared__ int ord[kMaxSub];
+  __shared__ int done;
+  const int t = threadIdx.x;
   const int j = blockIdx.x;
   const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
   const double* Xj = X + (size_t)j * g.nloc * m;
   const double* Sj = SX + (size_t)j * g.nloc * m;
-  for (int a = 0; a < m; ++a) {
-    double acc[kMaxSub];
-    for (int r = 0; r < kMaxSub; ++r) acc[r] = 0.0;
-    for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
-      const double xa = Xj[(size_t)l * m + a];
-      for (int r = 0; r < m; ++r) acc[r] += xa * Sj[(size_t)l * m + r];
-    }
-    for (int r = 0; r < m; ++r) {
-      const double v = block_sum(acc[r], sh);
-      if (threadIdx.x == 0) H[a * kMaxSub + r] = v;
-    }
+  gram_waves(Xj, Sj, g.nloc, m, part);   // H = X^T S X
+  __syncthreads();
+  if (t < kMaxSub * kMaxSub) {
+    const int a = t >> 4, b = t & 15;
+    const double h = a < m && b < m ? (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]) : 0.0;
+    const double ht = a < m && b < m ? (part[0][b * 16 + a] + part[1][b * 16 + a]) +
+                                           (part[2][b * 16 + a] + part[3][b * 16 + a])
+                                     : 0.0;
+    H[t] = 0.5 * (h + ht);   // symmetrised
+    Qm[t] = a == b ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // symmetrise, then cyclic Jacobi
-    for (int a = 0; a < m; ++a)
-      for (int b = a + 1; b < m; ++b) {
-        const double v = 0.5 * (H[a * kMaxSub + b] + H[b * kMaxSub + a]);
-        H[a * kMaxSub + b] = H[b * kMaxSub + a] = v;
-      }
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) Qm[a * kMaxSub + b] = a == b ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 30; ++sweep) {
+  // cyclic Jacobi: for each pair (p, q) every thread forms the rotation, and
+  // thread r < m applies it to entry r of columns p, q of H and Q, then to
+  // entry r of rows p, q of H
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (t == 0) {
       double off = 0.0, dia = 0.0;
       for (int a = 0; a < m; ++a)
         for (int b = 0; b < m; ++b) {
           const double v = H[a * kMaxSub + b];
           if (a == b) dia += v * v; else off += v * v;
         }
-      if (off <= 1e-30 * dia) break;
-      for (int p = 0; p < m; ++p)
-        for (int qq = p + 1; qq < m; ++qq) {
-          const double apq = H[p * kMaxSub + qq];
-          if (apq == 0.0) continue;
-          const double app = H[p * kMaxSub + p], aqq = H[qq * kMaxSub + qq];
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          const double c = 1.0 / sqrt(1.0 + tt * tt), s = tt * c;
-          for (int r = 0; r < m; ++r) {
-            const double hp = H[r * kMaxSub + p], hq = H[r * kMaxSub + qq];
-            H[r * kMaxSub + p] = c * hp - s * hq;
-            H[r * kMaxSub + qq] = s * hp + c * hq;
-          }
-          for (int r = 0; r < m; ++r) {
-            const double hp = H[p * kMaxSub + r], hq = H[qq * kMaxSub + r];
-            H[p * kMaxSub + r] = c * hp - s * hq;
-            H[qq * kMaxSub + r] = s * hp + c * hq;
-          }
-          for (int r = 0; r < m; ++r) {
-            const double qp = Qm[r * kMaxSub + p], qv = Qm[r * kMaxSub + qq];
-            Qm[r * kMaxSub + p] = c * qp - s * qv;
-            Qm[r * kMaxSub + qq] = s * qp + c * qv;
-          }
-        }
+      done = off <= 1e-30 * dia;
     }
+    __syncthreads();
+    if (done) break;
+    for (int p = 0; p < m; ++p)
+      for (int qq = p + 1; qq < m; ++qq) {
+        const double apq = H[p * kMaxSub + qq];
+        const double app = H[p * kMaxSub + p], aqq = H[qq * kMaxSub + qq];
+        __syncthreads();   // every thread has read the pivot entries
+        if (apq == 0.0) continue;
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + tt * tt), sn = tt * c;
+        if (t < m) {
+          const double hp = H[t * kMaxSub + p], hq = H[t * kMaxSub + qq];
+          H[t * kMaxSub + p] = c * hp - sn * hq;
+          H[t * kMaxSub + qq] = sn * hp + c * hq;
+          const double qp = Qm[t * kMaxSub + p], qv = Qm[t * kMaxSub + qq];
+          Qm[t * kMaxSub + p] = c * qp - sn * qv;
+          Qm[t * kMaxSub + qq] = sn * qp + c * qv;
+        }
+        __syncthreads();
+        if (t < m) {
+          const double hp = H[p * kMaxSub + t], hq = H[qq * kMaxSub + t];
+          H[p * kMaxSub + t] = c * hp - sn * hq;
+          H[qq * kMaxSub + t] = sn * hp + c * hq;
+        }
+        __syncthreads();
+      }
+  }
+  if (t == 0) {
     for (int a = 0; a < m; ++a) { th[a] = H[a * kMaxSub + a]; ord[a] = a; }
     for (int a = 1; a < m; ++a) {          // insertion sort, ascending
       const int o = ord[a];
@@ -334,32 +357,54 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
     }
   }
   __syncthreads();
+  if (t < kMaxSub * kMaxSub) {
+    const int r = t >> 4, i = t & 15;
+    Qo[t] = r < m && i < m ? Qm[r * kMaxSub + ord[i]] : 0.0;
+  }
+  __syncthreads();
   // residuals and the basis
   double racc[kMaxSub];
-  for (int r = 0; r < kMaxSub; ++r) racc[r] = 0.0;
+#pragma unroll
+  for (int i = 0; i < kMaxSub; ++i) racc[i] = 0.0;
   const int k = g.k;
-  for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
+  for (int l = t; l < g.nloc; l += kThreads) {
+    // an opaque offset keeps the compiler from hoisting all of Qo out of the
+    // loop into registers
+    int oz = 0;
+    asm volatile("" : "+v"(oz));
+    const double* Qv = Qo + oz;
+    double xr[kMaxSub], sr[kMaxSub];
+#pragma unroll
+    for (int r = 0; r < kMaxSub; ++r) {
+      xr[r] = r < m ? Xj[(size_t)l * m + r] : 0.0;
+      sr[r] = r < m ? Sj[(size_t)l * m + r] : 0.0;
+    }
     const double sd = dis[(size_t)j * g.nloc + l];
     const int ln = l / g.dim;
     const int lx = ln % g.bn, ly = (ln / g.bn) % g.bn, lz = ln / (g.bn * g.bn);
     int mult = axis_mult(g.s * jx + lx, g.s, g.nelx) * axis_mult(g.s * jy + ly, g.s, g.nely);
     if (g.dim == 3) mult *= axis_mult(g.s * jz + lz, g.s, g.nelz);
     const double chi = 1.0 / mult;
+#pragma unroll 1
     for (int i = 0; i < m; ++i) {
-      const int o = ord[i];
       double xv = 0.0, sv = 0.0;
-      for (int r = 0; r < m; ++r) {
-        xv += Xj[(size_t)l * m + r] * Qm[r * kMaxSub + o];
-        sv += Sj[(size_t)l * m + r] * Qm[r * kMaxSub + o];
+#pragma unroll
+      for (int r = 0; r < kMaxSub; ++r) {
+        const double qv = Qv[r * kMaxSub + i];
+        xv += xr[r] * qv;
+        sv += sr[r] * qv;
       }
-      const double res = sv - th[o] * xv;
-      racc[i] += res * res;
+      const double res = sv - th[ord[i]] * xv;
+#pragma unroll
+      for (int ii = 0; ii < kMaxSub; ++ii) racc[ii] += ii == i ? res * res : 0.0;
       if (i < k) phi[((size_t)j * g.nloc + l) * k + i] = chi * sd * xv;
     }
   }
-  for (int i = 0; i < m; ++i) {
+#pragma unroll
+  for (int i = 0; i < kMaxSub; ++i) {
+    if (i >= m) break;
     const double v = block_sum(racc[i], sh);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       lam[(size_t)j * m + i] = th[ord[i]];
       eres[(size_t)j * m + i] = sqrt(v);
     }
