@@ -144,7 +144,7 @@ struct StencilIn {
   int neumann;
   double* dis;
   double* twist;
-  const double* emod;   // moduli of the system's elements, precomputed (launch_local_factor)
+  const double* emod;   // element moduli, precomputed: [nsys][nel] (launch_local_factor)
 };
 
 // factor.hip
@@ -155,12 +155,15 @@ template <typename T>
 void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* flag,
                    hipStream_t st, bool tiles = false, const StencilIn* si = nullptr);
 // Tiled records of C_b of the twisted factorisation of each subdomain's
-// Dirichlet matrix (moduli from si.emod, si.twist optional), one workgroup
-// per subdomain, via the Schur complements (no Cholesky factor).
-// local_factor_fits tells whether it takes geometry g (block size and LDS).
+// Dirichlet matrix, one workgroup per (subdomain, system), via the Schur
+// complements (no Cholesky factor): moduli of system s at si.emod + s nel,
+// its records at out + s ostride, scratch si.twist [nsys][nsub][nb (nb+1)/2]
+// (optional). local_factor_fits tells whether it takes geometry g (block
+// size and LDS).
 bool local_factor_fits(const Geometry& g);
 template <typename T>
-void launch_local_factor(const StencilIn& si, T* out, int* flag, hipStream_t st);
+void launch_local_factor(const StencilIn& si, T* out, int* flag, int nsys, size_t ostride,
+                         hipStream_t st);
 void launch_solve_multi(const double* fac, const BtriShape& sh, int nmat, int m, const double* X,
                         double* Y, hipStream_t st);
 // dense symmetric inverse [nmat][n][n] of packed factors (n = nb * nblk)

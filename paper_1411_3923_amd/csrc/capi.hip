@@ -120,8 +120,8 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += (sizeof(double) + ts) * (size_t)g.nsub * g.nloc * g.k;
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
   p += ts * nsys * (trec + (size_t)g.nel);
-  p += sizeof(double) * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
-  if (mixed) p += sizeof(double) * (size_t)g.nel;
+  p += sizeof(double) * nsys * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
+  if (mixed) p += sizeof(double) * nsys * (size_t)g.nel;
   p += sizeof(double) * nsys * crec;
   if (g.nt <= kDenseCoarse) p += sizeof(double) * nsys * (size_t)g.nt * g.nt;
   p += 4 * sizeof(double) * nsys * g.ndof;
@@ -322,8 +322,8 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     unsigned char* em = nullptr;
     e |= alloc(em, ts * ns * (size_t)g.nel);
     h->emod = em;
-    e |= alloc(h->twist, (size_t)g.nsub * g.nb * (g.nb + 1) / 2);
-    if (h->mixed) e |= alloc(h->emod64, (size_t)g.nel);
+    e |= alloc(h->twist, (size_t)ns * g.nsub * g.nb * (g.nb + 1) / 2);
+    if (h->mixed) e |= alloc(h->emod64, (size_t)ns * g.nel);
     e |= alloc(h->cfac, ns * cfsz);
     if (g.nt <= kDenseCoarse) e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
     unsigned char* zl = nullptr;

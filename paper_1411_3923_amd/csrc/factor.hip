@@ -93,10 +93,11 @@ __device__ inline BoxNode box_node(const Geometry& g, int l) {
 // and L + 1; -1 and nblk - 1 are outside the box) into Es, zero outside the
 // mesh and, for the Neumann matrices, outside the cell; the support flags of
 // node layers L0, L0 + 1, L0 + 2 into fl. PRE: the moduli are read from
-// si.emod instead of being formed from the densities.
+// em (the system's block of si.emod) instead of being formed from the
+// densities.
 template <bool PRE = false>
 __device__ void stage_layers(const StencilIn& si, int jx, int jy, int jz, int L0, double* Es,
-                             uint8_t* fl, int tid = threadIdx.x) {
+                             uint8_t* fl, int tid = threadIdx.x, const double* em = nullptr) {
   const Geometry& g = si.g;
   const int d = g.dim, ew = layer_width(g), s = g.s;
   for (int i = tid; i < 3 * g.nb; i += kThreads) {
@@ -115,7 +116,7 @@ __device__ void stage_layers(const StencilIn& si, int jx, int jy, int jz, int L0
            (d == 2 || (ez >= s * jz && ez < s * jz + s));
     const int64_t el = ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez);
     if (PRE)
-      Es[i] = in ? si.emod[el] : 0.0;
+      Es[i] = in ? em[el] : 0.0;
     else
       Es[i] = in ? simp_modulus(si.rho[el], si.E0, si.Emin, si.penal) : 0.0;
   }
@@ -597,8 +598,8 @@ __host__ __device__ inline size_t local_factor_lds_bytes(const Geometry& g, cons
 // NB = g.nb: the block size is a compile-time constant, so that the
 // register block, the thread grid and the LDS offsets are immediates
 template <typename T, int NB>
-__global__ __launch_bounds__(kThreads) void k_local_factor(StencilIn si, T* __restrict__ out,
-                                                          int* __restrict__ flag) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NB <= 66 ? 3 : 2))) void k_local_factor(StencilIn si, T* __restrict__ out,
+                                                          int* __restrict__ flag, size_t ostride) {
   extern __shared__ __align__(16) unsigned char smem[];
   const Geometry& g = si.g;
   constexpr LfShape f = lf_pick_shape(NB);
@@ -617,7 +618,8 @@ __global__ __launch_bounds__(kThreads) void k_local_factor(StencilIn si, T* __re
   const int t = threadIdx.x;
   const bool act = t < R * C;   // the rest duplicate thread 0 and write nothing
   const int ti = act ? t / C : 0, tj = act ? t - (t / C) * C : 0;
-  const int j = blockIdx.x;
+  const int j = blockIdx.x, sys = blockIdx.y;
+  const double* em = si.emod + (size_t)sys * g.nel;
   int jx, jy, jz;
   sub_coords(g, j, jx, jy, jz);
   for (int i = t; i < nd * nd; i += kThreads) K0s[i] = si.K0[i];
@@ -625,8 +627,9 @@ __global__ __launch_bounds__(kThreads) void k_local_factor(StencilIn si, T* __re
   for (int i = t; i < 4 * ld; i += kThreads) pk[i] = 0.0;
   const int mid = nblk / 2;
   const int nbot = si.twist ? nblk - 1 - mid : 0;
-  double* TS = si.twist ? si.twist + (size_t)j * ((size_t)nb * (nb + 1) / 2) : nullptr;
-  T* O = out + (size_t)j * nblk * tsh.tstride;
+  double* TS = si.twist ? si.twist + ((size_t)sys * g.nsub + j) * ((size_t)nb * (nb + 1) / 2)
+                        : nullptr;
+  T* O = out + (size_t)sys * ostride + (size_t)j * nblk * tsh.tstride;
   double s[SR][SC];
 
   // owned entries to and from the dense LDS buffer
@@ -646,7 +649,7 @@ __global__ __launch_bounds__(kThreads) void k_local_factor(StencilIn si, T* __re
     // loop, where they would hold registers through the elimination
     int tq = t;
     asm volatile("" : "+v"(tq));
-    stage_layers<true>(si, jx, jy, jz, cur - 1, Es, fl, tq);
+    stage_layers<true>(si, jx, jy, jz, cur - 1, Es, fl, tq, em);
     __syncthreads();
     // sparse rows: row i couples to the nodes next to its node in a layer
     // (padding rows and outside nodes: column 0, value 0)
@@ -847,11 +850,12 @@ void launch_factor(const double* A, T* out, int nmat, const BtriShape& sh, int* 
 }
 
 template <typename T, int NB>
-void local_factor_as(const StencilIn& si, T* out, int* flag, hipStream_t st) {
+void local_factor_as(const StencilIn& si, T* out, int* flag, int nsys, size_t ostride,
+                     hipStream_t st) {
   static bool attr = false;
   if (!attr) { set_lds(&k_local_factor<T, NB>); attr = true; }
-  hipLaunchKernelGGL((k_local_factor<T, NB>), dim3(si.g.nsub), dim3(kThreads),
-                     local_factor_lds_bytes(si.g, lf_pick_shape(NB)), st, si, out, flag);
+  hipLaunchKernelGGL((k_local_factor<T, NB>), dim3(si.g.nsub, nsys), dim3(kThreads),
+                     local_factor_lds_bytes(si.g, lf_pick_shape(NB)), st, si, out, flag, ostride);
 }
 
 // block sizes with a compiled local factorisation: d (s + 1)^(d - 1) DOFs per
@@ -867,18 +871,20 @@ bool local_factor_fits(const Geometry& g) {
 }
 
 template <typename T>
-void launch_local_factor(const StencilIn& si, T* out, int* flag, hipStream_t st) {
+void launch_local_factor(const StencilIn& si, T* out, int* flag, int nsys, size_t ostride,
+                         hipStream_t st) {
   switch (si.g.nb) {
 #define TPCG_LF_CASE(n) \
-  case n: local_factor_as<T, n>(si, out, flag, st); break;
+  case n: local_factor_as<T, n>(si, out, flag, nsys, ostride, st); break;
     TPCG_LF_SIZES(TPCG_LF_CASE)
 #undef TPCG_LF_CASE
     default: break;   // callers check local_factor_fits first
   }
 }
 
-template void launch_local_factor<double>(const StencilIn&, double*, int*, hipStream_t);
-template void launch_local_factor<float>(const StencilIn&, float*, int*, hipStream_t);
+template void launch_local_factor<double>(const StencilIn&, double*, int*, int, size_t,
+                                          hipStream_t);
+template void launch_local_factor<float>(const StencilIn&, float*, int*, int, size_t, hipStream_t);
 
 template void launch_factor<double>(const double*, double*, int, const BtriShape&, int*,
                                     hipStream_t, bool, const StencilIn*);

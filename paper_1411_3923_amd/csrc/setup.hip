@@ -668,52 +668,45 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
 
   // --- 5 (second stream, beside the coarse factorisation, which occupies
   //     only one workgroup per system, and the coarse inverse): local
-  //     Dirichlet factors, one system at a time, as tiled C_b records (FP32
-  //     in mixed mode), and the moduli their layer couplings use ---
+  //     Dirichlet factors as tiled C_b records (FP32 in mixed mode), all
+  //     systems in one launch, and the moduli their layer couplings use ---
   {
     hipStream_t s2 = h.side;
     const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;
     const int64_t nm = (int64_t)nsys * g.nel;
-    const bool lf = local_factor_fits(g);
-    // FP64 moduli for the factorisations: those the solves use (all
-    // systems), or in mixed precision one system at a time in emod64
-    if (lf && !h.mixed)
-      hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho,
-                         reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
-    for (int sys = 0; sys < nsys; ++sys) {
-      StencilIn sd = si;
-      sd.rho = rho + (size_t)sys * g.nel;
-      sd.neumann = 0;
-      sd.dis = nullptr;
-      sd.twist = h.twist;   // one system at a time on this stream
-      if (lf && h.mixed) {
-        hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, sd.rho, h.emod64,
-                           (int64_t)g.nel, pr.E0, pr.Emin, pr.penal);
-        sd.emod = h.emod64;
-      } else if (lf) {
-        sd.emod = reinterpret_cast<const double*>(h.emod) + (size_t)sys * g.nel;
-      }
-      if (lf) {
+    StencilIn sd = si;
+    sd.neumann = 0;
+    sd.dis = nullptr;
+    sd.twist = h.twist;
+    if (local_factor_fits(g)) {
+      // FP64 moduli for the factorisations: those the solves use, or in
+      // mixed precision a separate FP64 copy
+      double* em = h.mixed ? h.emod64 : reinterpret_cast<double*>(h.emod);
+      hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho, em, nm, pr.E0,
+                         pr.Emin, pr.penal);
+      sd.emod = em;
+      if (h.mixed)
+        launch_local_factor<float>(sd, reinterpret_cast<float*>(h.lfac), h.dflag, nsys, trec, s2);
+      else
+        launch_local_factor<double>(sd, reinterpret_cast<double*>(h.lfac), h.dflag, nsys, trec,
+                                    s2);
+    } else {
+      for (int sys = 0; sys < nsys; ++sys) {   // one system at a time (shared twist scratch)
+        sd.rho = rho + (size_t)sys * g.nel;
         if (h.mixed)
-          launch_local_factor<float>(sd, reinterpret_cast<float*>(h.lfac) + sys * trec, h.dflag,
-                                     s2);
+          launch_factor<float>(nullptr, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub,
+                               lsh, h.dflag, s2, true, &sd);
         else
-          launch_local_factor<double>(sd, reinterpret_cast<double*>(h.lfac) + sys * trec,
-                                      h.dflag, s2);
-      } else if (h.mixed) {
-        launch_factor<float>(nullptr, reinterpret_cast<float*>(h.lfac) + sys * trec, g.nsub, lsh,
-                             h.dflag, s2, true, &sd);
-      } else {
-        launch_factor<double>(nullptr, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub,
-                              lsh, h.dflag, s2, true, &sd);
+          launch_factor<double>(nullptr, reinterpret_cast<double*>(h.lfac) + sys * trec, g.nsub,
+                                lsh, h.dflag, s2, true, &sd);
       }
+      if (!h.mixed)
+        hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho,
+                           reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
     }
     if (h.mixed)
       hipLaunchKernelGGL(k_moduli<float>, dim3(1024), dim3(kThreads), 0, s2, rho,
                          reinterpret_cast<float*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
-    else if (!lf)
-      hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho,
-                         reinterpret_cast<double*>(h.emod), nm, pr.E0, pr.Emin, pr.penal);
     hipEventRecord(h.join, s2);
   }
 

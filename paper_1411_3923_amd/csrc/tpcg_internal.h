@@ -96,8 +96,8 @@ struct Handle {
   double* eres = nullptr;            // [nsub][msub] residual norms
   void* lfac = nullptr;              // tiled D_b [nsys][nsub][nblk][tstride], double or float
   void* emod = nullptr;              // moduli the local factors were built from [nsys][nel], same type
-  double* twist = nullptr;           // Schur terms of the lower halves, [nsub][nb (nb + 1) / 2]
-  double* emod64 = nullptr;          // FP64 moduli of one system (mixed precision), [nel]
+  double* twist = nullptr;           // Schur terms of the lower halves, [nsys][nsub][nb (nb + 1) / 2]
+  double* emod64 = nullptr;          // FP64 moduli (mixed precision), [nsys][nel]
   double* cfac = nullptr;            // packed [nsys][nblkc][bstridec]
   double* cinv = nullptr;            // dense K_c^-1 [nsys][nt][nt] when nt <= kDenseCoarse
   double* build_ws = nullptr;        // work arrays of the preconditioner build
