@@ -148,7 +148,7 @@ def cpu_baseline(args):
 
 def short_name(name):
     """Kernel name without namespace, template arguments or parameter list."""
-    base = name.split("(")[0]
+    base = name.replace("(anonymous namespace)::", "").split("(")[0]
     base = base.split("<")[0]
     return base.split("::")[-1].replace("void ", "")
 
@@ -228,6 +228,87 @@ def summarize_traffic(fetch_csv, write_csv, command, out_json, out_md, kernel="k
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
+def loop_bytes(nsys=3, nelx=1024, nely=512, sub=32, k=6):
+    """Algorithmic HBM bytes per launch of the PCG-loop kernels, FP64, 2-d Q4,
+    every system running: each array the kernel must touch, read or written
+    once (the stored moduli, flags and coarse basis included)."""
+    nnodes = (nelx + 1) * (nely + 1)
+    ndof, nel = 2 * nnodes, nelx * nely
+    nsub = (nelx // sub) * (nely // sub)
+    nloc = 2 * (sub + 1) ** 2
+    nt = nsub * k
+    v = 8 * nsys * ndof                      # one FP64 vector of every system
+    zl = 8 * nsys * nsub * nloc              # local solutions
+    phi = 8 * nsub * k * nloc                # coarse basis, shared by the systems
+    return {
+        "k_apply_q4": 2 * v + 8 * nsys * nel + ndof,          # x, y, moduli, flags
+        "k_update_xr": 6 * v,                                  # u, p, r, q read; u, r written
+        "k_update_p": 3 * v,                                   # z, p read; p written
+        "k_extend": zl + 2 * v + ndof,                         # zloc, r read; z written
+        "k_coarse_add": phi + 2 * zl,                          # Phi read; zloc read and written
+        "k_restrict": phi + zl,                                # Phi and the boxes of r
+        "k_coarse_gemv": 8 * nsys * nt * nt,                   # dense K_c^-1
+    }
+
+
+def summarize_loop(fetch_csv, write_csv, trace_csv, command, out):
+    """Per-kernel HBM traffic and bandwidth of the PCG loop over the launches
+    in which all three systems run: bytes from two rocprofv3 --pmc runs of one
+    solve (scaled by the calibration copy), durations from a kernel trace of
+    the same workload."""
+    import csv
+
+    def counters(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        copy = next(r for r in rows if "copyBuffer" in r["Kernel_Name"])
+        scale = COPY_BYTES / (float(copy["Counter_Value"]) * 1024)
+        per = {}
+        for r in rows:
+            per.setdefault(short_name(r["Kernel_Name"]), []).append(
+                float(r["Counter_Value"]) * 1024 * scale)
+        return per
+
+    fetch, write = counters(fetch_csv, "FETCH_SIZE"), counters(write_csv, "WRITE_SIZE")
+    dur = {}
+    for r in sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"])):
+        dur.setdefault(short_name(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    alg = loop_bytes()
+    lines = ["# PCG-loop kernels: 1024x512 cantilever, 3 realisations, FP64", "",
+             "Commands (on one MI355X, from the repository root):", ""]
+    lines += ["    " + c for c in command.split(" ;; ")]
+    lines += ["", "Launches in which all three systems run (the first iterations of each solve; "
+              "the later ones carry one or two systems). Measured bytes: FETCH_SIZE + WRITE_SIZE, "
+              "each scaled by what it reads for a copy of known size. Bandwidth against the "
+              "8 TB/s HBM3E peak.", "",
+              "| kernel | launches | avg us | measured MB | measured GB/s | % peak "
+              "| algorithmic MB | algorithmic GB/s |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for name in ["k_apply_q4", "k_update_xr", "k_update_p", "k_restrict", "k_local_solves",
+                 "k_coarse_gemv", "k_coarse_add", "k_extend"]:
+        fv, wv, dv = fetch.get(name, []), write.get(name, []), dur.get(name, [])
+        if not fv or not dv:
+            continue
+        tot = [a + b for a, b in zip(fv, wv)]
+        top = max(tot)
+        idx = [i for i, x in enumerate(tot) if x > 0.8 * top]   # all three systems running
+        per_solve = len(tot)
+        nsolve = len(dv) // per_solve
+        ds = [dv[s * per_solve + i] for s in range(nsolve) for i in idx]
+        mb = sum(tot[i] for i in idx) / len(idx)
+        us = sum(ds) / len(ds)
+        a = alg.get(name)
+        if name == "k_local_solves":
+            a = None
+        lines.append(f"| {name} | {len(idx)} | {us:.1f} | {mb / 1e6:.1f} | {mb / us / 1e3:.0f} | "
+                     f"{mb / us / 1e3 / 80:.0f} | " +
+                     (f"{a / 1e6:.1f} | {a / us / 1e3:.0f} |" if a else "- | - |"))
+    lines += ["", "k_coarse_gemv runs on a second stream beside k_local_solves and shares the HBM "
+              "with it; the local solves' algorithmic bytes are in the bench line's roofline."]
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,6 +326,8 @@ def main():
                     help="write a profile summary of a rocprofv3 --stats run and exit (no GPU)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic of the roofline kernel from two --pmc runs and exit")
+    ap.add_argument("--summarize-loop", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "TRACE_CSV"),
+                    help="write the per-kernel PCG-loop traffic table and exit")
     ap.add_argument("--command", default="", help="command recorded in a summary")
     ap.add_argument("--title", default="1024x512 cantilever, 3 realisations, FP64")
     ap.add_argument("--bench-json", default=None, help="bench line of the traced run")
@@ -252,6 +335,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.command, args.out, args.title, args.bench_json)
+        return
+    if args.summarize_loop:
+        summarize_loop(*args.summarize_loop, args.command, args.out)
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic, args.command, TRAFFIC_FILE,
