@@ -76,7 +76,7 @@ typedef struct {
   int32_t ncoarse;      /* k: coarse vectors per subdomain */
   int32_t nsys_max;     /* systems (realisations) solved together, 1..4 */
   int32_t precision;    /* tpcg_precision */
-  int32_t eig_iters;    /* subspace iterations for the local eigenproblems (0: default 8) */
+  int32_t eig_iters;    /* subspace iterations for the local eigenproblems (0: default 6) */
   int32_t eig_extra;    /* extra (guard) vectors in the subspace (0: default k, capped at 16 total) */
   double eig_shift;     /* shift sigma of the shift-invert eigensolver (0: default 1e-5) */
 } tpcg_problem;

@@ -46,7 +46,7 @@ __host__ __device__ inline int q4_tiles(const Geometry& g) {
 // P3: penal == 3, the modulus without pow (whose code would otherwise hold
 // registers through the whole kernel)
 template <bool P3>
-__global__ __launch_bounds__(kThreads) void k_apply_q4(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_apply_q4(
     Geometry g, const double* __restrict__ rho, const double* __restrict__ x,
     double* __restrict__ y, const uint8_t* __restrict__ fixed, Q4Row K, double E0, double Emin,
     double penal, double* __restrict__ parts, Gate gate) {

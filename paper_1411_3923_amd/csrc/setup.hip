@@ -580,7 +580,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;
   const int m = h.msub;
-  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 8;
+  const int iters = pr.eig_iters > 0 ? pr.eig_iters : 6;
   MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
 
   // work arrays of the build, kept by the handle from one build to the next:
