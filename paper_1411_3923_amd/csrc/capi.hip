@@ -201,6 +201,7 @@ Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int
   g.maxit = maxit;
   g.tol2 = tol2;
   g.enabled = enabled;
+  g.test = 0;
   return g;
 }
 
@@ -398,8 +399,9 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
       Gate gn = make_gate(h, rr_next, it + 1, maxit, tol2, 1);
       launch_apply_K(*h, rho_phys, h->p, h->q, nsys, kPartPQ, gi, st);
       launch_update_xr(*h, u, nsys, gi, st);
-      launch_gate(*h, nsys, gn, st);
-      launch_precond(*h, h->r, h->z, nsys, gn, rz_next, it, flexible, st);
+      Gate gt = gn;   // the restriction takes this iteration's residual test
+      gt.test = 1;
+      launch_precond(*h, h->r, h->z, nsys, gt, rz_next, it, flexible, st);
       launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
       launch_update_p(*h, nsys, gn, 0, st);
     }

@@ -26,6 +26,8 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
                                                           Gate gate) {
   constexpr int NW = kSubThreads / 64;
   __shared__ double red[NW][kMaxSys * KM];
+  // systems still running after the previous test (a superset of those that
+  // pass this iteration's test, which is taken below, after the loads)
   unsigned run = 0;
   for (int sys = 0; sys < nsys; ++sys)
     if (gate_running(gate, sys)) run |= 1u << sys;
@@ -66,6 +68,35 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
       }
   }
   const int w = threadIdx.x >> 6;
+  if (gate.test && gate.enabled) {
+    // this iteration's residual test, all systems in one reduction (the same
+    // order in every workgroup); workgroup 0 publishes the flags
+    __shared__ double tst[NW][kMaxSys];
+    double rr[kMaxSys];
+#pragma unroll
+    for (int q = 0; q < kMaxSys; ++q) rr[q] = 0.0;
+    double* parts = const_cast<double*>(gate.parts);
+    for (int i = threadIdx.x; i < gate.np; i += kSubThreads)
+#pragma unroll
+      for (int q = 0; q < kMaxSys; ++q)
+        if ((run >> q) & 1u) rr[q] += part_slot(parts, gate.rr_slot, q)[i];
+#pragma unroll
+    for (int q = 0; q < kMaxSys; ++q) {
+      const double v = wave_sum(rr[q]);
+      if ((threadIdx.x & 63) == 0) tst[w][q] = v;
+    }
+    __syncthreads();
+    int* istate = const_cast<int*>(gate.istate);
+    for (int sys = 0; sys < nsys; ++sys) {
+      if (!((run >> sys) & 1u)) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) v += tst[w2][sys];
+      const bool go = v > gate.tol2 * scal_slot(parts, kScFF)[sys];
+      if (!go) run &= ~(1u << sys);
+      if (blockIdx.x == 0 && threadIdx.x == 0) istate[kStRun * kMaxSys + sys] = go ? 1 : 0;
+    }
+  }
 #pragma unroll
   for (int q = 0; q < kMaxSys; ++q)
 #pragma unroll

@@ -145,8 +145,9 @@ enum {
 // Per-system scalars of the iteration, [kNumScal][kMaxSys] doubles after the
 // partial slots and the four summary values per system: beta of the latest
 // direction update and r.z of the latest preconditioned residual, each
-// reduced once (k_beta) instead of by every workgroup that needs it.
-enum { kScBeta = 0, kScRZ = 1, kNumScal = 2 };
+// reduced once (k_beta) instead of by every workgroup that needs it, and
+// ||P f||^2 (stored by the first residual test).
+enum { kScBeta = 0, kScRZ = 1, kScFF = 2, kNumScal = 3 };
 constexpr size_t kPartsElems = (size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys +
                                (size_t)kNumScal * kMaxSys;
 
@@ -216,6 +217,7 @@ struct Gate {
   int maxit;
   double tol2;
   int enabled;     // 0: always run
+  int test;        // 1: the restriction takes the residual test itself
 };
 
 __device__ inline bool gate_running(const Gate& gt, int sys) {
@@ -233,6 +235,8 @@ inline int parts_for(int64_t work) {
 __host__ __device__ inline double* part_slot(double* parts, int slot, int sys) {
   return parts + ((size_t)slot * kMaxSys + sys) * kMaxParts;
 }
+
+
 
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files). All node-parallel kernels use

@@ -146,7 +146,10 @@ __global__ __launch_bounds__(kThreads) void k_gate(Gate gate, int* __restrict__ 
   double* parts = const_cast<double*>(gate.parts);
   const double rr = sum_parts(part_slot(parts, gate.rr_slot, sys), gate.np, sh);
   const double ff = sum_parts(part_slot(parts, kPartFF, sys), gate.np, sh);
-  if (threadIdx.x == 0) istate[kStRun * kMaxSys + sys] = rr > gate.tol2 * ff ? 1 : 0;
+  if (threadIdx.x == 0) {
+    istate[kStRun * kMaxSys + sys] = rr > gate.tol2 * ff ? 1 : 0;
+    scal_slot(parts, kScFF)[sys] = ff;   // for the tests taken inside kernels
+  }
 }
 
 __global__ void k_poll(Gate gate, int* __restrict__ istate) {
