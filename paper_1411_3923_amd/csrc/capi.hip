@@ -132,7 +132,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   // subspace, or the coarse assembly's arrays
   size_t eig = sizeof(double) * (rec + (size_t)g.nsub * g.nloc * (1 + 2 * msub));
   size_t coarse =
-      sizeof(double) * ((size_t)g.nsub * g.nebox * g.dim * g.k + pr.nsys_max * asm_coarse);
+      sizeof(double) * pr.nsys_max * ((size_t)g.nsub * g.nebox * g.dim * g.k + asm_coarse);
   return {p, std::max(eig, coarse)};
 }
 

@@ -417,12 +417,14 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
 
 // W[j][en][c][m] = (K Phi_j) at the node en of the cell grown by one node
 // layer (zero outside the mesh).
+// blockIdx.y = system: moduli at rho + y nel, W at W + y wstride
 template <int D, int KM>
 __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double* __restrict__ rho,
                                                       const double* __restrict__ K0,
                                                       const uint8_t* __restrict__ fixed,
                                                       const double* __restrict__ phi,
-                                                      double* __restrict__ W, MatParams mp) {
+                                                      double* __restrict__ W, size_t wstride,
+                                                      MatParams mp) {
   __shared__ double K0s[576];
   const int j = blockIdx.x;
   const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
@@ -431,7 +433,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
   for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
   __syncthreads();
   const double* ph = phi + (size_t)j * g.nloc * k;
-  double* Wj = W + (size_t)j * g.nebox * d * k;
+  double* Wj = W + blockIdx.y * wstride + (size_t)j * g.nebox * d * k;
+  rho += (size_t)blockIdx.y * g.nel;
   const int e = g.ebn;
   for (int en = threadIdx.x; en < g.nebox; en += kThreads) {
     const int ex_ = en % e, ey_ = (en / e) % e, ez_ = en / (e * e);
@@ -481,6 +484,85 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
       for (int mm = 0; mm < KM; ++mm)
         if (mm < k) Wj[((size_t)en * d + c) * k + mm] = (in_mesh && !fx) ? acc[c][mm] : 0.0;
     }
+  }
+}
+
+// Blocks Phi_l^T W_j of K_c for every neighbour l of j, one pass over the
+// nodes for all k x k mode pairs (k <= KM): thread-local outer products,
+// then one reduction per pair. grid.x = nsub * 3^d, grid.y = system.
+template <int KM>
+__global__ __launch_bounds__(kThreads) void k_coarse_assemble_all(Geometry g,
+                                                                  const double* __restrict__ phi,
+                                                                  const double* __restrict__ W,
+                                                                  size_t wstride,
+                                                                  double* __restrict__ cf,
+                                                                  size_t cstride) {
+  __shared__ double red[kThreads / 64][KM * KM];
+  const int nnb = g.dim == 3 ? 27 : 9;
+  const int j = blockIdx.x / nnb;
+  const int o = blockIdx.x - j * nnb;
+  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = g.dim == 3 ? o / 9 - 1 : 0;
+  const int lx = jx + ox, ly = jy + oy, lz = jz + oz;
+  if (lx < 0 || lx >= g.gx || ly < 0 || ly >= g.gy || lz < 0 || lz >= g.gz) return;
+  const int k = g.k, d = g.dim;
+  const int Rb = coarse_index(g, lx, ly, lz, 0), Cb = coarse_index(g, jx, jy, jz, 0);
+  const int rblk = Rb / g.nbc, cblk = Cb / g.nbc;
+  int slot;
+  if (rblk == cblk) slot = 0;
+  else if (rblk == cblk + 1) slot = 1;
+  else return;
+  const int l = lx + g.gx * (ly + g.gy * lz);
+  const double* pl = phi + (size_t)l * g.nloc * k;
+  const double* Wj = W + blockIdx.y * wstride + (size_t)j * g.nebox * d * k;
+  const int x0 = max(g.s * lx, g.s * jx - 1), x1 = min(g.s * lx + g.s, g.s * jx + g.s + 1);
+  const int y0 = max(g.s * ly, g.s * jy - 1), y1 = min(g.s * ly + g.s, g.s * jy + g.s + 1);
+  int z0 = 0, z1 = 0;
+  if (d == 3) { z0 = max(g.s * lz, g.s * jz - 1); z1 = min(g.s * lz + g.s, g.s * jz + g.s + 1); }
+  const int nxr = x1 - x0 + 1, nyr = y1 - y0 + 1, nzr = z1 - z0 + 1;
+  const int cnt = nxr * nyr * nzr;
+  double* blk = cf + blockIdx.y * cstride + ((size_t)rblk * 2 + slot) * g.nbc * g.nbc;
+  const int rin = Rb - rblk * g.nbc, cin = Cb - cblk * g.nbc;
+  const int e = g.ebn;
+  double acc[KM][KM];
+#pragma unroll
+  for (int a = 0; a < KM; ++a)
+#pragma unroll
+    for (int b = 0; b < KM; ++b) acc[a][b] = 0.0;
+  for (int idx = threadIdx.x; idx < cnt; idx += kThreads) {
+    const int nx = x0 + idx % nxr, ny = y0 + (idx / nxr) % nyr, nz = z0 + idx / (nxr * nyr);
+    const int lb = (nx - g.s * lx) + g.bn * ((ny - g.s * ly) + g.bn * (nz - g.s * lz));
+    const int eb = (nx - g.s * jx + 1) + e * ((ny - g.s * jy + 1) + e * (d == 3 ? nz - g.s * jz + 1 : 0));
+    for (int c = 0; c < d; ++c) {
+      const double* pv = pl + ((size_t)d * lb + c) * k;
+      const double* wv = Wj + ((size_t)eb * d + c) * k;
+      double p[KM], w[KM];
+#pragma unroll
+      for (int a = 0; a < KM; ++a) {
+        p[a] = a < k ? pv[a] : 0.0;
+        w[a] = a < k ? wv[a] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < KM; ++a)
+#pragma unroll
+        for (int b = 0; b < KM; ++b) acc[a][b] += p[a] * w[b];
+    }
+  }
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int a = 0; a < KM; ++a)
+#pragma unroll
+    for (int b = 0; b < KM; ++b) {
+      const double v = wave_sum(acc[a][b]);
+      if ((threadIdx.x & 63) == 0) red[wv][a * KM + b] = v;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k * k; i += kThreads) {
+    const int a = i / k, b = i - (i / k) * k;
+    double v = 0.0;
+#pragma unroll
+    for (int w2 = 0; w2 < kThreads / 64; ++w2) v += red[w2][a * KM + b];
+    blk[(size_t)(rin + a) * g.nbc + cin + b] = v;
   }
 }
 
@@ -589,7 +671,8 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   // block from the element moduli, so no assembled matrix is stored.
   const size_t nsl = (size_t)g.nsub * g.nloc;
   const size_t wsz = (size_t)g.nsub * g.nebox * g.dim * g.k;
-  const size_t need = std::max(rec + nsl * (1 + 2 * (size_t)m), wsz + asm_coarse * pr.nsys_max);
+  const size_t need =
+      std::max(rec + nsl * (1 + 2 * (size_t)m), (wsz + asm_coarse) * pr.nsys_max);
   if (h.build_elems < need) {
     if (h.build_ws) hipFree(h.build_ws);
     h.build_ws = dalloc<double>(need, err);
@@ -641,27 +724,33 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     hipLaunchKernelGGL(k_phi_modes<double>, dim3(1024), dim3(kThreads), 0, st, g, h.phi,
                        reinterpret_cast<double*>(h.phim));
 
-  // --- 4: coarse matrices and factors, per system ---
-  double* W = h.build_ws;
-  double* Ac = W + wsz;
+  // --- 4: coarse matrices and factors, all systems per launch ---
+  double* W = h.build_ws;                 // [nsys][wsz]
+  double* Ac = W + wsz * nsys;
   hipMemsetAsync(Ac, 0, sizeof(double) * asm_coarse * nsys, st);
   const int nnb = g.dim == 3 ? 27 : 9;
-  for (int sys = 0; sys < nsys; ++sys) {
-    const double* rs = rho + (size_t)sys * g.nel;
+  {
+    const dim3 wgrid(g.nsub, nsys);
     if (g.dim == 2 && g.k <= 8)
-      hipLaunchKernelGGL((k_coarse_W<2, 8>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
-                         h.fixed, h.phi, W, mp);
+      hipLaunchKernelGGL((k_coarse_W<2, 8>), wgrid, dim3(kThreads), 0, st, g, rho, h.K0, h.fixed,
+                         h.phi, W, wsz, mp);
     else if (g.dim == 2)
-      hipLaunchKernelGGL((k_coarse_W<2, kMaxK>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
-                         h.fixed, h.phi, W, mp);
+      hipLaunchKernelGGL((k_coarse_W<2, kMaxK>), wgrid, dim3(kThreads), 0, st, g, rho, h.K0,
+                         h.fixed, h.phi, W, wsz, mp);
     else if (g.k <= 8)
-      hipLaunchKernelGGL((k_coarse_W<3, 8>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
-                         h.fixed, h.phi, W, mp);
+      hipLaunchKernelGGL((k_coarse_W<3, 8>), wgrid, dim3(kThreads), 0, st, g, rho, h.K0, h.fixed,
+                         h.phi, W, wsz, mp);
     else
-      hipLaunchKernelGGL((k_coarse_W<3, kMaxK>), dim3(g.nsub), dim3(kThreads), 0, st, g, rs, h.K0,
-                         h.fixed, h.phi, W, mp);
-    hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi, W,
-                       Ac + sys * asm_coarse);
+      hipLaunchKernelGGL((k_coarse_W<3, kMaxK>), wgrid, dim3(kThreads), 0, st, g, rho, h.K0,
+                         h.fixed, h.phi, W, wsz, mp);
+  }
+  if (g.k <= 8) {
+    hipLaunchKernelGGL(k_coarse_assemble_all<8>, dim3(g.nsub * nnb, nsys), dim3(kThreads), 0, st,
+                       g, h.phi, W, wsz, Ac, asm_coarse);
+  } else {
+    for (int sys = 0; sys < nsys; ++sys)
+      hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi,
+                         W + sys * wsz, Ac + sys * asm_coarse);
   }
   hipEventRecord(h.fork, st);
   hipStreamWaitEvent(h.side, h.fork, 0);
