@@ -34,6 +34,8 @@ __device__ inline d4 mfma_nt(const double* A, const double* Bm, int ld, int nb, 
                              int k0, int k1, d4 acc) {
   const int l = threadIdx.x & 63;
   const int li = l & 15, lk = l >> 4;
+  // unrolled so that the LDS reads of several steps are in flight together
+#pragma unroll 4
   for (int k = k0; k < k1; k += 4) {
     const double a = lget(A, ld, nb, ra + li, k + lk);
     const double b = lget(Bm, ld, nb, rb + li, k + lk);
@@ -213,8 +215,13 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
       }
   };
   auto load = [&](double* dst, const double* src) {
-    for (int r = t / 16; r < nb; r += kThreads / 16)
-      for (int c = t % 16; c < nb; c += 16) dst[r * ld + c] = src[(size_t)r * nb + c];
+    // one flat, unrolled sweep: several loads of each thread in flight at once
+    const int n2 = nb * nb;
+#pragma unroll 8
+    for (int e = t; e < n2; e += kThreads) {
+      const int r = e / nb;
+      dst[r * ld + e - r * nb] = src[e];
+    }
   };
   // Twisted order (stencil input with si.twist set): the node layers below
   // the middle block mid = nblk / 2 are eliminated upwards from the last one
@@ -357,6 +364,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
     for (int J = wv; J + 1 < NT; J += 4)
       for (int I = J + 1; I < NT; ++I) {
         d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
         for (int k = 16 * J; k < 16 * I; k += 4) {
           const int kr = k + lq;   // row of D_KJ: the diagonal tile lives in X, the others in Y
           const double a = lget(X, ld, nb, 16 * I + li, kr);
@@ -437,6 +445,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
           for (int Q = 0; Q <= P; ++Q, ++tile) {
             if ((tile & 3) != wv) continue;
             d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
             for (int k = 16 * P; k < 16 * NT; k += 4) {
               const double a = dget(k + lq, 16 * P + li);   // A[i][kk] = D[k + kk][16 P + i]
               const double bb = dget(k + lq, 16 * Q + li);  // B[kk][j] = D[k + kk][16 Q + j]
