@@ -59,6 +59,24 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(
   const int slot_old = gate.rr_slot;
   const int slot_new = slot_old == kPartRR0 ? kPartRR1 : kPartRR0;
   bool run = gate_running(gate, sys);
+  const int d = g.dim;
+  const size_t off = (size_t)sys * g.ndof;
+  // the first node's loads go out before alpha is reduced, so that their
+  // latency overlaps the reduction
+  const int64_t n0 = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const bool has0 = run && n0 < g.nnodes;
+  double u0[3], p0[3], r0[3], q0[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u0[c] = p0[c] = r0[c] = q0[c] = 0.0;
+    if (has0 && c < d) {
+      const size_t i = off + d * n0 + c;
+      u0[c] = u[i];
+      p0[c] = p[i];
+      r0[c] = r[i];
+      q0[c] = q[i];
+    }
+  }
   double alpha = 0.0;
   if (run) {
     const double pq = sum_parts(part_slot(parts, kPartPQ, sys), np_pq, sh);
@@ -74,10 +92,19 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(
       part_slot(parts, slot_new, sys)[blockIdx.x] = part_slot(parts, slot_old, sys)[blockIdx.x];
     return;
   }
-  const int d = g.dim;
-  const size_t off = (size_t)sys * g.ndof;
   double arr = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
+  if (has0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (c < d) {
+        const size_t i = off + d * n0 + c;
+        u[i] = u0[c] + alpha * p0[c];
+        const double ri = r0[c] - alpha * q0[c];
+        r[i] = ri;
+        arr += ri * ri;
+      }
+  }
+  for (int64_t n = n0 + (int64_t)gridDim.x * kThreads; n < g.nnodes;
        n += (int64_t)gridDim.x * kThreads) {
     for (int c = 0; c < d; ++c) {
       const size_t i = off + d * n + c;
