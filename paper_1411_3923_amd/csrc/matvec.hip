@@ -55,18 +55,29 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ double2 xh[kHY * kHX];
   __shared__ double Eh[kEY * kEX];
   __shared__ double sh[4];
+  const int nnx = g.nnx, nny = g.nny;
+  const int ntx = (nnx + kTX - 1) / kTX, ntiles = q4_tiles(g);
+  // XCD-aware order: workgroups go to the chip's 8 XCDs in turn, so those
+  // of one system whose index agrees mod 8 share an XCD. With one tile per
+  // workgroup the remap below gives each such group a contiguous range of
+  // the system's tiles, whose shared halo lines then meet in that XCD's L2;
+  // every system still spreads over all XCDs
   const int sys = blockIdx.y;
+  int slot = blockIdx.x;
+  if (gridDim.x == ntiles) {
+    const int W = gridDim.x, w = blockIdx.x;
+    const int grp = w % 8, k = w / 8, per = W / 8, rem = W % 8;
+    slot = (grp < rem ? grp * (per + 1) : rem * (per + 1) + (grp - rem) * per) + k;
+  }
   if (!gate_running(gate, sys)) return;
   const int t = threadIdx.x;
   const double* xs = x + (size_t)sys * g.ndof;
   double* ys = y + (size_t)sys * g.ndof;
   const double* rs = rho + (size_t)sys * g.nel;
   const uint16_t* fx2 = reinterpret_cast<const uint16_t*>(fixed);   // both flags of a node
-  const int nnx = g.nnx, nny = g.nny;
-  const int ntx = (nnx + kTX - 1) / kTX, ntiles = q4_tiles(g);
   const int tx = t % kTX, ty = t / kTX;
   double acc = 0.0;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = slot; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % ntx) * kTX, y0 = (tile / ntx) * kTY;
     // every load of the tile is issued before any is used
     double2 hv[kHN];
@@ -165,7 +176,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   }
   if (parts) {
     const double v = block_sum(acc, sh);
-    if (t == 0) parts[(size_t)sys * kMaxParts + blockIdx.x] = v;
+    if (t == 0) parts[(size_t)sys * kMaxParts + slot] = v;
   }
 }
 
