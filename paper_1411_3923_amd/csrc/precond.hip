@@ -217,10 +217,16 @@ __global__ __launch_bounds__(kThreads) void k_extend(
   constexpr int d = D;
   const int s = g.s;
   const size_t zstride = (size_t)g.nsub * g.nloc;
+  // XCD-aware order (workgroups whose index agrees mod 8 share an XCD): each
+  // such group takes a contiguous range of node chunks, so the box rows that
+  // neighbouring chunks both read meet in one L2
+  const int W = gridDim.x, grp = blockIdx.x % 8, per = W / 8, rem = W % 8;
+  const int slot = (grp < rem ? grp * (per + 1) : rem * (per + 1) + (grp - rem) * per) +
+                   blockIdx.x / 8;
   double arz[kMaxSys], arzo[kMaxSys];
 #pragma unroll
   for (int q = 0; q < kMaxSys; ++q) arz[q] = arzo[q] = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
+  for (int64_t n = (int64_t)slot * kThreads + threadIdx.x; n < g.nnodes;
        n += (int64_t)gridDim.x * kThreads) {
     const int ix = (int)(n % g.nnx);
     const int iy = (int)((n / g.nnx) % g.nny);
@@ -271,10 +277,10 @@ __global__ __launch_bounds__(kThreads) void k_extend(
   for (int q = 0; q < kMaxSys; ++q) {
     if (!((run >> q) & 1u)) continue;
     const double v = block_sum(arz[q], sh);
-    if (threadIdx.x == 0) part_slot(parts, rz_slot, q)[blockIdx.x] = v;
+    if (threadIdx.x == 0) part_slot(parts, rz_slot, q)[slot] = v;
     if (flexible) {
       const double w = block_sum(arzo[q], sh);
-      if (threadIdx.x == 0) part_slot(parts, kPartRZO, q)[blockIdx.x] = w;
+      if (threadIdx.x == 0) part_slot(parts, kPartRZO, q)[slot] = w;
     }
   }
 }
