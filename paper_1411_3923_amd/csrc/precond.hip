@@ -32,7 +32,12 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
   for (int sys = 0; sys < nsys; ++sys)
     if (gate_running(gate, sys)) run |= 1u << sys;
   if (!run) return;
-  const int j = blockIdx.x;
+  // XCD-aware order: the workgroups whose index agrees mod 8 share an XCD
+  // and take a contiguous range of boxes, whose shared faces of r meet in
+  // one L2
+  const int W = gridDim.x, grp = blockIdx.x % 8, per = W / 8, rem = W % 8;
+  const int j = (grp < rem ? grp * (per + 1) : rem * (per + 1) + (grp - rem) * per) +
+                blockIdx.x / 8;
   int jx, jy, jz;
   sub_coords(g, j, jx, jy, jz);
   const int k = g.k;
