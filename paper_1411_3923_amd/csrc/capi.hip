@@ -124,7 +124,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   if (mixed) p += sizeof(double) * nsys * (size_t)g.nel;
   p += sizeof(double) * nsys * crec;
   if (g.nt <= kDenseCoarse) p += sizeof(double) * nsys * (size_t)g.nt * g.nt;
-  p += 4 * sizeof(double) * nsys * g.ndof;
+  p += 5 * sizeof(double) * nsys * g.ndof;
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
   p += sizeof(double) * kNumPartSlots * kMaxSys * kMaxParts + 4096;
@@ -148,7 +148,7 @@ void release(Handle* h) {
   if (!h) return;
   void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam,      h->eres, h->lfac,
                   h->emod,  h->twist, h->emod64, h->cfac, h->cinv, h->r,    h->z,
-                  h->p,     h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
+                  h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
                   h->dflag, h->build_ws};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -239,6 +239,7 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
   e |= alloc(h->r, ns * (size_t)g.ndof);
   e |= alloc(h->z, ns * (size_t)g.ndof);
   e |= alloc(h->p, ns * (size_t)g.ndof);
+  e |= alloc(h->p2, ns * (size_t)g.ndof);
   e |= alloc(h->q, ns * (size_t)g.ndof);
   e |= alloc(h->parts, kPartsElems);
   e |= alloc(h->istate, (size_t)kNumState * kMaxSys);
@@ -386,7 +387,12 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   h->prof_n = 0;
   launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, -1, flexible, st);
   launch_beta(*h, nsys, g0, kPartRZ0, flexible, 1, st);
-  launch_update_p(*h, nsys, g0, 1, st);
+  // 2-d: the direction update p = z + beta p runs inside the next operator
+  // launch, alternating between two buffers; 3-d: its own kernel
+  const bool fused = h->g.dim == 2;
+  double* pcur = h->p;
+  double* pnext = h->p2;
+  if (!fused) launch_update_p(*h, nsys, g0, 1, st);
   int it = 0;
   int chunk = 0;
   bool done = maxit == 0;
@@ -397,13 +403,18 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
       const int rz_next = (it & 1) ? kPartRZ0 : kPartRZ1;
       Gate gi = make_gate(h, rr_now, it, maxit, tol2, 1);
       Gate gn = make_gate(h, rr_next, it + 1, maxit, tol2, 1);
-      launch_apply_K(*h, rho_phys, h->p, h->q, nsys, kPartPQ, gi, st);
-      launch_update_xr(*h, u, nsys, gi, st);
+      if (fused) {
+        launch_apply_K_dir(*h, rho_phys, h->z, pcur, pnext, h->q, nsys, kPartPQ, gi, it == 0, st);
+        std::swap(pcur, pnext);
+      } else {
+        launch_apply_K(*h, rho_phys, pcur, h->q, nsys, kPartPQ, gi, st);
+      }
+      launch_update_xr(*h, u, pcur, nsys, gi, st);
       Gate gt = gn;   // the restriction takes this iteration's residual test
       gt.test = 1;
       launch_precond(*h, h->r, h->z, nsys, gt, rz_next, it, flexible, st);
       launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
-      launch_update_p(*h, nsys, gn, 0, st);
+      if (!fused) launch_update_p(*h, nsys, gn, 0, st);
     }
     const int slot = chunk & 1;
     Gate gp = make_gate(h, (it & 1) ? kPartRR1 : kPartRR0, it, maxit, tol2, 1);

@@ -45,11 +45,17 @@ __host__ __device__ inline int q4_tiles(const Geometry& g) {
 
 // P3: penal == 3, the modulus without pow (whose code would otherwise hold
 // registers through the whole kernel)
-template <bool P3>
+//
+// DIR: the CG direction update is fused in: the product is taken with
+// p = z + beta p_old (p = z when first), formed for the staged halo from z
+// and p_old = x, and the workgroup writes p for the nodes it owns to pnew
+// (a buffer other than x, since neighbouring tiles still read p_old).
+template <bool P3, bool DIR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_apply_q4(
     Geometry g, const double* __restrict__ rho, const double* __restrict__ x,
     double* __restrict__ y, const uint8_t* __restrict__ fixed, Q4Row K, double E0, double Emin,
-    double penal, double* __restrict__ parts, Gate gate) {
+    double penal, double* __restrict__ parts, Gate gate, const double* __restrict__ zdir,
+    double* __restrict__ pnew, const double* __restrict__ beta, int first) {
   constexpr int kHN = (kHY * kHX + kThreads - 1) / kThreads;   // staged values per thread
   constexpr int kEN = (kEY * kEX + kThreads - 1) / kThreads;
   __shared__ double2 xh[kHY * kHX];
@@ -74,6 +80,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   const double* xs = x + (size_t)sys * g.ndof;
   double* ys = y + (size_t)sys * g.ndof;
   const double* rs = rho + (size_t)sys * g.nel;
+  const double* zs = DIR ? zdir + (size_t)sys * g.ndof : nullptr;
+  double* ps = DIR ? pnew + (size_t)sys * g.ndof : nullptr;
+  const double bt = DIR && !first ? beta[sys] : 0.0;
   const uint16_t* fx2 = reinterpret_cast<const uint16_t*>(fixed);   // both flags of a node
   const int tx = t % kTX, ty = t / kTX;
   double acc = 0.0;
@@ -91,7 +100,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       hf[q] = 0xffffu;
       if (i < kHY * kHX && X >= 0 && X < nnx && Y >= 0 && Y < nny) {
         const int64_t n = X + (int64_t)nnx * Y;
-        hv[q] = *reinterpret_cast<const double2*>(xs + 2 * n);
+        if (DIR) {
+          const double2 zv = *reinterpret_cast<const double2*>(zs + 2 * n);
+          double2 pv = make_double2(0.0, 0.0);
+          if (!first) pv = *reinterpret_cast<const double2*>(xs + 2 * n);
+          hv[q] = make_double2(zv.x + bt * pv.x, zv.y + bt * pv.y);
+        } else {
+          hv[q] = *reinterpret_cast<const double2*>(xs + 2 * n);
+        }
         hf[q] = fx2[n];
       }
     }
@@ -169,6 +185,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         if (f & 0x00ffu) y0v = 0.0;
         if (f & 0xff00u) y1v = 0.0;
         *reinterpret_cast<double2*>(ys + 2 * n) = make_double2(y0v, y1v);
+        if (DIR) *reinterpret_cast<double2*>(ps + 2 * n) = w[1][1];   // the new p
         if (parts) acc += w[1][1].x * y0v + w[1][1].y * y1v;   // w[1][1]: P x at the node
       }
       __builtin_amdgcn_sched_barrier(0);   // one node at a time: fewer live registers
@@ -259,23 +276,35 @@ int apply_parts(const Geometry& g) {
 
 void launch_apply_K(const Handle& h, const double* rho, const double* x, double* y, int nsys,
                     int dot_slot, const Gate& gate, hipStream_t st) {
+  launch_apply_K_dir(h, rho, nullptr, x, nullptr, y, nsys, dot_slot, gate, 0, st);
+}
+
+void launch_apply_K_dir(const Handle& h, const double* rho, const double* z, const double* x,
+                        double* pnew, double* y, int nsys, int dot_slot, const Gate& gate,
+                        int first, hipStream_t st) {
   const Geometry& g = h.g;
   dim3 grid(apply_parts(g), nsys);
   double* parts = dot_slot >= 0 ? part_slot(h.parts, dot_slot, 0) : nullptr;
+  const double* beta = scal_slot(h.parts, kScBeta);
   const tpcg_problem& pr = h.prob;
   if (g.dim == 2) {
     Q4Row q;
     std::copy(h.K0q4, h.K0q4 + 8, q.q);
-    if (pr.penal == 3.0)
-      hipLaunchKernelGGL(k_apply_q4<true>, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, q,
-                         pr.E0, pr.Emin, pr.penal, parts, gate);
-    else
-      hipLaunchKernelGGL(k_apply_q4<false>, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, q,
-                         pr.E0, pr.Emin, pr.penal, parts, gate);
-  }
-  else
+#define TPCG_Q4(P3, DIR)                                                                      \
+  hipLaunchKernelGGL((k_apply_q4<P3, DIR>), grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, \
+                     q, pr.E0, pr.Emin, pr.penal, parts, gate, z, pnew, beta, first)
+    if (z) {
+      if (pr.penal == 3.0) TPCG_Q4(true, true);
+      else TPCG_Q4(false, true);
+    } else {
+      if (pr.penal == 3.0) TPCG_Q4(true, false);
+      else TPCG_Q4(false, false);
+    }
+#undef TPCG_Q4
+  } else {
     hipLaunchKernelGGL(k_apply_h8, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, h.K0,
                        pr.E0, pr.Emin, pr.penal, parts, gate);
+  }
 }
 
 }  // namespace tpcg

@@ -109,6 +109,7 @@ struct Handle {
   double* r = nullptr;               // [nsys_max][ndof]
   double* z = nullptr;
   double* p = nullptr;
+  double* p2 = nullptr;              // second direction buffer (fused update, 2-d)
   double* q = nullptr;
   void* zloc = nullptr;              // [nsys][nsub][nloc], double or float
   double* yc = nullptr;              // [nsys][nt]
@@ -251,11 +252,17 @@ int apply_parts(const Geometry& g);
 bool q4_structured(const double* K0);
 void launch_apply_K(const Handle& h, const double* rho, const double* x, double* y, int nsys,
                     int dot_slot, const Gate& gate, hipStream_t st);
+// 2-d only: y = P K P p with the direction update fused, p = z + beta x (beta
+// from launch_beta; p = z when first), p written to pnew (pnew != x)
+void launch_apply_K_dir(const Handle& h, const double* rho, const double* z, const double* x,
+                        double* pnew, double* y, int nsys, int dot_slot, const Gate& gate,
+                        int first, hipStream_t st);
 
 // vectors.hip
 void launch_residual_init(const Handle& h, const double* f, double* u, const double* q, int nsys,
                           hipStream_t st);
-void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hipStream_t st);
+void launch_update_xr(const Handle& h, double* u, const double* p, int nsys, const Gate& gate,
+                      hipStream_t st);
 // beta and r.z of the preconditioned residual whose r.z partials are in
 // rz_slot (first: beta = 0), into the scalar slots; flags a breakdown
 void launch_beta(const Handle& h, int nsys, const Gate& gate, int rz_slot, int flexible,

@@ -234,9 +234,10 @@ void launch_residual_init(const Handle& h, const double* f, double* u, const dou
                      h.parts, h.istate);
 }
 
-void launch_update_xr(const Handle& h, double* u, int nsys, const Gate& gate, hipStream_t st) {
+void launch_update_xr(const Handle& h, double* u, const double* p, int nsys, const Gate& gate,
+                      hipStream_t st) {
   dim3 grid(parts_for(h.g.nnodes), nsys);
-  hipLaunchKernelGGL(k_update_xr, grid, dim3(kThreads), 0, st, h.g, u, h.r, h.p, h.q, h.parts,
+  hipLaunchKernelGGL(k_update_xr, grid, dim3(kThreads), 0, st, h.g, u, h.r, p, h.q, h.parts,
                      h.istate, gate, apply_parts(h.g));
 }
 
