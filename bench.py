@@ -241,9 +241,9 @@ def loop_bytes(nsys=3, nelx=1024, nely=512, sub=32, k=6):
     zl = 8 * nsys * nsub * nloc              # local solutions
     phi = 8 * nsub * k * nloc                # coarse basis, shared by the systems
     return {
-        "k_apply_q4": 2 * v + 8 * nsys * nel + ndof,          # x, y, moduli, flags
+        "k_apply_q4": 4 * v + 8 * nsys * nel + ndof,          # z, p read; p', K p' written; moduli, flags
         "k_update_xr": 6 * v,                                  # u, p, r, q read; u, r written
-        "k_update_p": 3 * v,                                   # z, p read; p written
+        "k_update_p": 3 * v,                                   # z, p read; p written (3-d only)
         "k_extend": zl + 2 * v + ndof,                         # zloc, r read; z written
         "k_coarse_add": phi + 2 * zl,                          # Phi read; zloc read and written
         "k_restrict": phi + zl,                                # Phi and the boxes of r
