@@ -366,20 +366,34 @@ __device__ void btri_solve(const T* __restrict__ fac, const BtriShape sh, int nr
 // ---------------------------------------------------------------------------
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 
+// Address of element (r, c) of the operand, clamped into the record, and
+// whether the element is inside the matrix, the triangle or the band (else
+// it is zero).
 template <int MODE>
-__device__ inline double rec_elem(const double* M, const double* E, int nb, int pe, int r, int c) {
-  if (r >= nb || c >= nb) return 0.0;
-  if (MODE == 0) return c <= r ? M[r * nb + c] : 0.0;
-  if (MODE == 1) return c > r ? M[r * nb + c] : (r - c < pe ? E[r * pe + (r - c)] : 0.0);
-  if (MODE == 2) return r <= c ? M[c * nb + r] : 0.0;
-  return r > c ? M[c * nb + r] : (c - r < pe ? E[c * pe + (c - r)] : 0.0);
+__device__ inline const double* rec_addr(const double* M, const double* E, int nb, int pe, int r,
+                                         int c, bool& ok) {
+  const int rr = min(r, nb - 1), cc = min(c, nb - 1);
+  const bool in = r < nb && c < nb;
+  if (MODE == 0) { ok = in && c <= r; return M + rr * nb + cc; }
+  if (MODE == 2) { ok = in && r <= c; return M + cc * nb + rr; }
+  // B_b from the strict upper triangle of M and the band E
+  const int lo = MODE == 1 ? rr : cc, hi = MODE == 1 ? cc : rr;   // row / column of M
+  const int off = lo - hi;                                          // > 0 below the diagonal
+  const bool up = hi > lo;
+  ok = in && (up || off < pe);
+  return up ? M + lo * nb + hi : E + lo * pe + min(max(off, 0), pe - 1);
 }
 
-// dst = op(M) v  (or base - op(M) v); v, dst, base are [npad][16] in LDS
+// dst = op(M) v  (or base - op(M) v); v, dst, base are [npad][16] in LDS.
+// The wave index is made uniform so that the tile and k loops are scalar
+// loops and the accumulator stays in place between MFMAs. The operands of
+// four k-steps are read unconditionally from clamped addresses (the empty asm
+// keeps the compiler from moving the reads under their masks, which would
+// serialise them) and masked after one wait.
 template <int MODE>
 __device__ inline void rec_gemm16(const double* M, const double* E, int nb, int pe, int npad,
                                   const double* v, double* dst, const double* base) {
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
   const int li = l & 15, lq = l >> 4;
   for (int I = wv; 16 * I < npad; I += 4) {
     int k0 = 0, k1 = npad;
@@ -388,15 +402,32 @@ __device__ inline void rec_gemm16(const double* M, const double* E, int nb, int 
     if (MODE == 2) k0 = 16 * I;
     if (MODE == 3) k1 = min(npad, (16 * I + 15 + pe + 3) & ~3);
     dvec4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int k = k0; k < k1; k += 4) {
-      const double a = rec_elem<MODE>(M, E, nb, pe, 16 * I + li, k + lq);
+    const int r = 16 * I + li;
+    int k = k0;
+    for (; k + 16 <= k1; k += 16) {
+      double a[4], b[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = *rec_addr<MODE>(M, E, nb, pe, r, k + 4 * u + lq, ok[u]);
+        b[u] = v[(k + 4 * u + lq) * 16 + li];
+      }
+      asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]));
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok[u] ? a[u] : 0.0, b[u], acc, 0, 0, 0);
+    }
+    for (; k < k1; k += 4) {
+      bool ok;
+      double a = *rec_addr<MODE>(M, E, nb, pe, r, k + lq, ok);
       const double b = v[(k + lq) * 16 + li];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      asm volatile("" : "+v"(a));
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? a : 0.0, b, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int r = 16 * I + 4 * q + lq;
-      dst[r * 16 + li] = base ? base[r * 16 + li] - acc[q] : acc[q];
+      const int rq = 16 * I + 4 * q + lq;
+      dst[rq * 16 + li] = base ? base[rq * 16 + li] - acc[q] : acc[q];
     }
   }
 }

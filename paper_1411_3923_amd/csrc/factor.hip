@@ -29,17 +29,40 @@ __device__ inline double lget(const double* M, int ld, int nb, int r, int c) {
   return (r < nb && c < nb) ? M[r * ld + c] : 0.0;
 }
 
-// acc += A[ra.., k] * Bm[rb.., k]^T over k in [k0, k1) (k0 multiple of 4)
+// acc += A[ra.., k] * Bm[rb.., k]^T over k in [k0, k1) (k0 multiple of 4).
+// The operands of four k-steps are read from clamped addresses before their
+// MFMAs and masked after one wait (the empty asm keeps the compiler from
+// moving each read under its bounds test, which would serialise them).
 __device__ inline d4 mfma_nt(const double* A, const double* Bm, int ld, int nb, int ra, int rb,
                              int k0, int k1, d4 acc) {
   const int l = threadIdx.x & 63;
   const int li = l & 15, lk = l >> 4;
-  // unrolled so that the LDS reads of several steps are in flight together
-#pragma unroll 4
-  for (int k = k0; k < k1; k += 4) {
-    const double a = lget(A, ld, nb, ra + li, k + lk);
-    const double b = lget(Bm, ld, nb, rb + li, k + lk);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  const int a_off = min(ra + li, nb - 1) * ld, b_off = min(rb + li, nb - 1) * ld;
+  const bool a_in = ra + li < nb, b_in = rb + li < nb;
+  int k = k0;
+  for (; k + 16 <= k1; k += 16) {
+    double a[4], b[4];
+    bool ka[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = k + 4 * u + lk, cc = min(c, nb - 1);
+      ka[u] = c < nb;
+      a[u] = A[a_off + cc];
+      b[u] = Bm[b_off + cc];
+    }
+    asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(b[0]), "+v"(b[1]),
+                 "+v"(b[2]), "+v"(b[3]));
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a_in && ka[u] ? a[u] : 0.0,
+                                                b_in && ka[u] ? b[u] : 0.0, acc, 0, 0, 0);
+  }
+  for (; k < k1; k += 4) {
+    const int c = k + lk, cc = min(c, nb - 1);
+    double a = A[a_off + cc], b = Bm[b_off + cc];
+    asm volatile("" : "+v"(a), "+v"(b));
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a_in && c < nb ? a : 0.0, b_in && c < nb ? b : 0.0,
+                                              acc, 0, 0, 0);
   }
   return acc;
 }
@@ -171,7 +194,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   const int rstride = tiles ? tsh.tstride : sh.bstride;
   T* O = out + (size_t)blockIdx.x * nblk * rstride;
   const int t = threadIdx.x;
-  const int wv = t >> 6, l = t & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63;   // wave index, uniform
   const int li = l & 15, lq = l >> 4;
   double* tw = tmp + wv * 256;
   // stencil input: staged moduli, K0 and the Neumann diagonals of the last
