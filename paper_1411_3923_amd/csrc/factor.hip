@@ -221,18 +221,24 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
     }
   };
   // block (Lr, Lc) of the subdomain matrix from the staged layers
+  // Entries whose in-layer indices lie further apart than any two
+  // neighbouring nodes' DOFs (2d - 1 in 2d, d(bn + 1) + d - 1 in 3d) are
+  // structural zeros and skip the node decoding and the stencil.
+  const int span = sten ? (si.g.dim == 3 ? si.g.dim * (si.g.bn + 2) - 1 : 2 * si.g.dim - 1) : 0;
   auto fill = [&](double* dst, int Lr, int Lc, int L0) {
     for (int r = t / 16; r < nb; r += kThreads / 16)
       for (int c = t % 16; c < nb; c += 16) {
         const int lr = Lr * nb + r, lc = Lc * nb + c;
-        double v;
-        if (fl[(Lr - L0) * nb + r] || fl[(Lc - L0) * nb + c]) {
-          v = lr == lc ? (si.neumann ? si.fixed_diag + si.shift : 1.0) : 0.0;
-        } else {
-          v = stencil_entry(si.g, lr, lc, L0, Es, K0s);
-          if (si.neumann)
-            v = v / sqrt(dl[(Lr & 1) * nb + r] * dl[(Lc & 1) * nb + c]) +
-                (lr == lc ? si.shift : 0.0);
+        double v = 0.0;
+        if (abs(r - c) <= span) {
+          if (fl[(Lr - L0) * nb + r] || fl[(Lc - L0) * nb + c]) {
+            v = lr == lc ? (si.neumann ? si.fixed_diag + si.shift : 1.0) : 0.0;
+          } else {
+            v = stencil_entry(si.g, lr, lc, L0, Es, K0s);
+            if (si.neumann)
+              v = v / sqrt(dl[(Lr & 1) * nb + r] * dl[(Lc & 1) * nb + c]) +
+                  (lr == lc ? si.shift : 0.0);
+          }
         }
         dst[r * ld + c] = v;
       }
