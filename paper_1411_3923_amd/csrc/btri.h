@@ -437,9 +437,12 @@ __host__ __device__ inline size_t btri_solve16_lds_elems(const BtriShape& s) {
   return (size_t)s.bstride + 2 * (size_t)npad * 16;
 }
 
+// b0: the right-hand sides vanish in the blocks before b0 (so does y there):
+// the forward sweep starts at b0 and the backward sweep takes y_b = 0 below
+// it without reading out.
 template <int MAXV, typename Rhs, typename Out>
 __device__ void btri_solve16(const double* __restrict__ fac, const BtriShape sh, int nr, Rhs rhs,
-                             Out out, unsigned char* smem) {
+                             Out out, unsigned char* smem, int b0 = 0) {
   const int nb = sh.nb, nblk = sh.nblk, pe = sh.pe;
   const int npad = (nb + 15) & ~15;
   double* M = reinterpret_cast<double*>(smem);
@@ -482,7 +485,7 @@ __device__ void btri_solve16(const double* __restrict__ fac, const BtriShape sh,
     for (int u = 0; u < VR; ++u) {
       const int e = t + u * kThreads;
       const int i = e >> 4, r = e & 15;
-      if (e < nvec) vreg[u] = (i < nb && r < nr) ? out(b, i, r) : 0.0;
+      if (e < nvec) vreg[u] = (b >= b0 && i < nb && r < nr) ? out(b, i, r) : 0.0;
     }
   };
   auto vstore = [&](double* dst) {
@@ -498,17 +501,18 @@ __device__ void btri_solve16(const double* __restrict__ fac, const BtriShape sh,
       if (i < nb && r < nr) out(b, i, r) = src[e];
     }
   };
-  // forward
-  stage_load(0);
-  vload_rhs(0);
+  // forward, from block b0 (y_{b0-1} = 0)
+  stage_load(b0);
+  vload_rhs(b0);
   stage_store();
   vstore(va);
-  if (nblk > 1) { stage_load(1); vload_rhs(1); }
+  if (b0 + 1 < nblk) { stage_load(b0 + 1); vload_rhs(b0 + 1); }
+  else if (nblk > 1) { stage_load(nblk - 2); }
   __syncthreads();
   rec_gemm16<0>(M, E, nb, pe, npad, va, vb, nullptr);
   __syncthreads();
-  write_out(vb, 0);
-  for (int b = 1; b < nblk; ++b) {
+  write_out(vb, b0);
+  for (int b = b0 + 1; b < nblk; ++b) {
     vstore(va);                                   // r_b (va last read before the barrier)
     __syncthreads();
     rec_gemm16<1>(M, E, nb, pe, npad, vb, va, va);   // t_b = r_b - B_b y_{b-1}

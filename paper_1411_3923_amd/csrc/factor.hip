@@ -572,7 +572,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_inverse(const double* __restr
   btri_solve16<MAXV>(
       F, sh, nr, [&](int b, int i, int r) { return (b * nb + i == c0 + r) ? 1.0 : 0.0; },
       [&](int b, int i, int r) -> double& { return Xm[(size_t)(b * nb + i) * n + c0 + r]; },
-      smem);
+      smem, c0 / nb);
 }
 
 // ---------------------------------------------------------------------------
