@@ -154,7 +154,35 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemv(Geometry g, const doub
   const double* a = cinv + ((size_t)sys * g.nt + row) * g.nt;
   const double* y = yc + (size_t)sys * g.nt;
   double s = 0.0;
-  for (int c = lane; c < g.nt; c += 64) s += a[c] * y[c];
+  if ((g.nt & 1) == 0) {
+    // even rows are 16-byte aligned: 16-byte loads, four per lane in flight
+    const int n2 = g.nt / 2;
+    const double2* a2 = reinterpret_cast<const double2*>(a);
+    const double2* y2 = reinterpret_cast<const double2*>(y);
+    double s0 = 0.0, s1 = 0.0;
+    int c = lane;
+    for (; c + 3 * 64 < n2; c += 4 * 64) {
+      double2 v[4], w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[u] = a2[c + 64 * u];
+        w[u] = y2[c + 64 * u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s0 += v[u].x * w[u].x;
+        s1 += v[u].y * w[u].y;
+      }
+    }
+    for (; c < n2; c += 64) {
+      const double2 v = a2[c], w = y2[c];
+      s0 += v.x * w.x;
+      s1 += v.y * w.y;
+    }
+    s = s0 + s1;
+  } else {
+    for (int c = lane; c < g.nt; c += 64) s += a[c] * y[c];
+  }
   s = wave_sum(s);
   if (lane == 0) xc[(size_t)sys * g.nt + row] = s;
 }
@@ -374,19 +402,26 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   };
   if (h.mixed) restrict_launch<float>(h, r, nsys, gate, st);
   else restrict_launch<double>(h, r, nsys, gate, st);
-  // the coarse solves run beside the local ones on the side stream
-  hipEventRecord(h.fork, st);
-  hipStreamWaitEvent(h.side, h.fork, 0);
-  if (h.cinv)
-    hipLaunchKernelGGL(k_coarse_gemv, dim3(nsys * ((g.nt + 3) / 4)), dim3(kThreads), 0, h.side, g,
+  // The dense coarse product runs on the main stream ahead of the local
+  // solves: both are HBM-bound, and side by side they slowed each other more
+  // than the shorter one takes alone. The block-tridiagonal coarse solve (for
+  // coarse spaces too large for a dense inverse) occupies one workgroup per
+  // system and is latency-bound: it runs beside the local solves on the side
+  // stream.
+  const bool beside = h.cinv == nullptr;
+  if (!beside) {
+    hipLaunchKernelGGL(k_coarse_gemv, dim3(nsys * ((g.nt + 3) / 4)), dim3(kThreads), 0, st, g,
                        h.cinv, h.yc, h.xc, gate);
-  else
+  } else {
+    hipEventRecord(h.fork, st);
+    hipStreamWaitEvent(h.side, h.fork, 0);
     coarse_launch(h, nsys, gate, h.side);
-  hipEventRecord(h.join, h.side);
+    hipEventRecord(h.join, h.side);
+  }
   mark(0);
   launch_local_solves(h, r, nsys, gate, st);
   mark(1);
-  hipStreamWaitEvent(st, h.join, 0);
+  if (beside) hipStreamWaitEvent(st, h.join, 0);
   if (h.mixed) extend_launch<float>(h, r, z, nsys, gate, rz_slot, flexible, st);
   else extend_launch<double>(h, r, z, nsys, gate, rz_slot, flexible, st);
   if (prof) h.prof_it[h.prof_n++] = prof_it;
