@@ -304,8 +304,7 @@ def summarize_loop(fetch_csv, write_csv, trace_csv, command, out):
         lines.append(f"| {name} | {len(idx)} | {us:.1f} | {mb / 1e6:.1f} | {mb / us / 1e3:.0f} | "
                      f"{mb / us / 1e3 / 80:.0f} | " +
                      (f"{a / 1e6:.1f} | {a / us / 1e3:.0f} |" if a else "- | - |"))
-    lines += ["", "k_coarse_gemv runs on a second stream beside k_local_solves and shares the HBM "
-              "with it; the local solves' algorithmic bytes are in the bench line's roofline."]
+    lines += ["", "The local solves' algorithmic bytes are in the bench line's roofline."]
     open(out, "w").write("\n".join(lines) + "\n")
 
 
