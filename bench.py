@@ -237,6 +237,7 @@ def loop_bytes(nsys=3, nelx=1024, nely=512, sub=32, k=6):
     nsub = (nelx // sub) * (nely // sub)
     nloc = 2 * (sub + 1) ** 2
     nt = nsub * k
+    ct = (nt + 63) // 64                      # tile rows of the packed K_c^-1
     v = 8 * nsys * ndof                      # one FP64 vector of every system
     zl = 8 * nsys * nsub * nloc              # local solutions
     phi = 8 * nsub * k * nloc                # coarse basis, shared by the systems
@@ -247,7 +248,10 @@ def loop_bytes(nsys=3, nelx=1024, nely=512, sub=32, k=6):
         "k_extend": zl + 2 * v + ndof,                         # zloc, r read; z written
         "k_coarse_add": phi + 2 * zl,                          # Phi read; zloc read and written
         "k_restrict": phi + zl,                                # Phi and the boxes of r
-        "k_coarse_gemv": 8 * nsys * nt * nt,                   # dense K_c^-1
+        # lower 64 x 64 tiles of K_c^-1 read, tile partials written; the
+        # partials summed
+        "k_coarse_gemv_tiles": 8 * nsys * (ct * (ct + 1) // 2 * 64 * 64 + ct * ct * 64),
+        "k_coarse_gemv_sum": 8 * nsys * (ct * ct * 64 + nt),
     }
 
 

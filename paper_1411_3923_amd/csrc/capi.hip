@@ -123,7 +123,10 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += sizeof(double) * nsys * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
   if (mixed) p += sizeof(double) * nsys * (size_t)g.nel;
   p += sizeof(double) * nsys * crec;
-  if (g.nt <= kDenseCoarse) p += sizeof(double) * nsys * (size_t)g.nt * g.nt;
+  if (g.nt <= kDenseCoarse) {
+    const size_t T = coarse_tiles(g.nt);
+    p += sizeof(double) * nsys * ((size_t)g.nt * g.nt + T * (T + 1) / 2 * kCT * kCT + T * T * kCT);
+  }
   p += 5 * sizeof(double) * nsys * g.ndof;
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
@@ -147,7 +150,7 @@ int alloc(T*& p, size_t n) {
 void release(Handle* h) {
   if (!h) return;
   void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam,      h->eres, h->lfac,
-                  h->emod,  h->twist, h->emod64, h->cfac, h->cinv, h->r,    h->z,
+                  h->emod,  h->twist, h->emod64, h->cfac, h->cinv, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
                   h->dflag, h->build_ws};
   for (void* p : ptrs)
@@ -327,7 +330,12 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     e |= alloc(h->twist, (size_t)ns * g.nsub * g.nb * (g.nb + 1) / 2);
     if (h->mixed) e |= alloc(h->emod64, (size_t)ns * g.nel);
     e |= alloc(h->cfac, ns * cfsz);
-    if (g.nt <= kDenseCoarse) e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
+    if (g.nt <= kDenseCoarse) {
+      const size_t T = coarse_tiles(g.nt);
+      e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
+      e |= alloc(h->cpk, (size_t)ns * T * (T + 1) / 2 * kCT * kCT);
+      e |= alloc(h->cpart, (size_t)ns * T * T * kCT);
+    }
     unsigned char* zl = nullptr;
     e |= alloc(zl, ts * ns * (size_t)g.nsub * g.nloc);
     h->zloc = zl;

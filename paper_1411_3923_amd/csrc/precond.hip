@@ -140,51 +140,100 @@ __global__ __launch_bounds__(kThreads) void k_coarse_solve(Geometry g, const dou
       [&](int b, int i, int) -> double& { return xs[b * nbc + i]; }, smem);
 }
 
-// x_c = K_c^-1 y_c with the dense inverse: one wave per row, four rows per
-// workgroup; grid.x = nsys * ceil(nt / 4)
-__global__ __launch_bounds__(kThreads) void k_coarse_gemv(Geometry g, const double* __restrict__ cinv,
-                                                         const double* __restrict__ yc,
-                                                         double* __restrict__ xc, Gate gate) {
-  const int per_sys = (g.nt + 3) / 4;
-  const int sys = blockIdx.x / per_sys;
-  if (!gate_running(gate, sys)) return;
-  const int row = (blockIdx.x - sys * per_sys) * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= g.nt) return;
-  const double* a = cinv + ((size_t)sys * g.nt + row) * g.nt;
-  const double* y = yc + (size_t)sys * g.nt;
-  double s = 0.0;
-  if ((g.nt & 1) == 0) {
-    // even rows are 16-byte aligned: 16-byte loads, four per lane in flight
-    const int n2 = g.nt / 2;
-    const double2* a2 = reinterpret_cast<const double2*>(a);
-    const double2* y2 = reinterpret_cast<const double2*>(y);
-    double s0 = 0.0, s1 = 0.0;
-    int c = lane;
-    for (; c + 3 * 64 < n2; c += 4 * 64) {
-      double2 v[4], w[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        v[u] = a2[c + 64 * u];
-        w[u] = y2[c + 64 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        s0 += v[u].x * w[u].x;
-        s1 += v[u].y * w[u].y;
-      }
-    }
-    for (; c < n2; c += 64) {
-      const double2 v = a2[c], w = y2[c];
-      s0 += v.x * w.x;
-      s1 += v.y * w.y;
-    }
-    s = s0 + s1;
-  } else {
-    for (int c = lane; c < g.nt; c += 64) s += a[c] * y[c];
+// Tile (I, J), I >= J, of the lower tiles in row-major tile order.
+__device__ inline void coarse_tile_ij(int tile, int& I, int& J) {
+  I = 0;
+  while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+  J = tile - I * (I + 1) / 2;
+}
+
+// The lower 64 x 64 tiles (I >= J) of the symmetric K_c^-1, each row-major,
+// zero past nt. grid (T (T + 1) / 2, nsys).
+__global__ __launch_bounds__(kThreads) void k_pack_coarse_inverse(Geometry g,
+                                                                 const double* __restrict__ cinv,
+                                                                 double* __restrict__ cpk) {
+  const int sys = blockIdx.y, tile = blockIdx.x, nt = g.nt;
+  const int T = coarse_tiles(nt);
+  int I, J;
+  coarse_tile_ij(tile, I, J);
+  const double* src = cinv + (size_t)sys * nt * nt;
+  double* dst = cpk + ((size_t)sys * (T * (T + 1) / 2) + tile) * kCT * kCT;
+  for (int e = threadIdx.x; e < kCT * kCT; e += kThreads) {
+    const int r = I * kCT + e / kCT, c = J * kCT + e % kCT;
+    dst[e] = (r < nt && c < nt) ? src[(size_t)r * nt + c] : 0.0;
   }
-  s = wave_sum(s);
-  if (lane == 0) xc[(size_t)sys * g.nt + row] = s;
+}
+
+// Partial products of x_c = K_c^-1 y_c from the packed lower tiles, for the
+// running systems: tile (I, J) writes K_IJ y_J into slot [I][J] of row block
+// I and, below the diagonal, K_IJ^T y_I into slot [J][I] of row block J, so
+// every slot is written once. Wave w holds rows 16 w .. 16 w + 15 of the
+// tile, lane l column l (each row read as 512 contiguous bytes). Row sums go
+// through LDS (padded rows), column sums over the four waves.
+// grid (T (T + 1) / 2, nsys).
+__global__ __launch_bounds__(kThreads) void k_coarse_gemv_tiles(Geometry g,
+                                                               const double* __restrict__ cpk,
+                                                               const double* __restrict__ yc,
+                                                               double* __restrict__ cpart,
+                                                               Gate gate) {
+  __shared__ double rows[4][16][kCT + 1];
+  __shared__ double cols[4][kCT];
+  const int sys = blockIdx.y, tile = blockIdx.x, nt = g.nt;
+  if (!gate_running(gate, sys)) return;
+  const int T = coarse_tiles(nt);
+  int I, J;
+  coarse_tile_ij(tile, I, J);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  const double* A = cpk + ((size_t)sys * (T * (T + 1) / 2) + tile) * kCT * kCT + 16 * w * kCT;
+  const double* y = yc + (size_t)sys * nt;
+  double a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = A[q * kCT + l];
+  const int cj = J * kCT + l, ri = I * kCT + 16 * w;
+  const double yj = cj < nt ? y[cj] : 0.0;
+  double cs = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    rows[w][q][l] = a[q] * yj;
+    cs += a[q] * (ri + q < nt ? y[ri + q] : 0.0);
+  }
+  cols[w][l] = cs;
+  __syncthreads();
+  double* P = cpart + (size_t)sys * T * T * kCT;
+  {
+    // lane l: row l / 4 of the wave's 16, columns 16 (l % 4) .. + 15
+    const int q = l >> 2, h = l & 3;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += rows[w][q][16 * h + k];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (h == 0) P[((size_t)I * T + J) * kCT + 16 * w + q] = s;
+  }
+  if (I != J && w == 0)
+    P[((size_t)J * T + I) * kCT + l] = (cols[0][l] + cols[1][l]) + (cols[2][l] + cols[3][l]);
+}
+
+// x_c = the sum of a row block's T slots, in slot order. grid (ceil(nt /
+// 256), nsys).
+__global__ __launch_bounds__(kThreads) void k_coarse_gemv_sum(Geometry g,
+                                                             const double* __restrict__ cpart,
+                                                             double* __restrict__ xc, Gate gate) {
+  const int sys = blockIdx.y, nt = g.nt;
+  if (!gate_running(gate, sys)) return;
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  if (r >= nt) return;
+  const int T = coarse_tiles(nt);
+  const double* P = cpart + ((size_t)sys * T * T + (size_t)(r / kCT) * T) * kCT + r % kCT;
+  double s = 0.0;
+  for (int K0 = 0; K0 < T; K0 += 16) {   // sixteen reads in flight, added in slot order
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = K0 + u < T ? P[(size_t)(K0 + u) * kCT] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u];
+  }
+  xc[(size_t)sys * nt + r] = s;
 }
 
 // zloc_j += Phi_j x_c,j in place for every running system: workgroup
@@ -387,6 +436,12 @@ void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& 
 
 }  // namespace
 
+void launch_pack_coarse_inverse(const Handle& h, int nsys, hipStream_t st) {
+  const int T = coarse_tiles(h.g.nt);
+  hipLaunchKernelGGL(k_pack_coarse_inverse, dim3(T * (T + 1) / 2, nsys), dim3(kThreads), 0, st,
+                     h.g, h.cinv, h.cpk);
+}
+
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
                     int rz_slot, int prof_it, int flexible, hipStream_t st) {
   const Geometry& g = h.g;
@@ -410,8 +465,11 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   // stream.
   const bool beside = h.cinv == nullptr;
   if (!beside) {
-    hipLaunchKernelGGL(k_coarse_gemv, dim3(nsys * ((g.nt + 3) / 4)), dim3(kThreads), 0, st, g,
-                       h.cinv, h.yc, h.xc, gate);
+    const int T = coarse_tiles(g.nt);
+    hipLaunchKernelGGL(k_coarse_gemv_tiles, dim3(T * (T + 1) / 2, nsys), dim3(kThreads), 0, st, g,
+                       h.cpk, h.yc, h.cpart, gate);
+    hipLaunchKernelGGL(k_coarse_gemv_sum, dim3((g.nt + kThreads - 1) / kThreads, nsys),
+                       dim3(kThreads), 0, st, g, h.cpart, h.xc, gate);
   } else {
     hipEventRecord(h.fork, st);
     hipStreamWaitEvent(h.side, h.fork, 0);

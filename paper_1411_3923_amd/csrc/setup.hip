@@ -800,7 +800,10 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   }
 
   launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
-  if (h.cinv) launch_inverse(h.cfac, csh, nsys, h.cinv, st);
+  if (h.cinv) {
+    launch_inverse(h.cfac, csh, nsys, h.cinv, st);
+    launch_pack_coarse_inverse(h, nsys, st);
+  }
 
   hipStreamWaitEvent(st, h.join, 0);
   hipStreamSynchronize(st);

@@ -20,6 +20,8 @@ constexpr int kMaxK = 16;            // coarse vectors per subdomain
 constexpr int kMaxSub = 16;          // eigensolver subspace width
 constexpr int kMaxNb = 96;           // largest block of the block-tridiagonal kernels
 constexpr int kDenseCoarse = 12288;  // coarse dimensions up to this keep a dense K_c^-1
+constexpr int kCT = 64;              // tile edge of the packed K_c^-1
+__host__ __device__ inline int coarse_tiles(int nt) { return (nt + kCT - 1) / kCT; }
 
 // Structured-mesh and partition sizes. Everything is derived from the problem.
 struct Geometry {
@@ -100,6 +102,8 @@ struct Handle {
   double* emod64 = nullptr;          // FP64 moduli (mixed precision), [nsys][nel]
   double* cfac = nullptr;            // packed [nsys][nblkc][bstridec]
   double* cinv = nullptr;            // dense K_c^-1 [nsys][nt][nt] when nt <= kDenseCoarse
+  double* cpk = nullptr;             // its lower 64 x 64 tiles [nsys][T (T + 1) / 2][64][64]
+  double* cpart = nullptr;           // tile partials of K_c^-1 y_c [nsys][T][T][64]
   double* build_ws = nullptr;        // work arrays of the preconditioner build
   size_t build_elems = 0;
   hipStream_t side = nullptr;        // second stream for the coarse solve (forked per apply)
@@ -279,6 +283,8 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 
 // precond.hip: z = M^-1 r, gated; partials of r.z into rz_slot (and r.z_old into kPartRZO)
 // prof_it >= -1 records events around the block-solve launch when profiling is on
+// Packs the lower tiles of the dense coarse inverse (after it is formed).
+void launch_pack_coarse_inverse(const Handle& h, int nsys, hipStream_t st);
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
                     int rz_slot, int prof_it, int flexible, hipStream_t st);
 
