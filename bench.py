@@ -290,7 +290,7 @@ def summarize_loop(fetch_csv, write_csv, trace_csv, command, out):
               "| algorithmic MB | algorithmic GB/s |",
               "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for name in ["k_apply_q4", "k_update_xr", "k_update_p", "k_restrict", "k_local_solves",
-                 "k_coarse_gemv", "k_coarse_add", "k_extend"]:
+                 "k_coarse_gemv_tiles", "k_coarse_gemv_sum", "k_coarse_add", "k_extend"]:
         fv, wv, dv = fetch.get(name, []), write.get(name, []), dur.get(name, [])
         if not fv or not dv:
             continue
