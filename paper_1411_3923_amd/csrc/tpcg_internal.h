@@ -106,7 +106,7 @@ struct Handle {
   double* cpart = nullptr;           // tile partials of K_c^-1 y_c [nsys][T][T][64]
   double* build_ws = nullptr;        // work arrays of the preconditioner build
   size_t build_elems = 0;
-  hipStream_t side = nullptr;        // second stream for the coarse solve (forked per apply)
+  hipStream_t side = nullptr;        // second stream: the block coarse solve, the setup's local factors
   hipEvent_t fork = nullptr, join = nullptr;
 
   // workspace
