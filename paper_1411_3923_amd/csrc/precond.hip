@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
     for (int m = 0; m < KM; ++m) acc[q][m] = 0.0;
   // kRU box DOFs per thread at a time, all their loads issued before use
   // (one with the wide accumulators, which fill the registers)
-  constexpr int kRU = KM <= 8 ? 3 : 1;
+  constexpr int kRU = KM <= 8 ? 5 : 1;
   for (int l0 = threadIdx.x; l0 < g.nloc; l0 += kRU * kSubThreads) {
     double rv[kRU][kMaxSys];
 #pragma unroll
