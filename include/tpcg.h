@@ -71,14 +71,25 @@ typedef struct {
   double Emin;          /* void modulus (paper: 1e-9) */
   double penal;         /* SIMP exponent p */
   double nu;            /* Poisson ratio, < 0.5 */
-  int32_t sub;          /* subdomain (unit cell) edge s in elements; nel % sub == 0 */
+  int32_t sub[3];       /* subdomain (unit cell) edge per axis in elements, nel[a] % sub[a] == 0;
+                           the cells must be square (cubic): sub[0] == sub[1] (== sub[2] in 3D;
+                           sub[2] is ignored in 2D) */
   int32_t overlap;      /* element layers of overlap; only 1 is supported */
-  int32_t ncoarse;      /* k: coarse vectors per subdomain */
+  int32_t ncoarse;      /* k: coarse vectors per subdomain (the cap when lambda_thresh > 0) */
   int32_t nsys_max;     /* systems (realisations) solved together, 1..4 */
   int32_t precision;    /* tpcg_precision */
   int32_t eig_iters;    /* subspace iterations for the local eigenproblems (0: default 6) */
   int32_t eig_extra;    /* extra (guard) vectors in the subspace (0: default k, capped at 16 total) */
-  double eig_shift;     /* shift sigma of the shift-invert eigensolver (0: default 1e-5) */
+  double eig_shift;     /* shift sigma of the shift-invert eigensolver (0: default 1e-5); the
+                           factorised matrix is diag(K^N)^-1/2 K^N diag(K^N)^-1/2 + sigma I, so a
+                           sigma <= 0 on a floating cell (rigid-body modes at 0) is indefinite and
+                           the build returns TPCG_ENOTSPD */
+  double lambda_thresh; /* <= 0: exactly ncoarse vectors per subdomain; > 0: the eigenvectors with
+                           eigenvalue below lambda_thresh (Sec. 2.4: one global threshold), at
+                           most ncoarse per subdomain; unused columns are stored as zeros */
+  int32_t coarse_dense_max; /* coarse dimensions up to this keep a dense K_c^-1 applied as a
+                           product; larger ones use the block-tridiagonal coarse factor
+                           (0: default 12288) */
 } tpcg_problem;
 
 /* Per-system result of tpcg_pcg_solve. */
@@ -98,10 +109,12 @@ typedef struct {
  * cells are the unit cells); its unknowns are the nodes of the closed cell,
  * i.e. the cell grown by one element layer with zero displacement on the
  * grown boundary. Subdomains are numbered x fastest. `stream` is a
- * hipStream_t (NULL: the default stream). Returns TPCG_EINVAL for
- * nel % sub != 0, dim not in {2,3}, overlap != 1, ncoarse < 1 or larger
- * than the subdomain's DOFs, nsys_max not in 1..4, or subdomain blocks too
- * large for the on-chip factor kernels.
+ * hipStream_t (NULL: the default stream). Returns TPCG_EINVAL, before any
+ * device call, for nel % sub != 0, non-square (non-cubic) subdomains, dim
+ * not in {2,3}, overlap != 1, ncoarse < 1 or larger than the subdomain's
+ * DOFs, nsys_max not in 1..4, Emin <= 0, E0 < Emin, penal < 1, nu outside
+ * (-1, 0.5), a NaN lambda_thresh or a negative coarse_dense_max. The
+ * preconditioner's own size limits are checked by tpcg_build_coarse_basis.
  */
 int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask,
                          void* stream, tpcg_handle** out);
@@ -119,14 +132,26 @@ size_t tpcg_workspace_bytes(const tpcg_problem* prob, int32_t nsys);
  * chi_j(n) = 1/(number of subdomains containing n). For every system it then
  * factors the local Dirichlet matrices A_j (principal submatrices of K) and the
  * coarse matrix K_c = Phi^T K Phi (coarse projection equation). Blocks until
- * done. Returns TPCG_ENOTSPD if a factorisation meets a non-positive pivot.
+ * done. With lambda_thresh > 0 a subdomain keeps only the eigenvectors whose
+ * eigenvalue lies below it (at most ncoarse; Sec. 2.4 global threshold); the
+ * unused coarse unknowns get a unit diagonal in K_c and stay zero.
+ * Returns TPCG_EINVAL if a density is NaN or outside [0, 1], or if the
+ * subdomain blocks exceed the factor kernels' limits: node-row (2D) or
+ * node-layer (3D) blocks of even size at most 96 (2D s <= 47, 3D s in {1, 3}),
+ * element layers of at most 64 elements, coarse blocks (k times the
+ * subdomains of a cross-section along the axis with the most subdomains) of
+ * even size at most 96. TPCG_ENOMEM if device memory runs out (the handle is
+ * then unchanged and the build may be retried). TPCG_ENOTSPD if a
+ * factorisation meets a non-positive pivot.
  */
 int tpcg_build_coarse_basis(tpcg_handle* h, const double* rho_phys, int32_t nsys, int32_t rep);
 
 /*
  * y = P K(rho) P x with K assembled from E_e = E_min + (E0 - E_min) rho_e^p
  * times the unit element matrix (Sec. 2.2), P zeroing the supported DOFs.
- * rho_phys dev [nsys][n_el], x and y dev [nsys][n_dof]. Matrix-free.
+ * rho_phys dev [nsys][n_el], x and y dev [nsys][n_dof] (16-byte aligned).
+ * Matrix-free. The densities are checked first (one synchronisation):
+ * TPCG_EINVAL if one is NaN or outside [0, 1].
  */
 int tpcg_apply_K(tpcg_handle* h, const double* rho_phys, const double* x, double* y, int32_t nsys);
 
@@ -145,7 +170,9 @@ int tpcg_apply_precond(tpcg_handle* h, const double* r, double* z, int32_t nsys)
  * and the solution on exit. Stops system s when ||r||_2 <= rtol ||P f_s||_2
  * or after maxit iterations. The preconditioner may be stale (built for an
  * older rho); the solution is still that of the new rho. info: host [nsys].
- * Returns the worst status over the systems.
+ * A system whose densities hold a NaN or a value outside [0, 1] does not
+ * start and reports TPCG_EINVAL in its info (u then holds its initial guess
+ * with the supported DOFs zeroed). Returns the worst status over the systems.
  */
 int tpcg_pcg_solve(tpcg_handle* h, const double* rho_phys, const double* f, double* u,
                    int32_t nsys, double rtol, int32_t maxit, tpcg_info* info);
@@ -153,7 +180,9 @@ int tpcg_pcg_solve(tpcg_handle* h, const double* rho_phys, const double* f, doub
 /*
  * Compliance c_s = f_s^T u_s (dev [nsys]) and, if dc is not NULL, the element
  * sensitivities dc/drho_e = -p (E0 - E_min) rho_e^(p-1) u_e^T K0 u_e
- * (dev [nsys][n_el]) (Sec. 4.2: self-adjoint, no adjoint solve).
+ * (dev [nsys][n_el]) (Sec. 4.2: self-adjoint, no adjoint solve). With dc the
+ * densities are checked first (one synchronisation): TPCG_EINVAL if one is
+ * NaN or outside [0, 1].
  */
 int tpcg_compliance_and_sensitivity(tpcg_handle* h, const double* rho_phys, const double* u,
                                     const double* f, int32_t nsys, double* c, double* dc);
@@ -164,7 +193,8 @@ int tpcg_compliance_and_sensitivity(tpcg_handle* h, const double* rho_phys, cons
  * centres), truncated at the mesh boundary and renormalised (rmin <= 1: no
  * filtering); rho_phys[s] = H(rho_tilde; beta, eta[s]) for each threshold
  * (Sec. 4.4). rho dev [n_el], eta host [nsys], rho_tilde dev [n_el],
- * rho_phys dev [nsys][n_el].
+ * rho_phys dev [nsys][n_el]. TPCG_EINVAL if a design variable is NaN or
+ * outside [0, 1] (checked first, one synchronisation).
  */
 int tpcg_filter_project(tpcg_handle* h, const double* rho, double rmin, double beta,
                         const double* eta, int32_t nsys, double* rho_tilde, double* rho_phys);
@@ -187,6 +217,21 @@ int tpcg_filter_project_adjoint(tpcg_handle* h, const double* rho_tilde, double 
  */
 int tpcg_export_coarse_basis(tpcg_handle* h, double* phi, double* lambda, double* resid);
 
+/*
+ * Ritz values of the local eigenproblems (Sec. 2.4 discrete eigenproblem with
+ * the diag(K) weighting of Sec. 3.2) from the last build: lambda host
+ * [n_sub][m], the m smallest of each subdomain in ascending order, m at most
+ * tpcg_query_subspace (the eigensolver's subspace width; values beyond the
+ * ncoarse-th are less accurate); kj host [n_sub] (may be NULL): coarse
+ * vectors in use per subdomain (ncoarse, or fewer under lambda_thresh).
+ * TPCG_ESTATE before a build, TPCG_EINVAL for m out of range.
+ */
+int tpcg_export_eigenvalues(tpcg_handle* h, double* lambda, int32_t m, int32_t* kj);
+
+/* Width of the eigensolver's subspace (ncoarse + eig_extra, at most 16 and at
+ * most the subdomain's DOFs), or TPCG_EINVAL for a null handle. */
+int tpcg_query_subspace(const tpcg_handle* h);
+
 /* Sizes of the handle's structures: out[0] n_dof, out[1] n_el, out[2] n_sub,
  * out[3] n_loc, out[4] k, out[5] local block size, out[6] local block count,
  * out[7] coarse block size, out[8] coarse block count. */
@@ -204,6 +249,13 @@ int tpcg_query(const tpcg_handle* h, int64_t* out9);
  */
 int tpcg_set_profiling(tpcg_handle* h, int32_t on);
 int tpcg_profile_block_solves(const tpcg_handle* h, double* out3);
+
+/*
+ * Testing support for the allocation paths: the nth device allocation the
+ * library makes from this call on fails as if the device were out of memory
+ * (nth <= 0: none). Process-wide, not thread-safe.
+ */
+void tpcg_test_fail_alloc(int32_t nth);
 
 const char* tpcg_last_error(const tpcg_handle* h);
 void tpcg_destroy(tpcg_handle* h);

@@ -112,21 +112,35 @@ def local_eigenpairs(p, E_rep, fixed, j, k, K0=None):
     return lam, psi, dofs
 
 
-def coarse_basis(p, E_rep, fixed, k, K0=None):
-    """Global Phi = R_c^T (n_dof x J*k, sparse) and the per-subdomain eigenvalues."""
+def coarse_basis(p, E_rep, fixed, k, K0=None, thresh=0.0):
+    """Global Phi = R_c^T (sparse) and the per-subdomain eigenvalues.
+
+    thresh <= 0: the k smallest eigenvectors of every subdomain (n_dof x J*k).
+    thresh > 0: Sec. 2.4's global threshold, the eigenvectors whose
+    eigenvalue lies below thresh, at most k per subdomain; Phi then has
+    sum_j k_j columns in subdomain order. Returns (Phi, lams [J][k], kj [J]).
+    """
     chi = partition_of_unity(p)
-    rows, cols, vals, lams = [], [], [], []
+    rows, cols, vals, lams, kj = [], [], [], [], []
+    col = 0
     for j in range(p.n_sub):
         lam, psi, dofs = local_eigenpairs(p, E_rep, fixed, j, k, K0)
+        use = k if thresh <= 0 else int(np.sum(lam < thresh))
         w = chi[dofs // p.dim]
-        for m in range(k):
+        for m in range(use):
             rows.append(dofs)
-            cols.append(np.full(dofs.size, j * k + m))
+            cols.append(np.full(dofs.size, col))
             vals.append(w * psi[:, m])
+            col += 1
         lams.append(lam)
+        kj.append(use)
+    if col == 0:
+        return sp.csc_matrix((p.n_dof, 0)), np.array(lams), np.array(kj)
     Phi = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                        shape=(p.n_dof, p.n_sub * k)).tocsc()
-    return Phi, np.array(lams)
+                        shape=(p.n_dof, col)).tocsc()
+    if thresh <= 0:
+        return Phi, np.array(lams)
+    return Phi, np.array(lams), np.array(kj)
 
 
 # ---------------------------------------------------------------------------
@@ -154,8 +168,8 @@ class TwoLevelSchwarz:
                     self.local.append((dofs, _BandedCholesky(A)))
                 else:
                     self.local.append((dofs, _DenseCholesky(A.toarray())))
-        self.Phi = Phi
-        if Phi is not None:
+        self.Phi = Phi if (Phi is None or Phi.shape[1] > 0) else None
+        if self.Phi is not None:
             Kc = (Phi.T @ (K @ Phi)).toarray()
             self.Kc = Kc
             self.Kc_chol = sla.cho_factor(Kc, lower=True)

@@ -33,10 +33,11 @@ class Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("nel", ctypes.c_int32 * 3),
                 ("E0", ctypes.c_double), ("Emin", ctypes.c_double),
                 ("penal", ctypes.c_double), ("nu", ctypes.c_double),
-                ("sub", ctypes.c_int32), ("overlap", ctypes.c_int32),
+                ("sub", ctypes.c_int32 * 3), ("overlap", ctypes.c_int32),
                 ("ncoarse", ctypes.c_int32), ("nsys_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("eig_iters", ctypes.c_int32),
-                ("eig_extra", ctypes.c_int32), ("eig_shift", ctypes.c_double)]
+                ("eig_extra", ctypes.c_int32), ("eig_shift", ctypes.c_double),
+                ("lambda_thresh", ctypes.c_double), ("coarse_dense_max", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -50,8 +51,8 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_apply_K", "tpcg_apply_precond", "tpcg_pcg_solve",
            "tpcg_compliance_and_sensitivity", "tpcg_filter_project",
            "tpcg_filter_project_adjoint", "tpcg_export_coarse_basis", "tpcg_query",
-           "tpcg_set_profiling", "tpcg_profile_block_solves", "tpcg_last_error",
-           "tpcg_destroy"]
+           "tpcg_set_profiling", "tpcg_profile_block_solves", "tpcg_export_eigenvalues",
+           "tpcg_query_subspace", "tpcg_test_fail_alloc", "tpcg_last_error", "tpcg_destroy"]
 
 
 def load_library(path: str | None = None):
@@ -78,6 +79,10 @@ def load_library(path: str | None = None):
     lib.tpcg_query.argtypes = [P, ctypes.POINTER(ctypes.c_int64)]
     lib.tpcg_set_profiling.argtypes = [P, I32]
     lib.tpcg_profile_block_solves.argtypes = [P, ctypes.POINTER(D)]
+    lib.tpcg_export_eigenvalues.argtypes = [P, P, I32, P]
+    lib.tpcg_query_subspace.argtypes = [P]
+    lib.tpcg_test_fail_alloc.argtypes = [I32]
+    lib.tpcg_test_fail_alloc.restype = None
     lib.tpcg_last_error.argtypes = [P]
     lib.tpcg_last_error.restype = ctypes.c_char_p
     lib.tpcg_destroy.argtypes = [P]
@@ -90,14 +95,20 @@ def load_library(path: str | None = None):
 
 
 def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.0, nu=0.3,
-                 precision=FP64, eig_iters=0, eig_extra=0, eig_shift=0.0) -> Problem:
+                 precision=FP64, eig_iters=0, eig_extra=0, eig_shift=0.0, lambda_thresh=0.0,
+                 coarse_dense_max=0, overlap=1) -> Problem:
+    """tpcg_problem; `sub` is the subdomain edge (an int) or a per-axis tuple."""
     pr = Problem()
     pr.dim = dim
     nel = tuple(nel) + (1,) * (3 - len(nel))
     pr.nel[0], pr.nel[1], pr.nel[2] = nel[0], nel[1], nel[2] if dim == 3 else 1
     pr.E0, pr.Emin, pr.penal, pr.nu = E0, Emin, penal, nu
-    pr.sub, pr.overlap, pr.ncoarse, pr.nsys_max = sub, 1, ncoarse, nsys_max
+    subs = tuple(sub) if isinstance(sub, (tuple, list)) else (sub,) * dim
+    subs = subs + (subs[-1],) * (3 - len(subs))
+    pr.sub[0], pr.sub[1], pr.sub[2] = subs[0], subs[1], subs[2]
+    pr.overlap, pr.ncoarse, pr.nsys_max = overlap, ncoarse, nsys_max
     pr.precision, pr.eig_iters, pr.eig_extra, pr.eig_shift = precision, eig_iters, eig_extra, eig_shift
+    pr.lambda_thresh, pr.coarse_dense_max = lambda_thresh, coarse_dense_max
     return pr
 
 
@@ -223,6 +234,18 @@ class Handle:
         out = (ctypes.c_double * 3)()
         self._check(self.lib.tpcg_profile_block_solves(self.h, out))
         return dict(launches=int(out[0]), ms=out[1], bytes=out[2])
+
+    def export_eigenvalues(self, m=None):
+        """Ritz values [n_sub][m] (m defaults to the subspace width) and the
+        coarse vectors in use per subdomain."""
+        import numpy as np
+        msub = self.lib.tpcg_query_subspace(self.h)
+        m = msub if m is None else m
+        lam = np.zeros((self.n_sub, m))
+        kj = np.zeros(self.n_sub, dtype=np.int32)
+        self._check(self.lib.tpcg_export_eigenvalues(self.h, lam.ctypes.data_as(ctypes.c_void_p), m,
+                                                     kj.ctypes.data_as(ctypes.c_void_p)))
+        return lam, kj
 
     def export_coarse_basis(self):
         import numpy as np

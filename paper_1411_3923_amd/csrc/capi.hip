@@ -36,14 +36,18 @@ std::string make_geometry(const tpcg_problem& pr, Geometry& g) {
   g.nely = pr.nel[1];
   g.nelz = d == 3 ? pr.nel[2] : 1;
   if (g.nelx < 1 || g.nely < 1 || g.nelz < 1) return "element counts must be positive";
-  g.s = pr.sub;
+  g.s = pr.sub[0];
   if (g.s < 1) return "sub must be positive";
+  if (pr.sub[1] != g.s || (d == 3 && pr.sub[2] != g.s))
+    return "subdomains must be square (cubic in 3D): sub[0] == sub[1] (== sub[2])";
   if (g.nelx % g.s || g.nely % g.s || (d == 3 && g.nelz % g.s))
     return "element counts must be multiples of sub";
   if (pr.overlap != 1) return "only overlap = 1 is supported";
   if (!(pr.nu > -1.0 && pr.nu < 0.5)) return "nu must lie in (-1, 0.5)";
   if (!(pr.Emin > 0.0) || !(pr.E0 >= pr.Emin)) return "need 0 < Emin <= E0";
   if (!(pr.penal >= 1.0)) return "penal must be >= 1";
+  if (!(pr.lambda_thresh == pr.lambda_thresh)) return "lambda_thresh is NaN";
+  if (pr.coarse_dense_max < 0) return "coarse_dense_max must be >= 0";
   g.nnx = g.nelx + 1;
   g.nny = g.nely + 1;
   g.nnz = d == 3 ? g.nelz + 1 : 1;
@@ -70,6 +74,7 @@ std::string make_geometry(const tpcg_problem& pr, Geometry& g) {
   g.nblkc = cnt[g.caxis];
   g.nbc = g.k * (g.nsub / g.nblkc);
   g.nt = g.nsub * g.k;
+  g.dense_max = pr.coarse_dense_max > 0 ? pr.coarse_dense_max : kDenseCoarse;
   // packed factor records: B_{b+1} reaches pe diagonals below its main one
   {
     int64_t w = 1;
@@ -123,7 +128,8 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += sizeof(double) * nsys * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
   if (mixed) p += sizeof(double) * nsys * (size_t)g.nel;
   p += sizeof(double) * nsys * crec;
-  if (g.nt <= kDenseCoarse) {
+  p += sizeof(int) * (size_t)g.nsub;
+  if (g.nt <= g.dense_max) {
     const size_t T = coarse_tiles(g.nt);
     p += sizeof(double) * nsys * ((size_t)g.nt * g.nt + T * (T + 1) / 2 * kCT * kCT + T * T * kCT);
   }
@@ -139,17 +145,47 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   return {p, std::max(eig, coarse)};
 }
 
+// Fault injection for the tests of the allocation paths: the n-th device
+// allocation from now on fails (0: none).
+int g_fail_at = 0;
+int g_alloc_count = 0;
+
 template <typename T>
 int alloc(T*& p, size_t n) {
   void* v = nullptr;
-  if (hipMalloc(&v, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return TPCG_ENOMEM;
+  if (!device_alloc(&v, std::max<size_t>(n, 1) * sizeof(T))) return TPCG_ENOMEM;
   p = reinterpret_cast<T*>(v);
   return TPCG_OK;
 }
 
+// A group of device allocations that either all succeed or leave nothing
+// behind: the targets are assigned only when every allocation succeeded.
+struct AllocGroup {
+  std::vector<std::pair<void**, size_t>> want;
+  template <typename T>
+  void add(T*& dst, size_t elems) {
+    want.emplace_back(reinterpret_cast<void**>(&dst), std::max<size_t>(elems, 1) * sizeof(T));
+  }
+  void add_bytes(void*& dst, size_t bytes) { want.emplace_back(&dst, std::max<size_t>(bytes, 1)); }
+  int commit() {
+    std::vector<void*> got;
+    got.reserve(want.size());
+    for (auto& w : want) {
+      void* v = nullptr;
+      if (!device_alloc(&v, w.second)) {
+        for (void* q : got) hipFree(q);
+        return TPCG_ENOMEM;
+      }
+      got.push_back(v);
+    }
+    for (size_t i = 0; i < want.size(); ++i) *want[i].first = got[i];
+    return TPCG_OK;
+  }
+};
+
 void release(Handle* h) {
   if (!h) return;
-  void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam,      h->eres, h->lfac,
+  void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam, h->kj,     h->eres, h->lfac,
                   h->emod,  h->twist, h->emod64, h->cfac, h->cinv, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
                   h->dflag, h->build_ws};
@@ -174,6 +210,22 @@ int check_hip(Handle* h, const char* where) {
     h->err = std::string(where) + ": " + hipGetErrorString(e);
     return TPCG_EHIP;
   }
+  return TPCG_OK;
+}
+
+// Densities of the entry points that return after enqueueing are checked
+// here, synchronously: TPCG_EINVAL when any of nsys x n values is NaN or
+// outside [0, 1].
+int check_rho_sync(Handle* h, const double* rho, int64_t n, int nsys) {
+  int* hf = h->hpoll + 2 * kMaxSys;
+  hipMemsetAsync(h->dflag + 1, 0, sizeof(int), h->stream);
+  launch_check_rho(rho, n, nsys, h->dflag + 1, 0, 1, h->stream);
+  hipMemcpyAsync(hf, h->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+  hipStreamSynchronize(h->stream);
+  int rc = check_hip(h, "density check");
+  if (rc != TPCG_OK) return rc;
+  if (*hf) return fail(reinterpret_cast<tpcg_handle*>(h), TPCG_EINVAL,
+                       "densities must lie in [0, 1] (NaN or out-of-range value found)");
   return TPCG_OK;
 }
 
@@ -209,6 +261,20 @@ Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int
 }
 
 }  // namespace
+
+namespace tpcg {
+bool device_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  ++g_alloc_count;
+  if (g_fail_at > 0 && g_alloc_count == g_fail_at) return false;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();   // no stale error for the next check
+    *p = nullptr;
+    return false;
+  }
+  return true;
+}
+}  // namespace tpcg
 
 extern "C" {
 
@@ -253,7 +319,8 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
     fprintf(stderr, "tpcg_build_partition: out of device memory\n");
     return TPCG_ENOMEM;
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), 2 * kMaxSys * sizeof(int)) != hipSuccess ||
+  hipMemset(h->dflag, 0, 4 * sizeof(int));
+  if (hipHostMalloc(reinterpret_cast<void**>(&h->hpoll), (2 * kMaxSys + 1) * sizeof(int)) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming) != hipSuccess ||
       hipEventCreate(&h->t0) != hipSuccess || hipEventCreate(&h->t1) != hipSuccess ||
@@ -307,41 +374,38 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
   const Geometry& g = h->g;
   std::string lim = precond_limits(g);
   if (!lim.empty()) return fail(hh, TPCG_EINVAL, lim);
+  int rc = check_rho_sync(h, rho_phys, g.nel, nsys);
+  if (rc != TPCG_OK) return rc;
   h->basis_ready = 0;
   if (!h->phi) {
-    // preconditioner storage for nsys_max systems, allocated on first build
+    // preconditioner storage for nsys_max systems, allocated on the first
+    // build, all or nothing (a failed build leaves the handle as it was)
     const int ns = h->prob.nsys_max;
     const size_t fsz = (size_t)g.nblk * tile_shape(g.nb).tstride;
     const size_t cfsz = (size_t)g.nblkc * g.bstridec;
     const size_t ts = h->mixed ? 4 : 8;
-    int e = TPCG_OK;
-    e |= alloc(h->phi, (size_t)g.nsub * g.nloc * g.k);
-    unsigned char* pm = nullptr;
-    e |= alloc(pm, ts * (size_t)g.nsub * g.nloc * g.k);
-    h->phim = pm;
-    e |= alloc(h->lam, (size_t)g.nsub * h->msub);
-    e |= alloc(h->eres, (size_t)g.nsub * h->msub);
-    unsigned char* lf = nullptr;
-    e |= alloc(lf, ts * ns * g.nsub * fsz);
-    h->lfac = lf;
-    unsigned char* em = nullptr;
-    e |= alloc(em, ts * ns * (size_t)g.nel);
-    h->emod = em;
-    e |= alloc(h->twist, (size_t)ns * g.nsub * g.nb * (g.nb + 1) / 2);
-    if (h->mixed) e |= alloc(h->emod64, (size_t)ns * g.nel);
-    e |= alloc(h->cfac, ns * cfsz);
-    if (g.nt <= kDenseCoarse) {
+    AllocGroup a;
+    a.add(h->phi, (size_t)g.nsub * g.nloc * g.k);
+    a.add_bytes(h->phim, ts * (size_t)g.nsub * g.nloc * g.k);
+    a.add(h->lam, (size_t)g.nsub * h->msub);
+    a.add(h->kj, (size_t)g.nsub);
+    a.add(h->eres, (size_t)g.nsub * h->msub);
+    a.add_bytes(h->lfac, ts * ns * g.nsub * fsz);
+    a.add_bytes(h->emod, ts * ns * (size_t)g.nel);
+    a.add(h->twist, (size_t)ns * g.nsub * g.nb * (g.nb + 1) / 2);
+    if (h->mixed) a.add(h->emod64, (size_t)ns * g.nel);
+    a.add(h->cfac, ns * cfsz);
+    if (g.nt <= g.dense_max) {
       const size_t T = coarse_tiles(g.nt);
-      e |= alloc(h->cinv, (size_t)ns * g.nt * g.nt);
-      e |= alloc(h->cpk, (size_t)ns * T * (T + 1) / 2 * kCT * kCT);
-      e |= alloc(h->cpart, (size_t)ns * T * T * kCT);
+      a.add(h->cinv, (size_t)ns * g.nt * g.nt);
+      a.add(h->cpk, (size_t)ns * T * (T + 1) / 2 * kCT * kCT);
+      a.add(h->cpart, (size_t)ns * T * T * kCT);
     }
-    unsigned char* zl = nullptr;
-    e |= alloc(zl, ts * ns * (size_t)g.nsub * g.nloc);
-    h->zloc = zl;
-    e |= alloc(h->yc, ns * (size_t)g.nt);
-    e |= alloc(h->xc, ns * (size_t)g.nt);
-    if (e != TPCG_OK) return fail(hh, TPCG_ENOMEM, "out of device memory for the preconditioner");
+    a.add_bytes(h->zloc, ts * ns * (size_t)g.nsub * g.nloc);
+    a.add(h->yc, ns * (size_t)g.nt);
+    a.add(h->xc, ns * (size_t)g.nt);
+    if (a.commit() != TPCG_OK)
+      return fail(hh, TPCG_ENOMEM, "out of device memory for the preconditioner");
   }
   return build_preconditioner(*h, rho_phys, nsys, rep);
 }
@@ -353,6 +417,8 @@ int tpcg_apply_K(tpcg_handle* hh, const double* rho_phys, const double* x, doubl
   if (!rho_phys || !x || !y) return fail(hh, TPCG_EINVAL, "NULL array");
   if (!aligned16(x) || !aligned16(y)) return fail(hh, TPCG_EINVAL, "vectors must be 16-byte aligned");
   if (nsys < 1 || nsys > h->prob.nsys_max) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  int rc = check_rho_sync(h, rho_phys, h->g.nel, nsys);
+  if (rc != TPCG_OK) return rc;
   Gate nog = make_gate(h, kPartRR0, 0, 1, 0.0, 0);
   launch_apply_K(*h, rho_phys, x, y, nsys, -1, nog, h->stream);
   return check_hip(h, "tpcg_apply_K");
@@ -391,6 +457,8 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   nog.enabled = 0;
   launch_apply_K(*h, rho_phys, u, h->q, nsys, -1, nog, st);
   launch_residual_init(*h, f, u, h->q, nsys, st);
+  // a system with invalid densities never starts and reports TPCG_EINVAL
+  launch_check_rho(rho_phys, h->g.nel, nsys, h->istate + kStBreak * kMaxSys, 1, 2, st);
   launch_gate(*h, nsys, g0, st);
   h->prof_n = 0;
   launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, -1, flexible, st);
@@ -481,7 +549,8 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
       h->prof_launches += 1;
     }
   }
-  if (worst == TPCG_EBREAKDOWN) h->err = "PCG breakdown (p^T K p <= 0, r^T z <= 0 or NaN)";
+  if (worst == TPCG_EINVAL) h->err = "densities must lie in [0, 1] (NaN or out-of-range value found)";
+  else if (worst == TPCG_EBREAKDOWN) h->err = "PCG breakdown (p^T K p <= 0, r^T z <= 0 or NaN)";
   else if (worst == TPCG_ENOCONV) h->err = "maxit reached before rtol";
   return worst;
 }
@@ -493,6 +562,10 @@ int tpcg_compliance_and_sensitivity(tpcg_handle* hh, const double* rho_phys, con
   if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
   if (!rho_phys || !u || !f || !c) return fail(hh, TPCG_EINVAL, "NULL argument");
   if (nsys < 1 || nsys > h->prob.nsys_max) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  if (dc) {
+    int rc = check_rho_sync(h, rho_phys, h->g.nel, nsys);
+    if (rc != TPCG_OK) return rc;
+  }
   launch_compliance_sens(*h, rho_phys, u, f, nsys, c, dc, h->stream);
   return check_hip(h, "tpcg_compliance_and_sensitivity");
 }
@@ -506,6 +579,8 @@ int tpcg_filter_project(tpcg_handle* hh, const double* rho, double rmin, double 
   if (nsys < 1 || nsys > kMaxSys) return fail(hh, TPCG_EINVAL, "nsys out of range");
   if (!(beta > 0.0)) return fail(hh, TPCG_EINVAL, "beta must be > 0");
   if (rmin > 8.0) return fail(hh, TPCG_EINVAL, "rmin above 8 elements is not supported");
+  int rc = check_rho_sync(h, rho, h->g.nel, 1);
+  if (rc != TPCG_OK) return rc;
   launch_filter_project(*h, rho, rmin, beta, eta, nsys, rho_tilde, rho_phys, h->stream);
   return check_hip(h, "tpcg_filter_project");
 }
@@ -571,6 +646,33 @@ int tpcg_profile_block_solves(const tpcg_handle* hh, double* out3) {
   out3[1] = h->prof_ms;
   out3[2] = h->prof_bytes;
   return TPCG_OK;
+}
+
+int tpcg_export_eigenvalues(tpcg_handle* hh, double* lambda, int32_t m, int32_t* kj) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
+  if (m < 0 || m > h->msub) return fail(hh, TPCG_EINVAL, "m exceeds the eigensolver's subspace");
+  const Geometry& g = h->g;
+  hipStreamSynchronize(h->stream);
+  if (lambda && m > 0) {
+    std::vector<double> tmp((size_t)g.nsub * h->msub);
+    hipMemcpy(tmp.data(), h->lam, sizeof(double) * tmp.size(), hipMemcpyDeviceToHost);
+    for (int j = 0; j < g.nsub; ++j)
+      for (int i = 0; i < m; ++i) lambda[(size_t)j * m + i] = tmp[(size_t)j * h->msub + i];
+  }
+  if (kj) hipMemcpy(kj, h->kj, sizeof(int) * g.nsub, hipMemcpyDeviceToHost);
+  return check_hip(h, "tpcg_export_eigenvalues");
+}
+
+int tpcg_query_subspace(const tpcg_handle* hh) {
+  const Handle* h = H(hh);
+  return h ? h->msub : TPCG_EINVAL;
+}
+
+void tpcg_test_fail_alloc(int32_t nth) {
+  g_fail_at = nth > 0 ? nth : 0;
+  g_alloc_count = 0;
 }
 
 const char* tpcg_last_error(const tpcg_handle* hh) {

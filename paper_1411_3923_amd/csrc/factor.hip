@@ -897,8 +897,9 @@ void local_factor_as(const StencilIn& si, T* out, int* flag, int nsys, size_t os
 }
 
 // block sizes with a compiled local factorisation: d (s + 1)^(d - 1) DOFs per
-// node layer of a subdomain of s cells a side, 2-d s = 4 ... 40, 3-d s = 1 ... 4
-#define TPCG_LF_SIZES(X) X(10) X(18) X(34) X(50) X(66) X(82) X(12) X(27) X(48) X(75)
+// node layer of a subdomain of s cells a side, 2-d s = 4 ... 40, 3-d s = 1 and 3 (odd 3-d
+// blocks, s = 2 and 4, are refused by the preconditioner build)
+#define TPCG_LF_SIZES(X) X(10) X(18) X(34) X(50) X(66) X(82) X(12) X(48)
 
 bool local_factor_fits(const Geometry& g) {
   bool known = false;

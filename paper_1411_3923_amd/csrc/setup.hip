@@ -275,12 +275,15 @@ __device__ inline int axis_mult(int i, int s, int nel) {
 // Rayleigh-Ritz on span(X) with SX = S X: H = X^T S X, H = Q Theta Q^T
 // (cyclic Jacobi), Ritz vectors X Q in ascending order; writes the Ritz
 // values, the residual norms ||S x - theta x|| and Phi_j = chi D^-1/2 (X Q)[:, :k].
+// With thr > 0 only the Ritz vectors of Ritz values below thr (at most k)
+// are kept; the other columns of Phi_j are zero and kj[j] counts the kept.
 __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* __restrict__ X,
                                                     const double* __restrict__ SX,
                                                     const double* __restrict__ dis, int m,
                                                     double* __restrict__ lam,
                                                     double* __restrict__ eres,
-                                                    double* __restrict__ phi) {
+                                                    double* __restrict__ phi, double thr,
+                                                    int* __restrict__ kj) {
   __shared__ double sh[4];
   __shared__ double part[4][256];
   __shared__ double H[kMaxSub * kMaxSub];
@@ -362,6 +365,13 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
     Qo[t] = r < m && i < m ? Qm[r * kMaxSub + ord[i]] : 0.0;
   }
   __syncthreads();
+  // modes in use: the first kuse in ascending order
+  int kuse = g.k;
+  if (thr > 0.0) {
+    kuse = 0;
+    while (kuse < g.k && th[ord[kuse]] < thr) ++kuse;
+  }
+  if (t == 0) kj[j] = kuse;
   // residuals and the basis
   double racc[kMaxSub];
 #pragma unroll
@@ -397,7 +407,7 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
       const double res = sv - th[ord[i]] * xv;
 #pragma unroll
       for (int ii = 0; ii < kMaxSub; ++ii) racc[ii] += ii == i ? res * res : 0.0;
-      if (i < k) phi[((size_t)j * g.nloc + l) * k + i] = chi * sd * xv;
+      if (i < k) phi[((size_t)j * g.nloc + l) * k + i] = i < kuse ? chi * sd * xv : 0.0;
     }
   }
 #pragma unroll
@@ -490,13 +500,16 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
 // Blocks Phi_l^T W_j of K_c for every neighbour l of j, one pass over the
 // nodes for all k x k mode pairs (k <= KM): thread-local outer products,
 // then one reduction per pair. grid.x = nsub * 3^d, grid.y = system.
+// Unused modes (zero columns of Phi, threshold mode) get a unit diagonal, so
+// that K_c stays nonsingular and their coarse unknowns stay zero.
 template <int KM>
 __global__ __launch_bounds__(kThreads) void k_coarse_assemble_all(Geometry g,
                                                                   const double* __restrict__ phi,
                                                                   const double* __restrict__ W,
                                                                   size_t wstride,
                                                                   double* __restrict__ cf,
-                                                                  size_t cstride) {
+                                                                  size_t cstride,
+                                                                  const int* __restrict__ kj) {
   __shared__ double red[kThreads / 64][KM * KM];
   const int nnb = g.dim == 3 ? 27 : 9;
   const int j = blockIdx.x / nnb;
@@ -562,6 +575,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse_assemble_all(Geometry g,
     double v = 0.0;
 #pragma unroll
     for (int w2 = 0; w2 < kThreads / 64; ++w2) v += red[w2][a * KM + b];
+    if (l == j && a == b && a >= kj[j]) v = 1.0;
     blk[(size_t)(rin + a) * g.nbc + cin + b] = v;
   }
 }
@@ -571,7 +585,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse_assemble_all(Geometry g,
 // storage). grid.x = nsub * 3^d.
 __global__ __launch_bounds__(kThreads) void k_coarse_assemble(Geometry g, const double* __restrict__ phi,
                                                              const double* __restrict__ W,
-                                                             double* __restrict__ cf) {
+                                                             double* __restrict__ cf,
+                                                             const int* __restrict__ kj) {
   __shared__ double sh[4];
   const int nnb = g.dim == 3 ? 27 : 9;
   const int j = blockIdx.x / nnb;
@@ -614,7 +629,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse_assemble(Geometry g, const 
       }
     }
     for (int mm = 0; mm < k; ++mm) {
-      const double v = block_sum(acc[mm], sh);
+      double v = block_sum(acc[mm], sh);
+      if (l == j && mr == mm && mr >= kj[j]) v = 1.0;
       if (threadIdx.x == 0) blk[(size_t)(rin + mr) * g.nbc + cin + mm] = v;
     }
   }
@@ -647,7 +663,7 @@ template <typename T>
 T* dalloc(size_t n, int& err) {
   void* p = nullptr;
   if (n == 0) n = 1;
-  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) { err = TPCG_ENOMEM; return nullptr; }
+  if (!device_alloc(&p, n * sizeof(T))) { err = TPCG_ENOMEM; return nullptr; }
   return reinterpret_cast<T*>(p);
 }
 
@@ -663,7 +679,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;
   const int m = h.msub;
   const int iters = pr.eig_iters > 0 ? pr.eig_iters : 6;
-  MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift > 0.0 ? pr.eig_shift : 1.0e-5};
+  MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift != 0.0 ? pr.eig_shift : 1.0e-5};
 
   // work arrays of the build, kept by the handle from one build to the next:
   // the eigensolver's (Neumann factor, scaling, two subspace blocks), then the
@@ -675,6 +691,8 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
       std::max(rec + nsl * (1 + 2 * (size_t)m), (wsz + asm_coarse) * pr.nsys_max);
   if (h.build_elems < need) {
     if (h.build_ws) hipFree(h.build_ws);
+    h.build_ws = nullptr;
+    h.build_elems = 0;
     h.build_ws = dalloc<double>(need, err);
     h.build_elems = h.build_ws ? need : 0;
     if (err) { h.err = "out of device memory for the preconditioner build"; return err; }
@@ -716,7 +734,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     hipLaunchKernelGGL(k_neumann_apply<3>, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis,
                        X, Y, m, mp);
   hipLaunchKernelGGL(k_eig_rr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, Y, dis, m, h.lam,
-                     h.eres, h.phi);
+                     h.eres, h.phi, pr.lambda_thresh, h.kj);
   if (h.mixed)
     hipLaunchKernelGGL(k_phi_modes<float>, dim3(1024), dim3(kThreads), 0, st, g, h.phi,
                        reinterpret_cast<float*>(h.phim));
@@ -746,11 +764,11 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   }
   if (g.k <= 8) {
     hipLaunchKernelGGL(k_coarse_assemble_all<8>, dim3(g.nsub * nnb, nsys), dim3(kThreads), 0, st,
-                       g, h.phi, W, wsz, Ac, asm_coarse);
+                       g, h.phi, W, wsz, Ac, asm_coarse, h.kj);
   } else {
     for (int sys = 0; sys < nsys; ++sys)
       hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi,
-                         W + sys * wsz, Ac + sys * asm_coarse);
+                         W + sys * wsz, Ac + sys * asm_coarse, h.kj);
   }
   hipEventRecord(h.fork, st);
   hipStreamWaitEvent(h.side, h.fork, 0);

@@ -42,6 +42,7 @@ struct Geometry {
   int nbc, nblkc;                    // coarse block size, block count
   int pec, bstridec;                 // coarse packed factor
   int nt;                            // coarse dimension nsub * k
+  int dense_max;                     // coarse dimensions up to this keep a dense K_c^-1
   int ebn;                           // nodes per extended box edge (s + 3)
   int nebox;                         // nodes per extended box
   int ndpe;                          // DOFs per element (8 or 24)
@@ -95,6 +96,7 @@ struct Handle {
   double* phi = nullptr;             // [nsub][nloc][k]
   void* phim = nullptr;              // mode-major copy [nsub][k][nloc], double (FP32 when mixed)
   double* lam = nullptr;             // [nsub][msub] Ritz values
+  int* kj = nullptr;                 // [nsub] coarse vectors in use (the rest of the k columns are zero)
   double* eres = nullptr;            // [nsub][msub] residual norms
   void* lfac = nullptr;              // tiled D_b [nsys][nsub][nblk][tstride], double or float
   void* emod = nullptr;              // moduli the local factors were built from [nsys][nel], same type
@@ -120,7 +122,7 @@ struct Handle {
   double* xc = nullptr;              // [nsys][nt]
   double* parts = nullptr;           // reduction partials, see kParts* offsets
   int* istate = nullptr;             // per-system integer state, see kSt*
-  int* hpoll = nullptr;              // pinned host [2][kMaxSys]
+  int* hpoll = nullptr;              // pinned host [2][kMaxSys], then one validation flag
   int* dflag = nullptr;              // device error flags [4]
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -160,7 +162,8 @@ __host__ __device__ inline double* scal_slot(double* parts, int which) {
   return parts + (size_t)kNumPartSlots * kMaxSys * kMaxParts + 4 * kMaxSys + which * kMaxSys;
 }
 
-// Per-system integer state [kNumState][kMaxSys].
+// Per-system integer state [kNumState][kMaxSys]. kStBreak: 1 breakdown, 2
+// invalid densities (the system never starts).
 enum { kStLastIt = 0, kStBreak = 1, kStPoll = 2, kStRun = 3, kNumState = 4 };
 
 // ---------------------------------------------------------------------------
@@ -306,5 +309,14 @@ void launch_compliance_sens(const Handle& h, const double* rho, const double* u,
 
 // element.cpp
 void element_stiffness(int dim, double nu, double* K0 /* [ndpe*ndpe] */);
+
+// capi.hip: device allocation through the library's fault-injection counter
+// (tpcg_test_fail_alloc); false when the allocation failed
+bool device_alloc(void** p, size_t bytes);
+
+// vectors.hip: densities outside [0, 1] or NaN. Per system s of [nsys][n]
+// with a bad entry: flag[s * stride] = value.
+void launch_check_rho(const double* rho, int64_t n, int nsys, int* flag, int stride, int value,
+                      hipStream_t st);
 
 }  // namespace tpcg

@@ -185,6 +185,22 @@ __global__ void k_poll(Gate gate, int* __restrict__ istate) {
   if (threadIdx.x == 0) istate[kStPoll * kMaxSys + sys] = run ? 1 : 0;
 }
 
+// flag[sys * stride] = value when a density of system sys is NaN or outside
+// [0, 1] (racing writers store the same value)
+__global__ __launch_bounds__(kThreads) void k_check_rho(const double* __restrict__ rho, int64_t n,
+                                                       int* __restrict__ flag, int stride,
+                                                       int value) {
+  const int sys = blockIdx.y;
+  const double* rs = rho + (size_t)sys * n;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    const double v = rs[i];
+    bad |= !(v >= 0.0 && v <= 1.0);
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) flag[sys * stride] = value;
+}
+
 // partials of ||P (f - q)||^2 into slot Aux
 __global__ __launch_bounds__(kThreads) void k_true_residual(
     Geometry g, const double* __restrict__ f, const double* __restrict__ q,
@@ -216,7 +232,8 @@ __global__ void k_finalize(Gate gate, const double* __restrict__ parts,
   if (threadIdx.x == 0) {
     const int brk = istate[kStBreak * kMaxSys + sys];
     double status = TPCG_OK;
-    if (brk) status = TPCG_EBREAKDOWN;
+    if (brk == 2) status = TPCG_EINVAL;
+    else if (brk) status = TPCG_EBREAKDOWN;
     else if (!(rr <= gate.tol2 * ff)) status = TPCG_ENOCONV;
     out[4 * sys + 0] = istate[kStLastIt * kMaxSys + sys];
     out[4 * sys + 1] = status;
@@ -259,6 +276,15 @@ void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
 
 void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
   hipLaunchKernelGGL(k_poll, dim3(nsys), dim3(kThreads), 0, st, gate, h.istate);
+}
+
+void launch_check_rho(const double* rho, int64_t n, int nsys, int* flag, int stride, int value,
+                      hipStream_t st) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_check_rho, dim3((unsigned)b, nsys), dim3(kThreads), 0, st, rho, n, flag,
+                     stride, value);
 }
 
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st) {

@@ -1,0 +1,335 @@
+"""GPU parity tests at the shapes the product runs, and of every
+preconditioner path the build accepts, against the FP64 oracle:
+
+* the production subdomain shape (s = 32, k = 6, the 1024 x 512 cantilever's
+  local block size) on a 128 x 96 section: M^-1 r element by element and the
+  eigenpairs;
+* 3D (H8) subdomains (s = 3): M^-1 r and PCG against the direct solve;
+* the generic factorisation kernel for 2D block sizes without a compiled
+  local factorisation (s = 6, 12);
+* the block-tridiagonal coarse solve used when the coarse space is too large
+  for a dense inverse (forced with a small coarse_dense_max);
+* the eigenvalue-threshold mode (Sec. 2.4 global threshold);
+* the error paths: invalid densities, an indefinite shifted factorisation,
+  failed device allocations.
+
+Tolerances. M^-1 r is compared element by element as
+max_i |z_i - z_o,i| / max_i |z_o,i|. Both sides apply the same operator in
+FP64 through different but backward-stable factorisations (twisted
+Schur-complement inverses against banded Cholesky, a dense coarse inverse
+against a dense Cholesky), measured at a few 1e-15; the FP64 bound is
+1e-12. The mixed mode stores the local factors and the basis in FP32 (unit
+roundoff 6e-8), measured at 1e-7 to 2e-7 element by element; its bound is
+1e-6. Eigenvalues of the diagonally scaled Neumann matrices (spectrum in
+[0, ~4]) carry an absolute rounding error of a few 1e-16, so they are
+compared relative to max(|lambda|, 1e-6).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import density, fem, schwarz
+from paper_1411_3923_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1411_3923_amd as T  # noqa: E402
+from tests.gpu_common import dev, handle, host, rel  # noqa: E402
+
+CONVERGED_SWEEPS = 40
+
+
+def elementwise(a, b):
+    return float(np.max(np.abs(np.ravel(a) - np.ravel(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def production_section():
+    # the local block size of the 1024 x 512 cantilever (s = 32, k = 6) on a
+    # 4 x 3 grid of subdomains: two interior (floating) cells, edge cells on
+    # the clamp and the free end
+    return W.cantilever2d(128, 96, 32, 6)
+
+
+def projected(p):
+    rho = W.design_field(p)
+    _, rb = density.filter_project(p, rho, p.rmin, p.beta, p.etas)
+    return rb
+
+
+def oracle_precond(p, rb, rep, fixed, thresh=0.0):
+    E_rep = fem.simp_modulus(rb[rep], p.E0, p.Emin, p.penal)
+    out = schwarz.coarse_basis(p, E_rep, fixed, p.k, thresh=thresh)
+    Phi = out[0]
+    Ms = [schwarz.TwoLevelSchwarz(p, fem.assemble(p, fem.simp_modulus(r, p.E0, p.Emin, p.penal)),
+                                  fixed, Phi) for r in rb]
+    return Ms, out
+
+
+def residuals(p, nsys, seed):
+    fixed = W.fixed_mask(p)
+    r = np.random.default_rng(seed).standard_normal((nsys, p.n_dof))
+    r[:, fixed == 1] = 0.0
+    return r
+
+
+def gpu_precond(p, rb, precision, r, rep=0, **kw):
+    h = handle(p, precision=precision, nsys=len(rb), eig_iters=CONVERGED_SWEEPS, **kw)
+    h.build_coarse_basis(dev(rb), rep=rep)
+    z = dev(np.zeros_like(r))
+    h.apply_precond(dev(r), z)
+    return h, host(z)
+
+
+@pytest.fixture(scope="module")
+def section():
+    p = production_section()
+    rb = projected(p)
+    fixed = W.fixed_mask(p)
+    Ms, (Phi, lams) = oracle_precond(p, rb, 0, fixed)
+    r = residuals(p, p.nsys, 3)
+    want = np.stack([Ms[s].apply(r[s]) for s in range(p.nsys)])
+    return dict(p=p, rb=rb, fixed=fixed, r=r, want=want, lams=lams)
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED])
+def test_preconditioner_production_shape(section, precision):
+    p, r, want = section["p"], section["r"], section["want"]
+    h, z = gpu_precond(p, section["rb"], precision, r)
+    for s in range(p.nsys):
+        e, e2 = elementwise(z[s], want[s]), rel(z[s], want[s])
+        print(f"precond s=32 k=6 {'fp64' if precision == T.FP64 else 'mixed'} system {s}: "
+              f"elementwise {e:.3e} rel2 {e2:.3e}", flush=True)
+        assert e < (1e-12 if precision == T.FP64 else 1e-6), (s, e)
+    h.close()
+
+
+def test_eigenpairs_production_shape(section):
+    p, rb, fixed = section["p"], section["rb"], section["fixed"]
+    h = handle(p, nsys=1, eig_iters=CONVERGED_SWEEPS)
+    h.build_coarse_basis(dev(rb[:1]), rep=0)
+    phi, lam, res = h.export_coarse_basis()
+    phi = host(phi)
+    E = fem.simp_modulus(rb[0], p.E0, p.Emin, p.penal)
+    chi = schwarz.partition_of_unity(p)
+    worst_l, worst_a = 0.0, 0.0
+    for j in range(p.n_sub):
+        lo, psi, dofs = schwarz.local_eigenpairs(p, E, fixed, j, p.k + 1)
+        nodes = schwarz.subdomain_nodes(p, j)
+        alld = (p.dim * nodes[:, None] + np.arange(p.dim)[None, :]).ravel()
+        g = phi[j][fixed[alld] == 0]
+        scale = np.maximum(np.abs(lo[:p.k]), 1e-6)
+        worst_l = max(worst_l, float(np.max(np.abs(lam[j] - lo[:p.k]) / scale)))
+        if (lo[p.k] - lo[p.k - 1]) / lo[p.k] > 0.05:
+            qa, _ = np.linalg.qr(psi[:, :p.k] * chi[dofs // p.dim][:, None])
+            qb, _ = np.linalg.qr(g)
+            sv = np.linalg.svd(qa.T @ qb, compute_uv=False)
+            worst_a = max(worst_a, float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2))))
+    print(f"eigenpairs s=32 k=6: eigenvalue {worst_l:.3e} angle {worst_a:.3e} "
+          f"ritz residual {np.max(res):.3e}", flush=True)
+    assert worst_l < 1e-7 and worst_a < 1e-6 and np.max(res) < 1e-6
+    h.close()
+
+
+def small_3d(nel=(12, 6, 6)):
+    return W.cantilever3d(*nel, sub=3, k=6)
+
+
+def test_preconditioner_3d_matches_oracle():
+    p = small_3d()
+    rho = W.design_field(p)[None, :]
+    fixed = W.fixed_mask(p)
+    Ms, _ = oracle_precond(p, rho, 0, fixed)
+    r = residuals(p, 1, 4)
+    want = Ms[0].apply(r[0])
+    h, z = gpu_precond(p, rho, T.FP64, r)
+    e = elementwise(z[0], want)
+    print(f"precond 3d s=3: elementwise {e:.3e}", flush=True)
+    assert e < 1e-12
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED])
+@pytest.mark.parametrize("nel", [(12, 6, 6), (24, 12, 12)])
+def test_pcg_3d_matches_direct(precision, nel):
+    if nel == (24, 12, 12) and precision == T.MIXED:
+        pytest.skip("the larger 3D mesh runs in FP64 only (time)")
+    p = small_3d(nel)
+    rho = W.design_field(p)
+    f = W.load_vector(p)
+    u_o = fem.solve(p, rho)
+    c_o = fem.compliance(f, u_o)
+    h = handle(p, precision=precision, nsys=1)
+    h.build_coarse_basis(dev(rho[None, :]), rep=0)
+    u = dev(np.zeros(p.n_dof))
+    info = h.pcg_solve(dev(rho[None, :]), dev(f[None, :]), u, rtol=1e-12, maxit=3000)
+    uu = host(u)
+    tol = 1e-8 if precision == T.FP64 else 1e-6
+    print(f"pcg 3d {nel} {'fp64' if precision == T.FP64 else 'mixed'}: iters {info[0]['iters']} "
+          f"u {rel(uu, u_o):.3e} c {abs(fem.compliance(f, uu) - c_o) / c_o:.3e}", flush=True)
+    assert info[0]["status"] == 0, info
+    assert rel(uu, u_o) < tol
+    assert abs(fem.compliance(f, uu) - c_o) / c_o < tol
+    h.close()
+
+
+@pytest.mark.parametrize("sub", [6, 12])
+def test_generic_factor_path(sub):
+    # 2D block sizes 14 and 26 have no compiled local factorisation: the
+    # generic Cholesky-chain kernel builds the local factors
+    p = dataclasses.replace(W.mbb_64x32(), nel=(48, 24, 1), sub=sub, k=4, name=f"mbb_48x24_s{sub}")
+    rho = W.design_field(p)[None, :]
+    fixed = W.fixed_mask(p)
+    Ms, _ = oracle_precond(p, rho, 0, fixed)
+    r = residuals(p, 1, 5)
+    want = Ms[0].apply(r[0])
+    h, z = gpu_precond(p, rho, T.FP64, r)
+    e = elementwise(z[0], want)
+    f = W.load_vector(p)
+    u = dev(np.zeros(p.n_dof))
+    info = h.pcg_solve(dev(rho), dev(f[None, :]), u, rtol=1e-12, maxit=3000)
+    u_o = fem.solve(p, rho[0])
+    print(f"generic factor s={sub}: precond elementwise {e:.3e}, pcg iters {info[0]['iters']} "
+          f"u {rel(host(u), u_o):.3e}", flush=True)
+    assert e < 1e-12
+    assert info[0]["status"] == 0 and rel(host(u), u_o) < 1e-8
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED])
+def test_block_coarse_path(precision):
+    # coarse_dense_max = 1 forces the block-tridiagonal coarse solve (on the
+    # second stream, beside the local solves)
+    p = W.cantilever2d(128, 64, 16, 6)
+    rb = projected(p)
+    fixed = W.fixed_mask(p)
+    Ms, _ = oracle_precond(p, rb, 0, fixed)
+    r = residuals(p, p.nsys, 6)
+    h, z = gpu_precond(p, rb, precision, r, coarse_dense_max=1)
+    hd, zd = gpu_precond(p, rb, precision, r)   # the dense-inverse path
+    for s in range(p.nsys):
+        want = Ms[s].apply(r[s])
+        e, ed = elementwise(z[s], want), elementwise(zd[s], want)
+        print(f"block coarse {'fp64' if precision == T.FP64 else 'mixed'} system {s}: "
+              f"elementwise {e:.3e} (dense path {ed:.3e}), paths differ by "
+              f"{elementwise(z[s], zd[s]):.3e}", flush=True)
+        assert e < (1e-12 if precision == T.FP64 else 1e-6)
+        assert elementwise(z[s], zd[s]) < (1e-14 if precision == T.FP64 else 1e-7)
+    f = W.load_vector(p)
+    u = dev(np.zeros((p.nsys, p.n_dof)))
+    info = h.pcg_solve(dev(rb), dev(np.stack([f] * p.nsys)), u, rtol=1e-12, maxit=3000)
+    tol = 1e-8 if precision == T.FP64 else 1e-6
+    for s in range(p.nsys):
+        assert info[s]["status"] == 0
+        assert rel(host(u)[s], fem.solve(p, rb[s])) < tol
+    h.close()
+    hd.close()
+
+
+def test_threshold_mode():
+    p = production_section()
+    rb = projected(p)
+    fixed = W.fixed_mask(p)
+    E = fem.simp_modulus(rb[0], p.E0, p.Emin, p.penal)
+    _, lams = schwarz.coarse_basis(p, E, fixed, p.k)
+    v = np.sort(lams[:, 3])
+    i = int(np.argmax(np.diff(v)))
+    thr = float(np.sqrt(v[i] * v[i + 1]))            # in the widest gap of the 4th eigenvalues
+    Ms, (Phi, _, kj_o) = oracle_precond(p, rb, 0, fixed, thresh=thr)
+    r = residuals(p, p.nsys, 7)
+    h, z = gpu_precond(p, rb, T.FP64, r, lambda_thresh=thr)
+    lam_g, kj = h.export_eigenvalues()
+    print(f"threshold {thr:.3e}: kj gpu {kj.tolist()} oracle {kj_o.tolist()}", flush=True)
+    assert np.array_equal(kj, kj_o)
+    assert kj.sum() < p.k * p.n_sub
+    for s in range(p.nsys):
+        e = elementwise(z[s], Ms[s].apply(r[s]))
+        print(f"threshold precond system {s}: elementwise {e:.3e}", flush=True)
+        assert e < 1e-12
+    f = W.load_vector(p)
+    u = dev(np.zeros((p.nsys, p.n_dof)))
+    info = h.pcg_solve(dev(rb), dev(np.stack([f] * p.nsys)), u, rtol=1e-12, maxit=3000)
+    for s in range(p.nsys):
+        assert info[s]["status"] == 0
+        assert rel(host(u)[s], fem.solve(p, rb[s])) < 1e-8
+    h.close()
+
+
+def test_invalid_densities_are_rejected():
+    p = W.mbb_64x32()
+    rho = W.design_field(p)
+    f = dev(W.load_vector(p)[None, :])
+    h = handle(p, nsys=1)
+    good = dev(rho[None, :])
+    h.build_coarse_basis(good)
+    x = dev(np.ones(p.n_dof))
+    y = dev(np.zeros(p.n_dof))
+    for bad_value in (float("nan"), -0.25, 1.5):
+        bad = rho.copy()
+        bad[17] = bad_value
+        b = dev(bad[None, :])
+        for call in (lambda: h.apply_K(b, x, y), lambda: h.build_coarse_basis(b),
+                     lambda: h.compliance_and_sensitivity(b, x[None, :], f, dev(np.zeros(1)),
+                                                          dev(np.zeros((1, p.n_el)))),
+                     lambda: h.filter_project(dev(bad), 2.0, 8.0, [0.5], dev(np.zeros(p.n_el)),
+                                              dev(np.zeros((1, p.n_el))))):
+            with pytest.raises(T.TpcgError) as e:
+                call()
+            assert e.value.code == -1
+        h.build_coarse_basis(good)                 # the failed build left the state unbuilt
+        u = dev(np.zeros(p.n_dof))
+        with pytest.raises(T.TpcgError) as e:
+            h.pcg_solve(b, f, u, rtol=1e-8)
+        assert e.value.code == -1
+    # a valid solve still works on the same handle
+    u = dev(np.zeros(p.n_dof))
+    info = h.pcg_solve(good, f, u, rtol=1e-10)
+    assert info[0]["status"] == 0
+    h.close()
+
+
+def test_indefinite_shift_reports_enotspd():
+    # diag(K^N)^-1/2 K^N diag(K^N)^-1/2 - 0.5 I is indefinite on a floating
+    # cell (rigid-body modes at 0): the eigensolver's factorisation meets a
+    # non-positive pivot
+    p = W.mbb_64x32()
+    h = handle(p, nsys=1, eig_shift=-0.5)
+    with pytest.raises(T.TpcgError) as e:
+        h.build_coarse_basis(dev(W.design_field(p)[None, :]))
+    assert e.value.code == -4
+    h.close()
+
+
+def test_failed_allocation_leaves_the_handle_usable():
+    p = W.mbb_64x32()
+    rho = dev(W.design_field(p)[None, :])
+    f = dev(W.load_vector(p)[None, :])
+    lib = T.load_library()
+    # a failure inside the handle's creation
+    lib.tpcg_test_fail_alloc(3)
+    with pytest.raises(T.TpcgError) as e:
+        handle(p, nsys=1)
+    assert e.value.code == -2
+    lib.tpcg_test_fail_alloc(0)
+    # 15 preconditioner arrays (FP64, dense coarse inverse), then the build workspace
+    for nth in (1, 5, 12, 16):
+        h = handle(p, nsys=1)
+        lib.tpcg_test_fail_alloc(nth)
+        with pytest.raises(T.TpcgError) as e:
+            h.build_coarse_basis(rho)
+        assert e.value.code == -2, nth
+        lib.tpcg_test_fail_alloc(0)
+        # nothing half-built: the preconditioner is unusable until a build succeeds
+        with pytest.raises(T.TpcgError) as e:
+            h.apply_precond(f, dev(np.zeros(p.n_dof)))
+        assert e.value.code == -6
+        h.build_coarse_basis(rho)
+        u = dev(np.zeros(p.n_dof))
+        info = h.pcg_solve(rho, f, u, rtol=1e-12, maxit=2000)
+        assert info[0]["status"] == 0
+        assert rel(host(u), fem.solve(p, W.design_field(p))) < 1e-8
+        h.close()

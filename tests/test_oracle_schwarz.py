@@ -139,3 +139,149 @@ def test_contrast_independent_iterations():
     rho = W.design_field(p)
     one = schwarz.solve_pcg(p, [rho], rho, W.load_vector(p), W.fixed_mask(p), rtol=1e-8, coarse=False)
     assert one[0][1] > 1.5 * its[-1]                     # the coarse space is doing work
+
+
+# ---------------------------------------------------------------------------
+# Partition geometry and the partition-of-unity weighting of the coarse basis
+# (Sec. 2.4: phi = psi chi with sum_i chi_i = 1)
+# ---------------------------------------------------------------------------
+
+def test_subdomain_geometry_written_out():
+    # 4 x 4 Q4 mesh, 2 x 2 cells: the closed cell of subdomain 3 (top right)
+    # holds nodes ix, iy in {2, 3, 4}; its elements are ex, ey in {2, 3}
+    p = dataclasses.replace(W.mbb_64x32(), nel=(4, 4, 1), sub=2, k=1)
+    nx = 5
+    want_nodes = sorted(ix + nx * iy for iy in (2, 3, 4) for ix in (2, 3, 4))
+    assert sorted(schwarz.subdomain_nodes(p, 3).tolist()) == want_nodes
+    assert sorted(schwarz.subdomain_elements(p, 3).tolist()) == sorted(
+        ex + 4 * ey for ey in (2, 3) for ex in (2, 3))
+    # subdomain 1 is the bottom-right cell (x fastest numbering)
+    assert sorted(schwarz.subdomain_nodes(p, 1).tolist()) == sorted(
+        ix + nx * iy for iy in (0, 1, 2) for ix in (2, 3, 4))
+    # its free DOFs in local order: node x fastest, then the component
+    fixed = np.zeros(p.n_dof, dtype=np.uint8)
+    fixed[2 * (3 + nx * 1) + 1] = 1              # u_y of node (3, 1)
+    d = schwarz.subdomain_dofs(p, 1, fixed)
+    assert d.size == 2 * 9 - 1 and 2 * (3 + nx * 1) + 1 not in d
+    assert d[0] == 2 * 2 and d[1] == 2 * 2 + 1 and d[2] == 2 * 3
+    # 3D: 4 x 2 x 2 mesh, cells of 2: subdomain 1 covers x nodes 2..4
+    p3 = dataclasses.replace(W.cantilever3d(4, 2, 2, sub=2, k=1))
+    n3 = schwarz.subdomain_nodes(p3, 1)
+    assert n3.size == 27
+    assert sorted(n3.tolist()) == sorted(ix + 5 * (iy + 3 * iz) for iz in range(3)
+                                         for iy in range(3) for ix in (2, 3, 4))
+
+
+def _rigid_modes(p):
+    """Global rigid-body displacement fields (translations, infinitesimal rotations)."""
+    n = np.arange(p.nnodes)
+    nx, ny = p.nelx + 1, p.nely + 1
+    x = (n % nx).astype(float)
+    y = ((n // nx) % ny).astype(float)
+    z = (n // (nx * ny)).astype(float)
+    d = p.dim
+    modes = []
+    for c in range(d):
+        v = np.zeros(p.n_dof)
+        v[c::d] = 1.0
+        modes.append(v)
+    pairs = [(0, 1)] if d == 2 else [(0, 1), (1, 2), (0, 2)]
+    coords = [x, y, z]
+    for a, b in pairs:
+        v = np.zeros(p.n_dof)
+        v[a::d] = -coords[b]
+        v[b::d] = coords[a]
+        modes.append(v)
+    return modes
+
+
+def _span_residual(Phi, v):
+    A = Phi.toarray()
+    c, *_ = np.linalg.lstsq(A, v, rcond=None)
+    return np.linalg.norm(A @ c - v) / np.linalg.norm(v)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coarse_space_contains_global_rigid_motions(dim):
+    # With uniform material and no supports every cell floats, so each local
+    # eigenspace of eigenvalue 0 is exactly the local rigid motions. Because
+    # the chi_j sum to one at every node, sum_j chi_j R|_j = R: the global
+    # rigid motions lie in span(Phi). Dropping chi (weights 1), or weighting
+    # by another node's multiplicity, breaks the sum at the shared nodes.
+    if dim == 2:
+        p = dataclasses.replace(W.mbb_64x32(), nel=(12, 8, 1), sub=4, k=4, Emin=1.0)
+    else:
+        p = dataclasses.replace(W.cantilever3d(4, 4, 2, sub=2, k=7), Emin=1.0)
+    E = np.ones(p.n_el)
+    fixed = np.zeros(p.n_dof, dtype=np.uint8)
+    Phi, lams = schwarz.coarse_basis(p, E, fixed, p.k)
+    nz = 3 if dim == 2 else 6
+    assert np.all(np.abs(lams[:, :nz]) < 1e-12) and np.all(lams[:, nz] > 1e-6)
+    for v in _rigid_modes(p):
+        assert _span_residual(Phi, v) < 1e-12
+    # the same eigenvectors without the partition of unity do not reach them
+    rows, cols, vals = [], [], []
+    for j in range(p.n_sub):
+        lam, psi, dofs = schwarz.local_eigenpairs(p, E, fixed, j, p.k)
+        for m in range(p.k):
+            rows.append(dofs)
+            cols.append(np.full(dofs.size, j * p.k + m))
+            vals.append(psi[:, m])
+    import scipy.sparse as sps
+    bad = sps.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(p.n_dof, p.n_sub * p.k)).tocsc()
+    assert max(_span_residual(bad, v) for v in _rigid_modes(p)) > 1e-2
+
+
+def test_coarse_basis_partition_weights_per_node():
+    # every coarse vector equals chi(node) times a D-normalised eigenvector:
+    # at a node shared by 2 (4) cells the basis value is half (a quarter) of
+    # the eigenvector, the same for both components of the node
+    p = mbb(16, 8, 4, 3)
+    rho = W.design_field(p)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    fixed = W.fixed_mask(p)
+    Phi, _ = schwarz.coarse_basis(p, E, fixed, p.k)
+    A = Phi.toarray()
+    nx = p.nelx + 1
+    for j in (0, 5):
+        lam, psi, dofs = schwarz.local_eigenpairs(p, E, fixed, j, p.k)
+        for m in range(p.k):
+            col = A[dofs, j * p.k + m]
+            ratio = col / np.where(np.abs(psi[:, m]) > 1e-14, psi[:, m], np.nan)
+            nodes = dofs // 2
+            ix, iy = nodes % nx, nodes // nx
+            shared_x = (ix % p.sub == 0) & (ix > 0) & (ix < p.nelx)
+            shared_y = (iy % p.sub == 0) & (iy > 0) & (iy < p.nely)
+            want = 1.0 / ((1 + shared_x) * (1 + shared_y))
+            ok = ~np.isnan(ratio)
+            np.testing.assert_allclose(ratio[ok], want[ok], rtol=1e-12)
+
+
+def test_threshold_keeps_eigenvalues_below_it():
+    # Sec. 2.4: the eigenvectors of eigenvalues below one global threshold
+    p = mbb(32, 16, 8, 6)
+    rho = W.design_field(p)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    fixed = W.fixed_mask(p)
+    Phi_k, lams = schwarz.coarse_basis(p, E, fixed, p.k)
+    # a threshold in the widest gap between the subdomains' 4th eigenvalues
+    # (periodic cells repeat eigenvalues, so no eigenvalue may sit on it)
+    v = np.sort(lams[:, 3])
+    i = int(np.argmax(np.diff(v)))
+    thr = float(np.sqrt(v[i] * v[i + 1]))
+    Phi_t, lams_t, kj = schwarz.coarse_basis(p, E, fixed, p.k, thresh=thr)
+    for j in range(p.n_sub):
+        ev = np.linalg.eigvalsh(_scaled_neumann(p, E, fixed, j))
+        assert kj[j] == min(p.k, int(np.sum(ev < thr)))
+    assert Phi_t.shape[1] == kj.sum() < Phi_k.shape[1]
+    # a threshold above every kept eigenvalue gives the fixed-k basis
+    _, _, kj_all = schwarz.coarse_basis(p, E, fixed, p.k, thresh=2 * lams.max())
+    assert np.all(kj_all == p.k)
+
+
+def _scaled_neumann(p, E, fixed, j):
+    dofs = schwarz.subdomain_dofs(p, j, fixed)
+    KN = fem.assemble(p, E, elements=schwarz.subdomain_elements(p, j))[dofs][:, dofs].toarray()
+    d = np.diag(KN)
+    return KN / np.sqrt(np.outer(d, d))
