@@ -188,6 +188,30 @@ int tpcg_compliance_and_sensitivity(tpcg_handle* h, const double* rho_phys, cons
                                     const double* f, int32_t nsys, double* c, double* dc);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * compliance c_s = f_s^T u_s and, if dc is not NULL, the element
+ * sensitivities of tpcg_compliance_and_sensitivity, without a handle and
+ * without any device or host allocation. prob must be a problem accepted by
+ * tpcg_build_partition; fixed is the support mask as a device array (uint8
+ * [n_dof], nonzero = supported); rho_phys, u, f, c and dc as in
+ * tpcg_compliance_and_sensitivity; status (dev int32, may be NULL) is set to
+ * 0, or to 1 if a density is NaN or outside [0, 1] (the outputs are then
+ * unspecified). Work is enqueued on `stream` (a hipStream_t of the current
+ * device; NULL: the default stream) and the call returns without waiting.
+ * Scratch: a fixed library array of 576 + 4 * 2048 doubles per device
+ * (the element matrix and the reduction partials), held until the process
+ * ends; every call on a device shares it, so calls that overlap on one
+ * device (concurrent streams or threads) race. Limits: nsys in 1..4
+ * (TPCG_EINVAL beyond). TPCG_EHIP if the scratch address cannot be found or
+ * a launch fails.
+ */
+int tpcg_compliance_and_sensitivity_noalloc(const tpcg_problem* prob, const uint8_t* fixed,
+                                            const double* rho_phys, const double* u,
+                                            const double* f, int32_t nsys, double* c, double* dc,
+                                            int32_t* status, void* stream);
+
+/*
  * Density filter and smoothed Heaviside projection (Sec. 4.3):
  * rho_tilde = W rho with hat weights max(0, rmin - distance between element
  * centres), truncated at the mesh boundary and renormalised (rmin <= 1: no

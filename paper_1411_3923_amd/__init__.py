@@ -52,7 +52,8 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_compliance_and_sensitivity", "tpcg_filter_project",
            "tpcg_filter_project_adjoint", "tpcg_export_coarse_basis", "tpcg_query",
            "tpcg_set_profiling", "tpcg_profile_block_solves", "tpcg_export_eigenvalues",
-           "tpcg_query_subspace", "tpcg_test_fail_alloc", "tpcg_last_error", "tpcg_destroy"]
+           "tpcg_query_subspace", "tpcg_test_fail_alloc", "tpcg_last_error", "tpcg_destroy",
+           "tpcg_compliance_and_sensitivity_noalloc"]
 
 
 def load_library(path: str | None = None):
@@ -87,6 +88,8 @@ def load_library(path: str | None = None):
     lib.tpcg_last_error.restype = ctypes.c_char_p
     lib.tpcg_destroy.argtypes = [P]
     lib.tpcg_destroy.restype = None
+    lib.tpcg_compliance_and_sensitivity_noalloc.argtypes = [ctypes.POINTER(Problem), P, P, P, P,
+                                                            I32, P, P, P, V]
     for name in EXPORTS:
         getattr(lib, name)
     if path is None:
@@ -256,3 +259,23 @@ class Handle:
         self._check(self.lib.tpcg_export_coarse_basis(
             self.h, _ptr(phi), lam.ctypes.data_as(ctypes.c_void_p), res.ctypes.data_as(ctypes.c_void_p)))
         return phi.view(self.n_sub, self.n_loc, self.k), lam, res
+
+
+def compliance_and_sensitivity_noalloc(problem: Problem, fixed, rho_phys, u, f, c, dc=None,
+                                       status=None, stream=None):
+    """tpcg_compliance_and_sensitivity_noalloc: no handle, no device allocation.
+    `fixed` is the support mask as a uint8 device tensor [n_dof]; `status`
+    (an int32 device tensor of one element, optional) receives 1 for an
+    invalid density. Returns the status code of the call."""
+    import torch
+    lib = load_library()
+    nsys = c.numel()
+    n_dof = fixed.numel()
+    n_el = rho_phys.numel() // max(nsys, 1)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    rc = lib.tpcg_compliance_and_sensitivity_noalloc(
+        ctypes.byref(problem), _ptr(fixed, torch.uint8), _ptr(rho_phys, torch.float64, nsys * n_el),
+        _ptr(u, torch.float64, nsys * n_dof), _ptr(f, torch.float64, nsys * n_dof), nsys,
+        _ptr(c, torch.float64, nsys), _ptr(dc, torch.float64, nsys * n_el) if dc is not None else None,
+        _ptr(status, torch.int32, 1) if status is not None else None, ctypes.c_void_p(st.cuda_stream))
+    return rc

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -26,8 +27,9 @@ const Handle* H(const tpcg_handle* h) { return reinterpret_cast<const Handle*>(h
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// Derive the geometry; returns an error message or "" when the problem is usable.
-std::string make_geometry(const tpcg_problem& pr, Geometry& g) {
+// Derive the geometry; returns an error message, or nullptr when the problem
+// is usable (no heap allocation either way).
+const char* make_geometry(const tpcg_problem& pr, Geometry& g) {
   if (pr.dim != 2 && pr.dim != 3) return "dim must be 2 or 3";
   const int d = pr.dim;
   std::memset(&g, 0, sizeof(g));
@@ -90,7 +92,7 @@ std::string make_geometry(const tpcg_problem& pr, Geometry& g) {
   g.ebn = g.s + 3;
   g.nebox = d == 3 ? g.ebn * g.ebn * g.ebn : g.ebn * g.ebn;
   g.ndpe = d == 3 ? 24 : 8;
-  return "";
+  return nullptr;
 }
 
 // Limits of the block-tridiagonal factor kernels (checked when the
@@ -276,6 +278,104 @@ bool device_alloc(void** p, size_t bytes) {
 }
 }  // namespace tpcg
 
+// ---------------------------------------------------------------------------
+// Scratch of the entry point that allocates nothing
+// (tpcg_compliance_and_sensitivity_noalloc): the element matrix, then the
+// f^T u partials of up to kMaxSys systems. Every device holds its own copy
+// of this array until the process ends. Host code must not use the array's
+// name as a device address: its address on the current device comes from
+// hipGetSymbolAddress, looked up once per device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNaK0 = 576;                                   // 24 x 24 (H8) at most
+constexpr size_t kNaElems = kNaK0 + (size_t)kMaxSys * kMaxParts;
+constexpr int kNaMaxDev = 64;
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNaElems];
+
+namespace {
+
+std::mutex g_na_mu;
+double* g_na_ptr[kNaMaxDev] = {};
+
+// Address of `scratch` on the current device (looked up on the first call
+// on that device).
+int scratch_on_current_device(double** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaMaxDev) {
+    (void)hipGetLastError();
+    return TPCG_EHIP;
+  }
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return TPCG_EHIP;
+    }
+    g_na_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_na_ptr[dev];
+  return TPCG_OK;
+}
+
+// 64 values passed by value in the kernel arguments (no staging buffer):
+// dst[i] = v[i] for i < n; thread 0 of the first chunk also clears `flag`
+struct Vals64 {
+  double v[64];
+};
+
+__global__ void k_na_put(double* __restrict__ dst, Vals64 v, int n, int* __restrict__ flag) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = v.v[i];
+  if (flag && i == 0) *flag = 0;
+}
+
+}  // namespace
+
+extern "C" int tpcg_compliance_and_sensitivity_noalloc(const tpcg_problem* prob,
+                                                       const uint8_t* fixed, const double* rho_phys,
+                                                       const double* u, const double* f,
+                                                       int32_t nsys, double* c, double* dc,
+                                                       int32_t* status, void* stream) {
+  if (!prob || !fixed || !rho_phys || !u || !f || !c) return TPCG_EINVAL;
+  if (nsys < 1 || nsys > kMaxSys) {
+    fprintf(stderr, "tpcg_compliance_and_sensitivity_noalloc: nsys must lie in 1..%d\n", kMaxSys);
+    return TPCG_EINVAL;
+  }
+  Geometry g;
+  const char* msg = make_geometry(*prob, g);
+  if (msg) {
+    fprintf(stderr, "tpcg_compliance_and_sensitivity_noalloc: %s\n", msg);
+    return TPCG_EINVAL;
+  }
+  double* ws = nullptr;
+  int rc = scratch_on_current_device(&ws);
+  if (rc != TPCG_OK) return rc;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  double K0[kNaK0];
+  element_stiffness(g.dim, prob->nu, K0);
+  const int nk = g.ndpe * g.ndpe;
+  for (int o = 0; o < nk; o += 64) {
+    Vals64 v;
+    const int n = std::min(64, nk - o);
+    for (int i = 0; i < n; ++i) v.v[i] = K0[o + i];
+    hipLaunchKernelGGL(k_na_put, dim3(1), dim3(64), 0, st, ws + o, v, n,
+                       o == 0 ? reinterpret_cast<int*>(status) : nullptr);
+  }
+  if (status) launch_check_rho(rho_phys, g.nel, nsys, reinterpret_cast<int*>(status), 0, 1, st);
+  launch_compliance_sens_raw(g, fixed, ws, prob->E0, prob->Emin, prob->penal, ws + kNaK0, rho_phys,
+                             u, f, nsys, c, dc, st);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    fprintf(stderr, "tpcg_compliance_and_sensitivity_noalloc: %s\n", hipGetErrorString(e));
+    return TPCG_EHIP;
+  }
+  return TPCG_OK;
+}
+
 extern "C" {
 
 int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, void* stream,
@@ -283,9 +383,9 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
   if (!prob || !fixed_mask || !out) return TPCG_EINVAL;
   *out = nullptr;
   Geometry g;
-  std::string msg = make_geometry(*prob, g);
-  if (!msg.empty()) {
-    fprintf(stderr, "tpcg_build_partition: %s\n", msg.c_str());
+  const char* msg = make_geometry(*prob, g);
+  if (msg) {
+    fprintf(stderr, "tpcg_build_partition: %s\n", msg);
     return TPCG_EINVAL;
   }
   if (prob->nsys_max < 1 || prob->nsys_max > kMaxSys) {
@@ -359,7 +459,7 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
 size_t tpcg_workspace_bytes(const tpcg_problem* prob, int32_t nsys) {
   if (!prob) return 0;
   Geometry g;
-  if (!make_geometry(*prob, g).empty()) return 0;
+  if (make_geometry(*prob, g)) return 0;
   Sizes s = sizes(*prob, g, nsys);
   return s.persistent + s.setup_peak;
 }

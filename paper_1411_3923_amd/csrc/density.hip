@@ -162,10 +162,11 @@ __global__ __launch_bounds__(kThreads) void k_sensitivity(Geometry g, const doub
   }
 }
 
+// partials of f^T u over the free DOFs: part[sys * kMaxParts + workgroup]
 __global__ __launch_bounds__(kThreads) void k_fu_parts(Geometry g, const double* __restrict__ f,
                                                       const double* __restrict__ u,
                                                       const uint8_t* __restrict__ fixed,
-                                                      double* __restrict__ parts) {
+                                                      double* __restrict__ part) {
   __shared__ double sh[4];
   const int sys = blockIdx.y;
   const size_t off = (size_t)sys * g.ndof;
@@ -177,13 +178,13 @@ __global__ __launch_bounds__(kThreads) void k_fu_parts(Geometry g, const double*
       if (!fixed[i]) a += f[off + i] * u[off + i];
     }
   const double s = block_sum(a, sh);
-  if (threadIdx.x == 0) part_slot(parts, kPartAux, sys)[blockIdx.x] = s;
+  if (threadIdx.x == 0) part[(size_t)sys * kMaxParts + blockIdx.x] = s;
 }
 
-__global__ void k_fu_final(const double* __restrict__ parts, int np, double* __restrict__ c) {
+__global__ void k_fu_final(const double* __restrict__ part, int np, double* __restrict__ c) {
   __shared__ double sh[4];
   const int sys = blockIdx.x;
-  const double v = sum_parts(part_slot(const_cast<double*>(parts), kPartAux, sys), np, sh);
+  const double v = sum_parts(part + (size_t)sys * kMaxParts, np, sh);
   if (threadIdx.x == 0) c[sys] = v;
 }
 
@@ -212,21 +213,28 @@ void launch_filter_project_adjoint(const Handle& h, const double* rho_tilde, dou
                      h.g, rho_tilde, rmin, beta, e, nsys, g, out);
 }
 
+void launch_compliance_sens_raw(const Geometry& g, const uint8_t* fixed, const double* K0,
+                                double E0, double Emin, double penal, double* part,
+                                const double* rho, const double* u, const double* f, int nsys,
+                                double* c, double* dc, hipStream_t st) {
+  const int np = parts_for(g.nnodes);
+  hipLaunchKernelGGL(k_fu_parts, dim3(np, nsys), dim3(kThreads), 0, st, g, f, u, fixed, part);
+  hipLaunchKernelGGL(k_fu_final, dim3(nsys), dim3(kThreads), 0, st, part, np, c);
+  if (dc) {
+    if (g.dim == 2)
+      hipLaunchKernelGGL(k_sensitivity<2>, dim3(elem_blocks(g.nel), nsys), dim3(kThreads), 0, st,
+                         g, rho, u, fixed, K0, E0, Emin, penal, dc);
+    else
+      hipLaunchKernelGGL(k_sensitivity<3>, dim3(elem_blocks(g.nel), nsys), dim3(kThreads), 0, st,
+                         g, rho, u, fixed, K0, E0, Emin, penal, dc);
+  }
+}
+
 void launch_compliance_sens(const Handle& h, const double* rho, const double* u, const double* f,
                             int nsys, double* c, double* dc, hipStream_t st) {
-  const int np = parts_for(h.g.nnodes);
-  hipLaunchKernelGGL(k_fu_parts, dim3(np, nsys), dim3(kThreads), 0, st, h.g, f, u, h.fixed,
-                     h.parts);
-  hipLaunchKernelGGL(k_fu_final, dim3(nsys), dim3(kThreads), 0, st, h.parts, np, c);
-  if (dc) {
-    const tpcg_problem& pr = h.prob;
-    if (h.g.dim == 2)
-      hipLaunchKernelGGL(k_sensitivity<2>, dim3(elem_blocks(h.g.nel), nsys), dim3(kThreads), 0, st,
-                         h.g, rho, u, h.fixed, h.K0, pr.E0, pr.Emin, pr.penal, dc);
-    else
-      hipLaunchKernelGGL(k_sensitivity<3>, dim3(elem_blocks(h.g.nel), nsys), dim3(kThreads), 0, st,
-                         h.g, rho, u, h.fixed, h.K0, pr.E0, pr.Emin, pr.penal, dc);
-  }
+  const tpcg_problem& pr = h.prob;
+  launch_compliance_sens_raw(h.g, h.fixed, h.K0, pr.E0, pr.Emin, pr.penal,
+                             part_slot(h.parts, kPartAux, 0), rho, u, f, nsys, c, dc, st);
 }
 
 }  // namespace tpcg

@@ -306,6 +306,12 @@ void launch_filter_project_adjoint(const Handle& h, const double* rho_tilde, dou
                                    double* out, hipStream_t st);
 void launch_compliance_sens(const Handle& h, const double* rho, const double* u, const double* f,
                             int nsys, double* c, double* dc, hipStream_t st);
+// the same without a handle: supports, element matrix and partials
+// (part[sys * kMaxParts + i], i < parts_for(nnodes)) given as device pointers
+void launch_compliance_sens_raw(const Geometry& g, const uint8_t* fixed, const double* K0,
+                                double E0, double Emin, double penal, double* part,
+                                const double* rho, const double* u, const double* f, int nsys,
+                                double* c, double* dc, hipStream_t st);
 
 // element.cpp
 void element_stiffness(int dim, double nu, double* K0 /* [ndpe*ndpe] */);
