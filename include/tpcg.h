@@ -90,6 +90,10 @@ typedef struct {
   int32_t coarse_dense_max; /* coarse dimensions up to this keep a dense K_c^-1 applied as a
                            product; larger ones use the block-tridiagonal coarse factor
                            (0: default 12288) */
+  int32_t big_min_nb;   /* subdomain node-layer blocks of at least this many unknowns use the
+                           HBM-resident factors and solves (0: only blocks the on-chip kernels
+                           cannot take: more than 96 unknowns, an odd count, or layers of more
+                           than 64 elements) */
 } tpcg_problem;
 
 /* Per-system result of tpcg_pcg_solve. */

@@ -37,7 +37,8 @@ class Problem(ctypes.Structure):
                 ("ncoarse", ctypes.c_int32), ("nsys_max", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("eig_iters", ctypes.c_int32),
                 ("eig_extra", ctypes.c_int32), ("eig_shift", ctypes.c_double),
-                ("lambda_thresh", ctypes.c_double), ("coarse_dense_max", ctypes.c_int32)]
+                ("lambda_thresh", ctypes.c_double), ("coarse_dense_max", ctypes.c_int32),
+                ("big_min_nb", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -99,7 +100,7 @@ def load_library(path: str | None = None):
 
 def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.0, nu=0.3,
                  precision=FP64, eig_iters=0, eig_extra=0, eig_shift=0.0, lambda_thresh=0.0,
-                 coarse_dense_max=0, overlap=1) -> Problem:
+                 coarse_dense_max=0, overlap=1, big_min_nb=0) -> Problem:
     """tpcg_problem; `sub` is the subdomain edge (an int) or a per-axis tuple."""
     pr = Problem()
     pr.dim = dim
@@ -112,6 +113,7 @@ def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.
     pr.overlap, pr.ncoarse, pr.nsys_max = overlap, ncoarse, nsys_max
     pr.precision, pr.eig_iters, pr.eig_extra, pr.eig_shift = precision, eig_iters, eig_extra, eig_shift
     pr.lambda_thresh, pr.coarse_dense_max = lambda_thresh, coarse_dense_max
+    pr.big_min_nb = big_min_nb
     return pr
 
 

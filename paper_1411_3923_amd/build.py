@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtpcg.so")
-SOURCES = ["element.cpp", "matvec.hip", "vectors.hip", "precond.hip", "local.hip", "factor.hip", "setup.hip",
+SOURCES = ["element.cpp", "matvec.hip", "vectors.hip", "precond.hip", "local.hip", "factor.hip", "big.hip", "setup.hip",
            "density.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -170,6 +170,42 @@ void launch_solve_multi(const double* fac, const BtriShape& sh, int nmat, int m,
 void launch_inverse(const double* fac, const BtriShape& sh, int nmat, double* Xinv,
                     hipStream_t st);
 
+// (A_{b+1,b} v)[o] for a DOF o of node layer b + 1 (top = true, v on layer b)
+// or (A_{b+1,b}^T v)[o] = (A_{b,b+1} v)[o] for a DOF o of layer b (top =
+// false, v on layer b + 1): the stiffness of the element layer between the
+// two node layers, E[] its moduli indexed (ex + 1) + (bn + 1) (ey + 1) over
+// box-local element coordinates, zero outside the mesh. Supported DOFs are
+// masked by the caller.
+template <typename T>
+__device__ inline T layer_coupling(int d, int bn, const T* __restrict__ K0s,
+                                   const T* __restrict__ E, const T* __restrict__ v, int o,
+                                   bool top) {
+  const int nd = d == 3 ? 24 : 8;
+  const int m = o / d, c = o - m * d;
+  const int lx = m % bn, ly = d == 3 ? m / bn : 0;
+  const int ny = d == 3 ? 2 : 1, ylim = d == 3 ? bn : 1;
+  T acc = 0;
+  for (int hy = 0; hy < ny; ++hy)
+    for (int hx = 0; hx < 2; ++hx) {
+      // element with this node at its corner (hx, hy) of the top or bottom face
+      const int ex = lx - hx, ey = ly - hy;
+      const T Ee = E[(ex + 1) + (d == 3 ? (bn + 1) * (ey + 1) : 0)];
+      const int ca = d == 3 ? corner_of(hx, hy, top) : corner_of(hx, top, 0);
+      T s = 0;
+      for (int oy = 0; oy < ny; ++oy)
+        for (int ox = 0; ox < 2; ++ox) {
+          const int px = ex + ox, py = ey + oy;
+          if (px < 0 || px >= bn || py < 0 || py >= ylim) continue;
+          const int cb = d == 3 ? corner_of(ox, oy, !top) : corner_of(ox, !top, 0);
+          const T* kr = K0s + (d * ca + c) * nd + d * cb;
+          const T* vp = v + d * (px + bn * py);
+          for (int c2 = 0; c2 < d; ++c2) s += kr[c2] * vp[c2];
+        }
+      acc += Ee * s;
+    }
+  return acc;
+}
+
 // LDS element count of btri_solve for shape s and NR right-hand sides
 __host__ __device__ inline size_t btri_solve_lds_elems(const BtriShape& s, int nr) {
   return (size_t)s.bstride + 2 * (size_t)s.nb * nr + (size_t)kThreads * nr;

@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "big.h"
 #include "btri.h"
 
 using namespace tpcg;
@@ -95,18 +96,24 @@ const char* make_geometry(const tpcg_problem& pr, Geometry& g) {
   return nullptr;
 }
 
-// Limits of the block-tridiagonal factor kernels (checked when the
-// preconditioner is built; the matrix-free operator has none).
-std::string precond_limits(const Geometry& g) {
-  if (g.nb > kMaxNb || (g.nb & 1))
-    return "subdomain node rows/layers give blocks larger than 96 or of odd size";
-  if ((g.dim == 3 ? (g.bn + 1) * (g.bn + 1) : g.bn + 1) > 64)
-    return "element layers wider than one wave";
-  if (g.nbc > kMaxNb || (g.nbc & 1))
-    return "coarse blocks are larger than 96 or of odd size";
-  if (stage_bucket(stage_regs_for<double>(g.nb, g.pe)) < 0 ||
-      stage_bucket(stage_regs_for<double>(g.nbc, g.pec)) < 0)
+// Limits of the factor kernels (checked when the preconditioner is built;
+// the matrix-free operator has none): the on-chip block-tridiagonal kernels
+// for subdomain blocks up to 96 unknowns, the HBM-resident ones beyond
+// (big.h), and the block-tridiagonal coarse factor for coarse spaces above
+// dense_max.
+std::string precond_limits(const Geometry& g, int big) {
+  if (big) {
+    const char* why = big_limits(g);
+    if (why) return why;
+  } else if (stage_bucket(stage_regs_for<double>(g.nb, g.pe)) < 0) {
     return "factor records too long for the staged solve kernels";
+  }
+  if (g.nt > g.dense_max) {
+    if (g.nbc > kMaxNb || (g.nbc & 1))
+      return "coarse blocks larger than 96 or of odd size (coarse dimension above coarse_dense_max)";
+    if (stage_bucket(stage_regs_for<double>(g.nbc, g.pec)) < 0)
+      return "coarse factor records too long for the staged solve kernels";
+  }
   return "";
 }
 
@@ -116,35 +123,32 @@ struct Sizes {
 
 Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   const int mixed = pr.precision == TPCG_MIXED;
-  const int msub = std::min(kMaxSub, g.k + (pr.eig_extra > 0 ? pr.eig_extra : g.k));
-  const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;          // packed Neumann factors
-  const size_t trec = (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;   // tiled local factors
+  const int big = local_is_big(g, pr.big_min_nb);
+  int msub = std::min(kMaxSub, g.k + (pr.eig_extra > 0 ? pr.eig_extra : g.k));
+  if (msub > g.nloc) msub = g.nloc;
+  const size_t frec = big ? (size_t)g.nsub * g.nblk * big_shape(g).rec_dir
+                          : (size_t)g.nsub * g.nblk * tile_shape(g.nb).tstride;   // local factors
   const size_t crec = (size_t)g.nblkc * g.bstridec;                // packed coarse factor
-  const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   const size_t ts = mixed ? 4 : 8;
   size_t p = 0;
   p += g.ndof + sizeof(double) * g.ndpe * g.ndpe;
   p += (sizeof(double) + ts) * (size_t)g.nsub * g.nloc * g.k;
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
-  p += ts * nsys * (trec + (size_t)g.nel);
-  p += sizeof(double) * nsys * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
+  p += ts * nsys * (frec + (size_t)g.nel);
+  if (!big) p += sizeof(double) * nsys * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
   if (mixed) p += sizeof(double) * nsys * (size_t)g.nel;
-  p += sizeof(double) * nsys * crec;
   p += sizeof(int) * (size_t)g.nsub;
   if (g.nt <= g.dense_max) {
     const size_t T = coarse_tiles(g.nt);
-    p += sizeof(double) * nsys * ((size_t)g.nt * g.nt + T * (T + 1) / 2 * kCT * kCT + T * T * kCT);
+    p += sizeof(double) * nsys * (T * (T + 1) / 2 * kCT * kCT + T * T * kCT);
+  } else {
+    p += sizeof(double) * nsys * crec;
   }
   p += 5 * sizeof(double) * nsys * g.ndof;
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
   p += sizeof(double) * kNumPartSlots * kMaxSys * kMaxParts + 4096;
-  // work arrays of the build (kept by the handle): the Neumann factor and the
-  // subspace, or the coarse assembly's arrays
-  size_t eig = sizeof(double) * (rec + (size_t)g.nsub * g.nloc * (1 + 2 * msub));
-  size_t coarse =
-      sizeof(double) * pr.nsys_max * ((size_t)g.nsub * g.nebox * g.dim * g.k + asm_coarse);
-  return {p, std::max(eig, coarse)};
+  return {p, sizeof(double) * build_ws_elems(pr, g, big, msub)};
 }
 
 // Fault injection for the tests of the allocation paths: the n-th device
@@ -188,7 +192,7 @@ struct AllocGroup {
 void release(Handle* h) {
   if (!h) return;
   void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam, h->kj,     h->eres, h->lfac,
-                  h->emod,  h->twist, h->emod64, h->cfac, h->cinv, h->cpk, h->cpart, h->r, h->z,
+                  h->emod,  h->twist, h->emod64, h->cfac, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
                   h->dflag, h->build_ws};
   for (void* p : ptrs)
@@ -238,11 +242,14 @@ int check_rho_sync(Handle* h, const double* rho, int64_t n, int nsys) {
 // the inner element layers, the right-hand side (FP64) and the support flags
 // read once, the forward result written and read back and the solution
 // written.
-double local_solve_bytes(const Geometry& g, int elem) {
+double local_solve_bytes(const Geometry& g, int elem, int big) {
   const double tri = 0.5 * g.nb * (g.nb + 1.0);
   const double sw = g.dim == 3 ? (g.bn + 1.0) * (g.bn + 1.0) : g.bn + 1.0;
   const int mid = g.nblk / 2, nbot = g.nblk - 1 - mid;
-  const double reads = 2.0 * mid + 1.0 + (nbot > 0 ? 2.0 * nbot - 1.0 : 0.0);
+  // the HBM-resident solves run the forward and backward passes as separate
+  // launches, so the innermost block of the lower half is read twice too
+  const double reads = big ? 2.0 * g.nblk - 1.0
+                           : 2.0 * mid + 1.0 + (nbot > 0 ? 2.0 * nbot - 1.0 : 0.0);
   const double per = reads * tri * elem + (g.nblk - 1.0) * sw * elem +
                      (double)g.nloc * (8.0 + 1.0 + 3.0 * elem);
   return g.nsub * per;
@@ -399,6 +406,7 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
   h->g = g;
   h->stream = reinterpret_cast<hipStream_t>(stream);
   h->mixed = prob->precision == TPCG_MIXED;
+  h->big = local_is_big(g, prob->big_min_nb);
   h->msub = std::min(kMaxSub, g.k + (prob->eig_extra > 0 ? prob->eig_extra : g.k));
   if (h->msub > g.nloc) h->msub = g.nloc;
   const int ns = prob->nsys_max;
@@ -472,7 +480,7 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
   if (nsys < 1 || nsys > h->prob.nsys_max) return fail(hh, TPCG_EINVAL, "nsys out of range");
   if (rep < 0 || rep >= nsys) return fail(hh, TPCG_EINVAL, "rep out of range");
   const Geometry& g = h->g;
-  std::string lim = precond_limits(g);
+  std::string lim = precond_limits(g, h->big);
   if (!lim.empty()) return fail(hh, TPCG_EINVAL, lim);
   int rc = check_rho_sync(h, rho_phys, g.nel, nsys);
   if (rc != TPCG_OK) return rc;
@@ -481,7 +489,8 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     // preconditioner storage for nsys_max systems, allocated on the first
     // build, all or nothing (a failed build leaves the handle as it was)
     const int ns = h->prob.nsys_max;
-    const size_t fsz = (size_t)g.nblk * tile_shape(g.nb).tstride;
+    const size_t fsz = h->big ? (size_t)g.nblk * big_shape(g).rec_dir
+                              : (size_t)g.nblk * tile_shape(g.nb).tstride;
     const size_t cfsz = (size_t)g.nblkc * g.bstridec;
     const size_t ts = h->mixed ? 4 : 8;
     AllocGroup a;
@@ -492,14 +501,14 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     a.add(h->eres, (size_t)g.nsub * h->msub);
     a.add_bytes(h->lfac, ts * ns * g.nsub * fsz);
     a.add_bytes(h->emod, ts * ns * (size_t)g.nel);
-    a.add(h->twist, (size_t)ns * g.nsub * g.nb * (g.nb + 1) / 2);
+    if (!h->big) a.add(h->twist, (size_t)ns * g.nsub * g.nb * (g.nb + 1) / 2);
     if (h->mixed) a.add(h->emod64, (size_t)ns * g.nel);
-    a.add(h->cfac, ns * cfsz);
     if (g.nt <= g.dense_max) {
       const size_t T = coarse_tiles(g.nt);
-      a.add(h->cinv, (size_t)ns * g.nt * g.nt);
       a.add(h->cpk, (size_t)ns * T * (T + 1) / 2 * kCT * kCT);
       a.add(h->cpart, (size_t)ns * T * T * kCT);
+    } else {
+      a.add(h->cfac, ns * cfsz);
     }
     a.add_bytes(h->zloc, ts * ns * (size_t)g.nsub * g.nloc);
     a.add(h->yc, ns * (size_t)g.nt);
@@ -637,7 +646,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     // attribute each timed block-solve launch its algorithmic bytes: only the
     // systems still running at that iteration did work
     const Geometry& g = h->g;
-    const double per_sys = local_solve_bytes(g, h->mixed ? 4 : 8);
+    const double per_sys = local_solve_bytes(g, h->mixed ? 4 : 8, h->big);
     for (int i = 0; i < h->prof_n; ++i) {
       int running = 0;
       for (int s = 0; s < nsys; ++s) running += info[s].iters >= h->prof_it[i] + 2;

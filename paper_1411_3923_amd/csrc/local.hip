@@ -26,47 +26,12 @@
 // for the couplings into the next block. The next record is requested as
 // soon as the product is formed, and the barriers order LDS traffic only,
 // so the load flies across the two other phases.
+#include "big.h"
 #include "btri.h"
 
 namespace tpcg {
 
 namespace {
-
-// (A_{b+1,b} v)[o] for a DOF o of node layer b + 1 (top = true, v on layer b)
-// or (A_{b+1,b}^T v)[o] = (A_{b,b+1} v)[o] for a DOF o of layer b (top =
-// false, v on layer b + 1): the stiffness of the element layer between the
-// two node layers, E[] its moduli indexed (ex + 1) + (bn + 1) (ey + 1) over
-// box-local element coordinates, zero outside the mesh. Supported DOFs are
-// masked by the caller.
-template <typename T>
-__device__ inline T layer_coupling(int d, int bn, const T* __restrict__ K0s,
-                                   const T* __restrict__ E, const T* __restrict__ v, int o,
-                                   bool top) {
-  const int nd = d == 3 ? 24 : 8;
-  const int m = o / d, c = o - m * d;
-  const int lx = m % bn, ly = d == 3 ? m / bn : 0;
-  const int ny = d == 3 ? 2 : 1, ylim = d == 3 ? bn : 1;
-  T acc = 0;
-  for (int hy = 0; hy < ny; ++hy)
-    for (int hx = 0; hx < 2; ++hx) {
-      // element with this node at its corner (hx, hy) of the top or bottom face
-      const int ex = lx - hx, ey = ly - hy;
-      const T Ee = E[(ex + 1) + (d == 3 ? (bn + 1) * (ey + 1) : 0)];
-      const int ca = d == 3 ? corner_of(hx, hy, top) : corner_of(hx, top, 0);
-      T s = 0;
-      for (int oy = 0; oy < ny; ++oy)
-        for (int ox = 0; ox < 2; ++ox) {
-          const int px = ex + ox, py = ey + oy;
-          if (px < 0 || px >= bn || py < 0 || py >= ylim) continue;
-          const int cb = d == 3 ? corner_of(ox, oy, !top) : corner_of(ox, !top, 0);
-          const T* kr = K0s + (d * ca + c) * nd + d * cb;
-          const T* vp = v + d * (px + bn * py);
-          for (int c2 = 0; c2 < d; ++c2) s += kr[c2] * vp[c2];
-        }
-      acc += Ee * s;
-    }
-  return acc;
-}
 
 template <typename T>
 struct Vec16;
@@ -370,6 +335,17 @@ void local_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStr
 
 void launch_local_solves(Handle& h, const double* r, int nsys, const Gate& gate,
                          hipStream_t st) {
+  if (h.big) {
+    if (h.mixed)
+      big_local_solves<float>(h.g, r, reinterpret_cast<const float*>(h.lfac),
+                              reinterpret_cast<const float*>(h.emod), h.fixed, h.K0,
+                              reinterpret_cast<float*>(h.zloc), nsys, gate, st);
+    else
+      big_local_solves<double>(h.g, r, reinterpret_cast<const double*>(h.lfac),
+                               reinterpret_cast<const double*>(h.emod), h.fixed, h.K0,
+                               reinterpret_cast<double*>(h.zloc), nsys, gate, st);
+    return;
+  }
   if (h.mixed) local_launch<float>(h, r, nsys, gate, st);
   else local_launch<double>(h, r, nsys, gate, st);
 }

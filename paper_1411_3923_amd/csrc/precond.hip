@@ -147,23 +147,6 @@ __device__ inline void coarse_tile_ij(int tile, int& I, int& J) {
   J = tile - I * (I + 1) / 2;
 }
 
-// The lower 64 x 64 tiles (I >= J) of the symmetric K_c^-1, each row-major,
-// zero past nt. grid (T (T + 1) / 2, nsys).
-__global__ __launch_bounds__(kThreads) void k_pack_coarse_inverse(Geometry g,
-                                                                 const double* __restrict__ cinv,
-                                                                 double* __restrict__ cpk) {
-  const int sys = blockIdx.y, tile = blockIdx.x, nt = g.nt;
-  const int T = coarse_tiles(nt);
-  int I, J;
-  coarse_tile_ij(tile, I, J);
-  const double* src = cinv + (size_t)sys * nt * nt;
-  double* dst = cpk + ((size_t)sys * (T * (T + 1) / 2) + tile) * kCT * kCT;
-  for (int e = threadIdx.x; e < kCT * kCT; e += kThreads) {
-    const int r = I * kCT + e / kCT, c = J * kCT + e % kCT;
-    dst[e] = (r < nt && c < nt) ? src[(size_t)r * nt + c] : 0.0;
-  }
-}
-
 // Partial products of x_c = K_c^-1 y_c from the packed lower tiles, for the
 // running systems: tile (I, J) writes K_IJ y_J into slot [I][J] of row block
 // I and, below the diagonal, K_IJ^T y_I into slot [J][I] of row block J, so
@@ -436,12 +419,6 @@ void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& 
 
 }  // namespace
 
-void launch_pack_coarse_inverse(const Handle& h, int nsys, hipStream_t st) {
-  const int T = coarse_tiles(h.g.nt);
-  hipLaunchKernelGGL(k_pack_coarse_inverse, dim3(T * (T + 1) / 2, nsys), dim3(kThreads), 0, st,
-                     h.g, h.cinv, h.cpk);
-}
-
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
                     int rz_slot, int prof_it, int flexible, hipStream_t st) {
   const Geometry& g = h.g;
@@ -463,7 +440,7 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   // coarse spaces too large for a dense inverse) occupies one workgroup per
   // system and is latency-bound: it runs beside the local solves on the side
   // stream.
-  const bool beside = h.cinv == nullptr;
+  const bool beside = h.cpk == nullptr;
   if (!beside) {
     const int T = coarse_tiles(g.nt);
     hipLaunchKernelGGL(k_coarse_gemv_tiles, dim3(T * (T + 1) / 2, nsys), dim3(kThreads), 0, st, g,

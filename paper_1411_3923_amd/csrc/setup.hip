@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "big.h"
 #include "btri.h"
 
 namespace tpcg {
@@ -669,6 +670,28 @@ T* dalloc(size_t n, int& err) {
 
 }  // namespace
 
+size_t build_ws_elems(const tpcg_problem& pr, const Geometry& g, int big, int msub) {
+  const size_t nsl = (size_t)g.nsub * g.nloc;
+  const size_t m = msub;
+  size_t eig;
+  if (big) {
+    // Neumann records, D^-1/2, two subspace blocks, the representative
+    // moduli, then the factorisation's work arrays (later the multi-vector
+    // solves')
+    const BigShape bs = big_shape(g);
+    eig = (size_t)g.nsub * g.nblk * bs.rec_neu + nsl * (1 + 2 * m) + (size_t)g.nel +
+          std::max(big_factor_ws_elems(g, 1), big_multi_ws_elems(g));
+  } else {
+    eig = (size_t)g.nsub * g.nblk * g.bstride + nsl * (1 + 2 * m);
+  }
+  const size_t wsz = (size_t)g.nsub * g.nebox * g.dim * g.k;
+  const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
+  size_t coarse = (wsz + asm_coarse) * pr.nsys_max;
+  if (g.nt <= g.dense_max) coarse += coarse_dense_ws_elems(g, pr.nsys_max);
+  if (big) coarse += big_factor_ws_elems(g, pr.nsys_max);
+  return std::max(eig, coarse);
+}
+
 int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   const Geometry& g = h.g;
   hipStream_t st = h.stream;
@@ -676,7 +699,8 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   int err = TPCG_OK;
   const BtriShape lsh = local_shape(g), csh = coarse_shape(g);
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
-  const size_t rec = (size_t)g.nsub * g.nblk * g.bstride;
+  const size_t rec = h.big ? (size_t)g.nsub * g.nblk * big_shape(g).rec_neu
+                           : (size_t)g.nsub * g.nblk * g.bstride;
   const int m = h.msub;
   const int iters = pr.eig_iters > 0 ? pr.eig_iters : 6;
   MatParams mp{pr.E0, pr.Emin, pr.penal, pr.eig_shift != 0.0 ? pr.eig_shift : 1.0e-5};
@@ -687,8 +711,7 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   // block from the element moduli, so no assembled matrix is stored.
   const size_t nsl = (size_t)g.nsub * g.nloc;
   const size_t wsz = (size_t)g.nsub * g.nebox * g.dim * g.k;
-  const size_t need =
-      std::max(rec + nsl * (1 + 2 * (size_t)m), (wsz + asm_coarse) * pr.nsys_max);
+  const size_t need = build_ws_elems(pr, g, h.big, m);
   if (h.build_elems < need) {
     if (h.build_ws) hipFree(h.build_ws);
     h.build_ws = nullptr;
@@ -713,7 +736,24 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   double* X = dis + nsl;
   double* Y = X + nsl * m;
   const double* rrep = rho + (size_t)rep * g.nel;
-  {
+  BigFactorIn nin{};
+  double* fws = Y + nsl * m + g.nel;   // big path: factorisation, then multi-vector work arrays
+  if (h.big) {
+    // HBM-resident Neumann records from the representative system's moduli
+    double* emrep = Y + nsl * m;
+    hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, st, rrep, emrep,
+                       (int64_t)g.nel, pr.E0, pr.Emin, pr.penal);
+    nin.g = g;
+    nin.em = emrep;
+    nin.fixed = h.fixed;
+    nin.K0 = h.K0;
+    nin.dis = dis;
+    nin.shift = mp.shift;
+    nin.fixed_diag = kFixedDiag;
+    nin.neumann = 1;
+    nin.nsys = 1;
+    big_factor<double>(nin, nfac, fws, h.dflag, st);
+  } else {
     StencilIn sn = si;
     sn.rho = rrep;
     sn.neumann = 1;
@@ -723,7 +763,8 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   hipLaunchKernelGGL(k_eig_init, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
   hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
   for (int it = 0; it < iters; ++it) {
-    launch_solve_multi(nfac, lsh, g.nsub, m, X, Y, st);
+    if (h.big) big_solve_multi(nin, nfac, m, X, Y, fws, st);
+    else launch_solve_multi(nfac, lsh, g.nsub, m, X, Y, st);
     hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, Y, dis, m);
     std::swap(X, Y);
   }
@@ -745,6 +786,9 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   // --- 4: coarse matrices and factors, all systems per launch ---
   double* W = h.build_ws;                 // [nsys][wsz]
   double* Ac = W + wsz * nsys;
+  double* Sc = Ac + asm_coarse * nsys;    // dense coarse path: K_c's tiles, then the sweep's work
+  double* cws = Sc + (g.nt <= g.dense_max ? (size_t)nsys * big_nl(big_ntb(g.nt)) * kBTE : 0);
+  double* bws = Sc + (g.nt <= g.dense_max ? coarse_dense_ws_elems(g, nsys) : 0);   // big local factors
   hipMemsetAsync(Ac, 0, sizeof(double) * asm_coarse * nsys, st);
   const int nnb = g.dim == 3 ? 27 : 9;
   {
@@ -785,7 +829,20 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     sd.neumann = 0;
     sd.dis = nullptr;
     sd.twist = h.twist;
-    if (local_factor_fits(g)) {
+    if (h.big) {
+      double* em = h.mixed ? h.emod64 : reinterpret_cast<double*>(h.emod);
+      hipLaunchKernelGGL(k_moduli<double>, dim3(1024), dim3(kThreads), 0, s2, rho, em, nm, pr.E0,
+                         pr.Emin, pr.penal);
+      BigFactorIn din{};
+      din.g = g;
+      din.em = em;
+      din.fixed = h.fixed;
+      din.K0 = h.K0;
+      din.neumann = 0;
+      din.nsys = nsys;
+      if (h.mixed) big_factor<float>(din, reinterpret_cast<float*>(h.lfac), bws, h.dflag, s2);
+      else big_factor<double>(din, reinterpret_cast<double*>(h.lfac), bws, h.dflag, s2);
+    } else if (local_factor_fits(g)) {
       // FP64 moduli for the factorisations: those the solves use, or in
       // mixed precision a separate FP64 copy
       double* em = h.mixed ? h.emod64 : reinterpret_cast<double*>(h.emod);
@@ -817,11 +874,11 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
     hipEventRecord(h.join, s2);
   }
 
-  launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
-  if (h.cinv) {
-    launch_inverse(h.cfac, csh, nsys, h.cinv, st);
-    launch_pack_coarse_inverse(h, nsys, st);
-  }
+  // coarse level: the dense K_c^-1 by the block sweep on the matrix cores
+  // (its lower tiles feed the coarse product), or for coarse spaces too
+  // large for a dense inverse the block-tridiagonal factor
+  if (h.cpk) coarse_dense_inverse(g, Ac, asm_coarse, nsys, Sc, cws, h.cpk, h.dflag, st);
+  else launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
 
   hipStreamWaitEvent(st, h.join, 0);
   hipStreamSynchronize(st);

@@ -91,6 +91,7 @@ struct Handle {
 
   // preconditioner state
   int basis_ready = 0;
+  int big = 0;                       // subdomain blocks take the HBM-resident factors (big.h)
   int nsys_built = 0;
   int msub = 0;                      // eigensolver subspace width
   double* phi = nullptr;             // [nsub][nloc][k]
@@ -102,9 +103,10 @@ struct Handle {
   void* emod = nullptr;              // moduli the local factors were built from [nsys][nel], same type
   double* twist = nullptr;           // Schur terms of the lower halves, [nsys][nsub][nb (nb + 1) / 2]
   double* emod64 = nullptr;          // FP64 moduli (mixed precision), [nsys][nel]
-  double* cfac = nullptr;            // packed [nsys][nblkc][bstridec]
-  double* cinv = nullptr;            // dense K_c^-1 [nsys][nt][nt] when nt <= kDenseCoarse
-  double* cpk = nullptr;             // its lower 64 x 64 tiles [nsys][T (T + 1) / 2][64][64]
+  double* cfac = nullptr;            // block-tridiagonal coarse factor [nsys][nblkc][bstridec]
+                                     // (coarse dimensions above dense_max only)
+  double* cpk = nullptr;             // lower 64 x 64 tiles of the dense K_c^-1 (nt <= dense_max)
+                                     // [nsys][T (T + 1) / 2][64][64]
   double* cpart = nullptr;           // tile partials of K_c^-1 y_c [nsys][T][T][64]
   double* build_ws = nullptr;        // work arrays of the preconditioner build
   size_t build_elems = 0;
@@ -286,8 +288,6 @@ void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 
 // precond.hip: z = M^-1 r, gated; partials of r.z into rz_slot (and r.z_old into kPartRZO)
 // prof_it >= -1 records events around the block-solve launch when profiling is on
-// Packs the lower tiles of the dense coarse inverse (after it is formed).
-void launch_pack_coarse_inverse(const Handle& h, int nsys, hipStream_t st);
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
                     int rz_slot, int prof_it, int flexible, hipStream_t st);
 
@@ -296,6 +296,8 @@ void launch_local_solves(Handle& h, const double* r, int nsys, const Gate& gate,
 
 // setup.hip
 int build_preconditioner(Handle& h, const double* rho, int nsys, int rep);
+// work arrays (doubles) the preconditioner build keeps in the handle
+size_t build_ws_elems(const tpcg_problem& pr, const Geometry& g, int big, int msub);
 
 // density.hip
 void launch_filter_project(const Handle& h, const double* rho, double rmin, double beta,

@@ -1,0 +1,173 @@
+"""GPU parity tests of the HBM-resident factor path (subdomain node-layer
+blocks beyond the on-chip kernels: 3D cells of 16^3 elements give blocks of
+867 unknowns) against the FP64 oracle:
+
+* the path forced on the 64 x 32 MBB beam (s = 8) and on the production
+  subdomain shape (s = 32, k = 6): M^-1 r element by element against the
+  oracle and against the on-chip path, PCG against the direct solve;
+* 3D cells of 4^3 elements (odd block size 75, taken by this path only):
+  M^-1 r and PCG;
+* 3D cells of 8^3 elements: the local eigenpairs against the dense
+  eigensolver;
+* 3D cells of 16^3 elements (the 3D cantilever's subdomain shape, block
+  size 867): PCG against the direct solve in FP64 and mixed precision.
+
+Tolerances as in the other parity tests: M^-1 r element by element
+max|z - z_o| / max|z_o| below 1e-12 (FP64; both sides apply the same
+operator through different backward-stable factorisations) and 1e-6 (mixed:
+factors stored in FP32); displacement and compliance against the sparse
+direct solve below 1e-8 (FP64) and 1e-6 (mixed) at rtol 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import density, fem, schwarz
+from paper_1411_3923_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1411_3923_amd as T  # noqa: E402
+from tests.gpu_common import dev, handle, host, rel  # noqa: E402
+
+SWEEPS = 40
+FORCE = dict(big_min_nb=1)
+
+
+def elementwise(a, b):
+    return float(np.max(np.abs(np.ravel(a) - np.ravel(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def oracle_ms(p, rb, rep, fixed):
+    E_rep = fem.simp_modulus(rb[rep], p.E0, p.Emin, p.penal)
+    Phi = schwarz.coarse_basis(p, E_rep, fixed, p.k)[0]
+    return [schwarz.TwoLevelSchwarz(p, fem.assemble(p, fem.simp_modulus(r, p.E0, p.Emin, p.penal)),
+                                    fixed, Phi) for r in rb]
+
+
+def residuals(p, nsys, seed):
+    r = np.random.default_rng(seed).standard_normal((nsys, p.n_dof))
+    r[:, W.fixed_mask(p) == 1] = 0.0
+    return r
+
+
+def precond(p, rb, precision, r, **kw):
+    h = handle(p, precision=precision, nsys=len(rb), eig_iters=SWEEPS, **kw)
+    h.build_coarse_basis(dev(rb), rep=0)
+    z = dev(np.zeros_like(r))
+    h.apply_precond(dev(r), z)
+    return h, host(z)
+
+
+def pcg_vs_direct(h, p, rb, precision, label):
+    f = W.load_vector(p)
+    n = len(rb)
+    u = dev(np.zeros((n, p.n_dof)))
+    info = h.pcg_solve(dev(rb), dev(np.stack([f] * n)), u, rtol=1e-12, maxit=3000)
+    uu = host(u).reshape(n, p.n_dof)
+    tol = 1e-8 if precision == T.FP64 else 1e-6
+    for s in range(n):
+        u_o = fem.solve(p, rb[s])
+        c_o = fem.compliance(f, u_o)
+        eu, ec = rel(uu[s], u_o), abs(fem.compliance(f, uu[s]) - c_o) / c_o
+        print(f"{label} system {s}: iters {info[s]['iters']} u {eu:.3e} c {ec:.3e}", flush=True)
+        assert info[s]["status"] == 0, info
+        assert eu < tol and ec < tol
+    return info
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED], ids=["fp64", "mixed"])
+def test_big_path_mbb_matches_oracle(precision):
+    p = W.mbb_64x32()
+    rb = W.design_field(p)[None, :]
+    fixed = W.fixed_mask(p)
+    want = oracle_ms(p, rb, 0, fixed)[0].apply(residuals(p, 1, 11)[0])
+    h, z = precond(p, rb, precision, residuals(p, 1, 11), **FORCE)
+    e = elementwise(z[0], want)
+    print(f"big path mbb {'fp64' if precision == T.FP64 else 'mixed'}: precond {e:.3e}", flush=True)
+    assert e < (1e-12 if precision == T.FP64 else 1e-6)
+    pcg_vs_direct(h, p, rb, precision, "big path mbb")
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED], ids=["fp64", "mixed"])
+def test_big_path_production_shape(precision):
+    p = W.cantilever2d(128, 96, 32, 6)
+    _, rb = density.filter_project(p, W.design_field(p), p.rmin, p.beta, p.etas)
+    fixed = W.fixed_mask(p)
+    Ms = oracle_ms(p, rb, 0, fixed)
+    r = residuals(p, p.nsys, 12)
+    hb, zb = precond(p, rb, precision, r, **FORCE)
+    hs, zs = precond(p, rb, precision, r)
+    for s in range(p.nsys):
+        want = Ms[s].apply(r[s])
+        e, ep = elementwise(zb[s], want), elementwise(zb[s], zs[s])
+        print(f"big path s=32 {'fp64' if precision == T.FP64 else 'mixed'} system {s}: "
+              f"precond {e:.3e}, against the on-chip path {ep:.3e}", flush=True)
+        assert e < (1e-12 if precision == T.FP64 else 1e-6)
+        assert ep < (1e-12 if precision == T.FP64 else 1e-6)
+    pcg_vs_direct(hb, p, rb, precision, "big path s=32")
+    hb.close()
+    hs.close()
+
+
+def cube(nel, sub, k):
+    return W.cantilever3d(*nel, sub=sub, k=k)
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED], ids=["fp64", "mixed"])
+def test_big_path_3d_odd_blocks(precision):
+    p = cube((16, 8, 8), 4, 6)           # node layers of 3 * 5^2 = 75 unknowns
+    rb = W.design_field(p)[None, :]
+    fixed = W.fixed_mask(p)
+    want = oracle_ms(p, rb, 0, fixed)[0].apply(residuals(p, 1, 13)[0])
+    h, z = precond(p, rb, precision, residuals(p, 1, 13))
+    e = elementwise(z[0], want)
+    print(f"big path 3d s=4 {'fp64' if precision == T.FP64 else 'mixed'}: precond {e:.3e}",
+          flush=True)
+    assert e < (1e-12 if precision == T.FP64 else 1e-6)
+    pcg_vs_direct(h, p, rb, precision, "big path 3d s=4")
+    h.close()
+
+
+def test_big_path_3d_eigenpairs():
+    p = cube((16, 16, 8), 8, 8)          # node layers of 3 * 9^2 = 243 unknowns
+    rb = W.design_field(p)[None, :]
+    fixed = W.fixed_mask(p)
+    h = handle(p, nsys=1, eig_iters=SWEEPS)
+    h.build_coarse_basis(dev(rb), rep=0)
+    phi, lam, res = h.export_coarse_basis()
+    phi = host(phi)
+    E = fem.simp_modulus(rb[0], p.E0, p.Emin, p.penal)
+    chi = schwarz.partition_of_unity(p)
+    worst_l, worst_a = 0.0, 0.0
+    for j in range(p.n_sub):
+        lo, psi, dofs = schwarz.local_eigenpairs(p, E, fixed, j, p.k + 1)
+        nodes = schwarz.subdomain_nodes(p, j)
+        alld = (p.dim * nodes[:, None] + np.arange(p.dim)[None, :]).ravel()
+        g = phi[j][fixed[alld] == 0]
+        scale = np.maximum(np.abs(lo[:p.k]), 1e-6)
+        worst_l = max(worst_l, float(np.max(np.abs(lam[j] - lo[:p.k]) / scale)))
+        if (lo[p.k] - lo[p.k - 1]) / lo[p.k] > 0.05:
+            qa, _ = np.linalg.qr(psi[:, :p.k] * chi[dofs // p.dim][:, None])
+            qb, _ = np.linalg.qr(g)
+            sv = np.linalg.svd(qa.T @ qb, compute_uv=False)
+            worst_a = max(worst_a, float(np.sqrt(max(0.0, 1.0 - sv.min() ** 2))))
+    print(f"big path 3d s=8 eigenpairs: eigenvalue {worst_l:.3e} angle {worst_a:.3e} "
+          f"ritz residual {np.max(res):.3e}", flush=True)
+    assert worst_l < 1e-7 and worst_a < 1e-6 and np.max(res) < 1e-6
+    h.close()
+
+
+@pytest.mark.parametrize("precision", [T.FP64, T.MIXED], ids=["fp64", "mixed"])
+def test_big_path_3d_cantilever_cells(precision):
+    p = cube((32, 16, 16), 16, 8)        # the 3D cantilever's cells: blocks of 867 unknowns
+    rb = W.design_field(p)[None, :]
+    h = handle(p, precision=precision, nsys=1)
+    h.build_coarse_basis(dev(rb), rep=0)
+    info = pcg_vs_direct(h, p, rb, precision, "big path 3d s=16")
+    assert info[0]["iters"] < 200
+    h.close()
