@@ -102,17 +102,35 @@ def partition_of_unity(p):
 # Local eigenproblems (Sec. 2.4 discrete eigenproblem; Sec. 3.2 diag weighting)
 # ---------------------------------------------------------------------------
 
-def local_eigenpairs(p, E_rep, fixed, j, k, K0=None):
-    """k smallest eigenpairs of K_j^N psi = lambda diag(K_j^N) psi (D-orthonormal psi)."""
+def local_eigenpairs(p, E_rep, fixed, j, k, K0=None, method="dense"):
+    """k smallest eigenpairs of K_j^N psi = lambda diag(K_j^N) psi (D-orthonormal psi).
+
+    method "dense": LAPACK's generalised symmetric eigensolver on the dense
+    matrices. method "sparse" (large cells): ARPACK in shift-invert mode on
+    S = D^-1/2 K_j^N D^-1/2, whose eigenvalues are the same, shifted just
+    below zero so that S - sigma I is definite for floating cells, with
+    psi = D^-1/2 x; the same definition, for cells too large for a dense
+    eigensolver.
+    """
     dofs = subdomain_dofs(p, j, fixed)
     KN = fem.assemble(p, E_rep, K0, elements=subdomain_elements(p, j))
-    KN = KN[dofs][:, dofs].toarray()
+    KN = KN[dofs][:, dofs]
+    if method == "sparse":
+        import scipy.sparse.linalg as spla
+        d = KN.diagonal()
+        Dh = sp.diags(1.0 / np.sqrt(d))
+        S = (Dh @ KN @ Dh).tocsc()
+        lam, x = spla.eigsh(S, k=k, sigma=-1e-6, which="LM", tol=1e-13)
+        order = np.argsort(lam)
+        lam, x = lam[order], x[:, order]
+        return lam, x / np.sqrt(d)[:, None], dofs
+    KN = KN.toarray()
     D = np.diag(np.diag(KN))
     lam, psi = sla.eigh(KN, D, subset_by_index=[0, k - 1])
     return lam, psi, dofs
 
 
-def coarse_basis(p, E_rep, fixed, k, K0=None, thresh=0.0):
+def coarse_basis(p, E_rep, fixed, k, K0=None, thresh=0.0, method="dense"):
     """Global Phi = R_c^T (sparse) and the per-subdomain eigenvalues.
 
     thresh <= 0: the k smallest eigenvectors of every subdomain (n_dof x J*k).
@@ -124,7 +142,7 @@ def coarse_basis(p, E_rep, fixed, k, K0=None, thresh=0.0):
     rows, cols, vals, lams, kj = [], [], [], [], []
     col = 0
     for j in range(p.n_sub):
-        lam, psi, dofs = local_eigenpairs(p, E_rep, fixed, j, k, K0)
+        lam, psi, dofs = local_eigenpairs(p, E_rep, fixed, j, k, K0, method)
         use = k if thresh <= 0 else int(np.sum(lam < thresh))
         w = chi[dofs // p.dim]
         for m in range(use):
@@ -245,14 +263,15 @@ def pcg(matvec, precond, f, x0=None, rtol=1e-8, maxit=1000, callback=None):
 
 
 def solve_pcg(p, rho_phys_sys, rho_rep, f, fixed, k=None, rtol=1e-8, maxit=1000,
-              coarse=True, local=True):
-    """Oracle PCG for each system with the shared coarse basis from rho_rep."""
+              coarse=True, local=True, thresh=0.0, eig_method="dense"):
+    """Oracle PCG for each system with the shared coarse basis from rho_rep
+    (thresh > 0: the eigenvalue-threshold coarse space, at most k per cell)."""
     K0 = fem.element_K0(p.dim, p.nu)
     k = p.k if k is None else k
     Phi = None
     if coarse:
         E_rep = fem.simp_modulus(rho_rep, p.E0, p.Emin, p.penal)
-        Phi, _ = coarse_basis(p, E_rep, fixed, k, K0)
+        Phi = coarse_basis(p, E_rep, fixed, k, K0, thresh=thresh, method=eig_method)[0]
     out = []
     for rho in rho_phys_sys:
         E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)

@@ -159,6 +159,13 @@ def test_big_path_3d_eigenpairs():
     print(f"big path 3d s=8 eigenpairs: eigenvalue {worst_l:.3e} angle {worst_a:.3e} "
           f"ritz residual {np.max(res):.3e}", flush=True)
     assert worst_l < 1e-7 and worst_a < 1e-6 and np.max(res) < 1e-6
+    # M^-1 r with four 64-row tiles per block, element by element
+    r = residuals(p, 1, 14)
+    z = dev(np.zeros_like(r))
+    h.apply_precond(dev(r), z)
+    e = elementwise(host(z)[0], oracle_ms(p, rb, 0, fixed)[0].apply(r[0]))
+    print(f"big path 3d s=8: precond {e:.3e}", flush=True)
+    assert e < 1e-12
     h.close()
 
 

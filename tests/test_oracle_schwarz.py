@@ -285,3 +285,34 @@ def _scaled_neumann(p, E, fixed, j):
     KN = fem.assemble(p, E, elements=schwarz.subdomain_elements(p, j))[dofs][:, dofs].toarray()
     d = np.diag(KN)
     return KN / np.sqrt(np.outer(d, d))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sparse_eigensolver_matches_dense(dim):
+    # the shift-invert ARPACK route for large cells against the dense
+    # generalised eigensolver on cells both can take: the same eigenvalues,
+    # D-orthonormal vectors spanning the same space where the spectrum has a
+    # gap after the k-th value
+    if dim == 2:
+        p = mbb(nelx=32, nely=16, sub=8, k=6)
+    else:
+        p = W.cantilever3d(16, 8, 8, sub=4, k=8)
+    rho = W.design_field(p)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    fixed = W.fixed_mask(p)
+    for j in (0, p.n_sub // 2, p.n_sub - 1):
+        lo, po, dofs = schwarz.local_eigenpairs(p, E, fixed, j, p.k + 1)
+        ls, ps, dofs2 = schwarz.local_eigenpairs(p, E, fixed, j, p.k + 1, method="sparse")
+        assert np.array_equal(dofs, dofs2)
+        np.testing.assert_allclose(ls, lo, rtol=1e-8, atol=1e-12)
+        KN = fem.assemble(p, E, elements=schwarz.subdomain_elements(p, j))[dofs][:, dofs]
+        d = KN.diagonal()
+        np.testing.assert_allclose(ps.T @ (d[:, None] * ps), np.eye(p.k + 1), atol=1e-9)
+        # residual of the scaled problem S x = lambda x (S = D^-1/2 K D^-1/2, O(1) norm)
+        x = ps * np.sqrt(d)[:, None]
+        S = KN.toarray() / np.sqrt(np.outer(d, d))
+        assert np.abs(S @ x - x * ls[None, :]).max() < 1e-9
+        if (lo[p.k] - lo[p.k - 1]) > 0.05 * lo[p.k]:
+            qa, _ = np.linalg.qr(po[:, :p.k] * np.sqrt(d)[:, None])
+            qb, _ = np.linalg.qr(ps[:, :p.k] * np.sqrt(d)[:, None])
+            assert np.linalg.svd(qa.T @ qb, compute_uv=False).min() > 1 - 1e-9
