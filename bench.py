@@ -12,6 +12,15 @@ to the design field. All inputs are resident on the GPU before timing.
 value = sum over systems of (DOFs x PCG iterations) / step time (FP64).
 The same steps are then run with the mixed-precision preconditioner.
 
+--workload cantilever3d runs the trilinear-element cantilever of 192 x 96 x
+96 elements (5,447,811 DOFs, one system, layered 0/1 microstructure, no
+filter) on subdomains of 16^3 elements instead: one step = coarse basis and
+factors, PCG to 1e-8, compliance and sensitivities. Its layered design has
+about twelve near-zero modes per subdomain (two solid plates joined by void),
+so it runs with the paper's eigenvalue threshold (--lambda-thresh, default
+1e-6) and at most 16 coarse vectors per subdomain; --lambda-thresh 0
+--ncoarse 8 runs the fixed count of 8.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -27,14 +36,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "local_solves_cantilever2d_1024x512_traffic.json")
-KERNEL_SOURCES = ["paper_1411_3923_amd/csrc/btri.h", "paper_1411_3923_amd/csrc/local.hip"]
+TRAFFIC_FILES = {
+    "cantilever2d": os.path.join(ROOT, "profiles", "local_solves_cantilever2d_1024x512_traffic.json"),
+    "cantilever3d": os.path.join(ROOT, "profiles", "local_solves_cantilever3d_192x96x96_traffic.json"),
+}
+TRAFFIC_FILE = TRAFFIC_FILES["cantilever2d"]
+KERNEL_SOURCES = {
+    "cantilever2d": ["paper_1411_3923_amd/csrc/btri.h", "paper_1411_3923_amd/csrc/local.hip"],
+    "cantilever3d": ["paper_1411_3923_amd/csrc/btri.h", "paper_1411_3923_amd/csrc/big.hip",
+                     "paper_1411_3923_amd/csrc/big.h"],
+}
+ROOFLINE_KERNEL = {"cantilever2d": "k_local_solves<double>",
+                   "cantilever3d": "k_big_solve_{fwd,mid,bwd}<double>"}
 COPY_BYTES = 1 << 30
 
 
-def kernel_hash():
+def kernel_hash(workload="cantilever2d"):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[workload]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -51,8 +70,9 @@ def run_gpu(precision, args, p, rho_h, f_h):
     import paper_1411_3923_amd as T
     from paper_1411_3923_amd import workloads as W
 
-    pr = T.make_problem(p.dim, p.nel[:2], p.sub, p.k, p.nsys, p.E0, p.Emin, p.penal, p.nu,
-                        precision, eig_iters=args.eig_iters, eig_extra=args.eig_extra)
+    pr = T.make_problem(p.dim, p.nel[:p.dim], p.sub, p.k, p.nsys, p.E0, p.Emin, p.penal, p.nu,
+                        precision, eig_iters=args.eig_iters, eig_extra=args.eig_extra,
+                        lambda_thresh=args.lambda_thresh)
     h = T.Handle(pr, W.fixed_mask(p))
     d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
     rho = d(rho_h)
@@ -64,15 +84,21 @@ def run_gpu(precision, args, p, rho_h, f_h):
     dc = torch.zeros((p.nsys, p.n_el), dtype=torch.float64, device="cuda")
     dcr = torch.zeros((p.nsys, p.n_el), dtype=torch.float64, device="cuda")
 
+    filtered = p.rmin > 0.0
+    if not filtered:
+        rb.copy_(rho.view(1, -1).expand(p.nsys, -1))   # unfiltered design: rho_phys = rho
+
     def step():
         t0 = time.perf_counter()
-        h.filter_project(rho, p.rmin, p.beta, p.etas, rt, rb)
+        if filtered:
+            h.filter_project(rho, p.rmin, p.beta, p.etas, rt, rb)
         h.build_coarse_basis(rb, rep=0)          # blocks until the factors are done
         t1 = time.perf_counter()
         u.zero_()
         info = h.pcg_solve(rb, F, u, rtol=args.rtol, maxit=args.maxit)   # blocks
         h.compliance_and_sensitivity(rb, u, F, c, dc)
-        h.filter_project_adjoint(rt, p.rmin, p.beta, p.etas, dc, dcr)
+        if filtered:
+            h.filter_project_adjoint(rt, p.rmin, p.beta, p.etas, dc, dcr)
         return info, (t1 - t0) * 1e3
 
     for _ in range(args.warmup):
@@ -91,6 +117,7 @@ def run_gpu(precision, args, p, rho_h, f_h):
     t1 = time.perf_counter()
     prof = h.profile_block_solves()
     _, lam, eres = h.export_coarse_basis()
+    _, kj = h.export_eigenvalues()
     ms_step = (t1 - t0) * 1e3 / args.steps
     iters = [i["iters"] for i in infos[-1]]
     work = sum(p.n_dof * it for it in iters)
@@ -108,6 +135,8 @@ def run_gpu(precision, args, p, rho_h, f_h):
         "compliance": [float(x) for x in c.cpu()],
         "block_solves": prof,
         "eig_max_ritz_residual": float(np.max(eres)),
+        "coarse_vectors_per_subdomain": {"min": int(kj.min()), "max": int(kj.max()),
+                                         "mean": float(kj.mean()), "total": int(kj.sum())},
         "u": u.cpu().numpy(),
         "dc": dc.cpu().numpy(),
     }
@@ -126,24 +155,52 @@ def cpu_baseline(args):
         threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    p = W.cantilever2d(512, 128, 32, 6)
-    rho = W.design_field(p)
-    fixed, f = W.fixed_mask(p), W.load_vector(p)
-    t0 = time.perf_counter()
-    rt, rb = density.filter_project(p, rho, p.rmin, p.beta, p.etas)
-    res = schwarz.solve_pcg(p, list(rb), rb[0], f, fixed, rtol=args.rtol, maxit=args.maxit)
-    dcs = np.stack([fem.sensitivity(p, rb[s], res[s][0]) for s in range(p.nsys)])
-    [fem.compliance(f, r[0]) for r in res]
-    density.filter_project_adjoint(p, rt, p.rmin, p.beta, p.etas, dcs)
-    t1 = time.perf_counter()
-    work = sum(p.n_dof * r[1] for r in res)
+    if args.workload == "cantilever3d":
+        # a 32 x 16 x 16 section (two of the 16^3 cells) of the same layered
+        # design, the same coarse-space rule, the oracle's sparse shift-invert
+        # eigensolver (its dense one does not finish on cells of 14,739 DOFs)
+        p = W.cantilever3d(32, 16, 16, sub=16, k=args.ncoarse)
+        rho = W.design_field(p)
+        fixed, f = W.fixed_mask(p), W.load_vector(p)
+        t0 = time.perf_counter()
+        res = schwarz.solve_pcg(p, [rho], rho, f, fixed, rtol=args.rtol, maxit=args.maxit,
+                                thresh=args.lambda_thresh, eig_method="sparse")
+        fem.sensitivity(p, rho, res[0][0])
+        fem.compliance(f, res[0][0])
+        t1 = time.perf_counter()
+        work = p.n_dof * res[0][1]
+        sample = (f"one full step (spectral basis, PCG to {args.rtol:g}, sensitivities) on a "
+                  f"32x16x16-element section of the layered 3D cantilever (two 16^3 cells, "
+                  f"{p.n_dof} DOFs); {t1 - t0:.1f} s, {res[0][1]} iterations")
+    else:
+        p = W.cantilever2d(512, 128, 32, 6)
+        rho = W.design_field(p)
+        fixed, f = W.fixed_mask(p), W.load_vector(p)
+        t0 = time.perf_counter()
+        rt, rb = density.filter_project(p, rho, p.rmin, p.beta, p.etas)
+        res = schwarz.solve_pcg(p, list(rb), rb[0], f, fixed, rtol=args.rtol, maxit=args.maxit)
+        dcs = np.stack([fem.sensitivity(p, rb[s], res[s][0]) for s in range(p.nsys)])
+        [fem.compliance(f, r[0]) for r in res]
+        density.filter_project_adjoint(p, rt, p.rmin, p.beta, p.etas, dcs)
+        t1 = time.perf_counter()
+        work = sum(p.n_dof * r[1] for r in res)
+        sample = (f"one full step (filter+projection, spectral basis, 3-realisation PCG to "
+                  f"{args.rtol:g}, sensitivities, chain rule) on a 512x128-element section of "
+                  f"the cantilever workload (64 subdomains of 32x32, k=6; "
+                  f"{p.n_dof} DOFs/system); {t1 - t0:.1f} s, iterations "
+                  f"{[r[1] for r in res]}")
     return {"value": work / (t1 - t0), "unit": "DOF-iters/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": (f"one full step (filter+projection, spectral basis, 3-realisation PCG to "
-                       f"{args.rtol:g}, sensitivities, chain rule) on a 512x128-element section of "
-                       f"the cantilever workload (64 subdomains of 32x32, k=6; "
-                       f"{p.n_dof} DOFs/system); {t1 - t0:.1f} s, iterations "
-                       f"{[r[1] for r in res]}")}
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(), "kind": "oracle", "sample": sample}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return None
 
 
 def short_name(name):
@@ -184,12 +241,21 @@ def summarize_trace(stats_csv, command, out, title, bench_json=None):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
-def summarize_traffic(fetch_csv, write_csv, command, out_json, out_md, kernel="k_local_solves<double>"):
+def summarize_traffic(fetch_csv, write_csv, command, out_json, out_md, kernel="k_local_solves<double>",
+                      workload="cantilever2d"):
     """HBM bytes per launch of the roofline kernel from two rocprofv3 --pmc runs
     (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch). Each counter is scaled by
     what it reads for the first device-to-device copy of the run, a copy of
-    COPY_BYTES bytes in each direction."""
+    COPY_BYTES bytes in each direction. A kernel name with {a,b,c} counts the
+    three kernels of one local solve together (their i-th dispatches summed)."""
     import csv
+
+    if "{" in kernel:
+        head, rest = kernel.split("{", 1)
+        alts, tail = rest.split("}", 1)
+        keys = [head + a + tail.rstrip(">") for a in alts.split(",")]
+    else:
+        keys = [kernel.rstrip(">")]   # template arguments beyond the element type vary
 
     def load(path, counter):
         rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
@@ -197,8 +263,9 @@ def summarize_traffic(fetch_csv, write_csv, command, out_json, out_md, kernel="k
         copy = next(r for r in rows if "copyBuffer" in r["Kernel_Name"])
         kib_copy = float(copy["Counter_Value"])
         assert kib_copy * 1024 > COPY_BYTES / 4, "calibration copy not found"
-        key = kernel.rstrip(">")          # template arguments beyond the element type vary
-        vals = [float(r["Counter_Value"]) for r in rows if key in r["Kernel_Name"]]
+        per = [[float(r["Counter_Value"]) for r in rows if k in r["Kernel_Name"]] for k in keys]
+        n = min(len(v) for v in per)
+        vals = [sum(v[i] for v in per) for i in range(n)]
         return COPY_BYTES / (kib_copy * 1024), vals
 
     ff, fv = load(fetch_csv, "FETCH_SIZE")
@@ -210,12 +277,15 @@ def summarize_traffic(fetch_csv, write_csv, command, out_json, out_md, kernel="k
     wv = [wv[i] for i in busy if i < len(wv)]
     fetch = sum(fv) / len(fv) * 1024 * ff
     write = sum(wv) / len(wv) * 1024 * wf
-    res = {"kernel": kernel, "kernel_hash": kernel_hash(), "kernel_sources": KERNEL_SOURCES,
+    res = {"kernel": kernel, "kernel_hash": kernel_hash(workload),
+           "kernel_sources": KERNEL_SOURCES[workload],
            "bytes_per_launch": fetch + write, "fetch_bytes_per_launch": fetch,
            "write_bytes_per_launch": write, "fetch_scale": ff, "write_scale": wf,
            "launches": len(fv), "command": command}
     json.dump(res, open(out_json, "w"), indent=1)
-    lines = [f"# HBM traffic of {kernel}: 1024x512 cantilever, 3 realisations, FP64", "",
+    title = ("192x96x96 layered 3D cantilever, FP64" if workload == "cantilever3d"
+             else "1024x512 cantilever, 3 realisations, FP64")
+    lines = [f"# HBM traffic of {kernel}: {title}", "",
              "Commands (on one MI355X, from the repository root):", ""]
     lines += ["    " + c for c in command.split(" ;; ")]
     lines += ["", f"The first copy in each run moves {COPY_BYTES} bytes. FETCH_SIZE reads it as "
@@ -315,8 +385,13 @@ def summarize_loop(fetch_csv, write_csv, trace_csv, command, out):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["cantilever2d", "cantilever3d"], default="cantilever2d")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 10; 3 in 3D)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2; 1 in 3D)")
+    ap.add_argument("--ncoarse", type=int, default=0,
+                    help="coarse vectors per subdomain, the cap under a threshold (0: 6 in 2D, 16 in 3D)")
+    ap.add_argument("--lambda-thresh", type=float, default=None,
+                    help="eigenvalue threshold of the coarse space (default 0 in 2D, 1e-6 in 3D)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -342,9 +417,19 @@ def main():
     if args.summarize_loop:
         summarize_loop(*args.summarize_loop, args.command, args.out)
         return
+    three = args.workload == "cantilever3d"
+    if args.steps is None:
+        args.steps = 3 if three else 10
+    if args.warmup is None:
+        args.warmup = 1 if three else 2
+    if args.ncoarse <= 0:
+        args.ncoarse = 16 if three else 6
+    if args.lambda_thresh is None:
+        args.lambda_thresh = 1e-6 if three else 0.0
     if args.summarize_traffic:
-        summarize_traffic(*args.summarize_traffic, args.command, TRAFFIC_FILE,
-                          TRAFFIC_FILE.replace(".json", ".md"))
+        tf = TRAFFIC_FILES[args.workload]
+        summarize_traffic(*args.summarize_traffic, args.command, tf, tf.replace(".json", ".md"),
+                          kernel=ROOFLINE_KERNEL[args.workload], workload=args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve of one "
@@ -365,7 +450,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    p = W.cantilever2d(1024, 512, 32, 6)
+    if three:
+        p = W.cantilever3d(192, 96, 96, 16, args.ncoarse)
+    else:
+        p = W.cantilever2d(1024, 512, 32, args.ncoarse)
     rho_h = W.design_field(p)
     f_h = W.load_vector(p)
 
@@ -375,16 +463,17 @@ def main():
     prof = r64["block_solves"]
     achieved = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] > 0 else None
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        t = json.load(open(TRAFFIC_FILE))
-        if t.get("kernel_hash") == kernel_hash():
+    tf = TRAFFIC_FILES[args.workload]
+    if os.path.exists(tf):
+        t = json.load(open(tf))
+        if t.get("kernel_hash") == kernel_hash(args.workload):
             traffic = t.get("bytes_per_launch")
 
     def summary(r):
         return {k: r[k] for k in ("ms_per_step", "dof_iters_per_s", "solve_only_dof_iters_per_s",
                                   "solve_ms_p50", "solve_ms_p99", "setup_ms_p50", "iters",
                                   "relres", "true_relres", "status", "compliance",
-                                  "eig_max_ritz_residual")}
+                                  "eig_max_ritz_residual", "coarse_vectors_per_subdomain")}
 
     line = {
         "metric": "PCG solve time & DOF-iters/s to rel-res 1e-8 (FP64 vs mixed); p50/p99 latency",
@@ -399,13 +488,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "cantilever2d_q4_1024x512_3realisations", "elements": p.n_el,
-                   "dofs_per_system": p.n_dof, "systems": p.nsys, "subdomain": p.sub,
-                   "coarse_vectors": p.k, "rtol": args.rtol,
-                   "step": "filter+projection, basis+factor build, batched PCG, "
-                           "compliance+sensitivities, chain rule"},
+        "config": ({"workload": "cantilever3d_h8_192x96x96_layered", "elements": p.n_el,
+                    "dofs_per_system": p.n_dof, "systems": p.nsys, "subdomain": p.sub,
+                    "coarse_vectors_cap": p.k, "lambda_thresh": args.lambda_thresh,
+                    "rtol": args.rtol,
+                    "step": "basis+factor build, PCG, compliance+sensitivities"} if three else
+                   {"workload": "cantilever2d_q4_1024x512_3realisations", "elements": p.n_el,
+                    "dofs_per_system": p.n_dof, "systems": p.nsys, "subdomain": p.sub,
+                    "coarse_vectors": p.k, "rtol": args.rtol,
+                    "step": "filter+projection, basis+factor build, batched PCG, "
+                            "compliance+sensitivities, chain rule"}),
         "fp64": summary(r64),
-        "roofline": {"bound": "hbm", "kernel": "k_local_solves<double>",
+        "roofline": {"bound": "hbm", "kernel": ROOFLINE_KERNEL[args.workload],
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic,
