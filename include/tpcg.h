@@ -279,6 +279,20 @@ int tpcg_set_profiling(tpcg_handle* h, int32_t on);
 int tpcg_profile_block_solves(const tpcg_handle* h, double* out3);
 
 /*
+ * Launch mode of tpcg_pcg_solve. With graphs on, the chunks of four PCG
+ * iterations after the first are captured once into HIP graphs and replayed
+ * (a capture is redone when the solve's arguments change). With graphs off
+ * (the default: on MI355X the replay measured slightly slower than launching
+ * the same kernels from the host), when profiling is on, when the coarse
+ * level uses the block-tridiagonal factor, or when a capture fails (the
+ * handle then stays eager), every kernel is launched from the host. Results
+ * are bitwise the same in both modes. tpcg_last_solve_graph_chunks gives
+ * the number of chunks the last solve replayed from graphs.
+ */
+int tpcg_set_graphs(tpcg_handle* h, int32_t on);
+int tpcg_last_solve_graph_chunks(const tpcg_handle* h);
+
+/*
  * Testing support for the allocation paths: the nth device allocation the
  * library makes from this call on fails as if the device were out of memory
  * (nth <= 0: none). Process-wide, not thread-safe.

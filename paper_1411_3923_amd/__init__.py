@@ -54,7 +54,8 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_filter_project_adjoint", "tpcg_export_coarse_basis", "tpcg_query",
            "tpcg_set_profiling", "tpcg_profile_block_solves", "tpcg_export_eigenvalues",
            "tpcg_query_subspace", "tpcg_test_fail_alloc", "tpcg_last_error", "tpcg_destroy",
-           "tpcg_compliance_and_sensitivity_noalloc"]
+           "tpcg_compliance_and_sensitivity_noalloc", "tpcg_set_graphs",
+           "tpcg_last_solve_graph_chunks"]
 
 
 def load_library(path: str | None = None):
@@ -89,6 +90,8 @@ def load_library(path: str | None = None):
     lib.tpcg_last_error.restype = ctypes.c_char_p
     lib.tpcg_destroy.argtypes = [P]
     lib.tpcg_destroy.restype = None
+    lib.tpcg_set_graphs.argtypes = [P, I32]
+    lib.tpcg_last_solve_graph_chunks.argtypes = [P]
     lib.tpcg_compliance_and_sensitivity_noalloc.argtypes = [ctypes.POINTER(Problem), P, P, P, P,
                                                             I32, P, P, P, V]
     for name in EXPORTS:
@@ -231,6 +234,12 @@ class Handle:
             _ptr(dc_drho_phys, torch.float64, nsys * self.n_el),
             _ptr(dc_drho, torch.float64, nsys * self.n_el)))
         return dc_drho
+
+    def set_graphs(self, on=True):
+        self._check(self.lib.tpcg_set_graphs(self.h, 1 if on else 0))
+
+    def last_graph_chunks(self):
+        return int(self.lib.tpcg_last_solve_graph_chunks(self.h))
 
     def set_profiling(self, on=True):
         self._check(self.lib.tpcg_set_profiling(self.h, 1 if on else 0))

@@ -189,8 +189,21 @@ struct AllocGroup {
   }
 };
 
+void drop_graphs(Handle* h) {
+  for (auto& e : h->gexec)
+    if (e) {
+      hipGraphExecDestroy(e);
+      e = nullptr;
+    }
+  h->gkey.clear();
+}
+
 void release(Handle* h) {
   if (!h) return;
+  drop_graphs(h);
+  for (auto& ev : h->gprof_ev)
+    for (auto& e : ev)
+      if (e) hipEventDestroy(e);
   void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam, h->kj,     h->eres, h->lfac,
                   h->emod,  h->twist, h->emod64, h->cfac, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
@@ -266,6 +279,7 @@ Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int
   g.tol2 = tol2;
   g.enabled = enabled;
   g.test = 0;
+  g.itbase = nullptr;
   return g;
 }
 
@@ -516,6 +530,7 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     if (a.commit() != TPCG_OK)
       return fail(hh, TPCG_ENOMEM, "out of device memory for the preconditioner");
   }
+  ++h->build_gen;
   return build_preconditioner(*h, rho_phys, nsys, rep);
 }
 
@@ -578,32 +593,131 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   double* pcur = h->p;
   double* pnext = h->p2;
   if (!fused) launch_update_p(*h, nsys, g0, 1, st);
+  int* itbase = h->istate + kStIter * kMaxSys;
+  // one PCG iteration; `itg` is the gates' iteration (absolute, or an offset
+  // from the device counter when `rel`), its parity picks the partial slots
+  auto iteration = [&](int itg, bool rel, int first, int prof_it, double*& pc, double*& pn,
+                       hipStream_t st) {
+    const int rr_now = (itg & 1) ? kPartRR1 : kPartRR0;
+    const int rr_next = (itg & 1) ? kPartRR0 : kPartRR1;
+    const int rz_next = (itg & 1) ? kPartRZ0 : kPartRZ1;
+    Gate gi = make_gate(h, rr_now, itg, maxit, tol2, 1);
+    Gate gn = make_gate(h, rr_next, itg + 1, maxit, tol2, 1);
+    if (rel) gi.itbase = gn.itbase = itbase;
+    if (fused) {
+      launch_apply_K_dir(*h, rho_phys, h->z, pc, pn, h->q, nsys, kPartPQ, gi, first, st);
+      std::swap(pc, pn);
+    } else {
+      launch_apply_K(*h, rho_phys, pc, h->q, nsys, kPartPQ, gi, st);
+    }
+    launch_update_xr(*h, u, pc, nsys, gi, st);
+    Gate gt = gn;   // the restriction takes this iteration's residual test
+    gt.test = 1;
+    launch_precond(*h, h->r, h->z, nsys, gt, rz_next, prof_it, flexible, st);
+    launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
+    if (!fused) launch_update_p(*h, nsys, gn, 0, st);
+  };
+  // Chunks after the first replay a captured graph of kPollEvery iterations
+  // (a chunk starts at an even iteration with the direction buffers in their
+  // initial order, so one graph serves every chunk); the block coarse solve
+  // on the side stream stays eager, and so do solves that time their local
+  // solves with events (events recorded inside a graph cannot be timed).
+  const bool use_graphs = h->graphs_on && h->graphs_ok && h->cpk != nullptr && !h->prof_on;
+  if (use_graphs) {
+    std::vector<double> key = {(double)reinterpret_cast<uintptr_t>(rho_phys),
+                               (double)reinterpret_cast<uintptr_t>(f),
+                               (double)reinterpret_cast<uintptr_t>(u),
+                               (double)nsys, (double)maxit, tol2, (double)flexible,
+                               (double)h->prof_on, (double)h->build_gen};
+    if (key != h->gkey) {
+      drop_graphs(h);
+      h->gkey = key;
+    }
+  }
+  // captured on the handle's side stream (a stream of its own, which can be
+  // captured even when the handle's stream is the legacy default stream),
+  // replayed on the handle's stream
+  hipStream_t cs = h->side;
+  auto capture = [&](int g) {
+    if (h->prof_on)
+      for (auto& e : h->gprof_ev[g])
+        if (!e && hipEventCreate(&e) != hipSuccess) return false;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      fprintf(stderr, "tpcg_pcg_solve: graph capture not available (%s); eager launches\n",
+              hipGetErrorString(e));
+      return false;
+    }
+    h->cap_ev = h->prof_on ? h->gprof_ev[g] : nullptr;
+    h->cap_n = 0;
+    double* pc = h->p;
+    double* pn = h->p2;
+    for (int off = 0; off < kPollEvery; ++off) iteration(off, true, 0, off, pc, pn, cs);
+    h->cap_ev = nullptr;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess || !graph) {
+      fprintf(stderr, "tpcg_pcg_solve: graph capture failed (%s); eager launches\n",
+              hipGetErrorString(e));
+      return false;
+    }
+    e = hipGraphInstantiate(&h->gexec[g], graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      fprintf(stderr, "tpcg_pcg_solve: graph instantiation failed (%s); eager launches\n",
+              hipGetErrorString(e));
+      h->gexec[g] = nullptr;
+      return false;
+    }
+    return true;
+  };
   int it = 0;
   int chunk = 0;
+  int graph_it0[2] = {-1, -1};   // first iteration of the unharvested chunk of each graph
+  std::vector<std::pair<int, float>> gprof;   // (iteration, ms) of graph-timed local solves
+  auto harvest = [&](int g) {
+    if (graph_it0[g] < 0) return;
+    if (h->prof_on)
+      for (int k = 0; k < kPollEvery; ++k) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, h->gprof_ev[g][2 * k], h->gprof_ev[g][2 * k + 1]) == hipSuccess)
+          gprof.emplace_back(graph_it0[g] + k, ms);
+      }
+    graph_it0[g] = -1;
+  };
+  h->last_graph_chunks = 0;
   bool done = maxit == 0;
   while (!done) {
-    for (int c = 0; c < kPollEvery && it < maxit; ++c, ++it) {
-      const int rr_now = (it & 1) ? kPartRR1 : kPartRR0;
-      const int rr_next = (it & 1) ? kPartRR0 : kPartRR1;
-      const int rz_next = (it & 1) ? kPartRZ0 : kPartRZ1;
-      Gate gi = make_gate(h, rr_now, it, maxit, tol2, 1);
-      Gate gn = make_gate(h, rr_next, it + 1, maxit, tol2, 1);
-      if (fused) {
-        launch_apply_K_dir(*h, rho_phys, h->z, pcur, pnext, h->q, nsys, kPartPQ, gi, it == 0, st);
-        std::swap(pcur, pnext);
-      } else {
-        launch_apply_K(*h, rho_phys, pcur, h->q, nsys, kPartPQ, gi, st);
+    const int it0 = it;
+    bool graphed = false;
+    if (use_graphs && h->graphs_ok && chunk >= 1) {
+      const int g = chunk & 1;
+      if (!h->gexec[g] && !capture(g)) {
+        (void)hipGetLastError();
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(cs, &cst) == hipSuccess && cst != hipStreamCaptureStatusNone) {
+          hipGraph_t junk = nullptr;
+          hipStreamEndCapture(cs, &junk);
+          if (junk) hipGraphDestroy(junk);
+        }
+        (void)hipGetLastError();
+        h->cap_ev = nullptr;
+        h->graphs_ok = 0;
+        drop_graphs(h);
       }
-      launch_update_xr(*h, u, pcur, nsys, gi, st);
-      Gate gt = gn;   // the restriction takes this iteration's residual test
-      gt.test = 1;
-      launch_precond(*h, h->r, h->z, nsys, gt, rz_next, it, flexible, st);
-      launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
-      if (!fused) launch_update_p(*h, nsys, gn, 0, st);
+      if (h->gexec[g] && hipGraphLaunch(h->gexec[g], st) == hipSuccess) {
+        graphed = true;
+        graph_it0[g] = it0;
+        it = it0 + kPollEvery;
+        ++h->last_graph_chunks;
+      }
     }
+    if (!graphed)
+      for (int c = 0; c < kPollEvery && it < maxit; ++c, ++it)
+        iteration(it, false, it == 0, it, pcur, pnext, st);
     const int slot = chunk & 1;
     Gate gp = make_gate(h, (it & 1) ? kPartRR1 : kPartRR0, it, maxit, tol2, 1);
-    launch_poll(*h, nsys, gp, st);
+    launch_poll(*h, nsys, gp, it - it0, st);
     hipMemcpyAsync(h->hpoll + slot * kMaxSys, h->istate + kStPoll * kMaxSys, sizeof(int) * kMaxSys,
                    hipMemcpyDeviceToHost, st);
     hipEventRecord(h->ev[slot], st);
@@ -611,6 +725,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     if (chunk > 0) {
       const int prev = slot ^ 1;
       if (hipEventSynchronize(h->ev[prev]) != hipSuccess) break;
+      harvest(prev);
       int running = 0;
       for (int s = 0; s < nsys; ++s) running |= h->hpoll[prev * kMaxSys + s];
       if (!running) done = true;
@@ -626,6 +741,8 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   double hout[4 * kMaxSys];
   hipMemcpyAsync(hout, dout, sizeof(double) * 4 * nsys, hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
+  harvest(0);
+  harvest(1);
   int rc = check_hip(h, "tpcg_pcg_solve");
   if (rc != TPCG_OK) return rc;
   float ms = 0.0f;
@@ -647,16 +764,20 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     // systems still running at that iteration did work
     const Geometry& g = h->g;
     const double per_sys = local_solve_bytes(g, h->mixed ? 4 : 8, h->big);
-    for (int i = 0; i < h->prof_n; ++i) {
+    auto account = [&](int pit, float lms) {
       int running = 0;
-      for (int s = 0; s < nsys; ++s) running += info[s].iters >= h->prof_it[i] + 2;
-      if (!running) continue;
-      float lms = 0.0f;
-      hipEventElapsedTime(&lms, h->prof_ev[2 * i], h->prof_ev[2 * i + 1]);
+      for (int s = 0; s < nsys; ++s) running += info[s].iters >= pit + 2;
+      if (!running) return;
       h->prof_ms += lms;
       h->prof_bytes += running * per_sys;
       h->prof_launches += 1;
+    };
+    for (int i = 0; i < h->prof_n; ++i) {
+      float lms = 0.0f;
+      hipEventElapsedTime(&lms, h->prof_ev[2 * i], h->prof_ev[2 * i + 1]);
+      account(h->prof_it[i], lms);
     }
+    for (const auto& e : gprof) account(e.first, e.second);
   }
   if (worst == TPCG_EINVAL) h->err = "densities must lie in [0, 1] (NaN or out-of-range value found)";
   else if (worst == TPCG_EBREAKDOWN) h->err = "PCG breakdown (p^T K p <= 0, r^T z <= 0 or NaN)";
@@ -777,6 +898,19 @@ int tpcg_export_eigenvalues(tpcg_handle* hh, double* lambda, int32_t m, int32_t*
 int tpcg_query_subspace(const tpcg_handle* hh) {
   const Handle* h = H(hh);
   return h ? h->msub : TPCG_EINVAL;
+}
+
+int tpcg_set_graphs(tpcg_handle* hh, int32_t on) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  h->graphs_on = on ? 1 : 0;
+  if (!on) drop_graphs(h);
+  return TPCG_OK;
+}
+
+int tpcg_last_solve_graph_chunks(const tpcg_handle* hh) {
+  const Handle* h = H(hh);
+  return h ? h->last_graph_chunks : TPCG_EINVAL;
 }
 
 void tpcg_test_fail_alloc(int32_t nth) {

@@ -422,7 +422,8 @@ void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& 
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
                     int rz_slot, int prof_it, int flexible, hipStream_t st) {
   const Geometry& g = h.g;
-  const bool prof = h.prof_on && prof_it >= -1;
+  const bool cap = h.cap_ev != nullptr;   // inside a graph capture: its own event pairs
+  const bool prof = !cap && h.prof_on && prof_it >= -1;
   if (prof && (size_t)(2 * h.prof_n + 2) > h.prof_ev.size()) {
     const size_t old = h.prof_ev.size();
     h.prof_ev.resize(old + 512, nullptr);
@@ -431,6 +432,7 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   }
   auto mark = [&](int which) {
     if (prof) hipEventRecord(h.prof_ev[2 * h.prof_n + which], st);
+    if (cap && prof_it >= 0) hipEventRecord(h.cap_ev[2 * h.cap_n + which], st);
   };
   if (h.mixed) restrict_launch<float>(h, r, nsys, gate, st);
   else restrict_launch<double>(h, r, nsys, gate, st);
@@ -460,6 +462,7 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   if (h.mixed) extend_launch<float>(h, r, z, nsys, gate, rz_slot, flexible, st);
   else extend_launch<double>(h, r, z, nsys, gate, rz_slot, flexible, st);
   if (prof) h.prof_it[h.prof_n++] = prof_it;
+  if (cap && prof_it >= 0) ++h.cap_n;
 }
 
 }  // namespace tpcg

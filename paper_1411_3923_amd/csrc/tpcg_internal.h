@@ -129,6 +129,20 @@ struct Handle {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t t0 = nullptr, t1 = nullptr;
 
+  // PCG chunks replayed from HIP graphs: two instantiated graphs of
+  // kPollEvery iterations (chunks alternate between them, so that a chunk's
+  // timing events can be read while the next one runs), captured for the
+  // arguments in gkey and recaptured when they change
+  int graphs_on = 0;                 // off by default: measured slower than eager launches
+  int graphs_ok = 1;                 // 0 after a capture failed: eager launches only
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  std::vector<double> gkey;
+  hipEvent_t gprof_ev[2][8] = {};    // per graph: event pairs around its local solves
+  hipEvent_t* cap_ev = nullptr;      // during a capture: the events the marks record
+  int cap_n = 0;
+  int last_graph_chunks = 0;
+  int build_gen = 0;                 // preconditioner builds so far (part of the graphs' key)
+
   // optional event timing of the block-solve launches inside pcg_solve
   int prof_on = 0;
   int prof_n = 0;                    // launches recorded in the current solve
@@ -166,7 +180,10 @@ __host__ __device__ inline double* scal_slot(double* parts, int which) {
 
 // Per-system integer state [kNumState][kMaxSys]. kStBreak: 1 breakdown, 2
 // invalid densities (the system never starts).
-enum { kStLastIt = 0, kStBreak = 1, kStPoll = 2, kStRun = 3, kNumState = 4 };
+// kStIter: one counter (at istate[kStIter * kMaxSys]) of the iterations
+// issued before the current chunk; the poll kernel advances it, and the
+// kernels of a replayed chunk add it to their gate's iteration offset.
+enum { kStLastIt = 0, kStBreak = 1, kStPoll = 2, kStRun = 3, kStIter = 4, kNumState = 5 };
 
 // ---------------------------------------------------------------------------
 // Device helpers
@@ -228,11 +245,15 @@ struct Gate {
   double tol2;
   int enabled;     // 0: always run
   int test;        // 1: the restriction takes the residual test itself
+  const int* itbase;   // null: `it` is absolute; else it is an offset from *itbase
 };
+
+// absolute iteration index of the gated work
+__device__ inline int gate_it(const Gate& gt) { return gt.it + (gt.itbase ? *gt.itbase : 0); }
 
 __device__ inline bool gate_running(const Gate& gt, int sys) {
   if (!gt.enabled) return true;
-  if (gt.it >= gt.maxit) return false;
+  if (gate_it(gt) >= gt.maxit) return false;
   if (gt.istate[kStBreak * kMaxSys + sys]) return false;
   return gt.istate[kStRun * kMaxSys + sys] != 0;
 }
@@ -278,7 +299,8 @@ void launch_beta(const Handle& h, int nsys, const Gate& gate, int rz_slot, int f
                  int first, hipStream_t st);
 // p = z + beta p with the beta of launch_beta (first: p = z)
 void launch_update_p(const Handle& h, int nsys, const Gate& gate, int first, hipStream_t st);
-void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st);
+// running flags into kStPoll; advances the kStIter counter by `advance`
+void launch_poll(const Handle& h, int nsys, const Gate& gate, int advance, hipStream_t st);
 // residual test of gate.rr_slot into the kStRun flags
 void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st);
 // true residual of P(f - q) (q must hold K u) and out[sys] = {iters, status, relres, true_relres}

@@ -42,6 +42,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_init(
     if (blockIdx.x == 0) {
       istate[kStLastIt * kMaxSys + sys] = 0;
       istate[kStBreak * kMaxSys + sys] = 0;
+      if (sys == 0) istate[kStIter * kMaxSys] = 0;
     }
   }
 }
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(
   const double s = block_sum(arr, sh);
   if (threadIdx.x == 0) {
     part_slot(parts, slot_new, sys)[blockIdx.x] = s;
-    if (blockIdx.x == 0) istate[kStLastIt * kMaxSys + sys] = gate.it + 1;
+    if (blockIdx.x == 0) istate[kStLastIt * kMaxSys + sys] = gate_it(gate) + 1;
   }
 }
 
@@ -179,10 +180,13 @@ __global__ __launch_bounds__(kThreads) void k_gate(Gate gate, int* __restrict__ 
   }
 }
 
-__global__ void k_poll(Gate gate, int* __restrict__ istate) {
+__global__ void k_poll(Gate gate, int* __restrict__ istate, int advance) {
   const int sys = blockIdx.x;
   const bool run = gate_running(gate, sys);
-  if (threadIdx.x == 0) istate[kStPoll * kMaxSys + sys] = run ? 1 : 0;
+  if (threadIdx.x == 0) {
+    istate[kStPoll * kMaxSys + sys] = run ? 1 : 0;
+    if (sys == 0) istate[kStIter * kMaxSys] += advance;
+  }
 }
 
 // flag[sys * stride] = value when a density of system sys is NaN or outside
@@ -274,8 +278,8 @@ void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
   hipLaunchKernelGGL(k_gate, dim3(nsys), dim3(kThreads), 0, st, gate, h.istate);
 }
 
-void launch_poll(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
-  hipLaunchKernelGGL(k_poll, dim3(nsys), dim3(kThreads), 0, st, gate, h.istate);
+void launch_poll(const Handle& h, int nsys, const Gate& gate, int advance, hipStream_t st) {
+  hipLaunchKernelGGL(k_poll, dim3(nsys), dim3(kThreads), 0, st, gate, h.istate, advance);
 }
 
 void launch_check_rho(const double* rho, int64_t n, int nsys, int* flag, int stride, int value,
