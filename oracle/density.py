@@ -92,3 +92,41 @@ def non_discreteness(rho_bar):
     """M_nd = sum 4 rho (1 - rho) / n  (Sec. 5.2)."""
     r = np.asarray(rho_bar)
     return float(np.sum(4.0 * r * (1.0 - r)) / r.size)
+
+
+def robust_objective(c, dc, kappa=1.0, weights=None):
+    """Robust objective of Sec. 4.4, f = E[c] + kappa sqrt(Var[c]) over the
+    realisations (weights w_s, equal by default; population variance), and its
+    gradient df = sum_s w_s (1 + kappa (c_s - E[c]) / sqrt(Var[c])) dc_s (the
+    variance term's gradient taken as zero when Var[c] = 0).
+    c: [nsys]; dc: [nsys][n] gradients of the realisations' compliances.
+    Returns (f, mean, std, df)."""
+    c = np.asarray(c, dtype=np.float64)
+    dc = np.asarray(dc, dtype=np.float64)
+    w = np.full(c.size, 1.0 / c.size) if weights is None else np.asarray(weights, dtype=np.float64)
+    mean = float(np.sum(w * c))
+    var = float(np.sum(w * (c - mean) ** 2))
+    std = float(np.sqrt(var))
+    a = w * (1.0 + (kappa * (c - mean) / std if std > 0.0 else 0.0))
+    return mean + kappa * std, mean, std, np.tensordot(a, dc, axes=1)
+
+
+def tile_design(p, x_cell, cell):
+    """Element densities of a periodic design (Sec. 4.1): element e takes the
+    design variable of its position in the unit cell of cell = (cx, cy[, cz])
+    elements."""
+    dims = (p.nelx, p.nely) if p.dim == 2 else (p.nelx, p.nely, p.nelz)
+    grids = np.meshgrid(*[np.arange(n) for n in dims[::-1]], indexing="ij")
+    coords = [g.ravel() for g in grids[::-1]]
+    idx = coords[0] % cell[0] + cell[0] * (coords[1] % cell[1])
+    if p.dim == 3:
+        idx = idx + cell[0] * cell[1] * (coords[2] % cell[2])
+    return np.asarray(x_cell)[idx], idx
+
+
+def periodic_sum(p, g, cell):
+    """Sensitivity of a periodic design variable (Sec. 4.1): the sum of the
+    element sensitivities g over every element it controls."""
+    n = int(np.prod(cell[:p.dim]))
+    _, idx = tile_design(p, np.zeros(n), cell)
+    return np.bincount(idx, weights=np.asarray(g, dtype=np.float64), minlength=n)
