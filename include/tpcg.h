@@ -237,6 +237,33 @@ int tpcg_filter_project_adjoint(tpcg_handle* h, const double* rho_tilde, double 
                                 double* dc_drho);
 
 /*
+ * Robust objective over the realisations (Sec. 4.4: mean plus kappa times the
+ * standard deviation of the compliance; the paper uses kappa = 1 and three
+ * equally weighted realisations): out3 (dev [3]) = {E[c] + kappa std, E[c],
+ * std} with E[c] = sum_s w_s c_s and std^2 = sum_s w_s (c_s - E[c])^2 for c
+ * dev [nsys]; weights host [nsys] (NULL: 1/nsys each). If dc (dev
+ * [nsys][n_el], the gradients of the c_s, e.g. with respect to the design
+ * variables after tpcg_filter_project_adjoint) is not NULL, df (dev [n_el])
+ * receives the gradient sum_s w_s (1 + kappa (c_s - E[c]) / std) dc[s]
+ * (without the variance term when std = 0). TPCG_EINVAL for nsys outside
+ * 1..4, kappa < 0 or a negative weight.
+ */
+int tpcg_robust_objective(tpcg_handle* h, const double* c, const double* dc, int32_t nsys,
+                          double kappa, const double* weights, double* out3, double* df);
+
+/*
+ * Sensitivities of periodic design variables (Sec. 4.1: one design variable
+ * controls the element at the same position in every copy of the unit cell):
+ * gcell[s][v] = sum of g[s][e] over the elements e at position v of the unit
+ * cell of cell[0] x cell[1] (x cell[2] in 3D) elements, cells laid out from
+ * the mesh origin (partial cells at the far faces count), v = vx + cell[0]
+ * (vy + cell[1] vz). g dev [nsys][n_el], cell host [3], gcell dev
+ * [nsys][cell volume]. TPCG_EINVAL for a cell outside the mesh.
+ */
+int tpcg_periodic_sum(tpcg_handle* h, const double* g, int32_t nsys, const int32_t* cell,
+                      double* gcell);
+
+/*
  * Copy the coarse basis out (diagnostics and tests): phi dev
  * [n_sub][n_loc][k] (chi-weighted basis vectors on the subdomain's closed-cell
  * DOFs, node x fastest then component; may be NULL), lambda host [n_sub][k]

@@ -55,7 +55,7 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_set_profiling", "tpcg_profile_block_solves", "tpcg_export_eigenvalues",
            "tpcg_query_subspace", "tpcg_test_fail_alloc", "tpcg_last_error", "tpcg_destroy",
            "tpcg_compliance_and_sensitivity_noalloc", "tpcg_set_graphs",
-           "tpcg_last_solve_graph_chunks"]
+           "tpcg_last_solve_graph_chunks", "tpcg_robust_objective", "tpcg_periodic_sum"]
 
 
 def load_library(path: str | None = None):
@@ -91,6 +91,8 @@ def load_library(path: str | None = None):
     lib.tpcg_destroy.argtypes = [P]
     lib.tpcg_destroy.restype = None
     lib.tpcg_set_graphs.argtypes = [P, I32]
+    lib.tpcg_robust_objective.argtypes = [P, P, P, I32, D, ctypes.POINTER(D), P, P]
+    lib.tpcg_periodic_sum.argtypes = [P, P, I32, ctypes.POINTER(I32), P]
     lib.tpcg_last_solve_graph_chunks.argtypes = [P]
     lib.tpcg_compliance_and_sensitivity_noalloc.argtypes = [ctypes.POINTER(Problem), P, P, P, P,
                                                             I32, P, P, P, V]
@@ -234,6 +236,25 @@ class Handle:
             _ptr(dc_drho_phys, torch.float64, nsys * self.n_el),
             _ptr(dc_drho, torch.float64, nsys * self.n_el)))
         return dc_drho
+
+    def robust_objective(self, c, out3, dc=None, df=None, kappa=1.0, weights=None):
+        import torch
+        nsys = c.numel()
+        w = (ctypes.c_double * nsys)(*weights) if weights is not None else None
+        self._check(self.lib.tpcg_robust_objective(
+            self.h, _ptr(c, torch.float64, nsys),
+            _ptr(dc, torch.float64, nsys * self.n_el) if dc is not None else None, nsys, kappa, w,
+            _ptr(out3, torch.float64, 3), _ptr(df, torch.float64, self.n_el) if df is not None else None))
+        return out3, df
+
+    def periodic_sum(self, g, cell, gcell):
+        import torch
+        nsys = g.numel() // self.n_el
+        cl = tuple(cell) + (1,) * (3 - len(cell))
+        cv = (ctypes.c_int32 * 3)(*cl)
+        self._check(self.lib.tpcg_periodic_sum(self.h, _ptr(g, torch.float64, nsys * self.n_el), nsys,
+                                               cv, _ptr(gcell, torch.float64)))
+        return gcell
 
     def set_graphs(self, on=True):
         self._check(self.lib.tpcg_set_graphs(self.h, 1 if on else 0))

@@ -815,6 +815,38 @@ int tpcg_filter_project(tpcg_handle* hh, const double* rho, double rmin, double 
   return check_hip(h, "tpcg_filter_project");
 }
 
+int tpcg_robust_objective(tpcg_handle* hh, const double* c, const double* dc, int32_t nsys,
+                          double kappa, const double* weights, double* out3, double* df) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!c || !out3 || (dc && !df)) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (nsys < 1 || nsys > kMaxSys) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  if (!(kappa >= 0.0)) return fail(hh, TPCG_EINVAL, "kappa must be >= 0");
+  double w[kMaxSys];
+  for (int s = 0; s < nsys; ++s) {
+    w[s] = weights ? weights[s] : 1.0 / nsys;
+    if (!(w[s] >= 0.0)) return fail(hh, TPCG_EINVAL, "weights must be >= 0");
+  }
+  launch_robust(*h, c, dc, nsys, kappa, w, out3, df, h->stream);
+  return check_hip(h, "tpcg_robust_objective");
+}
+
+int tpcg_periodic_sum(tpcg_handle* hh, const double* g, int32_t nsys, const int32_t* cell,
+                      double* gcell) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!g || !cell || !gcell) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (nsys < 1 || nsys > kMaxSys) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  const int cz = h->g.dim == 3 ? cell[2] : 1;
+  if (cell[0] < 1 || cell[1] < 1 || cz < 1 || cell[0] > h->g.nelx || cell[1] > h->g.nely ||
+      cz > h->g.nelz)
+    return fail(hh, TPCG_EINVAL, "unit cell must lie within the mesh");
+  launch_periodic_sum(*h, g, nsys, cell[0], cell[1], cz, gcell, h->stream);
+  return check_hip(h, "tpcg_periodic_sum");
+}
+
 int tpcg_filter_project_adjoint(tpcg_handle* hh, const double* rho_tilde, double rmin, double beta,
                                 const double* eta, int32_t nsys, const double* dc_drho_phys,
                                 double* dc_drho) {

@@ -188,6 +188,67 @@ __global__ void k_fu_final(const double* __restrict__ part, int np, double* __re
   if (threadIdx.x == 0) c[sys] = v;
 }
 
+// Robust objective of the realisations' compliances (Sec. 4.4): every
+// thread forms the mean and the population standard deviation of c from the
+// weights in the same order; out = {E[c] + kappa std, E[c], std} and
+// df[i] = sum_s w_s (1 + kappa (c_s - E[c]) / std) dc[s][i] (no variance
+// term when std = 0).
+struct RobustW {
+  double w[kMaxSys];
+  double kappa;
+};
+
+__global__ __launch_bounds__(kThreads) void k_robust(const double* __restrict__ c,
+                                                    const double* __restrict__ dc, int nsys,
+                                                    int64_t n, RobustW rw, double* __restrict__ out,
+                                                    double* __restrict__ df) {
+  double mean = 0.0;
+  for (int s = 0; s < nsys; ++s) mean += rw.w[s] * c[s];
+  double var = 0.0;
+  for (int s = 0; s < nsys; ++s) var += rw.w[s] * (c[s] - mean) * (c[s] - mean);
+  const double sd = sqrt(var);
+  double a[kMaxSys];
+#pragma unroll
+  for (int s = 0; s < kMaxSys; ++s)
+    a[s] = s < nsys ? rw.w[s] * (1.0 + (sd > 0.0 ? rw.kappa * (c[s] - mean) / sd : 0.0)) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    out[0] = mean + rw.kappa * sd;
+    out[1] = mean;
+    out[2] = sd;
+  }
+  if (!dc) return;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double v = 0.0;
+    for (int s = 0; s < nsys; ++s) v += a[s] * dc[(size_t)s * n + i];
+    df[i] = v;
+  }
+}
+
+// Sum over the periodic copies (Sec. 4.1): gcell[s][v] = sum of g[s][e] over
+// the elements e at position v of the unit cell (cx, cy, cz), partial cells
+// at the far faces included. One workgroup per (cell variable, system);
+// copies summed in a fixed tree.
+__global__ __launch_bounds__(kThreads) void k_periodic_sum(Geometry g, const double* __restrict__ gin,
+                                                          int cx, int cy, int cz,
+                                                          double* __restrict__ gcell) {
+  __shared__ double sh[4];
+  const int v = blockIdx.x, sys = blockIdx.y;
+  const int vx = v % cx, vy = (v / cx) % cy, vz = v / (cx * cy);
+  const int qx = (g.nelx + cx - 1) / cx, qy = (g.nely + cy - 1) / cy, qz = (g.nelz + cz - 1) / cz;
+  const int64_t ncopy = (int64_t)qx * qy * qz;
+  const double* gs = gin + (size_t)sys * g.nel;
+  double acc = 0.0;
+  for (int64_t q = threadIdx.x; q < ncopy; q += kThreads) {
+    const int ax = (int)(q % qx), ay = (int)((q / qx) % qy), az = (int)(q / ((int64_t)qx * qy));
+    const int ex = ax * cx + vx, ey = ay * cy + vy, ez = az * cz + vz;
+    if (ex < g.nelx && ey < g.nely && ez < g.nelz)
+      acc += gs[ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)];
+  }
+  const double tot = block_sum(acc, sh);
+  if (threadIdx.x == 0) gcell[(size_t)sys * cx * cy * cz + v] = tot;
+}
+
 int elem_blocks(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
@@ -211,6 +272,21 @@ void launch_filter_project_adjoint(const Handle& h, const double* rho_tilde, dou
   for (int s = 0; s < nsys; ++s) e.v[s] = eta[s];
   hipLaunchKernelGGL(k_filter_project_adjoint, dim3(elem_blocks(h.g.nel)), dim3(kThreads), 0, st,
                      h.g, rho_tilde, rmin, beta, e, nsys, g, out);
+}
+
+void launch_robust(const Handle& h, const double* c, const double* dc, int nsys, double kappa,
+                   const double* w, double* out, double* df, hipStream_t st) {
+  RobustW rw{};
+  for (int s = 0; s < nsys; ++s) rw.w[s] = w[s];
+  rw.kappa = kappa;
+  hipLaunchKernelGGL(k_robust, dim3(dc ? elem_blocks(h.g.nel) : 1), dim3(kThreads), 0, st, c, dc,
+                     nsys, (int64_t)h.g.nel, rw, out, df);
+}
+
+void launch_periodic_sum(const Handle& h, const double* gin, int nsys, int cx, int cy, int cz,
+                         double* gcell, hipStream_t st) {
+  hipLaunchKernelGGL(k_periodic_sum, dim3(cx * cy * cz, nsys), dim3(kThreads), 0, st, h.g, gin, cx,
+                     cy, cz, gcell);
 }
 
 void launch_compliance_sens_raw(const Geometry& g, const uint8_t* fixed, const double* K0,

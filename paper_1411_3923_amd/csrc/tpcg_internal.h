@@ -330,6 +330,13 @@ void launch_filter_project_adjoint(const Handle& h, const double* rho_tilde, dou
                                    double* out, hipStream_t st);
 void launch_compliance_sens(const Handle& h, const double* rho, const double* u, const double* f,
                             int nsys, double* c, double* dc, hipStream_t st);
+// robust objective {E + kappa std, E, std} of c [nsys] (weights w, host) and,
+// if dc, its gradient df [n_el] from dc [nsys][n_el]
+void launch_robust(const Handle& h, const double* c, const double* dc, int nsys, double kappa,
+                   const double* w, double* out, double* df, hipStream_t st);
+// gcell [nsys][cx cy cz] = sums of gin [nsys][n_el] over the copies of a unit cell
+void launch_periodic_sum(const Handle& h, const double* gin, int nsys, int cx, int cy, int cz,
+                         double* gcell, hipStream_t st);
 // the same without a handle: supports, element matrix and partials
 // (part[sys * kMaxParts + i], i < parts_for(nnodes)) given as device pointers
 void launch_compliance_sens_raw(const Geometry& g, const uint8_t* fixed, const double* K0,
