@@ -203,6 +203,136 @@ def cpu_model():
     return None
 
 
+def run_serving(args, precision):
+    """The serving stream: requests with Poisson arrivals over a mix of 2D
+    and 3D meshes, each a robust optimisation run of `updates` warm-started
+    design updates with resident factors, admitted by device memory. Returns
+    per-request latencies (arrival to the last update's result) and totals."""
+    import collections
+
+    import numpy as np
+    import torch
+
+    import paper_1411_3923_amd as T
+    from paper_1411_3923_amd import workloads as W
+
+    budget = int(args.serving_budget_gb * (1 << 30))
+    srv = T.Server(budget, max_active=args.serving_slots)
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+    class Req:
+        def __init__(self, t, p, i):
+            self.t, self.p, self.i = t, p, i
+            self.nsys = 3 if p.dim == 2 else 1
+            self.step = 0
+            self.job = None
+            self.work = 0
+            self.solves = []
+
+        def start(self, sid):
+            p = self.p
+            self.sid = sid
+            self.rho = W.design_field(p)
+            self.F = d(np.stack([W.load_vector(p)] * self.nsys))
+            self.u = torch.zeros((self.nsys, p.n_dof), dtype=torch.float64, device="cuda")
+            self.c = torch.zeros(self.nsys, dtype=torch.float64, device="cuda")
+            self.dc = torch.zeros((self.nsys, p.n_el), dtype=torch.float64, device="cuda")
+            self.submit()
+
+        def submit(self):
+            p = self.p
+            if self.step > 0:
+                self.rho = np.clip(self.rho + 0.02 * W.design_noise(p, self.step, 100 + self.i), 0, 1)
+            self.R = d(self.rho)
+            kw = (dict(rmin=p.rmin, beta=p.beta, etas=p.etas) if p.dim == 2 else dict(rmin=0.0))
+            self.job = srv.submit(self.sid, self.R, self.F, self.u, self.c, self.dc, rtol=args.rtol,
+                                  maxit=args.maxit, rebuild=0, growth=1.5, **kw)
+
+    def problem(p):
+        return T.make_problem(p.dim, p.nel[:p.dim], p.sub, p.k, 3 if p.dim == 2 else 1, p.E0, p.Emin,
+                              p.penal, p.nu, precision,
+                              lambda_thresh=0.0 if p.dim == 2 else 1e-6)
+
+    def drive(reqs):
+        pending = collections.deque(sorted(reqs, key=lambda r: r.t))
+        waiting, active, done = collections.deque(), {}, []
+        t0 = time.perf_counter()
+        while pending or waiting or active:
+            now = time.perf_counter() - t0
+            busy = False
+            while pending and pending[0].t <= now:
+                waiting.append(pending.popleft())
+            while waiting:
+                r = waiting[0]
+                sid = srv.open(problem(r.p), W.fixed_mask(r.p), r.nsys)
+                if sid is None:
+                    break
+                waiting.popleft()
+                r.admitted = time.perf_counter() - t0
+                r.start(sid)
+                active[sid] = r
+                busy = True
+            for sid, r in list(active.items()):
+                res = srv.test(r.job)
+                if res is None:
+                    continue
+                busy = True
+                r.solves.append(res)
+                r.work += r.p.n_dof * sum(res["iters"])
+                r.step += 1
+                if r.step < args.serving_updates:
+                    r.submit()
+                else:
+                    srv.close(sid)
+                    r.finished = time.perf_counter() - t0
+                    done.append(r)
+                    del active[sid]
+            if not busy:
+                if pending and not waiting and not active:
+                    time.sleep(max(0.0, pending[0].t - (time.perf_counter() - t0)))
+                else:
+                    time.sleep(0.0002)
+        return done, time.perf_counter() - t0
+
+    # single-stream capacity: one request of every mesh kind, one at a time
+    kinds = [(0.0, p) for _, p in W.serving_requests(64, 1.0, seed=args.serving_seed,
+                                                      with_3d=not args.serving_2d_only)]
+    seen, calib = set(), []
+    for _, p in kinds:
+        key = (p.dim, p.nel)
+        if key not in seen:
+            seen.add(key)
+            calib.append(Req(0.0, p, 900 + len(calib)))
+    service = []
+    for r in calib:
+        done, wall = drive([r])
+        service.append(wall)
+    capacity = 1.0 / float(np.mean(service))
+    rate = 0.8 * capacity
+    reqs = [Req(t, p, i) for i, (t, p) in enumerate(
+        W.serving_requests(args.serving_requests, rate, seed=args.serving_seed,
+                           with_3d=not args.serving_2d_only))]
+    done, wall = drive(reqs)
+    srv.destroy()
+    lat = [r.finished - r.t for r in done]
+    solves = [s for r in done for s in r.solves]
+    return {
+        "requests": len(done), "updates_per_request": args.serving_updates,
+        "arrival_rate_per_s": rate, "single_stream_capacity_per_s": capacity,
+        "wall_s": wall, "requests_per_s": len(done) / wall,
+        "dof_iters_per_s": sum(r.work for r in done) / wall,
+        "latency_s_p50": percentile(lat, 50), "latency_s_p99": percentile(lat, 99),
+        "queue_wait_s_mean": float(np.mean([r.admitted - r.t for r in done])),
+        "job_solve_ms_p50": percentile([s["solve_ms"] for s in solves], 50),
+        "job_solve_ms_p99": percentile([s["solve_ms"] for s in solves], 99),
+        "basis_rebuilds_per_job": sum(s["rebuilt"] for s in solves) / len(solves),
+        "iters_mean": float(np.mean([max(s["iters"]) for s in solves])),
+        "failed_jobs": sum(1 for s in solves if s["status_all"] != 0 or max(s["status"]) != 0),
+        "meshes": sorted({r.p.name.split("_", 1)[1] for r in done}),
+        "budget_gb": args.serving_budget_gb, "slots": args.serving_slots,
+    }
+
+
 def short_name(name):
     """Kernel name without namespace, template arguments or parameter list."""
     base = name.replace("(anonymous namespace)::", "").split("(")[0]
@@ -385,7 +515,14 @@ def summarize_loop(fetch_csv, write_csv, trace_csv, command, out):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["cantilever2d", "cantilever3d"], default="cantilever2d")
+    ap.add_argument("--workload", choices=["cantilever2d", "cantilever3d", "serving"],
+                    default="cantilever2d")
+    ap.add_argument("--serving-requests", type=int, default=16)
+    ap.add_argument("--serving-updates", type=int, default=10)
+    ap.add_argument("--serving-budget-gb", type=float, default=160.0)
+    ap.add_argument("--serving-slots", type=int, default=6)
+    ap.add_argument("--serving-seed", type=int, default=1005)
+    ap.add_argument("--serving-2d-only", action="store_true")
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 10; 3 in 3D)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 2; 1 in 3D)")
     ap.add_argument("--ncoarse", type=int, default=0,
@@ -444,6 +581,25 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     T.load_library()
+    if args.workload == "serving":
+        mixed = run_serving(args, T.MIXED)
+        fp64 = None if args.no_mixed else run_serving(args, T.FP64)
+        line = {
+            "metric": "PCG solve time & DOF-iters/s to rel-res 1e-8 (FP64 vs mixed); p50/p99 latency",
+            "value": mixed["dof_iters_per_s"], "unit": "DOF-iters/s", "n_gpus": 1,
+            "steps": mixed["requests"], "warmup": 0,
+            "ms_per_step": 1e3 * mixed["wall_s"] / max(mixed["requests"], 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64 outer CG, f32 local solves and coarse-basis products", "data": "synthetic",
+            "config": {"workload": "serving_stream_q4_h8_mixed",
+                       "step": "one request: admission, 10 warm-started robust design updates "
+                               "(density pipeline, basis rule, batched PCG, sensitivities)",
+                       "rtol": args.rtol},
+            "serving_mixed": mixed, "serving_fp64": fp64,
+            "roofline": None, "cpu_baseline": None,
+        }
+        print(json.dumps(line), flush=True)
+        return
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

@@ -53,6 +53,7 @@ typedef struct tpcg_handle tpcg_handle;
 typedef enum {
   TPCG_OK = 0,
   TPCG_ENOCONV = 1,      /* warning: maxit reached; outputs valid */
+  TPCG_EAGAIN = 2,       /* not now: no capacity or not finished; nothing was changed, retry */
   TPCG_EINVAL = -1,      /* bad argument (size, null pointer, unsupported setting) */
   TPCG_ENOMEM = -2,      /* device allocation failed */
   TPCG_EHIP = -3,        /* HIP runtime error (sticky) */
@@ -149,6 +150,17 @@ size_t tpcg_workspace_bytes(const tpcg_problem* prob, int32_t nsys);
  * factorisation meets a non-positive pivot.
  */
 int tpcg_build_coarse_basis(tpcg_handle* h, const double* rho_phys, int32_t nsys, int32_t rep);
+
+/*
+ * Keep the spectral basis of the last tpcg_build_coarse_basis and rebuild
+ * everything else of the preconditioner for the physical densities rho_phys
+ * (dev [nsys][n_el]): the local Dirichlet factors and the coarse matrix
+ * K_c = Phi^T K Phi with its factor, per system. The basis re-use of Sec.
+ * 5.1 and Sec. 5.2: the expensive local eigenproblems are solved again only
+ * when the design has moved far enough. Blocks until done. TPCG_ESTATE
+ * before a first build; other errors as tpcg_build_coarse_basis.
+ */
+int tpcg_refactor(tpcg_handle* h, const double* rho_phys, int32_t nsys);
 
 /*
  * y = P K(rho) P x with K assembled from E_e = E_min + (E0 - E_min) rho_e^p
@@ -262,6 +274,84 @@ int tpcg_robust_objective(tpcg_handle* h, const double* c, const double* dc, int
  */
 int tpcg_periodic_sum(tpcg_handle* h, const double* g, int32_t nsys, const int32_t* cell,
                       double* gcell);
+
+/*
+ * Non-discreteness measure of a density field (Sec. 5.2): out (dev [1]) =
+ * sum_e 4 rho_e (1 - rho_e) / n_el for rho_phys dev [n_el].
+ */
+int tpcg_nondiscreteness(tpcg_handle* h, const double* rho_phys, double* out);
+
+/*
+ * Serving: many optimisation runs ("sessions") on one GPU. A session owns a
+ * handle (tpcg_build_partition) on a stream of its own, so its factors and
+ * coarse space stay resident in device memory across its design updates, and
+ * a worker thread. tpcg_server_open admits a session when its device memory
+ * (tpcg_server_session_bytes: tpcg_workspace_bytes plus the density buffers)
+ * fits in the rest of the server's budget and fewer than max_active sessions
+ * are open; otherwise it returns TPCG_EAGAIN and changes nothing (retry after
+ * a session closes). A job (tpcg_server_submit) is one design update of a
+ * session, run after the session's earlier jobs and concurrently with the
+ * jobs of other sessions (their kernels overlap on the device):
+ *   - physical densities of the nsys realisations from the design rho (dev
+ *     [n_el]) by tpcg_filter_project (rmin > 0; rmin <= 0: rho itself);
+ *   - the preconditioner rebuilt from realisation `rep` when the session has
+ *     none, when rebuild > 0, or (rebuild == 0, Sec. 5.2's rule) when the
+ *     previous job's PCG took more than `growth` times the lowest iteration
+ *     count seen since the last rebuild (rebuild < 0: never again);
+ *     otherwise the resident basis is kept and, with refactor, the local
+ *     and coarse factors are rebuilt for the job's design (tpcg_refactor);
+ *   - tpcg_pcg_solve of all realisations with u (dev [nsys][n_dof]) as the
+ *     initial guess (warm start from the previous design's displacements,
+ *     Sec. 5.2) and as the output; f dev [nsys][n_dof];
+ *   - c (dev [nsys]) and, if dc (dev [nsys][n_el]) is not NULL, the
+ *     sensitivities with respect to the design (chain rule through the
+ *     projection and filter);
+ *   - the non-discreteness of realisation `rep`.
+ * The caller keeps rho, f, u, c and dc alive and unmodified until the job is
+ * complete (tpcg_server_wait, or tpcg_server_test returning TPCG_OK; it
+ * returns TPCG_EAGAIN while the job runs). A result is read once.
+ * tpcg_server_close runs the session's remaining jobs, then frees it.
+ * The server uses the device current at tpcg_server_create; its functions
+ * may be called from several threads.
+ */
+typedef struct tpcg_server tpcg_server;
+
+typedef struct {
+  double rtol;          /* PCG relative residual */
+  int32_t maxit;
+  int32_t rebuild;      /* 0: iteration-count rule; > 0: every job; < 0: only the first */
+  double growth;        /* rule: rebuild when iterations > growth x the reference count (>= 1) */
+  double rmin, beta;    /* density filter radius (<= 0: no filter) and projection sharpness */
+  double eta[4];        /* projection thresholds of the realisations */
+  int32_t rep;          /* realisation the coarse basis is built from */
+  int32_t refactor;     /* 1: between basis rebuilds, refactor the local and coarse factors for
+                           the job's design (tpcg_refactor); 0: keep them as well */
+} tpcg_job_opts;
+
+typedef struct {
+  int32_t status_all;   /* tpcg_status of the job (a failure of any step) */
+  int32_t iters[4];     /* per realisation */
+  int32_t status[4];
+  double relres[4], true_relres[4];
+  int32_t rebuilt;      /* this job rebuilt the preconditioner with a new basis */
+  int32_t refactored;   /* this job refactored with the resident basis */
+  int32_t rebuilds;     /* rebuilds of the session so far */
+  double queue_ms;      /* from submission to the start of the job */
+  double build_ms, solve_ms, total_ms;
+  double m_nd;          /* non-discreteness of realisation rep */
+} tpcg_job_result;
+
+int tpcg_server_create(size_t budget_bytes, int32_t max_active, tpcg_server** out);
+size_t tpcg_server_session_bytes(const tpcg_problem* prob, int32_t nsys);
+int tpcg_server_open(tpcg_server* s, const tpcg_problem* prob, const uint8_t* fixed_mask,
+                     int32_t nsys, int64_t* session);
+int tpcg_server_submit(tpcg_server* s, int64_t session, const double* rho, const double* f,
+                       double* u, double* c, double* dc, const tpcg_job_opts* opts, int64_t* job);
+int tpcg_server_wait(tpcg_server* s, int64_t job, tpcg_job_result* out);
+int tpcg_server_test(tpcg_server* s, int64_t job, tpcg_job_result* out);
+int tpcg_server_close(tpcg_server* s, int64_t session);
+size_t tpcg_server_free_bytes(const tpcg_server* s);
+void tpcg_server_destroy(tpcg_server* s);
 
 /*
  * Copy the coarse basis out (diagnostics and tests): phi dev

@@ -9,7 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["Problem", "Handle", "TpcgError", "load_library", "FP64", "MIXED"]
+__all__ = ["Problem", "Handle", "Server", "TpcgError", "load_library", "FP64", "MIXED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libtpcg.so")
@@ -18,7 +18,7 @@ _lib = None
 FP64 = 0
 MIXED = 1
 
-STATUS = {0: "OK", 1: "ENOCONV", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
+STATUS = {0: "OK", 1: "ENOCONV", 2: "EAGAIN", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
           -5: "EBREAKDOWN", -6: "ESTATE"}
 
 
@@ -48,6 +48,23 @@ class Info(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class JobOpts(ctypes.Structure):
+    """Mirror of tpcg_job_opts."""
+    _fields_ = [("rtol", ctypes.c_double), ("maxit", ctypes.c_int32), ("rebuild", ctypes.c_int32),
+                ("growth", ctypes.c_double), ("rmin", ctypes.c_double), ("beta", ctypes.c_double),
+                ("eta", ctypes.c_double * 4), ("rep", ctypes.c_int32), ("refactor", ctypes.c_int32)]
+
+
+class JobResult(ctypes.Structure):
+    """Mirror of tpcg_job_result."""
+    _fields_ = [("status_all", ctypes.c_int32), ("iters", ctypes.c_int32 * 4),
+                ("status", ctypes.c_int32 * 4), ("relres", ctypes.c_double * 4),
+                ("true_relres", ctypes.c_double * 4), ("rebuilt", ctypes.c_int32),
+                ("refactored", ctypes.c_int32), ("rebuilds", ctypes.c_int32), ("queue_ms", ctypes.c_double),
+                ("build_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("m_nd", ctypes.c_double)]
+
+
 EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_basis",
            "tpcg_apply_K", "tpcg_apply_precond", "tpcg_pcg_solve",
            "tpcg_compliance_and_sensitivity", "tpcg_filter_project",
@@ -55,7 +72,10 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_set_profiling", "tpcg_profile_block_solves", "tpcg_export_eigenvalues",
            "tpcg_query_subspace", "tpcg_test_fail_alloc", "tpcg_last_error", "tpcg_destroy",
            "tpcg_compliance_and_sensitivity_noalloc", "tpcg_set_graphs",
-           "tpcg_last_solve_graph_chunks", "tpcg_robust_objective", "tpcg_periodic_sum"]
+           "tpcg_last_solve_graph_chunks", "tpcg_robust_objective", "tpcg_periodic_sum",
+           "tpcg_nondiscreteness", "tpcg_refactor", "tpcg_server_create", "tpcg_server_session_bytes",
+           "tpcg_server_open", "tpcg_server_submit", "tpcg_server_wait", "tpcg_server_test",
+           "tpcg_server_close", "tpcg_server_free_bytes", "tpcg_server_destroy"]
 
 
 def load_library(path: str | None = None):
@@ -91,6 +111,22 @@ def load_library(path: str | None = None):
     lib.tpcg_destroy.argtypes = [P]
     lib.tpcg_destroy.restype = None
     lib.tpcg_set_graphs.argtypes = [P, I32]
+    lib.tpcg_nondiscreteness.argtypes = [P, P, P]
+    lib.tpcg_refactor.argtypes = [P, P, I32]
+    I64 = ctypes.c_int64
+    lib.tpcg_server_create.argtypes = [ctypes.c_size_t, I32, ctypes.POINTER(P)]
+    lib.tpcg_server_session_bytes.argtypes = [ctypes.POINTER(Problem), I32]
+    lib.tpcg_server_session_bytes.restype = ctypes.c_size_t
+    lib.tpcg_server_open.argtypes = [P, ctypes.POINTER(Problem), P, I32, ctypes.POINTER(I64)]
+    lib.tpcg_server_submit.argtypes = [P, I64, P, P, P, P, P, ctypes.POINTER(JobOpts),
+                                       ctypes.POINTER(I64)]
+    lib.tpcg_server_wait.argtypes = [P, I64, ctypes.POINTER(JobResult)]
+    lib.tpcg_server_test.argtypes = [P, I64, ctypes.POINTER(JobResult)]
+    lib.tpcg_server_close.argtypes = [P, I64]
+    lib.tpcg_server_free_bytes.argtypes = [P]
+    lib.tpcg_server_free_bytes.restype = ctypes.c_size_t
+    lib.tpcg_server_destroy.argtypes = [P]
+    lib.tpcg_server_destroy.restype = None
     lib.tpcg_robust_objective.argtypes = [P, P, P, I32, D, ctypes.POINTER(D), P, P]
     lib.tpcg_periodic_sum.argtypes = [P, P, I32, ctypes.POINTER(I32), P]
     lib.tpcg_last_solve_graph_chunks.argtypes = [P]
@@ -180,6 +216,11 @@ class Handle:
         nsys = rho_phys.numel() // self.n_el
         return self._check(self.lib.tpcg_build_coarse_basis(
             self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el), nsys, rep))
+
+    def refactor(self, rho_phys):
+        import torch
+        nsys = rho_phys.numel() // self.n_el
+        return self._check(self.lib.tpcg_refactor(self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el), nsys))
 
     def apply_K(self, rho_phys, x, y):
         import torch
@@ -311,3 +352,97 @@ def compliance_and_sensitivity_noalloc(problem: Problem, fixed, rho_phys, u, f, 
         _ptr(c, torch.float64, nsys), _ptr(dc, torch.float64, nsys * n_el) if dc is not None else None,
         _ptr(status, torch.int32, 1) if status is not None else None, ctypes.c_void_p(st.cuda_stream))
     return rc
+
+
+def _result(r: JobResult, nsys: int) -> dict:
+    return dict(status_all=r.status_all, iters=list(r.iters)[:nsys], status=list(r.status)[:nsys],
+                relres=list(r.relres)[:nsys], true_relres=list(r.true_relres)[:nsys],
+                rebuilt=bool(r.rebuilt), refactored=bool(r.refactored), rebuilds=r.rebuilds, queue_ms=r.queue_ms,
+                build_ms=r.build_ms, solve_ms=r.solve_ms, total_ms=r.total_ms, m_nd=r.m_nd)
+
+
+class Server:
+    """Owns a tpcg_server: sessions admitted by device-memory budget, one
+    worker thread and stream per session, jobs = warm-started design updates."""
+
+    def __init__(self, budget_bytes: int, max_active: int = 8):
+        self.lib = load_library()
+        s = ctypes.c_void_p()
+        rc = self.lib.tpcg_server_create(int(budget_bytes), int(max_active), ctypes.byref(s))
+        if rc != 0:
+            raise TpcgError(rc, "tpcg_server_create failed")
+        self.s = s
+        self._nsys = {}
+        self._jobs = {}
+
+    def session_bytes(self, problem: Problem, nsys: int) -> int:
+        return int(self.lib.tpcg_server_session_bytes(ctypes.byref(problem), nsys))
+
+    def free_bytes(self) -> int:
+        return int(self.lib.tpcg_server_free_bytes(self.s))
+
+    def open(self, problem: Problem, fixed_mask, nsys: int):
+        """Session id, or None when the budget or the session cap is full."""
+        import numpy as np
+        fm = np.ascontiguousarray(np.asarray(fixed_mask, dtype=np.uint8))
+        sid = ctypes.c_int64()
+        rc = self.lib.tpcg_server_open(self.s, ctypes.byref(problem), fm.ctypes.data_as(ctypes.c_void_p),
+                                       nsys, ctypes.byref(sid))
+        if rc == 2:
+            return None
+        if rc != 0:
+            raise TpcgError(rc, "tpcg_server_open failed (see stderr)")
+        self._nsys[sid.value] = (nsys, problem)
+        return sid.value
+
+    def submit(self, session, rho, f, u, c, dc=None, rtol=1e-8, maxit=2000, rebuild=0,
+               growth=1.5, rmin=0.0, beta=8.0, etas=(0.5,), rep=0, refactor=True) -> int:
+        import torch
+        nsys, pr = self._nsys[session]
+        o = JobOpts()
+        o.rtol, o.maxit, o.rebuild, o.growth = rtol, maxit, rebuild, growth
+        o.rmin, o.beta, o.rep, o.refactor = rmin, beta, rep, 1 if refactor else 0
+        for i, e in enumerate(tuple(etas)[:4]):
+            o.eta[i] = e
+        job = ctypes.c_int64()
+        rc = self.lib.tpcg_server_submit(self.s, session, _ptr(rho, torch.float64), _ptr(f, torch.float64),
+                                         _ptr(u, torch.float64), _ptr(c, torch.float64, nsys),
+                                         _ptr(dc, torch.float64) if dc is not None else None,
+                                         ctypes.byref(o), ctypes.byref(job))
+        if rc != 0:
+            raise TpcgError(rc, "tpcg_server_submit failed")
+        self._jobs[job.value] = nsys
+        return job.value
+
+    def wait(self, job) -> dict:
+        r = JobResult()
+        rc = self.lib.tpcg_server_wait(self.s, job, ctypes.byref(r))
+        if rc != 0:
+            raise TpcgError(rc, "tpcg_server_wait failed")
+        return _result(r, self._jobs.pop(job))
+
+    def test(self, job):
+        r = JobResult()
+        rc = self.lib.tpcg_server_test(self.s, job, ctypes.byref(r))
+        if rc == 2:
+            return None
+        if rc != 0:
+            raise TpcgError(rc, "tpcg_server_test failed")
+        return _result(r, self._jobs.pop(job))
+
+    def close(self, session):
+        rc = self.lib.tpcg_server_close(self.s, session)
+        self._nsys.pop(session, None)
+        if rc != 0:
+            raise TpcgError(rc, "tpcg_server_close failed")
+
+    def destroy(self):
+        if getattr(self, "s", None):
+            self.lib.tpcg_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

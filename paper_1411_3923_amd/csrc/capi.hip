@@ -531,7 +531,21 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
       return fail(hh, TPCG_ENOMEM, "out of device memory for the preconditioner");
   }
   ++h->build_gen;
-  return build_preconditioner(*h, rho_phys, nsys, rep);
+  return build_preconditioner(*h, rho_phys, nsys, rep, 1);
+}
+
+int tpcg_refactor(tpcg_handle* hh, const double* rho_phys, int32_t nsys) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "no coarse basis to keep: build it first");
+  if (!rho_phys) return fail(hh, TPCG_EINVAL, "rho_phys is NULL");
+  if (nsys < 1 || nsys > h->prob.nsys_max) return fail(hh, TPCG_EINVAL, "nsys out of range");
+  int rc = check_rho_sync(h, rho_phys, h->g.nel, nsys);
+  if (rc != TPCG_OK) return rc;
+  h->basis_ready = 0;
+  ++h->build_gen;
+  return build_preconditioner(*h, rho_phys, nsys, 0, 0);
 }
 
 int tpcg_apply_K(tpcg_handle* hh, const double* rho_phys, const double* x, double* y, int32_t nsys) {
@@ -830,6 +844,15 @@ int tpcg_robust_objective(tpcg_handle* hh, const double* c, const double* dc, in
   }
   launch_robust(*h, c, dc, nsys, kappa, w, out3, df, h->stream);
   return check_hip(h, "tpcg_robust_objective");
+}
+
+int tpcg_nondiscreteness(tpcg_handle* hh, const double* rho_phys, double* out) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!rho_phys || !out) return fail(hh, TPCG_EINVAL, "NULL argument");
+  launch_nondiscreteness(*h, rho_phys, out, h->stream);
+  return check_hip(h, "tpcg_nondiscreteness");
 }
 
 int tpcg_periodic_sum(tpcg_handle* hh, const double* g, int32_t nsys, const int32_t* cell,

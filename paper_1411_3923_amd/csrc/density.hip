@@ -249,6 +249,25 @@ __global__ __launch_bounds__(kThreads) void k_periodic_sum(Geometry g, const dou
   if (threadIdx.x == 0) gcell[(size_t)sys * cx * cy * cz + v] = tot;
 }
 
+// partials of sum_e 4 rho_e (1 - rho_e) (the non-discreteness measure, Sec. 5.2)
+__global__ __launch_bounds__(kThreads) void k_mnd_parts(const double* __restrict__ rho, int64_t n,
+                                                       double* __restrict__ part) {
+  __shared__ double sh[4];
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    a += 4.0 * rho[i] * (1.0 - rho[i]);
+  const double s = block_sum(a, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_mnd_final(const double* __restrict__ part, int np, int64_t n,
+                            double* __restrict__ out) {
+  __shared__ double sh[4];
+  const double v = sum_parts(part, np, sh);
+  if (threadIdx.x == 0) out[0] = v / (double)n;
+}
+
 int elem_blocks(int64_t n) {
   int64_t b = (n + kThreads - 1) / kThreads;
   return (int)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
@@ -287,6 +306,13 @@ void launch_periodic_sum(const Handle& h, const double* gin, int nsys, int cx, i
                          double* gcell, hipStream_t st) {
   hipLaunchKernelGGL(k_periodic_sum, dim3(cx * cy * cz, nsys), dim3(kThreads), 0, st, h.g, gin, cx,
                      cy, cz, gcell);
+}
+
+void launch_nondiscreteness(const Handle& h, const double* rho, double* out, hipStream_t st) {
+  const int np = parts_for(h.g.nel);
+  double* part = part_slot(h.parts, kPartAux, 0);
+  hipLaunchKernelGGL(k_mnd_parts, dim3(np), dim3(kThreads), 0, st, rho, (int64_t)h.g.nel, part);
+  hipLaunchKernelGGL(k_mnd_final, dim3(1), dim3(kThreads), 0, st, part, np, (int64_t)h.g.nel, out);
 }
 
 void launch_compliance_sens_raw(const Geometry& g, const uint8_t* fixed, const double* K0,

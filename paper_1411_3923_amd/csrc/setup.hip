@@ -692,7 +692,7 @@ size_t build_ws_elems(const tpcg_problem& pr, const Geometry& g, int big, int ms
   return std::max(eig, coarse);
 }
 
-int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
+int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int with_basis) {
   const Geometry& g = h.g;
   hipStream_t st = h.stream;
   const tpcg_problem& pr = h.prob;
@@ -730,7 +730,8 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   si.penal = pr.penal;
   si.shift = mp.shift;
   si.fixed_diag = kFixedDiag;
-  // --- 1-3: spectral basis from system `rep` ---
+  // --- 1-3: spectral basis from system `rep` (kept as it is when !with_basis) ---
+  if (with_basis) {
   double* nfac = h.build_ws;
   double* dis = nfac + rec;
   double* X = dis + nsl;
@@ -782,6 +783,8 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep) {
   else
     hipLaunchKernelGGL(k_phi_modes<double>, dim3(1024), dim3(kThreads), 0, st, g, h.phi,
                        reinterpret_cast<double*>(h.phim));
+
+  }
 
   // --- 4: coarse matrices and factors, all systems per launch ---
   double* W = h.build_ws;                 // [nsys][wsz]

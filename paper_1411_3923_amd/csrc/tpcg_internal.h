@@ -317,7 +317,8 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
 void launch_local_solves(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st);
 
 // setup.hip
-int build_preconditioner(Handle& h, const double* rho, int nsys, int rep);
+// with_basis = 0: keep the spectral basis, rebuild the local and coarse factors
+int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int with_basis);
 // work arrays (doubles) the preconditioner build keeps in the handle
 size_t build_ws_elems(const tpcg_problem& pr, const Geometry& g, int big, int msub);
 
@@ -334,6 +335,8 @@ void launch_compliance_sens(const Handle& h, const double* rho, const double* u,
 // if dc, its gradient df [n_el] from dc [nsys][n_el]
 void launch_robust(const Handle& h, const double* c, const double* dc, int nsys, double kappa,
                    const double* w, double* out, double* df, hipStream_t st);
+// out[0] = sum_e 4 rho_e (1 - rho_e) / n_el (one density field)
+void launch_nondiscreteness(const Handle& h, const double* rho, double* out, hipStream_t st);
 // gcell [nsys][cx cy cz] = sums of gin [nsys][n_el] over the copies of a unit cell
 void launch_periodic_sum(const Handle& h, const double* gin, int nsys, int cx, int cy, int cz,
                          double* gcell, hipStream_t st);

@@ -247,3 +247,50 @@ def with_density(p: Problem, density: str, seed: int | None = None) -> Problem:
     """Copy of p with another density recipe (used by small test meshes)."""
     from dataclasses import replace
     return replace(p, density=density, seed=p.seed if seed is None else seed)
+
+
+# ----------------------------------------------------------------------------
+# Serving stream: arrivals and design updates (synthetic stand-ins for the
+# optimiser's requests; no part of the method)
+# ----------------------------------------------------------------------------
+
+SERVING_MESHES_2D = [(256, 128), (512, 256), (1024, 512), (2048, 1024)]
+SERVING_MESHES_3D = [(48, 48, 48), (96, 48, 48)]
+
+
+def serving_requests(n: int, rate_per_s: float, seed: int = 1005, with_3d: bool = True):
+    """n requests with Poisson arrivals (exponential gaps at rate_per_s): list
+    of (arrival time in s, Problem). Meshes uniformly from the 2D set (32 x 32
+    cells, k = 6, filtered and projected designs, 3 realisations) and, with
+    with_3d, the 3D set (16^3 cells, layered design, one realisation)."""
+    rng = np.random.default_rng(seed)
+    choices = [("2d", m) for m in SERVING_MESHES_2D]
+    if with_3d:
+        choices += [("3d", m) for m in SERVING_MESHES_3D]
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += rng.exponential(1.0 / rate_per_s)
+        kind, m = choices[rng.integers(len(choices))]
+        if kind == "2d":
+            p = cantilever2d(m[0], m[1], 32, 6, name=f"req{i}_cantilever2d_{m[0]}x{m[1]}")
+        else:
+            p = cantilever3d(m[0], m[1], m[2], 16, 16, name=f"req{i}_cantilever3d_{m[0]}x{m[1]}x{m[2]}")
+        out.append((t, p))
+    return out
+
+
+def design_noise(p: Problem, step: int, seed: int) -> np.ndarray:
+    """A smooth seeded field in [-1, 1] per element: the direction of a
+    synthetic design update (rho <- clip(rho + 0.02 noise, 0, 1))."""
+    rng = np.random.default_rng((seed, step))
+    dims = (p.nelx, p.nely) if p.dim == 2 else (p.nelx, p.nely, p.nelz)
+    grids = np.meshgrid(*[(np.arange(n) + 0.5) / n for n in dims[::-1]], indexing="ij")
+    xs = [g.ravel() for g in grids[::-1]]
+    s = np.zeros(p.n_el)
+    amp = rng.uniform(0.5, 1.0, 4)
+    for q in range(4):
+        k = rng.integers(0, 3, p.dim)
+        ph = rng.uniform(0.0, 2 * np.pi)
+        s += amp[q] * np.cos(2 * np.pi * sum(k[a] * xs[a] for a in range(p.dim)) + ph)
+    return s / amp.sum()
