@@ -193,6 +193,49 @@ def cpu_baseline(args):
             "nproc": os.cpu_count(), "cpu_model": cpu_model(), "kind": "oracle", "sample": sample}
 
 
+def section_errors(args):
+    """Errors of the GPU's FP64 and mixed results (u, c, dc of the three
+    realisations, PCG to the bench's rtol) against the oracle's sparse direct
+    solves, on the 512 x 128 section of the cantilever workload."""
+    import numpy as np
+    import torch
+
+    import paper_1411_3923_amd as T
+    from oracle import density, fem
+    from paper_1411_3923_amd import workloads as W
+
+    p = W.cantilever2d(512, 128, 32, 6)
+    rho = W.design_field(p)
+    f = W.load_vector(p)
+    _, rb = density.filter_project(p, rho, p.rmin, p.beta, p.etas)
+    uo = [fem.solve(p, rb[s]) for s in range(p.nsys)]
+    co = [fem.compliance(f, u) for u in uo]
+    dco = [fem.sensitivity(p, rb[s], uo[s]) for s in range(p.nsys)]
+    d = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    out = {}
+    for name, prec in (("fp64", T.FP64), ("mixed", T.MIXED)):
+        pr = T.make_problem(2, p.nel[:2], p.sub, p.k, p.nsys, p.E0, p.Emin, p.penal, p.nu, prec)
+        h = T.Handle(pr, W.fixed_mask(p))
+        R, F = d(rb), d(np.stack([f] * p.nsys))
+        h.build_coarse_basis(R, rep=0)
+        u = torch.zeros((p.nsys, p.n_dof), dtype=torch.float64, device="cuda")
+        h.pcg_solve(R, F, u, rtol=args.rtol, maxit=args.maxit)
+        c = torch.zeros(p.nsys, dtype=torch.float64, device="cuda")
+        dc = torch.zeros((p.nsys, p.n_el), dtype=torch.float64, device="cuda")
+        h.compliance_and_sensitivity(R, u, F, c, dc)
+        uh, ch, dch = u.cpu().numpy(), c.cpu().numpy(), dc.cpu().numpy()
+        out[name] = {
+            "u": [float(np.linalg.norm(uh[s] - uo[s]) / np.linalg.norm(uo[s])) for s in range(p.nsys)],
+            "compliance": [abs(float(ch[s]) - co[s]) / abs(co[s]) for s in range(p.nsys)],
+            "dc": [float(np.linalg.norm(dch[s] - dco[s]) / np.linalg.norm(dco[s]))
+                   for s in range(p.nsys)],
+            "against": "oracle sparse direct solve (SuperLU, two refinement steps), "
+                       "512x128 section of the cantilever workload, 3 realisations, "
+                       f"GPU PCG to {args.rtol:g}"}
+        h.close()
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -679,6 +722,11 @@ def main():
                                             if bmx["ms"] > 0 else None)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args)
+        if not three:
+            errs = section_errors(args)
+            line["fp64"]["error_vs_oracle_section"] = errs["fp64"]
+            if "mixed" in line:
+                line["mixed"]["error_vs_oracle_section"] = errs["mixed"]
     print(json.dumps(line), flush=True)
 
 

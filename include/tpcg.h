@@ -373,6 +373,14 @@ int tpcg_export_coarse_basis(tpcg_handle* h, double* phi, double* lambda, double
  */
 int tpcg_export_eigenvalues(tpcg_handle* h, double* lambda, int32_t m, int32_t* kj);
 
+/*
+ * Testing support: the record C_b (the inverse of the b-th Schur complement
+ * of the twisted elimination of the local Dirichlet matrix of subdomain sub
+ * in system sys) as a dense row-major nb x nb matrix in host memory out.
+ * Only for subdomain blocks on the HBM-resident path (TPCG_EINVAL otherwise).
+ */
+int tpcg_export_local_record(tpcg_handle* h, int32_t sys, int32_t sub, int32_t blk, double* out);
+
 /* Width of the eigensolver's subspace (ncoarse + eig_extra, at most 16 and at
  * most the subdomain's DOFs), or TPCG_EINVAL for a null handle. */
 int tpcg_query_subspace(const tpcg_handle* h);

@@ -73,7 +73,7 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_query_subspace", "tpcg_test_fail_alloc", "tpcg_last_error", "tpcg_destroy",
            "tpcg_compliance_and_sensitivity_noalloc", "tpcg_set_graphs",
            "tpcg_last_solve_graph_chunks", "tpcg_robust_objective", "tpcg_periodic_sum",
-           "tpcg_nondiscreteness", "tpcg_refactor", "tpcg_server_create", "tpcg_server_session_bytes",
+           "tpcg_nondiscreteness", "tpcg_refactor", "tpcg_export_local_record", "tpcg_server_create", "tpcg_server_session_bytes",
            "tpcg_server_open", "tpcg_server_submit", "tpcg_server_wait", "tpcg_server_test",
            "tpcg_server_close", "tpcg_server_free_bytes", "tpcg_server_destroy"]
 
@@ -113,6 +113,7 @@ def load_library(path: str | None = None):
     lib.tpcg_set_graphs.argtypes = [P, I32]
     lib.tpcg_nondiscreteness.argtypes = [P, P, P]
     lib.tpcg_refactor.argtypes = [P, P, I32]
+    lib.tpcg_export_local_record.argtypes = [P, I32, I32, I32, P]
     I64 = ctypes.c_int64
     lib.tpcg_server_create.argtypes = [ctypes.c_size_t, I32, ctypes.POINTER(P)]
     lib.tpcg_server_session_bytes.argtypes = [ctypes.POINTER(Problem), I32]
@@ -216,6 +217,14 @@ class Handle:
         nsys = rho_phys.numel() // self.n_el
         return self._check(self.lib.tpcg_build_coarse_basis(
             self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el), nsys, rep))
+
+    def export_local_record(self, sys, sub, blk):
+        """Dense C_b of the HBM-resident local factors (testing)."""
+        import numpy as np
+        out = np.zeros((self.nb, self.nb))
+        self._check(self.lib.tpcg_export_local_record(self.h, sys, sub, blk,
+                                                      out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def refactor(self, rho_phys):
         import torch

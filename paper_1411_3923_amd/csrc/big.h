@@ -60,7 +60,18 @@ void coarse_dense_inverse(const Geometry& g, const double* Ac, size_t astride, i
                           double* S, double* ws, double* cpk, int* flag, hipStream_t st);
 inline size_t coarse_dense_ws_elems(const Geometry& g, int nsys) {
   const int ntb = big_ntb(g.nt);
-  return (size_t)nsys * big_nl(ntb) * kBTE + sweep_ws_elems(nsys, ntb);
+  const size_t sweep = (size_t)nsys * big_nl(ntb) * kBTE + sweep_ws_elems(nsys, ntb);
+  const size_t dense = (size_t)nsys * g.nt * g.nt;   // the block-tridiagonal path's inverse
+  return sweep > dense ? sweep : dense;
+}
+// Lower tiles of a dense row-major K_c^-1 [nsys][nt][nt] into cpk.
+void coarse_pack_inverse(const Geometry& g, const double* inv, int nsys, double* cpk,
+                         hipStream_t st);
+// Whether the coarse matrix's blocks fit the on-chip block-tridiagonal
+// factor and inverse kernels (their column-chunk inverse spreads over the
+// chip; the sweep's 64 x 64 pivots are latency-bound at these sizes).
+inline bool coarse_btri_fits(const Geometry& g) {
+  return g.nbc <= 96 && (g.nbc & 1) == 0;
 }
 
 // Sizes of the HBM-resident local factors of geometry g.

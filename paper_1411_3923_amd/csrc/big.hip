@@ -28,6 +28,7 @@
 // every lower tile (one workgroup per tile, v_mfma_f64_16x16x4f64 with both
 // operands read as coalesced 512-byte fragments).
 #include <algorithm>
+#include <utility>
 
 #include "big.h"
 #include "btri.h"
@@ -59,51 +60,61 @@ __device__ inline void adec(int o, int& r, int& c) {
 // Symmetric block sweep
 // ---------------------------------------------------------------------------
 
-// P^-1 of the pivot tile of every matrix, by in-place Gauss-Jordan
-// elimination without pivoting (the pivots of an SPD matrix's sweep are its
-// Schur complements): step k maps a_kk -> 1/p, a_kj -> a_kj / p,
-// a_ij -> a_ij - a_ik a_kj / p, a_ik -> -a_ik / p. Thread t owns row t / 4,
-// columns 16 (t % 4) .. + 15. Result row-major into pinv.
-__global__ __launch_bounds__(kThreads) void k_sw_pivot(const double* __restrict__ S,
-                                                      size_t mstride, int K,
-                                                      double* __restrict__ pinv,
-                                                      int* __restrict__ flag) {
-  __shared__ double A[kBT][kBT + 1];
-  const int m = blockIdx.x, t = threadIdx.x;
+// P^-1 of the pivot tile of every matrix by the symmetric sweep of its 64
+// pivots, one wave per matrix: lane j keeps column j in registers; at step k
+// every lane publishes its entry of row k (= column k, the sweep keeps the
+// matrix symmetric), then
+//   a_ij -= a_ik a_kj / p,  a_ik <- a_ik / p,  a_kj <- a_kj / p,  a_kk <- -1/p
+// (p = a_kk > 0 for an SPD tile, the Schur complements' diagonals). After
+// the 64th step the tile holds -P^-1; P^-1 is written row-major.
+__global__ __launch_bounds__(64) void k_sw_pivot(const double* __restrict__ S, size_t mstride,
+                                                 int K, double* __restrict__ pinv,
+                                                 int* __restrict__ flag) {
+  __shared__ double col[kBT];
+  const int m = blockIdx.x, j = threadIdx.x;
   const double* src = S + (size_t)m * mstride + (size_t)big_ltile(K, K) * kBTE;
-  for (int o = t; o < kBTE; o += kThreads) {
-    int r, c;
-    cdec(o, r, c);
-    A[r][c] = src[o];
-  }
-  __syncthreads();
-  const int i = t >> 2, j0 = (t & 3) * 16;
+  // a[i] holds row (i + 8 kb) mod 64 of column j: the array turns by 8 after
+  // every block of 8 pivots, so that pivot row 8 kb + kk sits at a[kk] and
+  // every register index is a constant
+  double a[kBT];
+#pragma unroll
+  for (int i = 0; i < kBT; ++i) a[i] = src[big_cofs(i, j)];
   bool bad = false;
-  for (int k = 0; k < kBT; ++k) {
-    double p = A[k][k];
-    if (!(p > 0.0)) {
-      bad = true;
-      p = 1.0;
-    }
-    const double ip = 1.0 / p;
-    const double aik = A[i][k];
-    double akj[16];
+  for (int kb = 0; kb < kBT / 8; ++kb) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) akj[q] = A[k][j0 + q];
-    __syncthreads();
+    for (int kk = 0; kk < 8; ++kk) {
+      const int k = 8 * kb + kk;
+      const double akj = a[kk];
+      col[j] = akj;
+      __syncthreads();
+      double p = col[k];
+      if (!(p > 0.0)) {
+        bad = true;
+        p = 1.0;
+      }
+      const double ip = 1.0 / p;
+      const double sk = akj * ip;       // a_kj / p
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int j = j0 + q;
-      double v;
-      if (i == k) v = j == k ? ip : akj[q] * ip;
-      else v = j == k ? -aik * ip : A[i][j] - aik * (akj[q] * ip);
-      A[i][j] = v;
+      for (int i = 0; i < kBT; ++i) {
+        if (i == kk) continue;
+        const double aik = col[(i + 8 * kb) & (kBT - 1)];
+        a[i] = j == k ? aik * ip : a[i] - aik * sk;
+      }
+      a[kk] = j == k ? -ip : sk;
+      __syncthreads();
     }
-    __syncthreads();
+    double t[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = a[i];
+#pragma unroll
+    for (int i = 0; i < kBT - 8; ++i) a[i] = a[i + 8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) a[kBT - 8 + i] = t[i];
   }
-  if (bad && t == 0) flag[0] = 1;
+  if (bad && j == 0) flag[0] = 1;
   double* dst = pinv + (size_t)m * kBTE;
-  for (int o = t; o < kBTE; o += kThreads) dst[o] = A[o >> 6][o & 63];
+#pragma unroll
+  for (int i = 0; i < kBT; ++i) dst[i * kBT + j] = -a[i];
 }
 
 // Panels of step K for tile row I != K: V_I = A_IK (from tile (I, K), or
@@ -262,6 +273,21 @@ __global__ __launch_bounds__(kThreads) void k_coarse_store(Geometry g, const dou
     const int r = e >> 6, c = e & 63;
     const int R = kBT * I + r, C = kBT * J + c;
     D[e] = (R < nt && C < nt) ? -T[big_cofs(r, c)] : 0.0;
+  }
+}
+
+// Lower tiles of K_c^-1 (row-major in each tile, zero past nt) from a dense
+// row-major K_c^-1 [nsys][nt][nt] (the block-tridiagonal path's inverse).
+__global__ __launch_bounds__(kThreads) void k_coarse_pack(Geometry g, const double* __restrict__ inv,
+                                                         int nl, double* __restrict__ cpk) {
+  const int q = blockIdx.x, sys = blockIdx.y, nt = g.nt;
+  int I, J;
+  tile_rc(q, I, J);
+  const double* src = inv + (size_t)sys * nt * nt;
+  double* dst = cpk + ((size_t)sys * nl + q) * kBTE;
+  for (int e = threadIdx.x; e < kBTE; e += kThreads) {
+    const int r = kBT * I + (e >> 6), c = kBT * J + (e & 63);
+    dst[e] = (r < nt && c < nt) ? src[(size_t)r * nt + c] : 0.0;
   }
 }
 
@@ -1156,7 +1182,7 @@ void sweep_invert(double* S, size_t mstride, int nmat, int ntb, double* ws, int*
   double* Vp = Wp + (size_t)nmat * ntb * kBTE;
   const int nl = big_nl(ntb);
   for (int K = 0; K < ntb; ++K) {
-    hipLaunchKernelGGL(k_sw_pivot, dim3(nmat), dim3(kThreads), 0, st, S, mstride, K, pinv, flag);
+    hipLaunchKernelGGL(k_sw_pivot, dim3(nmat), dim3(64), 0, st, S, mstride, K, pinv, flag);
     if (ntb > 1)
       hipLaunchKernelGGL(k_sw_panel, dim3(ntb, nmat), dim3(kThreads), 0, st, S, mstride, ntb, K,
                          pinv, Wp, Vp);
@@ -1173,6 +1199,12 @@ void coarse_dense_inverse(const Geometry& g, const double* Ac, size_t astride, i
                      mstride);
   sweep_invert(S, mstride, nsys, ntb, ws, flag, st);
   hipLaunchKernelGGL(k_coarse_store, dim3(nl, nsys), dim3(kThreads), 0, st, g, S, mstride, nl, cpk);
+}
+
+void coarse_pack_inverse(const Geometry& g, const double* inv, int nsys, double* cpk,
+                         hipStream_t st) {
+  const int nl = big_nl(big_ntb(g.nt));
+  hipLaunchKernelGGL(k_coarse_pack, dim3(nl, nsys), dim3(kThreads), 0, st, g, inv, nl, cpk);
 }
 
 size_t big_factor_ws_elems(const Geometry& g, int nsys) {

@@ -108,7 +108,7 @@ std::string precond_limits(const Geometry& g, int big) {
   } else if (stage_bucket(stage_regs_for<double>(g.nb, g.pe)) < 0) {
     return "factor records too long for the staged solve kernels";
   }
-  if (g.nt > g.dense_max) {
+  if (g.nt > g.dense_max || coarse_btri_fits(g)) {
     if (g.nbc > kMaxNb || (g.nbc & 1))
       return "coarse blocks larger than 96 or of odd size (coarse dimension above coarse_dense_max)";
     if (stage_bucket(stage_regs_for<double>(g.nbc, g.pec)) < 0)
@@ -141,9 +141,8 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   if (g.nt <= g.dense_max) {
     const size_t T = coarse_tiles(g.nt);
     p += sizeof(double) * nsys * (T * (T + 1) / 2 * kCT * kCT + T * T * kCT);
-  } else {
-    p += sizeof(double) * nsys * crec;
   }
+  if (g.nt > g.dense_max || coarse_btri_fits(g)) p += sizeof(double) * nsys * crec;
   p += 5 * sizeof(double) * nsys * g.ndof;
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
@@ -521,9 +520,8 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
       const size_t T = coarse_tiles(g.nt);
       a.add(h->cpk, (size_t)ns * T * (T + 1) / 2 * kCT * kCT);
       a.add(h->cpart, (size_t)ns * T * T * kCT);
-    } else {
-      a.add(h->cfac, ns * cfsz);
     }
+    if (g.nt > g.dense_max || coarse_btri_fits(g)) a.add(h->cfac, ns * cfsz);
     a.add_bytes(h->zloc, ts * ns * (size_t)g.nsub * g.nloc);
     a.add(h->yc, ns * (size_t)g.nt);
     a.add(h->xc, ns * (size_t)g.nt);
@@ -903,6 +901,40 @@ int tpcg_export_coarse_basis(tpcg_handle* hh, double* phi, double* lambda, doubl
       for (int i = 0; i < g.k; ++i) dst[(size_t)j * g.k + i] = tmp[(size_t)j * h->msub + i];
   }
   return check_hip(h, "tpcg_export_coarse_basis");
+}
+
+int tpcg_export_local_record(tpcg_handle* hh, int32_t sys, int32_t sub, int32_t blk, double* out) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
+  const Geometry& g = h->g;
+  if (!h->big) return fail(hh, TPCG_EINVAL, "records of the on-chip path are not exported");
+  if (!out || sys < 0 || sys >= h->nsys_built || sub < 0 || sub >= g.nsub || blk < 0 ||
+      blk >= g.nblk)
+    return fail(hh, TPCG_EINVAL, "record index out of range");
+  const BigShape bs = big_shape(g);
+  const size_t off = ((size_t)(sys * g.nsub + sub) * g.nblk + blk) * bs.rec_dir;
+  std::vector<double> rec(bs.rec_dir);
+  hipStreamSynchronize(h->stream);
+  if (h->mixed) {
+    std::vector<float> tmp(bs.rec_dir);
+    hipMemcpy(tmp.data(), reinterpret_cast<float*>(h->lfac) + off, sizeof(float) * tmp.size(),
+              hipMemcpyDeviceToHost);
+    for (size_t i = 0; i < tmp.size(); ++i) rec[i] = tmp[i];
+  } else {
+    hipMemcpy(rec.data(), reinterpret_cast<double*>(h->lfac) + off, sizeof(double) * rec.size(),
+              hipMemcpyDeviceToHost);
+  }
+  const int nb = g.nb;
+  for (int r = 0; r < nb; ++r)
+    for (int c = 0; c < nb; ++c) {
+      const int R = r >= c ? r : c, C = r >= c ? c : r;   // lower tiles hold the symmetric matrix
+      const int I = R / kBT, J = C / kBT;
+      int rr = R % kBT, cc = C % kBT;
+      if (I == J) { rr = r % kBT; cc = c % kBT; }          // diagonal tiles are stored in full
+      out[(size_t)r * nb + c] = rec[(size_t)big_ltile(I, J) * kBTE + big_cofs(rr, cc)];
+    }
+  return check_hip(h, "tpcg_export_local_record");
 }
 
 int tpcg_query(const tpcg_handle* hh, int64_t* out) {

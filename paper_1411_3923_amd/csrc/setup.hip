@@ -877,11 +877,20 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int wi
     hipEventRecord(h.join, s2);
   }
 
-  // coarse level: the dense K_c^-1 by the block sweep on the matrix cores
-  // (its lower tiles feed the coarse product), or for coarse spaces too
-  // large for a dense inverse the block-tridiagonal factor
-  if (h.cpk) coarse_dense_inverse(g, Ac, asm_coarse, nsys, Sc, cws, h.cpk, h.dflag, st);
-  else launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
+  // coarse level: the dense K_c^-1 (its lower tiles feed the coarse
+  // product), from the block-tridiagonal factor and its column-chunk inverse
+  // when the coarse blocks fit those on-chip kernels, else by the block
+  // sweep on the matrix cores; for coarse spaces too large for a dense
+  // inverse, the block-tridiagonal factor alone
+  if (h.cpk && !coarse_btri_fits(g)) {
+    coarse_dense_inverse(g, Ac, asm_coarse, nsys, Sc, cws, h.cpk, h.dflag, st);
+  } else {
+    launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);
+    if (h.cpk) {
+      launch_inverse(h.cfac, csh, nsys, Sc, st);   // dense K_c^-1 in the coarse work area
+      coarse_pack_inverse(g, Sc, nsys, h.cpk, st);
+    }
+  }
 
   hipStreamWaitEvent(st, h.join, 0);
   hipStreamSynchronize(st);

@@ -159,14 +159,41 @@ def test_big_path_3d_eigenpairs():
     print(f"big path 3d s=8 eigenpairs: eigenvalue {worst_l:.3e} angle {worst_a:.3e} "
           f"ritz residual {np.max(res):.3e}", flush=True)
     assert worst_l < 1e-7 and worst_a < 1e-6 and np.max(res) < 1e-6
-    # M^-1 r with four 64-row tiles per block, element by element
-    r = residuals(p, 1, 14)
-    z = dev(np.zeros_like(r))
-    h.apply_precond(dev(r), z)
-    e = elementwise(host(z)[0], oracle_ms(p, rb, 0, fixed)[0].apply(r[0]))
+    # M^-1 r with four 64-row tiles per block, element by element. On this
+    # layered design the k-th eigenvalue sits in a cluster, so the span of
+    # the k smallest eigenvectors is not unique: the coarse part is formed
+    # from the GPU's own (checked) basis
+    e = precond_with_own_basis(h, p, rb[0], fixed, 14)
     print(f"big path 3d s=8: precond {e:.3e}", flush=True)
     assert e < 1e-12
     h.close()
+
+
+def precond_with_own_basis(h, p, rho, fixed, seed):
+    """max |z_gpu - z_o| / max |z_o| for z_o = the oracle's local solves plus
+    Phi (Phi^T K Phi)^-1 Phi^T r with the GPU's exported basis Phi."""
+    import scipy.sparse as sp
+    r = residuals(p, 1, seed)
+    z = dev(np.zeros_like(r))
+    h.apply_precond(dev(r), z)
+    K = fem.assemble(p, fem.simp_modulus(rho, p.E0, p.Emin, p.penal))
+    want = schwarz.TwoLevelSchwarz(p, K, fixed, None).apply(r[0])
+    phi = host(h.export_coarse_basis()[0])
+    k = phi.shape[2]
+    rows, cols, vals = [], [], []
+    for j in range(p.n_sub):
+        nodes = schwarz.subdomain_nodes(p, j)
+        dofs = (p.dim * nodes[:, None] + np.arange(p.dim)[None, :]).ravel()
+        for m in range(k):
+            rows.append(dofs)
+            cols.append(np.full(dofs.size, j * k + m))
+            vals.append(phi[j][:, m])
+    Phi = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                        shape=(p.n_dof, p.n_sub * k)).tocsc()
+    P = sp.diags((fixed == 0).astype(np.float64))
+    Kc = (Phi.T @ (P @ K @ P) @ Phi).toarray()
+    want = want + P @ (Phi @ np.linalg.solve(Kc, Phi.T @ (P @ r[0])))
+    return elementwise(host(z)[0], want)
 
 
 @pytest.mark.parametrize("precision", [T.FP64, T.MIXED], ids=["fp64", "mixed"])
@@ -175,6 +202,10 @@ def test_big_path_3d_cantilever_cells(precision):
     rb = W.design_field(p)[None, :]
     h = handle(p, precision=precision, nsys=1)
     h.build_coarse_basis(dev(rb), rep=0)
+    e = precond_with_own_basis(h, p, rb[0], W.fixed_mask(p), 15)
+    print(f"big path 3d s=16 {'fp64' if precision == T.FP64 else 'mixed'}: precond {e:.3e}",
+          flush=True)
+    assert e < (1e-12 if precision == T.FP64 else 1e-6)
     info = pcg_vs_direct(h, p, rb, precision, "big path 3d s=16")
     assert info[0]["iters"] < 200
     h.close()
