@@ -396,7 +396,8 @@ def summarize_trace(stats_csv, command, out, title, bench_json=None):
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['AverageNs']) / 1e3:.1f} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
     if bench_json:
-        b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        b = json.loads([ln for ln in open(bench_json).read().splitlines()
+                        if ln.startswith("{")][-1])
         rl = b["roofline"]
         lines += ["", f"The bench line of the same run timed {rl['kernel']} with HIP events on its "
                   f"stream: {rl['launches']} launches with work, {rl['avg_launch_ms'] * 1e3:.1f} us "
@@ -405,12 +406,25 @@ def summarize_trace(stats_csv, command, out, title, bench_json=None):
                   f"counts the near-empty launches after the systems converge."]
         trace_csv = os.path.join(os.path.dirname(stats_csv), "run_kernel_trace.csv")
         if os.path.exists(trace_csv):
-            key = rl["kernel"].split("<")[0]
-            d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
-                 for r in csv.DictReader(open(trace_csv)) if key in r["Kernel_Name"]]
-            busy = [x for x in d if x > 20.0][-rl["launches"]:]
-            lines += ["", f"In the trace, the last {len(busy)} launches of {key} that do work "
-                      f"(the timed steps) average {sum(busy) / len(busy):.1f} us."]
+            base = rl["kernel"].split("<")[0]
+            if "{" in base:   # a set of kernels launched once each per iteration
+                stem, alts = base.split("{")
+                keys = [stem + a for a in alts.rstrip("}").split(",")]
+            else:
+                keys = [base]
+            trace = list(csv.DictReader(open(trace_csv)))
+            total = 0.0
+            for key in keys:
+                d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+                     for r in trace
+                     if r["Kernel_Name"].split("<")[0].split("(")[0].strip() == key]
+                busy = [x for x in d if x > 20.0][-rl["launches"]:]
+                avg = sum(busy) / len(busy) if busy else 0.0
+                total += avg
+                lines += ["", f"In the trace, the last {len(busy)} launches of {key} that do "
+                          f"work (the timed steps) average {avg:.1f} us."]
+            if len(keys) > 1:
+                lines += ["", f"Together: {total:.1f} us per iteration."]
     open(out, "w").write("\n".join(lines) + "\n")
 
 
