@@ -64,6 +64,12 @@ typedef enum {
 
 typedef enum { TPCG_FP64 = 0, TPCG_MIXED = 1 } tpcg_precision;
 
+/* Preconditioner of tpcg_gmres_solve. */
+typedef enum {
+  TPCG_PC_ADDITIVE = 0,   /* two-level additive Schwarz (the one tpcg_pcg_solve uses) */
+  TPCG_PC_MSFEM_SGS = 1   /* the MsFEM coarse solve between symmetric Gauss-Seidel steps */
+} tpcg_precond_kind;
+
 /* Problem description. Sizes are in elements. */
 typedef struct {
   int32_t dim;          /* 2 (Q4 plane stress) or 3 (H8) */
@@ -192,6 +198,40 @@ int tpcg_apply_precond(tpcg_handle* h, const double* r, double* z, int32_t nsys)
  */
 int tpcg_pcg_solve(tpcg_handle* h, const double* rho_phys, const double* f, double* u,
                    int32_t nsys, double rtol, int32_t maxit, tpcg_info* info);
+
+/*
+ * z = B r with the paper's multiplicative preconditioner (Sec. 2.4.2): one
+ * symmetric Gauss-Seidel step S from zero, the MsFEM coarse correction, one
+ * more step:  x = S(r; 0);  x += Phi K_c^-1 Phi^T (r - K x);  z = S(r; x).
+ * S acts on node blocks (each node's d x d diagonal block solved exactly) in
+ * multicolour order: colour = parity of x + 2 parity of y (+ 4 parity of z),
+ * colours in increasing then decreasing order. K = P K(rho_phys) P with unit
+ * diagonal on the supported DOFs, which stay zero in z. The coarse basis and
+ * K_c^-1 are those of the last build (tpcg_build_coarse_basis); rho_phys may
+ * differ from the build's. r, z dev [nsys][n_dof] (16-byte aligned, distinct);
+ * nsys must equal the build's. TPCG_ESTATE before a build.
+ */
+int tpcg_apply_msfem(tpcg_handle* h, const double* rho_phys, const double* r, double* z,
+                     int32_t nsys);
+
+/*
+ * Solve K(rho_s) u_s = P f_s for all systems with restarted GMRES, the
+ * paper's solver (Sec. 2.4.2), preconditioned from the left by `precond`
+ * (tpcg_precond_kind). u dev [nsys][n_dof] holds the initial guess on entry
+ * and the solution on exit. System s stops when the preconditioned residual
+ * ||B P (f_s - K u_s)||_2 falls to rtol ||B P f_s||_2 (the measure of Sec.
+ * 3.3), or after maxit Arnoldi steps; a cycle holds `restart` steps (1..64).
+ * info (host [nsys]): iters = Arnoldi steps, relres = the preconditioned
+ * relative residual (GMRES's estimate), true_relres = ||P (f - K u)|| /
+ * ||P f||. Allocates the Krylov basis ((restart + 1) nsys n_dof doubles) on
+ * the first call, and again when a call needs a larger one (TPCG_ENOMEM if
+ * that fails; the handle stays usable). Blocks until done. Densities are
+ * checked first: TPCG_EINVAL if one is NaN or outside [0, 1]. Returns the
+ * worst status over the systems (TPCG_ENOCONV if maxit was reached).
+ */
+int tpcg_gmres_solve(tpcg_handle* h, const double* rho_phys, const double* f, double* u,
+                     int32_t nsys, double rtol, int32_t maxit, int32_t restart, int32_t precond,
+                     tpcg_info* info);
 
 /*
  * Compliance c_s = f_s^T u_s (dev [nsys]) and, if dc is not NULL, the element

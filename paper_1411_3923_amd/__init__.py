@@ -17,6 +17,8 @@ _lib = None
 
 FP64 = 0
 MIXED = 1
+PC_ADDITIVE = 0   # tpcg_precond_kind
+PC_MSFEM_SGS = 1
 
 STATUS = {0: "OK", 1: "ENOCONV", 2: "EAGAIN", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOTSPD",
           -5: "EBREAKDOWN", -6: "ESTATE"}
@@ -75,7 +77,8 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_last_solve_graph_chunks", "tpcg_robust_objective", "tpcg_periodic_sum",
            "tpcg_nondiscreteness", "tpcg_refactor", "tpcg_export_local_record", "tpcg_server_create", "tpcg_server_session_bytes",
            "tpcg_server_open", "tpcg_server_submit", "tpcg_server_wait", "tpcg_server_test",
-           "tpcg_server_close", "tpcg_server_free_bytes", "tpcg_server_destroy"]
+           "tpcg_server_close", "tpcg_server_free_bytes", "tpcg_server_destroy",
+           "tpcg_apply_msfem", "tpcg_gmres_solve"]
 
 
 def load_library(path: str | None = None):
@@ -95,6 +98,8 @@ def load_library(path: str | None = None):
     lib.tpcg_apply_K.argtypes = [P, P, P, P, I32]
     lib.tpcg_apply_precond.argtypes = [P, P, P, I32]
     lib.tpcg_pcg_solve.argtypes = [P, P, P, P, I32, D, I32, ctypes.POINTER(Info)]
+    lib.tpcg_apply_msfem.argtypes = [P, P, P, P, I32]
+    lib.tpcg_gmres_solve.argtypes = [P, P, P, P, I32, D, I32, I32, I32, ctypes.POINTER(Info)]
     lib.tpcg_compliance_and_sensitivity.argtypes = [P, P, P, P, I32, P, P]
     lib.tpcg_filter_project.argtypes = [P, P, D, D, ctypes.POINTER(D), I32, P, P]
     lib.tpcg_filter_project_adjoint.argtypes = [P, P, D, D, ctypes.POINTER(D), I32, P, P]
@@ -254,6 +259,27 @@ class Handle:
                                      _ptr(f, torch.float64, nsys * self.n_dof),
                                      _ptr(u, torch.float64, nsys * self.n_dof), nsys, rtol, maxit,
                                      info)
+        self._check(rc, allow_warn=True)
+        return [dict(iters=i.iters, status=i.status, relres=i.relres,
+                     true_relres=i.true_relres, seconds=i.seconds) for i in info]
+
+    def apply_msfem(self, rho_phys, r, z):
+        """z = B r with the MsFEM cycle between symmetric Gauss-Seidel steps."""
+        import torch
+        nsys = r.numel() // self.n_dof
+        self._check(self.lib.tpcg_apply_msfem(self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el),
+                                              _ptr(r, torch.float64, nsys * self.n_dof),
+                                              _ptr(z, torch.float64, nsys * self.n_dof), nsys))
+        return z
+
+    def gmres_solve(self, rho_phys, f, u, rtol=1e-8, maxit=1000, restart=50, precond=PC_MSFEM_SGS):
+        import torch
+        nsys = f.numel() // self.n_dof
+        info = (Info * nsys)()
+        rc = self.lib.tpcg_gmres_solve(self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el),
+                                       _ptr(f, torch.float64, nsys * self.n_dof),
+                                       _ptr(u, torch.float64, nsys * self.n_dof), nsys, rtol, maxit,
+                                       restart, precond, info)
         self._check(rc, allow_warn=True)
         return [dict(iters=i.iters, status=i.status, relres=i.relres,
                      true_relres=i.true_relres, seconds=i.seconds) for i in info]

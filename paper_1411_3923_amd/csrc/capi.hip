@@ -206,10 +206,13 @@ void release(Handle* h) {
   void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam, h->kj,     h->eres, h->lfac,
                   h->emod,  h->twist, h->emod64, h->cfac, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
-                  h->dflag, h->build_ws};
+                  h->dflag, h->build_ws, h->gm_V, h->gm_w, h->gm_i, h->gm_flags, h->gm_out};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);
+  if (h->gm_host) hipHostFree(h->gm_host);
+  for (auto& e : h->gm_ev)
+    if (e) hipEventDestroy(e);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);
   if (h->t0) hipEventDestroy(h->t0);
@@ -392,6 +395,42 @@ extern "C" int tpcg_compliance_and_sensitivity_noalloc(const tpcg_problem* prob,
   if (e != hipSuccess) {
     fprintf(stderr, "tpcg_compliance_and_sensitivity_noalloc: %s\n", hipGetErrorString(e));
     return TPCG_EHIP;
+  }
+  return TPCG_OK;
+}
+
+// GMRES storage: the small arrays once, the Krylov basis grown to (m + 1)
+// nsys vectors when a call needs more (all or nothing each time)
+int ensure_gmres(Handle* h, int m, int nsys) {
+  if (!h->gm_w) {
+    AllocGroup a;
+    a.add(h->gm_w, gmres_small_elems());
+    a.add(h->gm_i, (size_t)(kNumState + 4) * kMaxSys);
+    a.add(h->gm_flags, (size_t)2 * kMaxSys);
+    a.add(h->gm_out, (size_t)4 * kMaxSys);
+    if (a.commit() != TPCG_OK) {
+      (void)hipGetLastError();
+      return TPCG_ENOMEM;
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->gm_host), sizeof(int) * 2 * kMaxSys) != hipSuccess ||
+        hipEventCreateWithFlags(&h->gm_ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->gm_ev[1], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return TPCG_ENOMEM;
+    }
+  }
+  if ((size_t)(m + 1) * nsys > (size_t)(h->gm_m + 1) * h->gm_nsys || !h->gm_V) {
+    if (h->gm_V) hipFree(h->gm_V);
+    h->gm_V = nullptr;
+    h->gm_m = h->gm_nsys = 0;
+    AllocGroup a;
+    a.add(h->gm_V, (size_t)(m + 1) * nsys * h->g.ndof);
+    if (a.commit() != TPCG_OK) {
+      (void)hipGetLastError();
+      return TPCG_ENOMEM;
+    }
+    h->gm_m = m;
+    h->gm_nsys = nsys;
   }
   return TPCG_OK;
 }
@@ -793,6 +832,69 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   }
   if (worst == TPCG_EINVAL) h->err = "densities must lie in [0, 1] (NaN or out-of-range value found)";
   else if (worst == TPCG_EBREAKDOWN) h->err = "PCG breakdown (p^T K p <= 0, r^T z <= 0 or NaN)";
+  else if (worst == TPCG_ENOCONV) h->err = "maxit reached before rtol";
+  return worst;
+}
+
+int tpcg_apply_msfem(tpcg_handle* hh, const double* rho_phys, const double* r, double* z,
+                     int32_t nsys) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
+  if (!rho_phys || !r || !z) return fail(hh, TPCG_EINVAL, "NULL array");
+  if (r == z) return fail(hh, TPCG_EINVAL, "r and z must be distinct");
+  if (!aligned16(r) || !aligned16(z)) return fail(hh, TPCG_EINVAL, "vectors must be 16-byte aligned");
+  if (nsys != h->nsys_built) return fail(hh, TPCG_EINVAL, "nsys differs from the build");
+  int rc = check_rho_sync(h, rho_phys, h->g.nel, nsys);
+  if (rc != TPCG_OK) return rc;
+  Gate nog = make_gate(h, kPartRR0, 0, 1, 0.0, 0);
+  launch_msfem_cycle(*h, rho_phys, r, z, nsys, nog, h->stream);
+  return check_hip(h, "tpcg_apply_msfem");
+}
+
+int tpcg_gmres_solve(tpcg_handle* hh, const double* rho_phys, const double* f, double* u,
+                     int32_t nsys, double rtol, int32_t maxit, int32_t restart, int32_t precond,
+                     tpcg_info* info) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
+  if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
+  if (!rho_phys || !f || !u || !info) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (!aligned16(f) || !aligned16(u)) return fail(hh, TPCG_EINVAL, "vectors must be 16-byte aligned");
+  if (nsys != h->nsys_built) return fail(hh, TPCG_EINVAL, "nsys differs from the build");
+  if (!(rtol > 0.0) || maxit < 0) return fail(hh, TPCG_EINVAL, "rtol must be > 0 and maxit >= 0");
+  if (restart < 1 || restart > kGmMaxRestart)
+    return fail(hh, TPCG_EINVAL, "restart must lie in 1..64");
+  if (precond != TPCG_PC_ADDITIVE && precond != TPCG_PC_MSFEM_SGS)
+    return fail(hh, TPCG_EINVAL, "unknown preconditioner kind");
+  int rc = check_rho_sync(h, rho_phys, h->g.nel, nsys);
+  if (rc != TPCG_OK) return rc;
+  if (ensure_gmres(h, restart, nsys) != TPCG_OK)
+    return fail(hh, TPCG_ENOMEM, "GMRES basis allocation failed");
+  hipStream_t st = h->stream;
+  hipEventRecord(h->t0, st);
+  double hout[4 * kMaxSys];
+  rc = gmres_solve(*h, rho_phys, f, u, nsys, rtol, maxit, restart, precond, hout);
+  hipEventRecord(h->t1, st);
+  hipEventSynchronize(h->t1);
+  const int hrc = check_hip(h, "tpcg_gmres_solve");
+  if (hrc != TPCG_OK) return hrc;
+  if (rc != TPCG_OK) return fail(hh, rc, "GMRES: HIP error while polling");
+  float ms = 0.0f;
+  hipEventElapsedTime(&ms, h->t0, h->t1);
+  int worst = TPCG_OK;
+  for (int s = 0; s < nsys; ++s) {
+    info[s].iters = (int)hout[4 * s + 0];
+    info[s].status = (int)hout[4 * s + 1];
+    info[s].relres = hout[4 * s + 2];
+    info[s].true_relres = hout[4 * s + 3];
+    info[s].seconds = ms * 1e-3;
+    const int st_s = info[s].status;
+    if (st_s < 0 && (worst >= 0 || st_s < worst)) worst = st_s;
+    else if (worst == TPCG_OK && st_s > 0) worst = st_s;
+  }
+  if (worst == TPCG_EBREAKDOWN) h->err = "GMRES breakdown (NaN or a zero rotation)";
   else if (worst == TPCG_ENOCONV) h->err = "maxit reached before rtol";
   return worst;
 }

@@ -465,4 +465,19 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   if (cap && prof_it >= 0) ++h.cap_n;
 }
 
+void launch_coarse_only(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
+  const Geometry& g = h.g;
+  if (h.mixed) restrict_launch<float>(h, r, nsys, gate, st);
+  else restrict_launch<double>(h, r, nsys, gate, st);
+  if (h.cpk) {
+    const int T = coarse_tiles(g.nt);
+    hipLaunchKernelGGL(k_coarse_gemv_tiles, dim3(T * (T + 1) / 2, nsys), dim3(kThreads), 0, st, g,
+                       h.cpk, h.yc, h.cpart, gate);
+    hipLaunchKernelGGL(k_coarse_gemv_sum, dim3((g.nt + kThreads - 1) / kThreads, nsys),
+                       dim3(kThreads), 0, st, g, h.cpart, h.xc, gate);
+  } else {
+    coarse_launch(h, nsys, gate, st);
+  }
+}
+
 }  // namespace tpcg

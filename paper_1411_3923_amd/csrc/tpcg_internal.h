@@ -17,6 +17,8 @@ constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxParts = 2048;      // reduction partials per system and vector kernel
 constexpr int kMaxSys = 4;           // systems solved together
 constexpr int kMaxK = 16;            // coarse vectors per subdomain
+constexpr int kGmMaxRestart = 64;    // GMRES: longest cycle
+constexpr int kGmMaxVec = kGmMaxRestart + 1;
 constexpr int kMaxSub = 16;          // eigensolver subspace width
 constexpr int kMaxNb = 96;           // largest block of the block-tridiagonal kernels
 constexpr int kDenseCoarse = 12288;  // coarse dimensions up to this keep a dense K_c^-1
@@ -142,6 +144,19 @@ struct Handle {
   int cap_n = 0;
   int last_graph_chunks = 0;
   int build_gen = 0;                 // preconditioner builds so far (part of the graphs' key)
+
+  // restarted GMRES: the Krylov basis [gm_m + 1][gm_nsys][ndof] (allocated by
+  // the first solve, grown when a longer cycle or more systems ask for it),
+  // the small arrays (Hessenberg matrix, rotations, partial sums), per-system
+  // ints (the gate state, then counters), the flags the host polls
+  double* gm_V = nullptr;
+  int gm_m = 0, gm_nsys = 0;
+  double* gm_w = nullptr;
+  int* gm_i = nullptr;
+  int* gm_flags = nullptr;           // device [2][kMaxSys]
+  int* gm_host = nullptr;            // pinned host [2][kMaxSys]
+  double* gm_out = nullptr;          // device [4][kMaxSys]
+  hipEvent_t gm_ev[2] = {nullptr, nullptr};
 
   // optional event timing of the block-solve launches inside pcg_solve
   int prof_on = 0;
@@ -308,6 +323,18 @@ void launch_summary(const Handle& h, const double* f, int nsys, const Gate& gate
                     double* out /*dev [nsys][4]*/, hipStream_t st);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 
+// gmres.hip: restarted GMRES (cycle length m) with the MsFEM cycle or the
+// additive Schwarz preconditioner; hout [4][nsys]: iterations, status,
+// preconditioned relative residual estimate, true relative residual
+size_t gmres_small_elems();
+int gmres_solve(Handle& h, const double* rho, const double* f, double* u, int nsys, double rtol,
+                int maxit, int m, int precond, double* hout);
+// gmres.hip: xout = B rin with the MsFEM cycle (h.q and h.z are work vectors)
+void launch_msfem_cycle(Handle& h, const double* rho, const double* rin, double* xout, int nsys,
+                        const Gate& gate, hipStream_t st);
+// precond.hip: x_c = K_c^-1 Phi^T r into h.xc for every running system (the
+// coarse branch alone, on stream st)
+void launch_coarse_only(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st);
 // precond.hip: z = M^-1 r, gated; partials of r.z into rz_slot (and r.z_old into kPartRZO)
 // prof_it >= -1 records events around the block-solve launch when profiling is on
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,

@@ -28,3 +28,22 @@ def host(t):
 
 def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def gpu_basis(h, p):
+    """The handle's exported coarse basis as a sparse [n_dof][n_sub k] matrix
+    (subdomain j's column block j, its box DOFs in the handle's local order)."""
+    import scipy.sparse as sp
+    from oracle import schwarz
+    phi = host(h.export_coarse_basis()[0])
+    k = phi.shape[2]
+    rows, cols, vals = [], [], []
+    for j in range(p.n_sub):
+        nodes = schwarz.subdomain_nodes(p, j)
+        dofs = (p.dim * nodes[:, None] + np.arange(p.dim)[None, :]).ravel()
+        for m in range(k):
+            rows.append(dofs)
+            cols.append(np.full(dofs.size, j * k + m))
+            vals.append(phi[j][:, m])
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(p.n_dof, p.n_sub * k)).tocsc()
