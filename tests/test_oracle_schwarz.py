@@ -141,6 +141,20 @@ def test_contrast_independent_iterations():
     assert one[0][1] > 1.5 * its[-1]                     # the coarse space is doing work
 
 
+def test_one_level_grows_with_mesh_two_level_does_not():
+    # at a fixed cell size the one-level method needs more iterations as the
+    # mesh (the number of cells) grows; the coarse space removes that growth
+    two, one = [], []
+    for nx in (32, 64, 128):
+        p = dataclasses.replace(W.mbb_64x32(), nel=(nx, nx // 2, 1))
+        rho = W.design_field(p)
+        args = (p, [rho], rho, W.load_vector(p), W.fixed_mask(p))
+        two.append(schwarz.solve_pcg(*args, rtol=1e-8)[0][1])
+        one.append(schwarz.solve_pcg(*args, rtol=1e-8, coarse=False)[0][1])
+    assert one[2] > 4 * one[0] and one[1] > 2 * one[0], one
+    assert two[2] < 1.5 * two[0], two
+
+
 # ---------------------------------------------------------------------------
 # Partition geometry and the partition-of-unity weighting of the coarse basis
 # (Sec. 2.4: phi = psi chi with sum_i chi_i = 1)
