@@ -536,6 +536,53 @@ def loop_bytes(nsys=3, nelx=1024, nely=512, sub=32, k=6):
     }
 
 
+def summarize_mfma(csv_path, command, out, title):
+    """Matrix-core and vector FP64 work of the dense setup kernels from one
+    rocprofv3 --pmc run (SQ_INSTS_VALU_MFMA_MOPS_F64: units of 512 flops;
+    SQ_INSTS_VALU_FLOPS_FP64; SQ_VALU_MFMA_BUSY_CYCLES against GRBM_GUI_ACTIVE
+    over the chip's 1024 SIMDs), durations from the same run's timestamps."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(csv_path)):
+        k = short_name(r["Kernel_Name"])
+        d = per.setdefault(k, {})
+        e = d.setdefault(int(r["Dispatch_Id"]), {"us": (int(r["End_Timestamp"]) -
+                                                         int(r["Start_Timestamp"])) / 1e3})
+        e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    rows = []
+    for k, d in per.items():
+        ds = list(d.values())
+        n = len(ds)
+        us = sum(x["us"] for x in ds) / n
+        mf = sum(x.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for x in ds) * 512 / n
+        vf = sum(x.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) for x in ds) / n
+        busy = sum(x.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for x in ds)
+        act = sum(x.get("GRBM_GUI_ACTIVE", 0.0) for x in ds)
+        # GRBM_GUI_ACTIVE comes summed over the 8 XCDs, each counting the
+        # same active cycles: one XCD's count is the kernel's active time
+        util = 100.0 * busy / (act / 8 * 1024) if act > 0 else 0.0
+        if us * n < 200 and mf == 0:
+            continue
+        rows.append((us * n, k, n, us, mf, vf, util))
+    rows.sort(reverse=True)
+    lines = [f"# FP64 matrix-core use of the setup kernels: {title}", "",
+             "Command (on one MI355X, from the repository root):", "", "    " + command, "",
+             "Per dispatch (mean over the run's dispatches of the kernel). MFMA flops = "
+             "SQ_INSTS_VALU_MFMA_MOPS_F64 x 512; achieved = MFMA flops / duration, against "
+             "the 78.6 TFLOP/s FP64 matrix-core peak; MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / "
+             "(active cycles x 1024 SIMDs), active cycles = GRBM_GUI_ACTIVE / 8 (the counter "
+             "comes summed over the 8 XCDs). The VALU column is SQ_INSTS_VALU_FLOPS_FP64 as "
+             "the counter reports it. Durations come from the counter run (kernels "
+             "serialised).", "",
+             "| kernel | dispatches | avg us | MFMA GFLOP | MFMA TFLOP/s | % of 78.6 "
+             "| MFMA busy % | VALU FP64 counter (G) |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for _, k, n, us, mf, vf, util in rows:
+        tf = mf / (us * 1e-6) / 1e12 if us > 0 else 0.0
+        lines.append(f"| {k} | {n} | {us:.1f} | {mf / 1e9:.3f} | {tf:.2f} | "
+                     f"{100 * tf / 78.6:.1f} | {util:.1f} | {vf / 1e9:.3f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 def summarize_loop(fetch_csv, write_csv, trace_csv, command, out):
     """Per-kernel HBM traffic and bandwidth of the PCG loop over the launches
     in which all three systems run: bytes from two rocprofv3 --pmc runs of one
@@ -628,6 +675,8 @@ def main():
                     help="write the HBM traffic of the roofline kernel from two --pmc runs and exit")
     ap.add_argument("--summarize-loop", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "TRACE_CSV"),
                     help="write the per-kernel PCG-loop traffic table and exit")
+    ap.add_argument("--summarize-mfma", metavar="COUNTER_CSV",
+                    help="write the matrix-core table of a rocprofv3 --pmc run and exit")
     ap.add_argument("--command", default="", help="command recorded in a summary")
     ap.add_argument("--title", default="1024x512 cantilever, 3 realisations, FP64")
     ap.add_argument("--bench-json", default=None, help="bench line of the traced run")
@@ -635,6 +684,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.command, args.out, args.title, args.bench_json)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(args.summarize_mfma, args.command, args.out, args.title)
         return
     if args.summarize_loop:
         summarize_loop(*args.summarize_loop, args.command, args.out)
