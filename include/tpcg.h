@@ -455,6 +455,30 @@ int tpcg_profile_block_solves(const tpcg_handle* h, double* out3);
  * the number of chunks the last solve replayed from graphs.
  */
 int tpcg_set_graphs(tpcg_handle* h, int32_t on);
+
+/*
+ * Autotuning of the launch choices that leave results bit for bit the same
+ * (off by default). PCG: graph replay on or off and the chunk length between
+ * convergence polls (4 or 8 iterations), measured over the handle's first
+ * solves (one warm-up, then each candidate twice; graph candidates only when
+ * profiling is off and the dense coarse inverse is in use), ranked by the
+ * best time per iteration; while tuning, tpcg_set_graphs is overridden.
+ * GMRES: Krylov vectors per workgroup of the dot-product kernel (4, 8 or 16),
+ * timed on the handle's basis at the first tpcg_gmres_solve. Choices are
+ * stored in a text file keyed by device and problem ($TPCG_TUNE_CACHE, else
+ * $XDG_CACHE_HOME/tpcg/tune.txt, else $HOME/.cache/tpcg/tune.txt; nothing is
+ * stored if it cannot be written); a handle whose key is stored takes the
+ * choice at its first solve. Not an optimisation of the numerics: every
+ * candidate computes the same bits.
+ */
+int tpcg_set_autotune(tpcg_handle* h, int32_t on);
+
+/*
+ * State of the autotuner, out (host [8]): on, PCG choice made, taken from
+ * the cache, graphs on, poll interval, GMRES choice made, GMRES vectors per
+ * workgroup, solves measured so far.
+ */
+int tpcg_query_tune(const tpcg_handle* h, int32_t* out);
 int tpcg_last_solve_graph_chunks(const tpcg_handle* h);
 
 /*

@@ -78,7 +78,7 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_nondiscreteness", "tpcg_refactor", "tpcg_export_local_record", "tpcg_server_create", "tpcg_server_session_bytes",
            "tpcg_server_open", "tpcg_server_submit", "tpcg_server_wait", "tpcg_server_test",
            "tpcg_server_close", "tpcg_server_free_bytes", "tpcg_server_destroy",
-           "tpcg_apply_msfem", "tpcg_gmres_solve"]
+           "tpcg_apply_msfem", "tpcg_gmres_solve", "tpcg_set_autotune", "tpcg_query_tune"]
 
 
 def load_library(path: str | None = None):
@@ -99,6 +99,8 @@ def load_library(path: str | None = None):
     lib.tpcg_apply_precond.argtypes = [P, P, P, I32]
     lib.tpcg_pcg_solve.argtypes = [P, P, P, P, I32, D, I32, ctypes.POINTER(Info)]
     lib.tpcg_apply_msfem.argtypes = [P, P, P, P, I32]
+    lib.tpcg_set_autotune.argtypes = [P, I32]
+    lib.tpcg_query_tune.argtypes = [P, ctypes.POINTER(I32)]
     lib.tpcg_gmres_solve.argtypes = [P, P, P, P, I32, D, I32, I32, I32, ctypes.POINTER(Info)]
     lib.tpcg_compliance_and_sensitivity.argtypes = [P, P, P, P, I32, P, P]
     lib.tpcg_filter_project.argtypes = [P, P, D, D, ctypes.POINTER(D), I32, P, P]
@@ -262,6 +264,16 @@ class Handle:
         self._check(rc, allow_warn=True)
         return [dict(iters=i.iters, status=i.status, relres=i.relres,
                      true_relres=i.true_relres, seconds=i.seconds) for i in info]
+
+    def set_autotune(self, on=True):
+        self._check(self.lib.tpcg_set_autotune(self.h, 1 if on else 0))
+
+    def query_tune(self):
+        out = (ctypes.c_int32 * 8)()
+        self._check(self.lib.tpcg_query_tune(self.h, out))
+        keys = ("on", "pcg_decided", "from_cache", "graphs", "poll", "gmres_decided",
+                "gmres_chunk", "solves_measured")
+        return dict(zip(keys, list(out)))
 
     def apply_msfem(self, rho_phys, r, z):
         """z = B r with the MsFEM cycle between symmetric Gauss-Seidel steps."""

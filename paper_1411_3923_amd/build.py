@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtpcg.so")
 SOURCES = ["element.cpp", "matvec.hip", "vectors.hip", "precond.hip", "local.hip", "factor.hip", "big.hip", "setup.hip",
-           "density.hip", "gmres.hip", "capi.hip", "server.hip"]
+           "density.hip", "gmres.hip", "tune.hip", "capi.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

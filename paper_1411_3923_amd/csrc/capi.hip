@@ -16,7 +16,6 @@ using namespace tpcg;
 
 namespace {
 
-constexpr int kPollEvery = 4;   // PCG iterations between convergence polls
 
 int fail(tpcg_handle* hh, int code, const std::string& msg) {
   if (hh) reinterpret_cast<Handle*>(hh)->err = msg;
@@ -621,9 +620,11 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   if (!aligned16(f) || !aligned16(u)) return fail(hh, TPCG_EINVAL, "vectors must be 16-byte aligned");
   if (nsys != h->nsys_built) return fail(hh, TPCG_EINVAL, "nsys differs from the build");
   if (!(rtol > 0.0) || maxit < 0) return fail(hh, TPCG_EINVAL, "rtol must be > 0 and maxit >= 0");
+  tune_before_solve(*h);
   hipStream_t st = h->stream;
   const double tol2 = rtol * rtol;
   const int flexible = h->mixed;
+  const int pe = std::min(std::max(h->poll_every, 1), kMaxPoll);   // iterations per chunk
   const auto wall0 = std::chrono::steady_clock::now();
   hipEventRecord(h->t0, st);
   // r0 = P (f - K u0); z0 = M^-1 r0; p0 = z0
@@ -668,7 +669,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
     if (!fused) launch_update_p(*h, nsys, gn, 0, st);
   };
-  // Chunks after the first replay a captured graph of kPollEvery iterations
+  // Chunks after the first replay a captured graph of poll_every iterations
   // (a chunk starts at an even iteration with the direction buffers in their
   // initial order, so one graph serves every chunk); the block coarse solve
   // on the side stream stays eager, and so do solves that time their local
@@ -679,7 +680,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
                                (double)reinterpret_cast<uintptr_t>(f),
                                (double)reinterpret_cast<uintptr_t>(u),
                                (double)nsys, (double)maxit, tol2, (double)flexible,
-                               (double)h->prof_on, (double)h->build_gen};
+                               (double)h->prof_on, (double)h->build_gen, (double)pe};
     if (key != h->gkey) {
       drop_graphs(h);
       h->gkey = key;
@@ -703,7 +704,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     h->cap_n = 0;
     double* pc = h->p;
     double* pn = h->p2;
-    for (int off = 0; off < kPollEvery; ++off) iteration(off, true, 0, off, pc, pn, cs);
+    for (int off = 0; off < pe; ++off) iteration(off, true, 0, off, pc, pn, cs);
     h->cap_ev = nullptr;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
@@ -729,7 +730,7 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
   auto harvest = [&](int g) {
     if (graph_it0[g] < 0) return;
     if (h->prof_on)
-      for (int k = 0; k < kPollEvery; ++k) {
+      for (int k = 0; k < pe; ++k) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, h->gprof_ev[g][2 * k], h->gprof_ev[g][2 * k + 1]) == hipSuccess)
           gprof.emplace_back(graph_it0[g] + k, ms);
@@ -759,12 +760,12 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
       if (h->gexec[g] && hipGraphLaunch(h->gexec[g], st) == hipSuccess) {
         graphed = true;
         graph_it0[g] = it0;
-        it = it0 + kPollEvery;
+        it = it0 + pe;
         ++h->last_graph_chunks;
       }
     }
     if (!graphed)
-      for (int c = 0; c < kPollEvery && it < maxit; ++c, ++it)
+      for (int c = 0; c < pe && it < maxit; ++c, ++it)
         iteration(it, false, it == 0, it, pcur, pnext, st);
     const int slot = chunk & 1;
     Gate gp = make_gate(h, (it & 1) ? kPartRR1 : kPartRR0, it, maxit, tol2, 1);
@@ -830,6 +831,11 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     }
     for (const auto& e : gprof) account(e.first, e.second);
   }
+  {
+    int most = 0;
+    for (int s = 0; s < nsys; ++s) most = std::max(most, info[s].iters);
+    tune_after_solve(*h, ms, most);
+  }
   if (worst == TPCG_EINVAL) h->err = "densities must lie in [0, 1] (NaN or out-of-range value found)";
   else if (worst == TPCG_EBREAKDOWN) h->err = "PCG breakdown (p^T K p <= 0, r^T z <= 0 or NaN)";
   else if (worst == TPCG_ENOCONV) h->err = "maxit reached before rtol";
@@ -872,6 +878,7 @@ int tpcg_gmres_solve(tpcg_handle* hh, const double* rho_phys, const double* f, d
   if (rc != TPCG_OK) return rc;
   if (ensure_gmres(h, restart, nsys) != TPCG_OK)
     return fail(hh, TPCG_ENOMEM, "GMRES basis allocation failed");
+  tune_gmres(*h, nsys, restart);
   hipStream_t st = h->stream;
   hipEventRecord(h->t0, st);
   double hout[4 * kMaxSys];
@@ -1094,6 +1101,27 @@ int tpcg_set_graphs(tpcg_handle* hh, int32_t on) {
   if (!h) return TPCG_EINVAL;
   h->graphs_on = on ? 1 : 0;
   if (!on) drop_graphs(h);
+  return TPCG_OK;
+}
+
+int tpcg_set_autotune(tpcg_handle* hh, int32_t on) {
+  Handle* h = H(hh);
+  if (!h) return TPCG_EINVAL;
+  h->tune_on = on ? 1 : 0;
+  return TPCG_OK;
+}
+
+int tpcg_query_tune(const tpcg_handle* hh, int32_t* out) {
+  const Handle* h = H(hh);
+  if (!h || !out) return TPCG_EINVAL;
+  out[0] = h->tune_on;
+  out[1] = h->tune_decided;
+  out[2] = h->tune_from_cache;
+  out[3] = h->graphs_on;
+  out[4] = h->poll_every;
+  out[5] = h->tune_gm_decided;
+  out[6] = h->gm_chunk;
+  out[7] = h->tune_seen;
   return TPCG_OK;
 }
 

@@ -28,8 +28,6 @@ namespace tpcg {
 
 namespace {
 
-constexpr int kGmChunk = 8;   // basis vectors per workgroup of the dot-product kernel
-
 // layout of the small device arrays (doubles)
 constexpr size_t kGmH = 0;                                               // [sys][col][kGmMaxVec]
 constexpr size_t kGmCS = kGmH + (size_t)kMaxSys * kGmMaxRestart * kGmMaxVec;
@@ -255,12 +253,16 @@ __global__ __launch_bounds__(kThreads) void k_gm_zero(double* __restrict__ x, in
     xs[i] = 0.0;
 }
 
-// partials of V_i . w for i in [kGmChunk z, kGmChunk z + kGmChunk) and < nvec.
-// V_i of system s at V + (i nsys + s) n; w [nsys][n].
+// partials of V_i . w for i in [CH z, CH z + CH) and < nvec. V_i of system s
+// at V + (i nsys + s) n; w [nsys][n]. Each partial covers the same entries in
+// the same order whatever CH is (the grouping only decides which workgroup
+// forms it).
+template <int CH>
 __global__ __launch_bounds__(kThreads) void k_gm_dots(const double* __restrict__ V, int nvec,
                                                       int nsys, const double* __restrict__ w,
                                                       double* __restrict__ part, int64_t n,
                                                       Gate gate) {
+  constexpr int kGmChunk = CH;
   __shared__ double sh[4];
   const int sys = blockIdx.y;
   if (!gate_running(gate, sys)) return;
@@ -531,7 +533,50 @@ int vec_parts(const Geometry& g) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, kMaxParts));
 }
 
+void launch_dots(const Handle& h, int chunk, const double* V, int nv, int nsys, const double* w,
+                 double* part, int np, const Gate& gate, hipStream_t st) {
+  const int64_t n = h.g.ndof;
+#define TPCG_DOTS(CH)                                                                          \
+  hipLaunchKernelGGL(k_gm_dots<CH>, dim3(np, nsys, (nv + CH - 1) / CH), dim3(kThreads), 0, st, \
+                     V, nv, nsys, w, part, n, gate)
+  if (chunk == 4) TPCG_DOTS(4);
+  else if (chunk == 16) TPCG_DOTS(16);
+  else TPCG_DOTS(8);
+#undef TPCG_DOTS
+}
+
 }  // namespace
+
+double gmres_time_dots(Handle& h, int nsys, int nv, int chunk) {
+  const int np = vec_parts(h.g);
+  Gate all{};
+  all.parts = h.parts;
+  all.istate = h.gm_i;
+  all.rr_slot = kPartRR0;
+  all.maxit = INT_MAX;
+  all.enabled = 0;
+  hipStream_t st = h.stream;
+  const double* V = h.gm_V;
+  const double* w = h.gm_V + (size_t)nv * nsys * h.g.ndof;   // vector nv of the basis
+  launch_dots(h, chunk, V, nv, nsys, w, h.gm_w + kGmPart, np, all, st);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) hipEventDestroy(a);
+    (void)hipGetLastError();
+    return -1.0;
+  }
+  hipEventRecord(a, st);
+  constexpr int kReps = 3;
+  for (int r = 0; r < kReps; ++r)
+    launch_dots(h, chunk, V, nv, nsys, w, h.gm_w + kGmPart, np, all, st);
+  hipEventRecord(b, st);
+  hipEventSynchronize(b);
+  float ms = -1.0f;
+  hipEventElapsedTime(&ms, a, b);
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms > 0.0f ? ms / kReps : -1.0;
+}
 
 size_t gmres_small_elems() {
   return kGmPart2 + (size_t)kMaxSys * 2 * kMaxParts;
@@ -608,8 +653,7 @@ int gmres_solve(Handle& h, const double* rho, const double* f, double* u, int ns
     else launch_precond(h, rin, xout, nsys, run, kPartAux, -2, 0, st);
   };
   auto norm_into_slot0 = [&](const double* v) {
-    hipLaunchKernelGGL(k_gm_dots, dim3(np, nsys, 1), dim3(kThreads), 0, st, v, 1, nsys, v,
-                       w + kGmPart, n, run);
+    launch_dots(h, h.gm_chunk, v, 1, nsys, v, w + kGmPart, np, run, st);
   };
   hipLaunchKernelGGL(k_gm_reset, dim3(1), dim3(64), 0, st, nsys, istate, gi);
   // the preconditioned load and its norm
@@ -635,16 +679,13 @@ int gmres_solve(Handle& h, const double* rho, const double* f, double* u, int ns
       launch_apply_K(h, rho, V(j), h.p, nsys, -1, run, st);
       apply_B(h.p, wj);
       const int nv = j + 1;
-      const dim3 dgrid(np, nsys, (nv + kGmChunk - 1) / kGmChunk);
       // classical Gram-Schmidt, twice
-      hipLaunchKernelGGL(k_gm_dots, dgrid, dim3(kThreads), 0, st, V(0), nv, nsys, wj, w + kGmPart,
-                         n, run);
+      launch_dots(h, h.gm_chunk, V(0), nv, nsys, wj, w + kGmPart, np, run, st);
       hipLaunchKernelGGL(k_gm_sum, dim3(nv, nsys), dim3(kThreads), 0, st, w + kGmPart, np,
                          w + kGmHA, kGmMaxVec, run);
       hipLaunchKernelGGL(k_gm_orth, vgrid, dim3(kThreads), 0, st, V(0), nv, nsys, w + kGmHA, wj,
                          nullptr, n, run);
-      hipLaunchKernelGGL(k_gm_dots, dgrid, dim3(kThreads), 0, st, V(0), nv, nsys, wj, w + kGmPart,
-                         n, run);
+      launch_dots(h, h.gm_chunk, V(0), nv, nsys, wj, w + kGmPart, np, run, st);
       hipLaunchKernelGGL(k_gm_sum, dim3(nv, nsys), dim3(kThreads), 0, st, w + kGmPart, np,
                          w + kGmHB, kGmMaxVec, run);
       hipLaunchKernelGGL(k_gm_orth, vgrid, dim3(kThreads), 0, st, V(0), nv, nsys, w + kGmHB, wj,

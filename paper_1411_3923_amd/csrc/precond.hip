@@ -1,13 +1,12 @@
 // Two-level additive Schwarz preconditioner application (Sec. 2.4.2 with the
 // additive form; coarse space of Sec. 2.4):
 //   z = sum_j R_j^T A_j^-1 R_j r + Phi K_c^-1 Phi^T r
-// in five launches:
+// in four launches:
 //   1. restriction y_c = Phi^T r            (one workgroup per subdomain)
 //   2. local solves A_j^-1 R_j r for every (system, subdomain)   } concurrent:
 //   3. coarse solve x_c = K_c^-1 y_c                             } forked stream
-//   4. zloc_j += Phi_j x_c,j                (one workgroup per subdomain)
-//   5. extension z(n) = sum_{j owns n} zloc_j(n), with the fused partial sums
-//      of r.z (and r.z_old for the flexible beta).
+//   4. extension z(n) = sum_{j owns n} (zloc_j(n) + (Phi_j x_c,j)(n)), with
+//      the fused partial sums of r.z (and r.z_old for the flexible beta).
 #include "btri.h"
 
 namespace tpcg {
@@ -15,7 +14,6 @@ namespace tpcg {
 namespace {
 
 constexpr int kSubThreads = 256;    // restriction: one workgroup per subdomain
-constexpr int kAddChunk = 256;      // coarse addition: box DOFs per workgroup
 
 // One workgroup per subdomain, all running systems together (Phi, mode-major,
 // read once); KM >= k bounds the accumulators.
@@ -219,59 +217,14 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemv_sum(Geometry g,
   xc[(size_t)sys * nt + r] = s;
 }
 
-// zloc_j += Phi_j x_c,j in place for every running system: workgroup
-// (j, chunk) updates kAddChunk box DOFs of subdomain j, one per thread; Phi
-// (mode-major, [nsub][k][nloc]) read once for all systems, every access
-// contiguous.
-template <typename T, typename P, int KM>
-__global__ __launch_bounds__(kAddChunk) void k_coarse_add(Geometry g, T* __restrict__ zloc,
-                                                          const P* __restrict__ phim,
-                                                          const double* __restrict__ xc, int nsys,
-                                                          Gate gate) {
-  unsigned run = 0;
-  for (int sys = 0; sys < nsys; ++sys)
-    if (gate_running(gate, sys)) run |= 1u << sys;
-  if (!run) return;
-  const int j = blockIdx.x;
-  const int l = blockIdx.y * kAddChunk + threadIdx.x;
-  if (l >= g.nloc) return;
-  int jx, jy, jz;
-  sub_coords(g, j, jx, jy, jz);
-  const int k = g.k;
-  const int ci = coarse_index(g, jx, jy, jz, 0);
-  double xv[kMaxSys][KM];
-#pragma unroll
-  for (int q = 0; q < kMaxSys; ++q)
-#pragma unroll
-    for (int m = 0; m < KM; ++m)
-      xv[q][m] = (m < k && ((run >> q) & 1u)) ? xc[(size_t)q * g.nt + ci + m] : 0.0;
-  const P* ph = phim + (size_t)j * k * g.nloc;
-  const size_t zstride = (size_t)g.nsub * g.nloc;
-  T* zj = zloc + (size_t)j * g.nloc;
-  double a[kMaxSys];
-#pragma unroll
-  for (int q = 0; q < kMaxSys; ++q) a[q] = 0.0;
-#pragma unroll
-  for (int m = 0; m < KM; ++m)
-    if (m < k) {
-      const double p = (double)ph[(size_t)m * g.nloc + l];
-#pragma unroll
-      for (int q = 0; q < kMaxSys; ++q) a[q] += p * xv[q][m];
-    }
-#pragma unroll
-  for (int q = 0; q < kMaxSys; ++q)
-    if ((run >> q) & 1u) {
-      T* zq = zj + q * zstride + l;
-      *zq = (T)((double)*zq + a[q]);
-    }
-}
-
-// z(n) = P sum_{j owns n} zloc_j(n) for every running system, with the fused
-// partial sums of r.z (and r.z_old for the flexible beta). zloc already holds
-// the coarse part.
-template <typename T, int D>
+// z(n) = P sum_{j owns n} (zloc_j(n) + (Phi_j x_c,j)(n)) for every running
+// system: the local solutions and the prolonged coarse solution in one pass
+// (Phi mode-major, [nsub][k][nloc], read along box rows), with the fused
+// partial sums of r.z (and r.z_old for the flexible beta).
+template <typename T, int D, int KM>
 __global__ __launch_bounds__(kThreads) void k_extend(
     Geometry g, const double* __restrict__ r, double* __restrict__ z, const T* __restrict__ zloc,
+    const T* __restrict__ phim, const double* __restrict__ xc,
     const uint8_t* __restrict__ fixed, double* __restrict__ parts, int rz_slot, int flexible,
     int nsys, Gate gate) {
   __shared__ double sh[4];
@@ -316,11 +269,27 @@ __global__ __launch_bounds__(kThreads) void k_extend(
           const int j = jx + g.gx * (jy + g.gy * jz);
           const int ln = (ix - s * jx) + g.bn * ((iy - s * jy) + g.bn * (iz - s * jz));
           const T* zj = zloc + (size_t)j * g.nloc + (size_t)d * ln;
+          const T* pj = phim + (size_t)j * g.k * g.nloc + (size_t)d * ln;
+          const double* xj = xc + coarse_index(g, jx, jy, jz, 0);
 #pragma unroll
           for (int q = 0; q < kMaxSys; ++q)
             if ((run >> q) & 1u)
 #pragma unroll
               for (int c = 0; c < D; ++c) acc[q][c] += (double)zj[q * zstride + c];
+#pragma unroll
+          for (int m = 0; m < KM; ++m) {
+            if (m >= g.k) break;
+            double pv[D];
+#pragma unroll
+            for (int c = 0; c < D; ++c) pv[c] = (double)pj[(size_t)m * g.nloc + c];
+#pragma unroll
+            for (int q = 0; q < kMaxSys; ++q)
+              if ((run >> q) & 1u) {
+                const double xv = xj[(size_t)q * g.nt + m];
+#pragma unroll
+                for (int c = 0; c < D; ++c) acc[q][c] += pv[c] * xv;
+              }
+          }
         }
 #pragma unroll
     for (int c = 0; c < D; ++c) {
@@ -395,26 +364,25 @@ void restrict_launch(Handle& h, const double* r, int nsys, const Gate& gate, hip
                        h.yc, nsys, gate);
 }
 
-// zloc += Phi x_c, then z = P sum_j R_j^T zloc_j with the r.z partials
+// z = P sum_j R_j^T (zloc_j + Phi_j x_c,j) with the r.z partials
 template <typename T>
 void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& gate, int rz_slot,
                    int flexible, hipStream_t st) {
   const Geometry& g = h.g;
   const T* pm = reinterpret_cast<const T*>(h.phim);
-  T* zl = reinterpret_cast<T*>(h.zloc);
-  const dim3 agrid(g.nsub, (g.nloc + kAddChunk - 1) / kAddChunk);
-  if (g.k <= 8)
-    hipLaunchKernelGGL((k_coarse_add<T, T, 8>), agrid, dim3(kAddChunk), 0, st, g, zl, pm, h.xc,
-                       nsys, gate);
-  else
-    hipLaunchKernelGGL((k_coarse_add<T, T, kMaxK>), agrid, dim3(kAddChunk), 0, st, g, zl, pm,
-                       h.xc, nsys, gate);
-  if (g.dim == 2)
-    hipLaunchKernelGGL((k_extend<T, 2>), dim3(parts_for(g.nnodes)), dim3(kThreads), 0, st, g, r, z,
-                       zl, h.fixed, h.parts, rz_slot, flexible, nsys, gate);
-  else
-    hipLaunchKernelGGL((k_extend<T, 3>), dim3(parts_for(g.nnodes)), dim3(kThreads), 0, st, g, r, z,
-                       zl, h.fixed, h.parts, rz_slot, flexible, nsys, gate);
+  const T* zl = reinterpret_cast<const T*>(h.zloc);
+  const dim3 grid(parts_for(g.nnodes));
+#define TPCG_EXTEND(D, KM)                                                                     \
+  hipLaunchKernelGGL((k_extend<T, D, KM>), grid, dim3(kThreads), 0, st, g, r, z, zl, pm, h.xc,  \
+                     h.fixed, h.parts, rz_slot, flexible, nsys, gate)
+  if (g.dim == 2) {
+    if (g.k <= 8) TPCG_EXTEND(2, 8);
+    else TPCG_EXTEND(2, kMaxK);
+  } else {
+    if (g.k <= 8) TPCG_EXTEND(3, 8);
+    else TPCG_EXTEND(3, kMaxK);
+  }
+#undef TPCG_EXTEND
 }
 
 }  // namespace

@@ -253,6 +253,8 @@ int tpcg_server_open(tpcg_server* sv, const tpcg_problem* prob, const uint8_t* f
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) rc = TPCG_EHIP;
   }
   if (rc == TPCG_OK) rc = tpcg_build_partition(prob, fixed_mask, s->stream, &s->h);
+  // a session solves many times: its handle tunes its launches (bitwise neutral)
+  if (rc == TPCG_OK) tpcg_set_autotune(s->h, 1);
   if (rc == TPCG_OK) {
     void* p[4] = {nullptr, nullptr, nullptr, nullptr};
     const size_t n[4] = {(size_t)s->nel, (size_t)nsys * s->nel, (size_t)nsys * s->nel, 1};

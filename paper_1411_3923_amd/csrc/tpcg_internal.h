@@ -17,6 +17,7 @@ constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
 constexpr int kMaxParts = 2048;      // reduction partials per system and vector kernel
 constexpr int kMaxSys = 4;           // systems solved together
 constexpr int kMaxK = 16;            // coarse vectors per subdomain
+constexpr int kMaxPoll = 8;          // longest PCG chunk between convergence polls
 constexpr int kGmMaxRestart = 64;    // GMRES: longest cycle
 constexpr int kGmMaxVec = kGmMaxRestart + 1;
 constexpr int kMaxSub = 16;          // eigensolver subspace width
@@ -132,14 +133,28 @@ struct Handle {
   hipEvent_t t0 = nullptr, t1 = nullptr;
 
   // PCG chunks replayed from HIP graphs: two instantiated graphs of
-  // kPollEvery iterations (chunks alternate between them, so that a chunk's
+  // poll_every iterations (chunks alternate between them, so that a chunk's
   // timing events can be read while the next one runs), captured for the
   // arguments in gkey and recaptured when they change
+  int poll_every = 4;                // PCG iterations between convergence polls
   int graphs_on = 0;                 // off by default: measured slower than eager launches
   int graphs_ok = 1;                 // 0 after a capture failed: eager launches only
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   std::vector<double> gkey;
-  hipEvent_t gprof_ev[2][8] = {};    // per graph: event pairs around its local solves
+  hipEvent_t gprof_ev[2][2 * kMaxPoll] = {};   // per graph: event pairs around its local solves
+
+  // autotuning of launch choices that leave every result bit for bit the
+  // same (tune.hip): the PCG launch mode and poll interval, measured over
+  // the handle's first solves, and the GMRES dot-product grouping; the
+  // choices are kept in an on-disk cache keyed by device and problem
+  int tune_on = 0;
+  int tune_decided = 0;              // the PCG choice is in force
+  int tune_from_cache = 0;
+  int tune_seen = 0;                 // solves seen while measuring
+  int tune_cand = -1;                // candidate of the running solve (-1: warm-up or none)
+  double tune_ms[4] = {0.0, 0.0, 0.0, 0.0};   // best ms per iteration of each candidate
+  int tune_gm_decided = 0;
+  int gm_chunk = 8;                  // Krylov vectors per workgroup of the GMRES dot products
   hipEvent_t* cap_ev = nullptr;      // during a capture: the events the marks record
   int cap_n = 0;
   int last_graph_chunks = 0;
@@ -323,6 +338,14 @@ void launch_summary(const Handle& h, const double* f, int nsys, const Gate& gate
                     double* out /*dev [nsys][4]*/, hipStream_t st);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 
+// tune.hip: the autotuner's hooks around a PCG solve, and its choice of the
+// GMRES dot-product grouping (a short measurement on the handle's stream)
+void tune_before_solve(Handle& h);
+void tune_after_solve(Handle& h, double ms, int iters);
+void tune_gmres(Handle& h, int nsys, int m);
+// gmres.hip: ms per launch of the dot-product kernel with `chunk` vectors
+// per workgroup on nv basis vectors (for the autotuner)
+double gmres_time_dots(Handle& h, int nsys, int nv, int chunk);
 // gmres.hip: restarted GMRES (cycle length m) with the MsFEM cycle or the
 // additive Schwarz preconditioner; hout [4][nsys]: iterations, status,
 // preconditioned relative residual estimate, true relative residual
