@@ -130,19 +130,42 @@ def local_eigenpairs(p, E_rep, fixed, j, k, K0=None, method="dense"):
     return lam, psi, dofs
 
 
-def coarse_basis(p, E_rep, fixed, k, K0=None, thresh=0.0, method="dense"):
+def unique_cells(p, E_rep, fixed):
+    """Subdomains whose local eigenproblems are the same matrices (Sec. 2.4:
+    periodic microstructures repeat the same agglomerate): equal moduli of the
+    cell's elements in cell order and equal supports of the box DOFs in box
+    order. Returns rep [J], the first subdomain with the same data, for each."""
+    seen, rep = {}, []
+    for j in range(p.n_sub):
+        nodes = subdomain_nodes(p, j)
+        dofs = (p.dim * nodes[:, None] + np.arange(p.dim)[None, :]).ravel()
+        key = (np.asarray(E_rep)[subdomain_elements(p, j)].tobytes(),
+               np.asarray(fixed)[dofs].tobytes())
+        rep.append(seen.setdefault(key, j))
+    return np.array(rep)
+
+
+def coarse_basis(p, E_rep, fixed, k, K0=None, thresh=0.0, method="dense", dedup=False):
     """Global Phi = R_c^T (sparse) and the per-subdomain eigenvalues.
 
     thresh <= 0: the k smallest eigenvectors of every subdomain (n_dof x J*k).
     thresh > 0: Sec. 2.4's global threshold, the eigenvectors whose
     eigenvalue lies below thresh, at most k per subdomain; Phi then has
     sum_j k_j columns in subdomain order. Returns (Phi, lams [J][k], kj [J]).
+    dedup: solve each distinct eigenproblem once (unique_cells) and give its
+    eigenpairs to every subdomain with the same matrices; the partition of
+    unity is still that of each subdomain.
     """
     chi = partition_of_unity(p)
     rows, cols, vals, lams, kj = [], [], [], [], []
     col = 0
+    rep = unique_cells(p, E_rep, fixed) if dedup else np.arange(p.n_sub)
+    solved = {}
     for j in range(p.n_sub):
-        lam, psi, dofs = local_eigenpairs(p, E_rep, fixed, j, k, K0, method)
+        if rep[j] not in solved:
+            solved[rep[j]] = local_eigenpairs(p, E_rep, fixed, rep[j], k, K0, method)[:2]
+        lam, psi = solved[rep[j]]
+        dofs = subdomain_dofs(p, j, fixed)
         use = k if thresh <= 0 else int(np.sum(lam < thresh))
         w = chi[dofs // p.dim]
         for m in range(use):

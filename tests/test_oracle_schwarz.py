@@ -330,3 +330,40 @@ def test_sparse_eigensolver_matches_dense(dim):
             qa, _ = np.linalg.qr(po[:, :p.k] * np.sqrt(d)[:, None])
             qb, _ = np.linalg.qr(ps[:, :p.k] * np.sqrt(d)[:, None])
             assert np.linalg.svd(qa.T @ qb, compute_uv=False).min() > 1 - 1e-9
+
+
+def test_unique_cells_of_the_periodic_mbb_beam():
+    # C1: every 8 x 8 cell holds the same microstructure, so the local
+    # eigenproblems differ only through the supports: the cells of the left
+    # column (u_x = 0 on their left box edge), the bottom-right cell (the
+    # roller at node (64, 4), inside that cell's right edge) and all others:
+    # three distinct eigenproblems for the 32 subdomains
+    p = W.mbb_64x32()
+    rho = W.design_field(p)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    fixed = W.fixed_mask(p)
+    rep = schwarz.unique_cells(p, E, fixed)
+    assert len(set(rep.tolist())) == 3
+    gx = p.nelx // p.sub
+    left = [j for j in range(p.n_sub) if j % gx == 0]
+    assert len(set(rep[left].tolist())) == 1 and rep[left[0]] == 0
+    assert rep[gx - 1] == gx - 1                             # the roller cell is its own
+    others = [j for j in range(p.n_sub) if j % gx != 0 and j != gx - 1]
+    assert len(set(rep[others].tolist())) == 1
+
+
+def test_dedup_basis_equals_full_basis():
+    # the eigenproblems of equal cells are the same matrices: solving each
+    # once gives the basis of solving all of them
+    p = W.mbb_64x32()
+    rho = W.design_field(p)
+    E = fem.simp_modulus(rho, p.E0, p.Emin, p.penal)
+    fixed = W.fixed_mask(p)
+    a, la = schwarz.coarse_basis(p, E, fixed, p.k)
+    b, lb = schwarz.coarse_basis(p, E, fixed, p.k, dedup=True)
+    np.testing.assert_allclose(lb, la, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(b.toarray(), a.toarray(), rtol=0, atol=1e-12 * abs(a).max())
+    # a non-periodic design has no equal cells
+    p2 = W.cantilever2d(64, 32, 16, 4)
+    E2 = fem.simp_modulus(W.design_field(p2), p2.E0, p2.Emin, p2.penal)
+    assert len(set(schwarz.unique_cells(p2, E2, W.fixed_mask(p2)).tolist())) == p2.n_sub
