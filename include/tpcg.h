@@ -101,6 +101,11 @@ typedef struct {
                            HBM-resident factors and solves (0: only blocks the on-chip kernels
                            cannot take: more than 96 unknowns, an odd count, or layers of more
                            than 64 elements) */
+  int32_t dedup;        /* 1: one local eigenproblem per distinct cell (Sec. 2.4: equal
+                           agglomerates of a periodic microstructure): subdomains whose cell
+                           densities (of the representative system) and box supports are equal
+                           take the eigenpairs of the first, with their own partition of unity.
+                           On-chip path only (ignored for HBM-resident blocks). 0: every cell */
 } tpcg_problem;
 
 /* Per-system result of tpcg_pcg_solve. */
@@ -420,6 +425,10 @@ int tpcg_export_eigenvalues(tpcg_handle* h, double* lambda, int32_t m, int32_t* 
  * Only for subdomain blocks on the HBM-resident path (TPCG_EINVAL otherwise).
  */
 int tpcg_export_local_record(tpcg_handle* h, int32_t sys, int32_t sub, int32_t blk, double* out);
+
+/* Local eigenproblems solved by the last basis build: the distinct cells with
+ * dedup on, else n_sub (0 before a build); TPCG_EINVAL for a null handle. */
+int tpcg_query_unique_cells(const tpcg_handle* h);
 
 /* Width of the eigensolver's subspace (ncoarse + eig_extra, at most 16 and at
  * most the subdomain's DOFs), or TPCG_EINVAL for a null handle. */

@@ -40,7 +40,7 @@ class Problem(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("eig_iters", ctypes.c_int32),
                 ("eig_extra", ctypes.c_int32), ("eig_shift", ctypes.c_double),
                 ("lambda_thresh", ctypes.c_double), ("coarse_dense_max", ctypes.c_int32),
-                ("big_min_nb", ctypes.c_int32)]
+                ("big_min_nb", ctypes.c_int32), ("dedup", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -78,7 +78,8 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_nondiscreteness", "tpcg_refactor", "tpcg_export_local_record", "tpcg_server_create", "tpcg_server_session_bytes",
            "tpcg_server_open", "tpcg_server_submit", "tpcg_server_wait", "tpcg_server_test",
            "tpcg_server_close", "tpcg_server_free_bytes", "tpcg_server_destroy",
-           "tpcg_apply_msfem", "tpcg_gmres_solve", "tpcg_set_autotune", "tpcg_query_tune"]
+           "tpcg_apply_msfem", "tpcg_gmres_solve", "tpcg_set_autotune", "tpcg_query_tune",
+           "tpcg_query_unique_cells"]
 
 
 def load_library(path: str | None = None):
@@ -100,6 +101,7 @@ def load_library(path: str | None = None):
     lib.tpcg_pcg_solve.argtypes = [P, P, P, P, I32, D, I32, ctypes.POINTER(Info)]
     lib.tpcg_apply_msfem.argtypes = [P, P, P, P, I32]
     lib.tpcg_set_autotune.argtypes = [P, I32]
+    lib.tpcg_query_unique_cells.argtypes = [P]
     lib.tpcg_query_tune.argtypes = [P, ctypes.POINTER(I32)]
     lib.tpcg_gmres_solve.argtypes = [P, P, P, P, I32, D, I32, I32, I32, ctypes.POINTER(Info)]
     lib.tpcg_compliance_and_sensitivity.argtypes = [P, P, P, P, I32, P, P]
@@ -149,7 +151,7 @@ def load_library(path: str | None = None):
 
 def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.0, nu=0.3,
                  precision=FP64, eig_iters=0, eig_extra=0, eig_shift=0.0, lambda_thresh=0.0,
-                 coarse_dense_max=0, overlap=1, big_min_nb=0) -> Problem:
+                 coarse_dense_max=0, overlap=1, big_min_nb=0, dedup=0) -> Problem:
     """tpcg_problem; `sub` is the subdomain edge (an int) or a per-axis tuple."""
     pr = Problem()
     pr.dim = dim
@@ -163,6 +165,7 @@ def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.
     pr.precision, pr.eig_iters, pr.eig_extra, pr.eig_shift = precision, eig_iters, eig_extra, eig_shift
     pr.lambda_thresh, pr.coarse_dense_max = lambda_thresh, coarse_dense_max
     pr.big_min_nb = big_min_nb
+    pr.dedup = dedup
     return pr
 
 
@@ -264,6 +267,10 @@ class Handle:
         self._check(rc, allow_warn=True)
         return [dict(iters=i.iters, status=i.status, relres=i.relres,
                      true_relres=i.true_relres, seconds=i.seconds) for i in info]
+
+    def unique_cells(self):
+        """Local eigenproblems solved by the last basis build."""
+        return self.lib.tpcg_query_unique_cells(self.h)
 
     def set_autotune(self, on=True):
         self._check(self.lib.tpcg_set_autotune(self.h, 1 if on else 0))

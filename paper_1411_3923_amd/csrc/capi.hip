@@ -77,6 +77,7 @@ const char* make_geometry(const tpcg_problem& pr, Geometry& g) {
   g.nbc = g.k * (g.nsub / g.nblkc);
   g.nt = g.nsub * g.k;
   g.dense_max = pr.coarse_dense_max > 0 ? pr.coarse_dense_max : kDenseCoarse;
+  g.submap = nullptr;
   // packed factor records: B_{b+1} reaches pe diagonals below its main one
   {
     int64_t w = 1;
@@ -137,6 +138,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   if (!big) p += sizeof(double) * nsys * (size_t)g.nsub * g.nb * (g.nb + 1) / 2;
   if (mixed) p += sizeof(double) * nsys * (size_t)g.nel;
   p += sizeof(int) * (size_t)g.nsub;
+  p += (sizeof(unsigned long long) + 4 * sizeof(int)) * (size_t)g.nsub;   // distinct-cell maps
   if (g.nt <= g.dense_max) {
     const size_t T = coarse_tiles(g.nt);
     p += sizeof(double) * nsys * (T * (T + 1) / 2 * kCT * kCT + T * T * kCT);
@@ -205,7 +207,8 @@ void release(Handle* h) {
   void* ptrs[] = {h->fixed, h->K0,   h->phi,  h->phim,   h->lam, h->kj,     h->eres, h->lfac,
                   h->emod,  h->twist, h->emod64, h->cfac, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
-                  h->dflag, h->build_ws, h->gm_V, h->gm_w, h->gm_i, h->gm_flags, h->gm_out};
+                  h->dflag, h->build_ws, h->gm_V, h->gm_w, h->gm_i, h->gm_flags, h->gm_out,
+                  h->cell_sig, h->submap_d, h->dedup_pairs, h->dedup_flag};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);
@@ -549,6 +552,10 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     a.add_bytes(h->phim, ts * (size_t)g.nsub * g.nloc * g.k);
     a.add(h->lam, (size_t)g.nsub * h->msub);
     a.add(h->kj, (size_t)g.nsub);
+    a.add(h->cell_sig, (size_t)g.nsub);
+    a.add(h->submap_d, (size_t)g.nsub);
+    a.add(h->dedup_pairs, (size_t)2 * g.nsub);
+    a.add(h->dedup_flag, (size_t)g.nsub);
     a.add(h->eres, (size_t)g.nsub * h->msub);
     a.add_bytes(h->lfac, ts * ns * g.nsub * fsz);
     a.add_bytes(h->emod, ts * ns * (size_t)g.nel);
@@ -1089,6 +1096,11 @@ int tpcg_export_eigenvalues(tpcg_handle* hh, double* lambda, int32_t m, int32_t*
   }
   if (kj) hipMemcpy(kj, h->kj, sizeof(int) * g.nsub, hipMemcpyDeviceToHost);
   return check_hip(h, "tpcg_export_eigenvalues");
+}
+
+int tpcg_query_unique_cells(const tpcg_handle* hh) {
+  const Handle* h = H(hh);
+  return h ? h->nrep : TPCG_EINVAL;
 }
 
 int tpcg_query_subspace(const tpcg_handle* hh) {

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_btri_factor(const double* __restri
   uint8_t* fl = reinterpret_cast<uint8_t*>(dl + (sten ? 2 * nb : 0));   // flags of 3 node layers
   int jx = 0, jy = 0, jz = 0;
   if (sten) {
-    sub_coords(si.g, blockIdx.x, jx, jy, jz);
+    sub_coords(si.g, phys_sub(si.g, blockIdx.x), jx, jy, jz);
     for (int i = t; i < si.g.ndpe * si.g.ndpe; i += kThreads) K0s[i] = si.K0[i];
   }
   // Neumann diagonal of node layer L (needs the layers L - 1 and L staged

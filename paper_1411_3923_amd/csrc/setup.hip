@@ -42,11 +42,11 @@ __device__ inline double hash_uniform(uint64_t a) {
 
 __global__ __launch_bounds__(kThreads) void k_eig_init(Geometry g, double* __restrict__ X,
                                                       const double* __restrict__ dis, int m) {
-  const int j = blockIdx.x;
+  const int j = blockIdx.x, jp = phys_sub(g, j);   // start vectors seeded by the subdomain
   for (int e = threadIdx.x; e < g.nloc * m; e += kThreads) {
     const int l = e / m;
     const double v = dis[(size_t)j * g.nloc + l] > 0.0
-                         ? hash_uniform(((uint64_t)j * g.nloc + l) * 64 + (e - l * m))
+                         ? hash_uniform(((uint64_t)jp * g.nloc + l) * 64 + (e - l * m))
                          : 0.0;
     X[(size_t)j * g.nloc * m + e] = v;
   }
@@ -214,8 +214,8 @@ __global__ __launch_bounds__(kThreads) void k_neumann_apply(Geometry g, const do
                                                            double* __restrict__ Y, int m,
                                                            MatParams mp) {
   __shared__ double K0s[576];
-  const int j = blockIdx.x;
-  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const int j = blockIdx.x, jp = phys_sub(g, j);
+  const int jx = jp % g.gx, jy = (jp / g.gx) % g.gy, jz = jp / (g.gx * g.gy);
   constexpr int d = D, nd = D == 3 ? 24 : 8;
   for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
   __syncthreads();
@@ -273,6 +273,116 @@ __device__ inline int axis_mult(int i, int s, int nel) {
   return (i % s == 0 && i > 0 && i < nel) ? 2 : 1;
 }
 
+// ---------------------------------------------------------------------------
+// Distinct cells (Sec. 2.4: equal agglomerates of a periodic microstructure
+// share their local eigenproblem). The eigenproblem of subdomain j is fixed
+// by the densities of its cell's elements (cell order) and the supports of
+// its box DOFs (box order).
+// ---------------------------------------------------------------------------
+
+__device__ inline uint64_t mix64(uint64_t x) {   // the splitmix64 finaliser
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+
+__device__ inline int64_t cell_element(const Geometry& g, int jx, int jy, int jz, int q) {
+  const int ex = q % g.s, ey = (q / g.s) % g.s, ez = g.dim == 3 ? q / (g.s * g.s) : 0;
+  return (int64_t)(g.s * jx + ex) +
+         (int64_t)g.nelx * ((g.s * jy + ey) + (int64_t)g.nely * (g.s * jz + ez));
+}
+
+// sig[j] = the sum mod 2^64 of a mix of every (position, value) of the
+// subdomain's data: equal data, equal signature (candidates are then
+// compared exactly)
+__global__ __launch_bounds__(kThreads) void k_cell_sig(Geometry g, const double* __restrict__ rho,
+                                                      const uint8_t* __restrict__ fixed,
+                                                      unsigned long long* __restrict__ sig) {
+  __shared__ unsigned long long part[kThreads];
+  const int j = blockIdx.x;
+  int jx, jy, jz;
+  sub_coords(g, j, jx, jy, jz);
+  const int ncell = g.dim == 3 ? g.s * g.s * g.s : g.s * g.s;
+  uint64_t acc = 0;
+  for (int q = threadIdx.x; q < ncell; q += kThreads) {
+    uint64_t bits;
+    const double v = rho[cell_element(g, jx, jy, jz, q)];
+    memcpy(&bits, &v, sizeof(bits));
+    acc += mix64(bits ^ mix64((uint64_t)q));
+  }
+  for (int l = threadIdx.x; l < g.nloc; l += kThreads)
+    acc += mix64(((uint64_t)fixed[box_dof(g, jx, jy, jz, l)] + 1) ^ mix64((uint64_t)(ncell + l)));
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t s = 0;
+    for (int i = 0; i < kThreads; ++i) s += part[i];
+    sig[j] = s;
+  }
+}
+
+// flag[i] = 1 if subdomain pairs[2 i] differs from pairs[2 i + 1] anywhere
+__global__ __launch_bounds__(kThreads) void k_cell_same(Geometry g, const double* __restrict__ rho,
+                                                       const uint8_t* __restrict__ fixed,
+                                                       const int* __restrict__ pairs,
+                                                       int* __restrict__ flag) {
+  const int i = blockIdx.x;
+  const int a = pairs[2 * i], b = pairs[2 * i + 1];
+  int ax, ay, az, bx, by, bz;
+  sub_coords(g, a, ax, ay, az);
+  sub_coords(g, b, bx, by, bz);
+  const int ncell = g.dim == 3 ? g.s * g.s * g.s : g.s * g.s;
+  int diff = 0;
+  for (int q = threadIdx.x; q < ncell; q += kThreads) {
+    const double va = rho[cell_element(g, ax, ay, az, q)], vb = rho[cell_element(g, bx, by, bz, q)];
+    uint64_t ua, ub;
+    memcpy(&ua, &va, sizeof(ua));
+    memcpy(&ub, &vb, sizeof(ub));
+    diff |= ua != ub;
+  }
+  for (int l = threadIdx.x; l < g.nloc; l += kThreads)
+    diff |= fixed[box_dof(g, ax, ay, az, l)] != fixed[box_dof(g, bx, by, bz, l)];
+  diff = __syncthreads_or(diff);
+  if (threadIdx.x == 0) flag[i] = diff;
+}
+
+__device__ inline int box_mult(const Geometry& g, int jx, int jy, int jz, int ln) {
+  const int lx = ln % g.bn, ly = (ln / g.bn) % g.bn, lz = ln / (g.bn * g.bn);
+  int mult = axis_mult(g.s * jx + lx, g.s, g.nelx) * axis_mult(g.s * jy + ly, g.s, g.nely);
+  if (g.dim == 3) mult *= axis_mult(g.s * jz + lz, g.s, g.nelz);
+  return mult;
+}
+
+// The eigenpairs of each duplicate pairs[2 i] from its representative
+// pairs[2 i + 1]: Phi with the duplicate's partition-of-unity weights (the
+// weights are 1/2^n, so the rescaling is exact), Ritz values, residuals and
+// the count of vectors in use.
+__global__ __launch_bounds__(kThreads) void k_dedup_scatter(Geometry g, const int* __restrict__ pairs,
+                                                           double* __restrict__ phi,
+                                                           double* __restrict__ lam,
+                                                           double* __restrict__ eres,
+                                                           int* __restrict__ kj, int m) {
+  const int i = blockIdx.x;
+  const int a = pairs[2 * i], b = pairs[2 * i + 1];
+  int ax, ay, az, bx, by, bz;
+  sub_coords(g, a, ax, ay, az);
+  sub_coords(g, b, bx, by, bz);
+  const int k = g.k;
+  for (int e = threadIdx.x; e < g.nloc * k; e += kThreads) {
+    const int l = e / k;
+    const int ln = l / g.dim;
+    const double f = (double)box_mult(g, bx, by, bz, ln);
+    const double w = (double)box_mult(g, ax, ay, az, ln);
+    phi[(size_t)a * g.nloc * k + e] = phi[(size_t)b * g.nloc * k + e] * f / w;
+  }
+  for (int r = threadIdx.x; r < m; r += kThreads) {
+    lam[(size_t)a * m + r] = lam[(size_t)b * m + r];
+    eres[(size_t)a * m + r] = eres[(size_t)b * m + r];
+  }
+  if (threadIdx.x == 0) kj[a] = kj[b];
+}
+
 // Rayleigh-Ritz on span(X) with SX = S X: H = X^T S X, H = Q Theta Q^T
 // (cyclic Jacobi), Ritz vectors X Q in ascending order; writes the Ritz
 // values, the residual norms ||S x - theta x|| and Phi_j = chi D^-1/2 (X Q)[:, :k].
@@ -294,8 +404,9 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
   __shared__ int ord[kMaxSub];
   __shared__ int done;
   const int t = threadIdx.x;
-  const int j = blockIdx.x;
-  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const int j = blockIdx.x;            // work arrays: launch index
+  const int jp = phys_sub(g, j);       // outputs and geometry: the subdomain
+  const int jx = jp % g.gx, jy = (jp / g.gx) % g.gy, jz = jp / (g.gx * g.gy);
   const double* Xj = X + (size_t)j * g.nloc * m;
   const double* Sj = SX + (size_t)j * g.nloc * m;
   gram_waves(Xj, Sj, g.nloc, m, part);   // H = X^T S X
@@ -372,7 +483,7 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
     kuse = 0;
     while (kuse < g.k && th[ord[kuse]] < thr) ++kuse;
   }
-  if (t == 0) kj[j] = kuse;
+  if (t == 0) kj[jp] = kuse;
   // residuals and the basis
   double racc[kMaxSub];
 #pragma unroll
@@ -408,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
       const double res = sv - th[ord[i]] * xv;
 #pragma unroll
       for (int ii = 0; ii < kMaxSub; ++ii) racc[ii] += ii == i ? res * res : 0.0;
-      if (i < k) phi[((size_t)j * g.nloc + l) * k + i] = i < kuse ? chi * sd * xv : 0.0;
+      if (i < k) phi[((size_t)jp * g.nloc + l) * k + i] = i < kuse ? chi * sd * xv : 0.0;
     }
   }
 #pragma unroll
@@ -416,8 +527,8 @@ __global__ __launch_bounds__(kThreads) void k_eig_rr(Geometry g, const double* _
     if (i >= m) break;
     const double v = block_sum(racc[i], sh);
     if (t == 0) {
-      lam[(size_t)j * m + i] = th[ord[i]];
-      eres[(size_t)j * m + i] = sqrt(v);
+      lam[(size_t)jp * m + i] = th[ord[i]];
+      eres[(size_t)jp * m + i] = sqrt(v);
     }
   }
 }
@@ -437,8 +548,8 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
                                                       double* __restrict__ W, size_t wstride,
                                                       MatParams mp) {
   __shared__ double K0s[576];
-  const int j = blockIdx.x;
-  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
+  const int j = blockIdx.x, jp = phys_sub(g, j);
+  const int jx = jp % g.gx, jy = (jp / g.gx) % g.gy, jz = jp / (g.gx * g.gy);
   constexpr int d = D, nd = D == 3 ? 24 : 8;
   const int k = g.k;
   for (int i = threadIdx.x; i < nd * nd; i += kThreads) K0s[i] = K0[i];
@@ -692,6 +803,66 @@ size_t build_ws_elems(const tpcg_problem& pr, const Geometry& g, int big, int ms
   return std::max(eig, coarse);
 }
 
+// Distinct cells of the representative design: signatures on the GPU, groups
+// on the host, every candidate duplicate compared exactly on the GPU (a
+// signature collision leaves the cell its own representative). Writes the
+// representatives to h.submap_d (ascending) and the (duplicate,
+// representative) pairs to h.dedup_pairs. Synchronises the stream.
+int distinct_cells(Handle& h, const double* rrep, hipStream_t st, int& nrep, int& npairs) {
+  const Geometry& g = h.g;
+  hipLaunchKernelGGL(k_cell_sig, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.fixed, h.cell_sig);
+  std::vector<unsigned long long> sig(g.nsub);
+  hipMemcpyAsync(sig.data(), h.cell_sig, sizeof(unsigned long long) * g.nsub,
+                 hipMemcpyDeviceToHost, st);
+  if (hipStreamSynchronize(st) != hipSuccess) return TPCG_EHIP;
+  std::vector<int> rep(g.nsub);
+  {
+    std::vector<std::pair<unsigned long long, int>> order(g.nsub);
+    for (int j = 0; j < g.nsub; ++j) order[j] = {sig[j], j};
+    std::sort(order.begin(), order.end());
+    for (size_t i = 0; i < order.size(); ++i)
+      rep[order[i].second] = (i > 0 && order[i].first == order[i - 1].first)
+                                 ? rep[order[i - 1].second]
+                                 : order[i].second;   // the lowest index of the group
+  }
+  std::vector<int> pairs;
+  for (int j = 0; j < g.nsub; ++j)
+    if (rep[j] != j) {
+      pairs.push_back(j);
+      pairs.push_back(rep[j]);
+    }
+  if (!pairs.empty()) {
+    const int np = (int)pairs.size() / 2;
+    hipMemcpyAsync(h.dedup_pairs, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice,
+                   st);
+    hipLaunchKernelGGL(k_cell_same, dim3(np), dim3(kThreads), 0, st, g, rrep, h.fixed,
+                       h.dedup_pairs, h.dedup_flag);
+    std::vector<int> differ(np);
+    hipMemcpyAsync(differ.data(), h.dedup_flag, sizeof(int) * np, hipMemcpyDeviceToHost, st);
+    if (hipStreamSynchronize(st) != hipSuccess) return TPCG_EHIP;
+    for (int i = 0; i < np; ++i)
+      if (differ[i]) rep[pairs[2 * i]] = pairs[2 * i];
+  }
+  std::vector<int> reps;
+  pairs.clear();
+  for (int j = 0; j < g.nsub; ++j) {
+    if (rep[j] == j) {
+      reps.push_back(j);
+    } else {
+      pairs.push_back(j);
+      pairs.push_back(rep[j]);
+    }
+  }
+  nrep = (int)reps.size();
+  npairs = (int)pairs.size() / 2;
+  hipMemcpyAsync(h.submap_d, reps.data(), sizeof(int) * reps.size(), hipMemcpyHostToDevice, st);
+  if (npairs > 0)
+    hipMemcpyAsync(h.dedup_pairs, pairs.data(), sizeof(int) * pairs.size(), hipMemcpyHostToDevice,
+                   st);
+  // the host vectors must outlive the copies
+  return hipStreamSynchronize(st) == hipSuccess ? TPCG_OK : TPCG_EHIP;
+}
+
 int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int with_basis) {
   const Geometry& g = h.g;
   hipStream_t st = h.stream;
@@ -739,6 +910,17 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int wi
   const double* rrep = rho + (size_t)rep * g.nel;
   BigFactorIn nin{};
   double* fws = Y + nsl * m + g.nel;   // big path: factorisation, then multi-vector work arrays
+  // distinct cells only (the on-chip path): the eigen phase runs on the
+  // representatives, launch index c working on subdomain submap[c], and the
+  // duplicates take their eigenpairs afterwards
+  Geometry ge = g;
+  int nrep = g.nsub, npairs = 0;
+  if (pr.dedup && !h.big) {
+    const int rc = distinct_cells(h, rrep, st, nrep, npairs);
+    if (rc != TPCG_OK) return rc;
+    ge.submap = h.submap_d;
+  }
+  h.nrep = nrep;
   if (h.big) {
     // HBM-resident Neumann records from the representative system's moduli
     double* emrep = Y + nsl * m;
@@ -756,27 +938,31 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int wi
     big_factor<double>(nin, nfac, fws, h.dflag, st);
   } else {
     StencilIn sn = si;
+    sn.g = ge;
     sn.rho = rrep;
     sn.neumann = 1;
     sn.dis = dis;
-    launch_factor<double>(nullptr, nfac, g.nsub, lsh, h.dflag, st, false, &sn);
+    launch_factor<double>(nullptr, nfac, nrep, lsh, h.dflag, st, false, &sn);
   }
-  hipLaunchKernelGGL(k_eig_init, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
-  hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, dis, m);
+  hipLaunchKernelGGL(k_eig_init, dim3(nrep), dim3(kThreads), 0, st, ge, X, dis, m);
+  hipLaunchKernelGGL(k_eig_cholqr, dim3(nrep), dim3(kThreads), 0, st, ge, X, dis, m);
   for (int it = 0; it < iters; ++it) {
     if (h.big) big_solve_multi(nin, nfac, m, X, Y, fws, st);
-    else launch_solve_multi(nfac, lsh, g.nsub, m, X, Y, st);
-    hipLaunchKernelGGL(k_eig_cholqr, dim3(g.nsub), dim3(kThreads), 0, st, g, Y, dis, m);
+    else launch_solve_multi(nfac, lsh, nrep, m, X, Y, st);
+    hipLaunchKernelGGL(k_eig_cholqr, dim3(nrep), dim3(kThreads), 0, st, ge, Y, dis, m);
     std::swap(X, Y);
   }
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_neumann_apply<2>, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis,
+    hipLaunchKernelGGL(k_neumann_apply<2>, dim3(nrep), dim3(kThreads), 0, st, ge, rrep, h.K0, dis,
                        X, Y, m, mp);
   else
-    hipLaunchKernelGGL(k_neumann_apply<3>, dim3(g.nsub), dim3(kThreads), 0, st, g, rrep, h.K0, dis,
+    hipLaunchKernelGGL(k_neumann_apply<3>, dim3(nrep), dim3(kThreads), 0, st, ge, rrep, h.K0, dis,
                        X, Y, m, mp);
-  hipLaunchKernelGGL(k_eig_rr, dim3(g.nsub), dim3(kThreads), 0, st, g, X, Y, dis, m, h.lam,
+  hipLaunchKernelGGL(k_eig_rr, dim3(nrep), dim3(kThreads), 0, st, ge, X, Y, dis, m, h.lam,
                      h.eres, h.phi, pr.lambda_thresh, h.kj);
+  if (npairs > 0)
+    hipLaunchKernelGGL(k_dedup_scatter, dim3(npairs), dim3(kThreads), 0, st, g, h.dedup_pairs,
+                       h.phi, h.lam, h.eres, h.kj, m);
   if (h.mixed)
     hipLaunchKernelGGL(k_phi_modes<float>, dim3(1024), dim3(kThreads), 0, st, g, h.phi,
                        reinterpret_cast<float*>(h.phim));

@@ -49,7 +49,12 @@ struct Geometry {
   int ebn;                           // nodes per extended box edge (s + 3)
   int nebox;                         // nodes per extended box
   int ndpe;                          // DOFs per element (8 or 24)
+  const int* submap;                 // eigen phase over distinct cells only: the subdomain of
+                                     // each launch index (device array; nullptr: identity)
 };
+
+// subdomain of launch index c of the eigen phase
+__device__ inline int phys_sub(const Geometry& g, int c) { return g.submap ? g.submap[c] : c; }
 
 // Coarse index of (subdomain j, mode m): block-major along `caxis`.
 __host__ __device__ inline int coarse_index(const Geometry& g, int jx, int jy, int jz, int m) {
@@ -112,6 +117,14 @@ struct Handle {
                                      // [nsys][T (T + 1) / 2][64][64]
   double* cpart = nullptr;           // tile partials of K_c^-1 y_c [nsys][T][T][64]
   double* build_ws = nullptr;        // work arrays of the preconditioner build
+  // one eigenproblem per distinct cell (tpcg_problem.dedup): signatures, the
+  // distinct cells' subdomains, (duplicate, representative) pairs, flags of
+  // the exact comparison; nrep = eigenproblems solved by the last build
+  unsigned long long* cell_sig = nullptr;   // [nsub]
+  int* submap_d = nullptr;                  // [nsub]
+  int* dedup_pairs = nullptr;               // [nsub][2]
+  int* dedup_flag = nullptr;                // [nsub]
+  int nrep = 0;
   size_t build_elems = 0;
   hipStream_t side = nullptr;        // second stream: the block coarse solve, the setup's local factors
   hipEvent_t fork = nullptr, join = nullptr;
