@@ -260,6 +260,38 @@ def section_errors(args):
     return out
 
 
+def hbm_measured():
+    """Achievable HBM bandwidth on this GPU, beside the 8 TB/s spec peak: a
+    device-to-device copy of 2 GiB (read + write bytes) and a read-only sum
+    over 4 GiB, each the median of 10 event-timed launches."""
+    import torch
+    out = {}
+    n = (2 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    big = torch.ones(2 * n, dtype=torch.float64, device="cuda")
+
+    def timed(fn, nbytes):
+        fn()
+        ms = []
+        for _ in range(10):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        return nbytes / (percentile(ms, 50) * 1e-3) / 1e9
+
+    out["copy_GBs"] = timed(lambda: dst.copy_(src), 2 * 8 * n)
+    out["read_GBs"] = timed(lambda: big.sum(), 8 * 2 * n)
+    out["note"] = ("torch copy_ (read + write bytes) and sum (read bytes) on the current "
+                   "stream; the roofline frac is against the 8 TB/s spec peak")
+    del src, dst, big
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -816,6 +848,7 @@ def main():
         bmx = rmx["block_solves"]
         line["mixed"]["block_solves_GBs"] = (bmx["bytes"] / (bmx["ms"] * 1e-3) / 1e9
                                             if bmx["ms"] > 0 else None)
+    line["roofline"]["hbm_measured"] = hbm_measured()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args)
         if not three:

@@ -132,6 +132,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   const size_t ts = mixed ? 4 : 8;
   size_t p = 0;
   p += g.ndof + sizeof(double) * g.ndpe * g.ndpe;
+  p += sizeof(double) * (size_t)kMaxSys * g.nel;   // filter adjoint factors
   p += (sizeof(double) + ts) * (size_t)g.nsub * g.nloc * g.k;
   p += 2 * sizeof(double) * (size_t)g.nsub * msub;
   p += ts * nsys * (frec + (size_t)g.nel);
@@ -208,7 +209,7 @@ void release(Handle* h) {
                   h->emod,  h->twist, h->emod64, h->cfac, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
                   h->dflag, h->build_ws, h->gm_V, h->gm_w, h->gm_i, h->gm_flags, h->gm_out,
-                  h->cell_sig, h->submap_d, h->dedup_pairs, h->dedup_flag};
+                  h->cell_sig, h->submap_d, h->dedup_pairs, h->dedup_flag, h->fscratch};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);
@@ -472,6 +473,7 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
   e |= alloc(h->p, ns * (size_t)g.ndof);
   e |= alloc(h->p2, ns * (size_t)g.ndof);
   e |= alloc(h->q, ns * (size_t)g.ndof);
+  e |= alloc(h->fscratch, (size_t)kMaxSys * g.nel);
   e |= alloc(h->parts, kPartsElems);
   e |= alloc(h->istate, (size_t)kNumState * kMaxSys);
   e |= alloc(h->dflag, 4);

@@ -79,16 +79,35 @@ __global__ __launch_bounds__(kThreads) void k_filter_project(Geometry g, const d
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_filter_project_adjoint(
+// ge[s][e] = gin[s][e] H'(rt_e) / sum_k w_ek: the adjoint's factor of each
+// element (the weight sum and the projection's derivative once per element)
+__global__ __launch_bounds__(kThreads) void k_filter_adjoint_scale(
     Geometry g, const double* __restrict__ rt, double rmin, double beta, Etas eta, int nsys,
-    const double* __restrict__ gin, double* __restrict__ out) {
+    const double* __restrict__ gin, double* __restrict__ ge) {
+  const int R = rmin > 1.0 ? (int)ceil(rmin) - 1 : 0;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < g.nel;
+       e += (int64_t)gridDim.x * kThreads) {
+    double den = 1.0;
+    if (R > 0) {
+      int ex, ey, ez;
+      elem_coords(g, e, ex, ey, ez);
+      den = weight_sum(g, ex, ey, ez, rmin, R);
+    }
+    const double x = rt[e];
+    for (int s = 0; s < nsys; ++s)
+      ge[(size_t)s * g.nel + e] = gin[(size_t)s * g.nel + e] * heaviside_d(x, beta, eta.v[s]) / den;
+  }
+}
+
+// dc/drho_i = sum_{e near i} w_ie ge_e (the filter weights are symmetric)
+__global__ __launch_bounds__(kThreads) void k_filter_project_adjoint(
+    Geometry g, double rmin, int nsys, const double* __restrict__ ge, double* __restrict__ out) {
   const int R = rmin > 1.0 ? (int)ceil(rmin) - 1 : 0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < g.nel;
        i += (int64_t)gridDim.x * kThreads) {
     double acc[kMaxSys] = {0.0, 0.0, 0.0, 0.0};
     if (R == 0) {
-      for (int s = 0; s < nsys; ++s)
-        acc[s] = gin[(size_t)s * g.nel + i] * heaviside_d(rt[i], beta, eta.v[s]);
+      for (int s = 0; s < nsys; ++s) acc[s] = ge[(size_t)s * g.nel + i];
     } else {
       int ix, iy, iz;
       elem_coords(g, i, ix, iy, iz);
@@ -101,9 +120,7 @@ __global__ __launch_bounds__(kThreads) void k_filter_project_adjoint(
             const double w = rmin - sqrt((double)(dx * dx + dy * dy + dz * dz));
             if (w <= 0.0) continue;
             const int64_t e = x + (int64_t)g.nelx * (y + (int64_t)g.nely * z);
-            const double ws = w / weight_sum(g, x, y, z, rmin, R);
-            for (int s = 0; s < nsys; ++s)
-              acc[s] += ws * gin[(size_t)s * g.nel + e] * heaviside_d(rt[e], beta, eta.v[s]);
+            for (int s = 0; s < nsys; ++s) acc[s] += w * ge[(size_t)s * g.nel + e];
           }
     }
     for (int s = 0; s < nsys; ++s) out[(size_t)s * g.nel + i] = acc[s];
@@ -289,8 +306,10 @@ void launch_filter_project_adjoint(const Handle& h, const double* rho_tilde, dou
                                    double* out, hipStream_t st) {
   Etas e{};
   for (int s = 0; s < nsys; ++s) e.v[s] = eta[s];
+  hipLaunchKernelGGL(k_filter_adjoint_scale, dim3(elem_blocks(h.g.nel)), dim3(kThreads), 0, st,
+                     h.g, rho_tilde, rmin, beta, e, nsys, g, h.fscratch);
   hipLaunchKernelGGL(k_filter_project_adjoint, dim3(elem_blocks(h.g.nel)), dim3(kThreads), 0, st,
-                     h.g, rho_tilde, rmin, beta, e, nsys, g, out);
+                     h.g, rmin, nsys, h.fscratch, out);
 }
 
 void launch_robust(const Handle& h, const double* c, const double* dc, int nsys, double kappa,

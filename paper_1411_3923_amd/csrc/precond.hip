@@ -14,6 +14,7 @@ namespace tpcg {
 namespace {
 
 constexpr int kSubThreads = 256;    // restriction: one workgroup per subdomain
+constexpr int kXcStage = 2048;      // extension: coarse-solution entries staged per workgroup
 
 // One workgroup per subdomain, all running systems together (Phi, mode-major,
 // read once); KM >= k bounds the accumulators.
@@ -228,12 +229,13 @@ __global__ __launch_bounds__(kThreads) void k_extend(
     const uint8_t* __restrict__ fixed, double* __restrict__ parts, int rz_slot, int flexible,
     int nsys, Gate gate) {
   __shared__ double sh[4];
+  __shared__ double xs[kXcStage];
   unsigned run = 0;
   for (int sys = 0; sys < nsys; ++sys)
     if (gate_running(gate, sys)) run |= 1u << sys;
   if (!run) return;
   constexpr int d = D;
-  const int s = g.s;
+  const int s = g.s, k = g.k;
   const size_t zstride = (size_t)g.nsub * g.nloc;
   // XCD-aware order (workgroups whose index agrees mod 8 share an XCD): each
   // such group takes a contiguous range of node chunks, so the box rows that
@@ -244,8 +246,32 @@ __global__ __launch_bounds__(kThreads) void k_extend(
   double arz[kMaxSys], arzo[kMaxSys];
 #pragma unroll
   for (int q = 0; q < kMaxSys; ++q) arz[q] = arzo[q] = 0.0;
-  for (int64_t n = (int64_t)slot * kThreads + threadIdx.x; n < g.nnodes;
-       n += (int64_t)gridDim.x * kThreads) {
+  for (int64_t base = (int64_t)slot * kThreads; base < g.nnodes;
+       base += (int64_t)gridDim.x * kThreads) {
+    // x_c of the boxes this chunk of nodes can touch (every box column of
+    // its node rows) staged in LDS; x_c from global memory when they do not fit
+    const int64_t last = min(base + (int64_t)kThreads, g.nnodes) - 1;
+    const int64_t r0 = base / g.nnx, r1 = last / g.nnx;   // node rows, iy + nny iz
+    const int iy0 = (int)(r0 % g.nny), iz0 = (int)(r0 / g.nny);
+    const int iy1 = (int)(r1 % g.nny), iz1 = (int)(r1 / g.nny);
+    int ylo = iy0 == 0 ? 0 : (iy0 - 1) / s, yhi = min(g.gy - 1, iy1 / s);
+    if (iz1 != iz0) { ylo = 0; yhi = g.gy - 1; }
+    const int zlo = d == 3 ? (iz0 == 0 ? 0 : (iz0 - 1) / s) : 0;
+    const int zhi = d == 3 ? min(g.gz - 1, iz1 / s) : 0;
+    const int ny = yhi - ylo + 1;
+    const int cnt = g.gx * ny * (zhi - zlo + 1) * k;
+    const bool staged = cnt * nsys <= kXcStage;
+    __syncthreads();   // the previous chunk's reads of xs are done
+    if (staged)
+      for (int e = threadIdx.x; e < cnt * nsys; e += kThreads) {
+        const int q = e / cnt, rr = e - q * cnt;
+        const int box = rr / k, m = rr - box * k;
+        const int jx = box % g.gx, jy = ylo + (box / g.gx) % ny, jz = zlo + box / (g.gx * ny);
+        xs[e] = ((run >> q) & 1u) ? xc[(size_t)q * g.nt + coarse_index(g, jx, jy, jz, m)] : 0.0;
+      }
+    __syncthreads();
+    const int64_t n = base + threadIdx.x;
+    if (n >= g.nnodes) continue;
     const int ix = (int)(n % g.nnx);
     const int iy = (int)((n / g.nnx) % g.nny);
     const int iz = (int)(n / ((int64_t)g.nnx * g.nny));
@@ -254,7 +280,8 @@ __global__ __launch_bounds__(kThreads) void k_extend(
     int z0 = 0, z1 = 0;
     if (d == 3) { z0 = iz == 0 ? 0 : (iz - 1) / s; z1 = min(g.gz - 1, iz / s); }
     // a node lies in at most two subdomains along each axis (overlap of one
-    // cell): all candidate loads are issued, predicated, before any is summed
+    // cell); per subdomain: its local solution, then the prolonged coarse
+    // solution mode by mode
     double acc[kMaxSys][3];
 #pragma unroll
     for (int q = 0; q < kMaxSys; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0.0;
@@ -269,26 +296,57 @@ __global__ __launch_bounds__(kThreads) void k_extend(
           const int j = jx + g.gx * (jy + g.gy * jz);
           const int ln = (ix - s * jx) + g.bn * ((iy - s * jy) + g.bn * (iz - s * jz));
           const T* zj = zloc + (size_t)j * g.nloc + (size_t)d * ln;
-          const T* pj = phim + (size_t)j * g.k * g.nloc + (size_t)d * ln;
+          const T* pj = phim + (size_t)j * k * g.nloc + (size_t)d * ln;
           const double* xj = xc + coarse_index(g, jx, jy, jz, 0);
-#pragma unroll
-          for (int q = 0; q < kMaxSys; ++q)
-            if ((run >> q) & 1u)
-#pragma unroll
-              for (int c = 0; c < D; ++c) acc[q][c] += (double)zj[q * zstride + c];
-#pragma unroll
-          for (int m = 0; m < KM; ++m) {
-            if (m >= g.k) break;
-            double pv[D];
-#pragma unroll
-            for (int c = 0; c < D; ++c) pv[c] = (double)pj[(size_t)m * g.nloc + c];
+          const int sb = ((jz - zlo) * ny + (jy - ylo)) * g.gx + jx;   // staged box
+          if constexpr (D == 2) {
+            typedef T T2 __attribute__((ext_vector_type(2)));
 #pragma unroll
             for (int q = 0; q < kMaxSys; ++q)
               if ((run >> q) & 1u) {
-                const double xv = xj[(size_t)q * g.nt + m];
-#pragma unroll
-                for (int c = 0; c < D; ++c) acc[q][c] += pv[c] * xv;
+                const T2 v = *reinterpret_cast<const T2*>(zj + q * zstride);
+                acc[q][0] += (double)v.x;
+                acc[q][1] += (double)v.y;
               }
+          } else {
+#pragma unroll
+            for (int q = 0; q < kMaxSys; ++q)
+              if ((run >> q) & 1u)
+#pragma unroll
+                for (int c = 0; c < D; ++c) acc[q][c] += (double)zj[q * zstride + c];
+          }
+          // modes in groups of eight: the group's basis values loaded together
+#pragma unroll
+          for (int m0 = 0; m0 < KM; m0 += 8) {
+            if (m0 >= k) break;
+            double pv[8][D];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int m = m0 + u;
+              if constexpr (D == 2) {
+                typedef T T2 __attribute__((ext_vector_type(2)));
+                const T2 v = m < k ? *reinterpret_cast<const T2*>(pj + (size_t)m * g.nloc) : T2{0, 0};
+                pv[u][0] = (double)v.x;
+                pv[u][1] = (double)v.y;
+              } else {
+#pragma unroll
+                for (int c = 0; c < D; ++c) pv[u][c] = m < k ? (double)pj[(size_t)m * g.nloc + c] : 0.0;
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int m = m0 + u;
+              if (m < k) {
+#pragma unroll
+                for (int q = 0; q < kMaxSys; ++q)
+                  if ((run >> q) & 1u) {
+                    const double xv =
+                        staged ? xs[(q * cnt / k + sb) * k + m] : xj[(size_t)q * g.nt + m];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) acc[q][c] += pv[u][c] * xv;
+                  }
+              }
+            }
           }
         }
 #pragma unroll

@@ -117,6 +117,7 @@ struct Handle {
                                      // [nsys][T (T + 1) / 2][64][64]
   double* cpart = nullptr;           // tile partials of K_c^-1 y_c [nsys][T][T][64]
   double* build_ws = nullptr;        // work arrays of the preconditioner build
+  double* fscratch = nullptr;        // [kMaxSys][nel] element factors of the filter adjoint
   // one eigenproblem per distinct cell (tpcg_problem.dedup): signatures, the
   // distinct cells' subdomains, (duplicate, representative) pairs, flags of
   // the exact comparison; nrep = eigenproblems solved by the last build

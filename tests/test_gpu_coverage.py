@@ -315,7 +315,7 @@ def test_failed_allocation_leaves_the_handle_usable():
         handle(p, nsys=1)
     assert e.value.code == -2
     lib.tpcg_test_fail_alloc(0)
-    # 14 preconditioner arrays (FP64, dense coarse inverse), then the build workspace
+    # 18 preconditioner arrays (FP64, dense coarse inverse), then the build workspace
     for nth in (1, 5, 12, 14):
         h = handle(p, nsys=1)
         lib.tpcg_test_fail_alloc(nth)
