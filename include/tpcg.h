@@ -101,6 +101,11 @@ typedef struct {
                            HBM-resident factors and solves (0: only blocks the on-chip kernels
                            cannot take: more than 96 unknowns, an odd count, or layers of more
                            than 64 elements) */
+  int32_t coarse_band;  /* 1: the coarse level always as the HBM-resident block-tridiagonal
+                           factor (S_b^-1 and the multipliers, applied by chains of block
+                           products beside the local solves); 0: only when the coarse
+                           dimension exceeds coarse_dense_max and its blocks do not fit the
+                           on-chip factor kernels (more than 96 or odd) */
   int32_t dedup;        /* 1: one local eigenproblem per distinct cell (Sec. 2.4: equal
                            agglomerates of a periodic microstructure): subdomains whose cell
                            densities (of the representative system) and box supports are equal

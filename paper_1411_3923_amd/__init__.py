@@ -40,7 +40,8 @@ class Problem(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("eig_iters", ctypes.c_int32),
                 ("eig_extra", ctypes.c_int32), ("eig_shift", ctypes.c_double),
                 ("lambda_thresh", ctypes.c_double), ("coarse_dense_max", ctypes.c_int32),
-                ("big_min_nb", ctypes.c_int32), ("dedup", ctypes.c_int32)]
+                ("big_min_nb", ctypes.c_int32), ("coarse_band", ctypes.c_int32),
+                ("dedup", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -151,7 +152,7 @@ def load_library(path: str | None = None):
 
 def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.0, nu=0.3,
                  precision=FP64, eig_iters=0, eig_extra=0, eig_shift=0.0, lambda_thresh=0.0,
-                 coarse_dense_max=0, overlap=1, big_min_nb=0, dedup=0) -> Problem:
+                 coarse_dense_max=0, overlap=1, big_min_nb=0, dedup=0, coarse_band=0) -> Problem:
     """tpcg_problem; `sub` is the subdomain edge (an int) or a per-axis tuple."""
     pr = Problem()
     pr.dim = dim
@@ -166,6 +167,7 @@ def make_problem(dim, nel, sub, ncoarse, nsys_max=1, E0=1.0, Emin=1e-9, penal=3.
     pr.lambda_thresh, pr.coarse_dense_max = lambda_thresh, coarse_dense_max
     pr.big_min_nb = big_min_nb
     pr.dedup = dedup
+    pr.coarse_band = coarse_band
     return pr
 
 

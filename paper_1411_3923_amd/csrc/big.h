@@ -53,6 +53,26 @@ inline size_t sweep_ws_elems(int nmat, int ntb) {
 // flag[0] = 1 on a non-positive pivot. ws: sweep_ws_elems(nmat, ntb).
 void sweep_invert(double* S, size_t mstride, int nmat, int ntb, double* ws, int* flag,
                   hipStream_t st);
+// The same sweep over the pivots of the first npiv tiles only (the
+// remaining tiles receive the Schur complement and the multipliers).
+void sweep_pivots(double* S, size_t mstride, int nmat, int ntb, int npiv, double* ws, int* flag,
+                  hipStream_t st);
+
+// Coarse matrix as an HBM-resident block-tridiagonal LDL^T factorisation:
+// per system, row-major nbc x nbc blocks S_b^-1 [nblkc], L_{b,b-1} [nblkc]
+// (block 0 unused) and L_{b+1,b}^T [nblkc] (the last unused). From the
+// block-tridiagonal assembly Ac [nsys][nblkc][2][nbc][nbc].
+inline size_t coarse_band_elems(const Geometry& g) { return 3 * (size_t)g.nblkc * g.nbc * g.nbc; }
+inline size_t coarse_band_ws_elems(const Geometry& g, int nsys) {
+  const int ntb2 = 2 * big_ntb(g.nbc);
+  return (size_t)nsys * big_nl(ntb2) * kBTE + sweep_ws_elems(nsys, ntb2);
+}
+void coarse_band_factor(const Geometry& g, const double* Ac, size_t astride, int nsys,
+                        double* cband, double* ws, int* flag, hipStream_t st);
+// x_c = K_c^-1 y_c for every running system ([nsys][nt]): the forward chain
+// into cw ([nsys][nt]), the block-diagonal solve, the backward chain.
+void coarse_band_solve(const Geometry& g, const double* cband, const double* yc, double* xc,
+                       double* cw, int nsys, const Gate& gate, hipStream_t st);
 
 // Dense coarse path: K_c from its block-tridiagonal assembly (Ac [nsys][nblkc][2][nbc][nbc])
 // into lower tiles, the sweep, and the lower tiles of K_c^-1 (row-major, zero past nt) into cpk.

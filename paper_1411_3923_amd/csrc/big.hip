@@ -292,6 +292,133 @@ __global__ __launch_bounds__(kThreads) void k_coarse_pack(Geometry g, const doub
 }
 
 // ---------------------------------------------------------------------------
+// Coarse matrix as an HBM-resident block-tridiagonal factorisation (coarse
+// spaces too large for a dense inverse, with blocks too large for the on-chip
+// kernels). K_c = L D L^T with D = diag(S_b), L_{b+1,b} = A_{b+1,b} S_b^-1.
+// A window of two block rows holds [S_b; A_{b+1,b} A_{b+1,b+1}] as lower
+// tiles; sweeping only the first block's pivots leaves -S_b^-1 in the first
+// block, L_{b+1,b} below it and S_{b+1} in the second, which then moves up.
+// Stored per system, row-major nbc x nbc: S_b^-1, L_{b,b-1} and L_{b+1,b}^T.
+// ---------------------------------------------------------------------------
+
+// tiles of block row b + 1 of the window (second = 1: the coupling and
+// diagonal blocks of block row b + 1 of the assembly; second = 0, first
+// block: A_00), identity on the padding. grid (nl2, nsys).
+__global__ __launch_bounds__(kThreads) void k_cb_fill(Geometry g, const double* __restrict__ Ac,
+                                                     size_t astride, int br, int ntb, int second,
+                                                     double* __restrict__ W, size_t wstride) {
+  const int q = blockIdx.x, sys = blockIdx.y;
+  int I, J;
+  tile_rc(q, I, J);
+  const bool lead = I < ntb;                      // tile of the first block
+  if (second ? lead : !lead) return;
+  const double* A = Ac + (size_t)sys * astride;
+  const int nbc = g.nbc;
+  const size_t bsz = (size_t)nbc * nbc;
+  double* T = W + (size_t)sys * wstride + (size_t)q * kBTE;
+  for (int o = threadIdx.x; o < kBTE; o += kThreads) {
+    int r, c;
+    cdec(o, r, c);
+    const int R = kBT * (lead ? I : I - ntb) + r;     // row in its block
+    const bool cdiag = !lead && J >= ntb;
+    const int C = kBT * (cdiag ? J - ntb : J) + c;
+    double v;
+    if (lead) {
+      v = (R < nbc && C < nbc) ? A[(size_t)(2 * br) * bsz + (size_t)R * nbc + C] : (R == C ? 1.0 : 0.0);
+    } else if (cdiag) {
+      v = (R < nbc && C < nbc) ? A[(size_t)(2 * br) * bsz + (size_t)R * nbc + C] : (R == C ? 1.0 : 0.0);
+    } else {
+      v = (R < nbc && C < nbc) ? A[(size_t)(2 * br + 1) * bsz + (size_t)R * nbc + C] : 0.0;
+    }
+    T[o] = v;
+  }
+}
+
+// second block -> first block (tile (I, J), I, J >= ntb, to (I - ntb, J -
+// ntb); the targets lie before every source in tile order). grid (nl, nsys).
+__global__ __launch_bounds__(kThreads) void k_cb_shift(int ntb, double* __restrict__ W,
+                                                      size_t wstride) {
+  const int q = blockIdx.x, sys = blockIdx.y;
+  int I, J;
+  tile_rc(q, I, J);   // tile of the first block
+  double* Wm = W + (size_t)sys * wstride;
+  const double* src = Wm + (size_t)big_ltile(I + ntb, J + ntb) * kBTE;
+  double* dst = Wm + (size_t)q * kBTE;
+  for (int o = threadIdx.x; o < kBTE; o += kThreads) dst[o] = src[o];
+}
+
+// S_b^-1 = -(first block) and, with coupling = 1, L_{b+1,b} (the tiles below
+// it) and its transpose, row-major and trimmed to nbc. grid (nl2, nsys).
+__global__ __launch_bounds__(kThreads) void k_cb_extract(Geometry g, const double* __restrict__ W,
+                                                        size_t wstride, int ntb, int b,
+                                                        int coupling, double* __restrict__ cband) {
+  const int q = blockIdx.x, sys = blockIdx.y;
+  int I, J;
+  tile_rc(q, I, J);
+  const int nbc = g.nbc, nblk = g.nblkc;
+  const size_t bsz = (size_t)nbc * nbc;
+  double* base = cband + (size_t)sys * 3 * nblk * bsz;
+  double* Si = base + (size_t)b * bsz;
+  double* Lf = base + (size_t)(nblk + b + 1) * bsz;    // L_{b+1,b}
+  double* Lt = base + (size_t)(2 * nblk + b) * bsz;    // L_{b+1,b}^T
+  const double* T = W + (size_t)sys * wstride + (size_t)q * kBTE;
+  const bool lead = I < ntb;
+  if (!lead && (!coupling || J >= ntb)) return;
+  for (int o = threadIdx.x; o < kBTE; o += kThreads) {
+    int r, c;
+    cdec(o, r, c);
+    const double v = T[o];
+    if (lead) {
+      // one triangle of a diagonal tile gives both halves (its two halves
+      // agree only up to rounding)
+      if (I == J && r < c) continue;
+      const int R = kBT * I + r, C = kBT * J + c;
+      if (R < nbc && C < nbc) {
+        Si[(size_t)R * nbc + C] = -v;
+        Si[(size_t)C * nbc + R] = -v;
+      }
+    } else {
+      const int R = kBT * (I - ntb) + r, C = kBT * J + c;
+      if (R < nbc && C < nbc) {
+        Lf[(size_t)R * nbc + C] = v;
+        Lt[(size_t)C * nbc + R] = v;
+      }
+    }
+  }
+}
+
+// out = a - M v (a null: out = M v) for the nbc x nbc row-major blocks M of
+// every running system: block blockIdx.y of a batch, at stride bstride in M,
+// a, v and out (bvstride); eight rows per workgroup, two per wave.
+// grid (ceil(nbc / 8), nb, nsys).
+__global__ __launch_bounds__(kThreads) void k_cb_gemv(int nbc, const double* __restrict__ M,
+                                                     size_t msys, size_t bstride,
+                                                     const double* a, const double* __restrict__ v,
+                                                     double* out, size_t vsys, size_t bvstride,
+                                                     Gate gate) {
+  const int sys = blockIdx.z, bb = blockIdx.y;
+  if (!gate_running(gate, sys)) return;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int r0 = (blockIdx.x * 4 + w) * 2;
+  const double* Mb = M + (size_t)sys * msys + (size_t)bb * bstride;
+  const double* vb = v + (size_t)sys * vsys + (size_t)bb * bvstride;
+  double acc0 = 0.0, acc1 = 0.0;
+  const bool has0 = r0 < nbc, has1 = r0 + 1 < nbc;
+  for (int c = l; c < nbc; c += 64) {
+    const double x = vb[c];
+    if (has0) acc0 += Mb[(size_t)r0 * nbc + c] * x;
+    if (has1) acc1 += Mb[(size_t)(r0 + 1) * nbc + c] * x;
+  }
+  acc0 = wave_sum(acc0);
+  acc1 = wave_sum(acc1);
+  if (l == 0) {
+    const size_t ob = (size_t)sys * vsys + (size_t)bb * bvstride;
+    if (has0) out[ob + r0] = a ? a[ob + r0] - acc0 : acc0;
+    if (has1) out[ob + r0 + 1] = a ? a[ob + r0 + 1] - acc1 : acc1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Local factors
 // ---------------------------------------------------------------------------
 
@@ -1176,12 +1303,17 @@ bool local_is_big(const Geometry& g, int big_min_nb) {
 
 void sweep_invert(double* S, size_t mstride, int nmat, int ntb, double* ws, int* flag,
                   hipStream_t st) {
+  sweep_pivots(S, mstride, nmat, ntb, ntb, ws, flag, st);
+}
+
+void sweep_pivots(double* S, size_t mstride, int nmat, int ntb, int npiv, double* ws, int* flag,
+                  hipStream_t st) {
   if (nmat <= 0) return;
   double* pinv = ws;
   double* Wp = pinv + (size_t)nmat * kBTE;
   double* Vp = Wp + (size_t)nmat * ntb * kBTE;
   const int nl = big_nl(ntb);
-  for (int K = 0; K < ntb; ++K) {
+  for (int K = 0; K < npiv; ++K) {
     hipLaunchKernelGGL(k_sw_pivot, dim3(nmat), dim3(64), 0, st, S, mstride, K, pinv, flag);
     if (ntb > 1)
       hipLaunchKernelGGL(k_sw_panel, dim3(ntb, nmat), dim3(kThreads), 0, st, S, mstride, ntb, K,
@@ -1214,6 +1346,60 @@ size_t big_factor_ws_elems(const Geometry& g, int nsys) {
          + nmat * (size_t)bs.npad * bs.npad    // pass-1 products
          + nmat * (size_t)g.nb * 27            // coupling coefficients
          + sweep_ws_elems((int)nmat, bs.ntb);
+}
+
+void coarse_band_factor(const Geometry& g, const double* Ac, size_t astride, int nsys,
+                        double* cband, double* ws, int* flag, hipStream_t st) {
+  const int ntb = big_ntb(g.nbc), ntb2 = 2 * ntb;
+  const int nl = big_nl(ntb), nl2 = big_nl(ntb2);
+  const size_t wstride = (size_t)nl2 * kBTE;
+  double* W = ws;
+  double* sws = W + (size_t)nsys * wstride;
+  const int nblk = g.nblkc;
+  hipLaunchKernelGGL(k_cb_fill, dim3(nl2, nsys), dim3(kThreads), 0, st, g, Ac, astride, 0, ntb, 0,
+                     W, wstride);
+  for (int b = 0; b < nblk; ++b) {
+    if (b > 0)
+      hipLaunchKernelGGL(k_cb_shift, dim3(nl, nsys), dim3(kThreads), 0, st, ntb, W, wstride);
+    const int coupling = b + 1 < nblk;
+    if (coupling) {
+      hipLaunchKernelGGL(k_cb_fill, dim3(nl2, nsys), dim3(kThreads), 0, st, g, Ac, astride, b + 1,
+                         ntb, 1, W, wstride);
+      sweep_pivots(W, wstride, nsys, ntb2, ntb, sws, flag, st);
+    } else {
+      sweep_pivots(W, wstride, nsys, ntb, ntb, sws, flag, st);   // the first block's tiles alone
+    }
+    hipLaunchKernelGGL(k_cb_extract, dim3(coupling ? nl2 : nl, nsys), dim3(kThreads), 0, st, g, W,
+                       wstride, ntb, b, coupling, cband);
+  }
+}
+
+void coarse_band_solve(const Geometry& g, const double* cband, const double* yc, double* xc,
+                       double* cw, int nsys, const Gate& gate, hipStream_t st) {
+  const int nbc = g.nbc, nblk = g.nblkc, nt = g.nt;
+  const size_t bsz = (size_t)nbc * nbc;
+  const size_t msys = 3 * (size_t)nblk * bsz;
+  const double* Si = cband;
+  const double* Lf = cband + (size_t)nblk * bsz;
+  const double* Lt = cband + 2 * (size_t)nblk * bsz;
+  const unsigned gx = (unsigned)((nbc + 7) / 8);
+  // forward: w_0 = r_0, w_b = r_b - L_{b,b-1} w_{b-1}
+  hipMemcpy2DAsync(cw, sizeof(double) * nt, yc, sizeof(double) * nt, sizeof(double) * nbc, nsys,
+                   hipMemcpyDeviceToDevice, st);
+  for (int b = 1; b < nblk; ++b)
+    hipLaunchKernelGGL(k_cb_gemv, dim3(gx, 1, nsys), dim3(kThreads), 0, st, nbc,
+                       Lf + (size_t)b * bsz, msys, (size_t)0, yc + (size_t)b * nbc,
+                       cw + (size_t)(b - 1) * nbc, cw + (size_t)b * nbc, (size_t)nt, (size_t)0,
+                       gate);
+  // y_b = S_b^-1 w_b for every block at once
+  hipLaunchKernelGGL(k_cb_gemv, dim3(gx, nblk, nsys), dim3(kThreads), 0, st, nbc, Si, msys, bsz,
+                     (const double*)nullptr, cw, xc, (size_t)nt, (size_t)nbc, gate);
+  // backward: x_b = y_b - L_{b+1,b}^T x_{b+1}
+  for (int b = nblk - 2; b >= 0; --b)
+    hipLaunchKernelGGL(k_cb_gemv, dim3(gx, 1, nsys), dim3(kThreads), 0, st, nbc,
+                       Lt + (size_t)b * bsz, msys, (size_t)0, xc + (size_t)b * nbc,
+                       xc + (size_t)(b + 1) * nbc, xc + (size_t)b * nbc, (size_t)nt, (size_t)0,
+                       gate);
 }
 
 namespace {

@@ -78,6 +78,7 @@ const char* make_geometry(const tpcg_problem& pr, Geometry& g) {
   g.nt = g.nsub * g.k;
   g.dense_max = pr.coarse_dense_max > 0 ? pr.coarse_dense_max : kDenseCoarse;
   g.submap = nullptr;
+  g.cband = pr.coarse_band ? 1 : 0;   // set below once the coarse blocks are known
   // packed factor records: B_{b+1} reaches pe diagonals below its main one
   {
     int64_t w = 1;
@@ -93,6 +94,7 @@ const char* make_geometry(const tpcg_problem& pr, Geometry& g) {
   g.ebn = g.s + 3;
   g.nebox = d == 3 ? g.ebn * g.ebn * g.ebn : g.ebn * g.ebn;
   g.ndpe = d == 3 ? 24 : 8;
+  if (g.nt > g.dense_max && !coarse_btri_fits(g)) g.cband = 1;
   return nullptr;
 }
 
@@ -108,9 +110,7 @@ std::string precond_limits(const Geometry& g, int big) {
   } else if (stage_bucket(stage_regs_for<double>(g.nb, g.pe)) < 0) {
     return "factor records too long for the staged solve kernels";
   }
-  if (g.nt > g.dense_max || coarse_btri_fits(g)) {
-    if (g.nbc > kMaxNb || (g.nbc & 1))
-      return "coarse blocks larger than 96 or of odd size (coarse dimension above coarse_dense_max)";
+  if (!g.cband && (g.nt > g.dense_max || coarse_btri_fits(g))) {
     if (stage_bucket(stage_regs_for<double>(g.nbc, g.pec)) < 0)
       return "coarse factor records too long for the staged solve kernels";
   }
@@ -140,11 +140,12 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   if (mixed) p += sizeof(double) * nsys * (size_t)g.nel;
   p += sizeof(int) * (size_t)g.nsub;
   p += (sizeof(unsigned long long) + 4 * sizeof(int)) * (size_t)g.nsub;   // distinct-cell maps
-  if (g.nt <= g.dense_max) {
+  if (g.nt <= g.dense_max && !g.cband) {
     const size_t T = coarse_tiles(g.nt);
     p += sizeof(double) * nsys * (T * (T + 1) / 2 * kCT * kCT + T * T * kCT);
   }
-  if (g.nt > g.dense_max || coarse_btri_fits(g)) p += sizeof(double) * nsys * crec;
+  if (!g.cband && (g.nt > g.dense_max || coarse_btri_fits(g))) p += sizeof(double) * nsys * crec;
+  if (g.cband) p += sizeof(double) * nsys * (coarse_band_elems(g) + (size_t)g.nt);
   p += 5 * sizeof(double) * nsys * g.ndof;
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
@@ -209,7 +210,8 @@ void release(Handle* h) {
                   h->emod,  h->twist, h->emod64, h->cfac, h->cpk, h->cpart, h->r, h->z,
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
                   h->dflag, h->build_ws, h->gm_V, h->gm_w, h->gm_i, h->gm_flags, h->gm_out,
-                  h->cell_sig, h->submap_d, h->dedup_pairs, h->dedup_flag, h->fscratch};
+                  h->cell_sig, h->submap_d, h->dedup_pairs, h->dedup_flag, h->fscratch,
+                  h->cband, h->cband_w};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);
@@ -563,12 +565,16 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     a.add_bytes(h->emod, ts * ns * (size_t)g.nel);
     if (!h->big) a.add(h->twist, (size_t)ns * g.nsub * g.nb * (g.nb + 1) / 2);
     if (h->mixed) a.add(h->emod64, (size_t)ns * g.nel);
-    if (g.nt <= g.dense_max) {
+    if (g.nt <= g.dense_max && !g.cband) {
       const size_t T = coarse_tiles(g.nt);
       a.add(h->cpk, (size_t)ns * T * (T + 1) / 2 * kCT * kCT);
       a.add(h->cpart, (size_t)ns * T * T * kCT);
     }
-    if (g.nt > g.dense_max || coarse_btri_fits(g)) a.add(h->cfac, ns * cfsz);
+    if (!g.cband && (g.nt > g.dense_max || coarse_btri_fits(g))) a.add(h->cfac, ns * cfsz);
+    if (g.cband) {
+      a.add(h->cband, (size_t)ns * coarse_band_elems(g));
+      a.add(h->cband_w, (size_t)ns * g.nt);
+    }
     a.add_bytes(h->zloc, ts * ns * (size_t)g.nsub * g.nloc);
     a.add(h->yc, ns * (size_t)g.nt);
     a.add(h->xc, ns * (size_t)g.nt);

@@ -7,6 +7,7 @@
 //   3. coarse solve x_c = K_c^-1 y_c                             } forked stream
 //   4. extension z(n) = sum_{j owns n} (zloc_j(n) + (Phi_j x_c,j)(n)), with
 //      the fused partial sums of r.z (and r.z_old for the flexible beta).
+#include "big.h"
 #include "btri.h"
 
 namespace tpcg {
@@ -478,7 +479,8 @@ void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate&
   } else {
     hipEventRecord(h.fork, st);
     hipStreamWaitEvent(h.side, h.fork, 0);
-    coarse_launch(h, nsys, gate, h.side);
+    if (g.cband) coarse_band_solve(g, h.cband, h.yc, h.xc, h.cband_w, nsys, gate, h.side);
+    else coarse_launch(h, nsys, gate, h.side);
     hipEventRecord(h.join, h.side);
   }
   mark(0);
@@ -501,6 +503,8 @@ void launch_coarse_only(Handle& h, const double* r, int nsys, const Gate& gate, 
                        h.cpk, h.yc, h.cpart, gate);
     hipLaunchKernelGGL(k_coarse_gemv_sum, dim3((g.nt + kThreads - 1) / kThreads, nsys),
                        dim3(kThreads), 0, st, g, h.cpart, h.xc, gate);
+  } else if (g.cband) {
+    coarse_band_solve(g, h.cband, h.yc, h.xc, h.cband_w, nsys, gate, st);
   } else {
     coarse_launch(h, nsys, gate, st);
   }

@@ -798,7 +798,8 @@ size_t build_ws_elems(const tpcg_problem& pr, const Geometry& g, int big, int ms
   const size_t wsz = (size_t)g.nsub * g.nebox * g.dim * g.k;
   const size_t asm_coarse = (size_t)g.nblkc * 2 * g.nbc * g.nbc;
   size_t coarse = (wsz + asm_coarse) * pr.nsys_max;
-  if (g.nt <= g.dense_max) coarse += coarse_dense_ws_elems(g, pr.nsys_max);
+  if (g.nt <= g.dense_max && !g.cband) coarse += coarse_dense_ws_elems(g, pr.nsys_max);
+  if (g.cband) coarse += coarse_band_ws_elems(g, pr.nsys_max);
   if (big) coarse += big_factor_ws_elems(g, pr.nsys_max);
   return std::max(eig, coarse);
 }
@@ -976,8 +977,10 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int wi
   double* W = h.build_ws;                 // [nsys][wsz]
   double* Ac = W + wsz * nsys;
   double* Sc = Ac + asm_coarse * nsys;    // dense coarse path: K_c's tiles, then the sweep's work
-  double* cws = Sc + (g.nt <= g.dense_max ? (size_t)nsys * big_nl(big_ntb(g.nt)) * kBTE : 0);
-  double* bws = Sc + (g.nt <= g.dense_max ? coarse_dense_ws_elems(g, nsys) : 0);   // big local factors
+  const bool dense = g.nt <= g.dense_max && !g.cband;
+  double* cws = Sc + (dense ? (size_t)nsys * big_nl(big_ntb(g.nt)) * kBTE : 0);
+  double* bws = Sc + (dense ? coarse_dense_ws_elems(g, nsys)
+                            : (g.cband ? coarse_band_ws_elems(g, nsys) : 0));   // big local factors
   hipMemsetAsync(Ac, 0, sizeof(double) * asm_coarse * nsys, st);
   const int nnb = g.dim == 3 ? 27 : 9;
   {
@@ -1068,7 +1071,9 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int wi
   // when the coarse blocks fit those on-chip kernels, else by the block
   // sweep on the matrix cores; for coarse spaces too large for a dense
   // inverse, the block-tridiagonal factor alone
-  if (h.cpk && !coarse_btri_fits(g)) {
+  if (g.cband) {
+    coarse_band_factor(g, Ac, asm_coarse, nsys, h.cband, Sc, h.dflag, st);
+  } else if (h.cpk && !coarse_btri_fits(g)) {
     coarse_dense_inverse(g, Ac, asm_coarse, nsys, Sc, cws, h.cpk, h.dflag, st);
   } else {
     launch_factor<double>(Ac, h.cfac, nsys, csh, h.dflag, st);

@@ -49,6 +49,7 @@ struct Geometry {
   int ebn;                           // nodes per extended box edge (s + 3)
   int nebox;                         // nodes per extended box
   int ndpe;                          // DOFs per element (8 or 24)
+  int cband;                         // coarse level as the HBM-resident block-tridiagonal factor
   const int* submap;                 // eigen phase over distinct cells only: the subdomain of
                                      // each launch index (device array; nullptr: identity)
 };
@@ -118,6 +119,8 @@ struct Handle {
   double* cpart = nullptr;           // tile partials of K_c^-1 y_c [nsys][T][T][64]
   double* build_ws = nullptr;        // work arrays of the preconditioner build
   double* fscratch = nullptr;        // [kMaxSys][nel] element factors of the filter adjoint
+  double* cband = nullptr;           // HBM-resident coarse factor [nsys][coarse_band_elems]
+  double* cband_w = nullptr;         // its solve's forward-chain vector [nsys][nt]
   // one eigenproblem per distinct cell (tpcg_problem.dedup): signatures, the
   // distinct cells' subdomains, (duplicate, representative) pairs, flags of
   // the exact comparison; nrep = eigenproblems solved by the last build
