@@ -254,7 +254,7 @@ def with_density(p: Problem, density: str, seed: int | None = None) -> Problem:
 # optimiser's requests; no part of the method)
 # ----------------------------------------------------------------------------
 
-SERVING_MESHES_2D = [(256, 128), (512, 256), (1024, 512), (2048, 1024)]
+SERVING_MESHES_2D = [(256, 128), (512, 256), (1024, 512), (2048, 1024), (4096, 3072)]
 SERVING_MESHES_3D = [(48, 48, 48), (96, 48, 48)]
 
 
