@@ -379,6 +379,8 @@ def run_serving(args, precision):
                 r.solves.append(res)
                 r.work += r.p.n_dof * sum(res["iters"])
                 r.step += 1
+                print(f"serving: {r.p.name} update {r.step} iters {res['iters']} "
+                      f"at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
                 if r.step < args.serving_updates:
                     r.submit()
                 else:

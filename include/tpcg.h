@@ -210,6 +210,19 @@ int tpcg_pcg_solve(tpcg_handle* h, const double* rho_phys, const double* f, doub
                    int32_t nsys, double rtol, int32_t maxit, tpcg_info* info);
 
 /*
+ * The same solve enqueued on the handle's stream without any host wait (the
+ * serving path's form): every iteration up to maxit is launched, each system
+ * stopping at its own convergence (the launches after it return at once),
+ * then the per-system results are written to info_dev (device memory, [nsys]
+ * tpcg_info records; seconds = 0). Returns after enqueueing; synchronise the
+ * stream before reading u or info_dev. Results are bitwise those of
+ * tpcg_pcg_solve with the same arguments. Choose maxit near the expected
+ * count: every iteration up to it is launched.
+ */
+int tpcg_pcg_solve_async(tpcg_handle* h, const double* rho_phys, const double* f, double* u,
+                         int32_t nsys, double rtol, int32_t maxit, tpcg_info* info_dev);
+
+/*
  * z = B r with the paper's multiplicative preconditioner (Sec. 2.4.2): one
  * symmetric Gauss-Seidel step S from zero, the MsFEM coarse correction, one
  * more step:  x = S(r; 0);  x += Phi K_c^-1 Phi^T (r - K x);  z = S(r; x).

@@ -80,7 +80,7 @@ EXPORTS = ["tpcg_build_partition", "tpcg_workspace_bytes", "tpcg_build_coarse_ba
            "tpcg_server_open", "tpcg_server_submit", "tpcg_server_wait", "tpcg_server_test",
            "tpcg_server_close", "tpcg_server_free_bytes", "tpcg_server_destroy",
            "tpcg_apply_msfem", "tpcg_gmres_solve", "tpcg_set_autotune", "tpcg_query_tune",
-           "tpcg_query_unique_cells"]
+           "tpcg_query_unique_cells", "tpcg_pcg_solve_async"]
 
 
 def load_library(path: str | None = None):
@@ -101,6 +101,7 @@ def load_library(path: str | None = None):
     lib.tpcg_apply_precond.argtypes = [P, P, P, I32]
     lib.tpcg_pcg_solve.argtypes = [P, P, P, P, I32, D, I32, ctypes.POINTER(Info)]
     lib.tpcg_apply_msfem.argtypes = [P, P, P, P, I32]
+    lib.tpcg_pcg_solve_async.argtypes = [P, P, P, P, I32, D, I32, P]
     lib.tpcg_set_autotune.argtypes = [P, I32]
     lib.tpcg_query_unique_cells.argtypes = [P]
     lib.tpcg_query_tune.argtypes = [P, ctypes.POINTER(I32)]
@@ -302,6 +303,27 @@ class Handle:
                                        _ptr(u, torch.float64, nsys * self.n_dof), nsys, rtol, maxit,
                                        restart, precond, info)
         self._check(rc, allow_warn=True)
+        return [dict(iters=i.iters, status=i.status, relres=i.relres,
+                     true_relres=i.true_relres, seconds=i.seconds) for i in info]
+
+    def pcg_solve_async(self, rho_phys, f, u, info_dev, rtol=1e-8, maxit=1000):
+        """Enqueue the solve; per-system results go to info_dev (a device
+        uint8 tensor of nsys * sizeof(Info) bytes, read with read_info)."""
+        import torch
+        nsys = f.numel() // self.n_dof
+        if info_dev.numel() < nsys * ctypes.sizeof(Info) or info_dev.device.type != "cuda":
+            raise ValueError("info_dev: device tensor of nsys * sizeof(Info) bytes")
+        rc = self.lib.tpcg_pcg_solve_async(self.h, _ptr(rho_phys, torch.float64, nsys * self.n_el),
+                                           _ptr(f, torch.float64, nsys * self.n_dof),
+                                           _ptr(u, torch.float64, nsys * self.n_dof), nsys, rtol,
+                                           maxit, ctypes.c_void_p(info_dev.data_ptr()))
+        self._check(rc)
+
+    @staticmethod
+    def read_info(info_dev, nsys):
+        """Per-system results written by pcg_solve_async (synchronises)."""
+        raw = bytes(info_dev.cpu().numpy().tobytes())[: nsys * ctypes.sizeof(Info)]
+        info = (Info * nsys).from_buffer_copy(raw)
         return [dict(iters=i.iters, status=i.status, relres=i.relres,
                      true_relres=i.true_relres, seconds=i.seconds) for i in info]
 

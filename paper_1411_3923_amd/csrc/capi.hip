@@ -275,6 +275,18 @@ double local_solve_bytes(const Geometry& g, int elem, int big) {
   return g.nsub * per;
 }
 
+// the summary values [nsys][4] (iterations, status, recursive and true
+// relative residual) as tpcg_info records in device memory
+__global__ void k_info_pack(const double* __restrict__ dout, int nsys, tpcg_info* __restrict__ info) {
+  const int sys = threadIdx.x;
+  if (sys >= nsys) return;
+  info[sys].iters = (int32_t)dout[4 * sys + 0];
+  info[sys].status = (int32_t)dout[4 * sys + 1];
+  info[sys].relres = dout[4 * sys + 2];
+  info[sys].true_relres = dout[4 * sys + 3];
+  info[sys].seconds = 0.0;
+}
+
 Gate make_gate(const Handle* h, int rr_slot, int it, int maxit, double tol2, int enabled) {
   Gate g;
   g.parts = h->parts;
@@ -625,17 +637,20 @@ int tpcg_apply_precond(tpcg_handle* hh, const double* r, double* z, int32_t nsys
   return check_hip(h, "tpcg_apply_precond");
 }
 
-int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, double* u,
-                   int32_t nsys, double rtol, int32_t maxit, tpcg_info* info) {
+// info -> host results after polling (the synchronous solve); dinfo ->
+// device results, every iteration up to maxit enqueued with no host wait
+static int pcg_solve_impl(tpcg_handle* hh, const double* rho_phys, const double* f, double* u,
+                          int32_t nsys, double rtol, int32_t maxit, tpcg_info* info,
+                          tpcg_info* dinfo) {
   Handle* h = H(hh);
   if (!h) return TPCG_EINVAL;
   if (h->sticky) return fail(hh, TPCG_EHIP, "handle has a sticky HIP error");
   if (!h->basis_ready) return fail(hh, TPCG_ESTATE, "preconditioner not built");
-  if (!rho_phys || !f || !u || !info) return fail(hh, TPCG_EINVAL, "NULL argument");
+  if (!rho_phys || !f || !u || (!info && !dinfo)) return fail(hh, TPCG_EINVAL, "NULL argument");
   if (!aligned16(f) || !aligned16(u)) return fail(hh, TPCG_EINVAL, "vectors must be 16-byte aligned");
   if (nsys != h->nsys_built) return fail(hh, TPCG_EINVAL, "nsys differs from the build");
   if (!(rtol > 0.0) || maxit < 0) return fail(hh, TPCG_EINVAL, "rtol must be > 0 and maxit >= 0");
-  tune_before_solve(*h);
+  if (!dinfo) tune_before_solve(*h);
   hipStream_t st = h->stream;
   const double tol2 = rtol * rtol;
   const int flexible = h->mixed;
@@ -684,6 +699,18 @@ int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, dou
     launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
     if (!fused) launch_update_p(*h, nsys, gn, 0, st);
   };
+  if (dinfo) {
+    // asynchronous: every iteration enqueued (the gates stop each system at
+    // its own convergence; the launches after it return at once), then the
+    // summary into device memory
+    for (int it = 0; it < maxit; ++it) iteration(it, false, it == 0, -2, pcur, pnext, st);
+    Gate gf = make_gate(h, (maxit & 1) ? kPartRR1 : kPartRR0, maxit, maxit, tol2, 1);
+    launch_apply_K(*h, rho_phys, u, h->q, nsys, -1, nog, st);
+    double* dout = h->parts + (size_t)kNumPartSlots * kMaxSys * kMaxParts;
+    launch_summary(*h, f, nsys, gf, dout, st);
+    hipLaunchKernelGGL(k_info_pack, dim3(1), dim3(64), 0, st, dout, nsys, dinfo);
+    return check_hip(h, "tpcg_pcg_solve_async");
+  }
   // Chunks after the first replay a captured graph of poll_every iterations
   // (a chunk starts at an even iteration with the direction buffers in their
   // initial order, so one graph serves every chunk); the block coarse solve
@@ -919,6 +946,17 @@ int tpcg_gmres_solve(tpcg_handle* hh, const double* rho_phys, const double* f, d
   if (worst == TPCG_EBREAKDOWN) h->err = "GMRES breakdown (NaN or a zero rotation)";
   else if (worst == TPCG_ENOCONV) h->err = "maxit reached before rtol";
   return worst;
+}
+
+int tpcg_pcg_solve(tpcg_handle* hh, const double* rho_phys, const double* f, double* u,
+                   int32_t nsys, double rtol, int32_t maxit, tpcg_info* info) {
+  return pcg_solve_impl(hh, rho_phys, f, u, nsys, rtol, maxit, info, nullptr);
+}
+
+int tpcg_pcg_solve_async(tpcg_handle* hh, const double* rho_phys, const double* f, double* u,
+                         int32_t nsys, double rtol, int32_t maxit, tpcg_info* info_dev) {
+  if (!info_dev) return fail(hh, TPCG_EINVAL, "NULL info");
+  return pcg_solve_impl(hh, rho_phys, f, u, nsys, rtol, maxit, nullptr, info_dev);
 }
 
 int tpcg_compliance_and_sensitivity(tpcg_handle* hh, const double* rho_phys, const double* u,
