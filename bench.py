@@ -559,7 +559,6 @@ def loop_bytes(nsys=3, nelx=1024, nely=512, sub=32, k=6):
     return {
         "k_apply_q4": 4 * v + 8 * nsys * nel + ndof,          # z, p read; p', K p' written; moduli, flags
         "k_update_xr": 6 * v,                                  # u, p, r, q read; u, r written
-        "k_update_p": 3 * v,                                   # z, p read; p written (3-d only)
         "k_extend": zl + phi + 2 * v + ndof,                   # zloc, Phi, r read; z written
         "k_restrict": phi + zl,                                # Phi and the boxes of r
         # lower 64 x 64 tiles of K_c^-1 read, tile partials written; the
@@ -650,7 +649,7 @@ def summarize_loop(fetch_csv, write_csv, trace_csv, command, out):
               "| kernel | launches | avg us | measured MB | measured GB/s | % peak "
               "| algorithmic MB | algorithmic GB/s |",
               "|---|---:|---:|---:|---:|---:|---:|---:|"]
-    for name in ["k_apply_q4", "k_update_xr", "k_update_p", "k_restrict", "k_local_solves",
+    for name in ["k_apply_q4", "k_update_xr", "k_restrict", "k_local_solves",
                  "k_coarse_gemv_tiles", "k_coarse_gemv_sum", "k_extend"]:
         fv, wv, dv = fetch.get(name, []), write.get(name, []), dur.get(name, [])
         if not fv or not dv:

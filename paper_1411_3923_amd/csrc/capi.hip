@@ -520,6 +520,11 @@ int tpcg_build_partition(const tpcg_problem* prob, const uint8_t* fixed_mask, vo
       delete h;
       return TPCG_EINVAL;
     }
+  } else if (!h8_structured(K0.data(), h->K0h8)) {
+    fprintf(stderr, "tpcg_build_partition: H8 element matrix without the cube's structure\n");
+    release(h);
+    delete h;
+    return TPCG_EINVAL;
   }
   hipMemcpy(h->fixed, fixed_mask, g.ndof, hipMemcpyHostToDevice);
   hipMemset(h->istate, 0, sizeof(int) * kNumState * kMaxSys);
@@ -669,12 +674,10 @@ static int pcg_solve_impl(tpcg_handle* hh, const double* rho_phys, const double*
   h->prof_n = 0;
   launch_precond(*h, h->r, h->z, nsys, g0, kPartRZ0, -1, flexible, st);
   launch_beta(*h, nsys, g0, kPartRZ0, flexible, 1, st);
-  // 2-d: the direction update p = z + beta p runs inside the next operator
-  // launch, alternating between two buffers; 3-d: its own kernel
-  const bool fused = h->g.dim == 2;
+  // the direction update p = z + beta p runs inside the next operator
+  // launch, alternating between two buffers
   double* pcur = h->p;
   double* pnext = h->p2;
-  if (!fused) launch_update_p(*h, nsys, g0, 1, st);
   int* itbase = h->istate + kStIter * kMaxSys;
   // one PCG iteration; `itg` is the gates' iteration (absolute, or an offset
   // from the device counter when `rel`), its parity picks the partial slots
@@ -686,18 +689,13 @@ static int pcg_solve_impl(tpcg_handle* hh, const double* rho_phys, const double*
     Gate gi = make_gate(h, rr_now, itg, maxit, tol2, 1);
     Gate gn = make_gate(h, rr_next, itg + 1, maxit, tol2, 1);
     if (rel) gi.itbase = gn.itbase = itbase;
-    if (fused) {
-      launch_apply_K_dir(*h, rho_phys, h->z, pc, pn, h->q, nsys, kPartPQ, gi, first, st);
-      std::swap(pc, pn);
-    } else {
-      launch_apply_K(*h, rho_phys, pc, h->q, nsys, kPartPQ, gi, st);
-    }
+    launch_apply_K_dir(*h, rho_phys, h->z, pc, pn, h->q, nsys, kPartPQ, gi, first, st);
+    std::swap(pc, pn);
     launch_update_xr(*h, u, pc, nsys, gi, st);
     Gate gt = gn;   // the restriction takes this iteration's residual test
     gt.test = 1;
     launch_precond(*h, h->r, h->z, nsys, gt, rz_next, prof_it, flexible, st);
     launch_beta(*h, nsys, gn, rz_next, flexible, 0, st);
-    if (!fused) launch_update_p(*h, nsys, gn, 0, st);
   };
   if (dinfo) {
     // asynchronous: every iteration enqueued (the gates stop each system at

@@ -4,9 +4,12 @@
 // Each node's row is gathered from the node's elements: for each element e
 // around the node, the rows of E_e K0 that belong to the node times the
 // element's nodal displacements. No atomics; each output is written once.
-// K0 lives in LDS; the SIMP modulus is evaluated in the kernel.
+// Both kernels stage a tile's halo in LDS and take K0 from scalar registers
+// (the element matrices' symmetry leaves eight distinct entries in 2-d and
+// twelve classes in 3-d); the SIMP modulus is evaluated in the kernel.
 #include <algorithm>
 #include <cmath>
+#include <utility>
 
 #include "tpcg_internal.h"
 
@@ -197,59 +200,224 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   }
 }
 
+// H8: the mesh is cut into tiles of kBX x kBY x kBZ nodes, one node per
+// thread (a wave is one z-layer of the tile). A workgroup stages the tile's
+// one-node halo of P x in LDS, component-major so that the lanes of a wave
+// read consecutive doubles, and the moduli of the elements touching the tile
+// (zero outside the mesh, as are the halo values there). A thread then takes
+// its node's 27 neighbours in turn: it reads the neighbour's three values once
+// and adds them into t_a, the partial row of the node as corner a of each of
+// its 8 elements that also holds the neighbour; the row is sum_a E_a t_a.
+//
+// The trilinear unit-cube matrix has twelve classes of entries. Reflect the
+// element so that corner a goes to corner 0: corner b goes to the corner e
+// with e_j = |p_b,j - p_a,j| (p: the corner's position), and the displacement
+// components along the reflected axes change sign. So
+//   K0[(a,i),(b,c)] = tau_i(a) tau_c(a) R(e)[i][c],  tau_j(a) = -1 if p_a,j = 1,
+// where R(e) is the block of corner 0's rows. The axis permutations fix
+// corner 0, and with the symmetry of K0 they leave twelve values in R, up to
+// sign (h8_class). Class and sign are compile-time functions of the loop
+// counters; the twelve values are uniform over the launch and passed by
+// value, so every product reads K0 from scalar registers.
+constexpr int kBX = 16, kBY = 4, kBZ = 4;                        // nodes per tile
+constexpr int kGX = kBX + 2, kGY = kBY + 2, kGZ = kBZ + 2;       // halo of nodes
+constexpr int kFX = kBX + 1, kFY = kBY + 1, kFZ = kBZ + 1;       // elements touching it
+constexpr int kGN = kGX * kGY * kGZ, kGV = 3 * kGN, kFN = kFX * kFY * kFZ;
+static_assert(kBX * kBY * kBZ == kThreads, "one node per thread");
+
+struct H8Row {
+  double q[12];
+};
+
+struct H8Cls {
+  int q, s;   // class and sign
+};
+
+// class and sign of R(e)[i][c], e given as its three bits
+__host__ __device__ constexpr H8Cls h8_class(int ex, int ey, int ez, int i, int c) {
+  const int ei = i == 0 ? ex : (i == 1 ? ey : ez);
+  const int ec = c == 0 ? ex : (c == 1 ? ey : ez);
+  const int n1 = ex + ey + ez;
+  if (n1 == 0) return {i == c ? 0 : 1, 1};
+  if (n1 == 3) return {i == c ? 10 : 11, 1};
+  if (n1 == 1) {   // b along one edge from a
+    if (i == c) return {ei ? 2 : 3, 1};
+    if (ei) return {4, 1};
+    if (ec) return {4, -1};
+    return {5, 1};
+  }
+  // b across a face from a
+  if (i == c) return {ei ? 6 : 7, 1};
+  if (ei && ec) return {8, 1};
+  return {9, ec ? -1 : 1};
+}
+
+__host__ __device__ constexpr int corner_bit(int a, int j) {
+  return j == 0 ? ((a & 3) == 1 || (a & 3) == 2) : (j == 1 ? (a & 3) >= 2 : a >= 4);
+}
+
+__host__ __device__ inline int h8_tiles(const Geometry& g) {
+  return ((g.nnx + kBX - 1) / kBX) * ((g.nny + kBY - 1) / kBY) * ((g.nnz + kBZ - 1) / kBZ);
+}
+
+// tr[A] += the products of neighbour M's values u with the K0 entries that
+// couple corner A to the neighbour's corner (when the neighbour is a corner
+// of the element in which the node is corner A); every index and sign is a
+// compile-time constant
+template <int M, int A, int IC>
+__device__ __forceinline__ void h8_term(double (&tr)[8][3], const double (&u)[3], const H8Row& K) {
+  constexpr int mx = M % 3 - 1, my = (M / 3) % 3 - 1, mz = M / 9 - 1;
+  constexpr int bx = corner_bit(A, 0) + mx, by = corner_bit(A, 1) + my, bz = corner_bit(A, 2) + mz;
+  if constexpr (bx >= 0 && bx <= 1 && by >= 0 && by <= 1 && bz >= 0 && bz <= 1) {
+    constexpr int I = IC / 3, C = IC % 3;
+    constexpr H8Cls k = h8_class(mx != 0, my != 0, mz != 0, I, C);
+    constexpr int sg = k.s * (corner_bit(A, C) ? -1 : 1);
+    tr[A][I] += (sg > 0 ? K.q[k.q] : -K.q[k.q]) * u[C];
+  }
+}
+
+template <int M, int A, int... IC>
+__device__ __forceinline__ void h8_corner(double (&tr)[8][3], const double (&u)[3], const H8Row& K,
+                                          std::integer_sequence<int, IC...>) {
+  (h8_term<M, A, IC>(tr, u, K), ...);
+}
+
+template <int M, int... A>
+__device__ __forceinline__ void h8_neighbour(double (&tr)[8][3], const double* __restrict__ x0,
+                                             const double* __restrict__ x1,
+                                             const double* __restrict__ x2, const H8Row& K,
+                                             std::integer_sequence<int, A...>) {
+  constexpr int off = (M % 3 - 1) + kGX * ((M / 3) % 3 - 1) + kGX * kGY * (M / 9 - 1);
+  const double u[3] = {x0[off], x1[off], x2[off]};
+  (h8_corner<M, A>(tr, u, K, std::make_integer_sequence<int, 9>{}), ...);
+  // a row of three neighbours at a time: the next row's loads are not
+  // hoisted above this row's products (fewer live registers)
+  if constexpr (M % 3 == 2) __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int... M>
+__device__ __forceinline__ void h8_rows(double (&tr)[8][3], const double* __restrict__ x0,
+                                        const double* __restrict__ x1,
+                                        const double* __restrict__ x2, const H8Row& K,
+                                        std::integer_sequence<int, M...>) {
+  (h8_neighbour<M>(tr, x0, x1, x2, K, std::make_integer_sequence<int, 8>{}), ...);
+}
+
+// P3 and DIR as for Q4
+template <bool P3, bool DIR>
 __global__ __launch_bounds__(kThreads) void k_apply_h8(
     Geometry g, const double* __restrict__ rho, const double* __restrict__ x,
-    double* __restrict__ y, const uint8_t* __restrict__ fixed, const double* __restrict__ K0,
-    double E0, double Emin, double penal, double* __restrict__ parts, Gate gate) {
-  __shared__ double K0s[576];
+    double* __restrict__ y, const uint8_t* __restrict__ fixed, H8Row K, double E0, double Emin,
+    double penal, double* __restrict__ parts, Gate gate, const double* __restrict__ zdir,
+    double* __restrict__ pnew, const double* __restrict__ beta, int first) {
+  constexpr int kGQ = (kGV + kThreads - 1) / kThreads;   // staged values per thread
+  constexpr int kFQ = (kFN + kThreads - 1) / kThreads;
+  __shared__ double xh[3][kGN];
+  __shared__ double Eh[kFN];
   __shared__ double sh[4];
   const int sys = blockIdx.y;
   if (!gate_running(gate, sys)) return;
-  for (int i = threadIdx.x; i < 576; i += kThreads) K0s[i] = K0[i];
-  __syncthreads();
+  const int nnx = g.nnx, nny = g.nny, nnz = g.nnz;
+  const int ntx = (nnx + kBX - 1) / kBX, nty = (nny + kBY - 1) / kBY;
+  const int ntiles = h8_tiles(g);
+  // XCD-aware order (workgroups whose index agrees mod 8 share an XCD): each
+  // such group takes a contiguous range of slots and each slot a contiguous
+  // range of tiles, so that neighbouring tiles' shared halo lines meet in one L2
+  const int W = gridDim.x, grp = blockIdx.x % 8, per = W / 8, rem = W % 8;
+  const int slot = (grp < rem ? grp * (per + 1) : rem * (per + 1) + (grp - rem) * per) +
+                   blockIdx.x / 8;
+  const int tbeg = (int)((int64_t)slot * ntiles / W);
+  const int tend = (int)((int64_t)(slot + 1) * ntiles / W);
   const double* xs = x + (size_t)sys * g.ndof;
   double* ys = y + (size_t)sys * g.ndof;
   const double* rs = rho + (size_t)sys * g.nel;
-  const int nnx = g.nnx, nny = g.nny;
-  const int64_t lay = (int64_t)nnx * nny;
+  const double* zs = DIR ? zdir + (size_t)sys * g.ndof : nullptr;
+  double* ps = DIR ? pnew + (size_t)sys * g.ndof : nullptr;
+  const double bt = DIR && !first ? beta[sys] : 0.0;
+  const int t = threadIdx.x;
+  const int lx = t % kBX, ly = (t / kBX) % kBY, lz = t / (kBX * kBY);
+  const int hc = (lx + 1) + kGX * ((ly + 1) + kGY * (lz + 1));   // the node in the halo
+  const int ec = lx + kFX * (ly + kFY * lz);   // its element at offset (-1, -1, -1)
   double acc = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < g.nnodes;
-       n += (int64_t)gridDim.x * kThreads) {
-    const int ix = (int)(n % nnx);
-    const int iy = (int)((n / nnx) % nny);
-    const int iz = (int)(n / lay);
-    double yv[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < 8; ++a) {
-      const int dx = (a & 3) == 1 || (a & 3) == 2;
-      const int dy = (a & 3) >= 2;
-      const int dz = a >= 4;
-      const int ex = ix - dx, ey = iy - dy, ez = iz - dz;
-      if (ex < 0 || ex >= g.nelx || ey < 0 || ey >= g.nely || ez < 0 || ez >= g.nelz) continue;
-      const double E = simp_modulus(rs[ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)],
-                                    E0, Emin, penal);
-      const int64_t n0 = ex + nnx * (ey + (int64_t)nny * ez);
-      const int64_t nd[8] = {n0, n0 + 1, n0 + 1 + nnx, n0 + nnx,
-                             n0 + lay, n0 + lay + 1, n0 + lay + 1 + nnx, n0 + lay + nnx};
-      double t[3] = {0.0, 0.0, 0.0};
-      for (int b = 0; b < 8; ++b) {
+  for (int tile = tbeg; tile < tend; ++tile) {
+    const int x0 = (tile % ntx) * kBX, y0 = ((tile / ntx) % nty) * kBY, z0 = tile / (ntx * nty) * kBZ;
+    // the staging indices below depend on the thread only; recomputed per
+    // tile (an empty asm hides that from the compiler) they hold no registers
+    // through the products
+    int tq = t;
+    asm volatile("" : "+v"(tq));
+    // every load of the tile is issued before any is used; halo rows (one per
+    // (y, z) of the halo) are 3 kGX contiguous values
+    double hv[kGQ];
+    uint8_t hf[kGQ];
+    double rv[kFQ];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const int64_t dof = 3 * nd[b] + c;
-          const double u = fixed[dof] ? 0.0 : xs[dof];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) t[i] += K0s[(3 * a + i) * 24 + 3 * b + c] * u;
+    for (int q = 0; q < kGQ; ++q) {
+      const int i = tq + q * kThreads;
+      const int row = i / (3 * kGX), off = i - row * (3 * kGX);
+      const int X = x0 - 1 + off / 3, Y = y0 - 1 + row % kGY, Z = z0 - 1 + row / kGY;
+      hv[q] = 0.0;
+      hf[q] = 1;
+      if (i < kGV && X >= 0 && X < nnx && Y >= 0 && Y < nny && Z >= 0 && Z < nnz) {
+        const int64_t dof = 3 * ((int64_t)(x0 - 1) + nnx * (Y + (int64_t)nny * Z)) + off;
+        if (DIR) {
+          const double zv = zs[dof];
+          const double pv = first ? 0.0 : xs[dof];
+          hv[q] = zv + bt * pv;
+        } else {
+          hv[q] = xs[dof];
         }
+        hf[q] = fixed[dof];
       }
-#pragma unroll
-      for (int i = 0; i < 3; ++i) yv[i] += E * t[i];
     }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const int64_t dof = 3 * n + i;
-      const bool fx = fixed[dof];
-      if (fx) yv[i] = 0.0;
-      ys[dof] = yv[i];
-      if (parts) acc += (fx ? 0.0 : xs[dof]) * yv[i];
+    for (int q = 0; q < kFQ; ++q) {
+      const int i = tq + q * kThreads;
+      const int ex = x0 - 1 + i % kFX, ey = y0 - 1 + (i / kFX) % kFY, ez = z0 - 1 + i / (kFX * kFY);
+      rv[q] = -1.0;   // outside the mesh
+      if (i < kFN && ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely && ez >= 0 && ez < g.nelz)
+        rv[q] = rs[ex + (int64_t)g.nelx * (ey + (int64_t)g.nely * ez)];
+    }
+    __syncthreads();   // the previous tile's LDS reads are done
+#pragma unroll
+    for (int q = 0; q < kGQ; ++q) {
+      const int i = tq + q * kThreads;
+      const int row = i / (3 * kGX), off = i - row * (3 * kGX);
+      if (i < kGV) xh[off % 3][off / 3 + kGX * row] = hf[q] ? 0.0 : hv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kFQ; ++q) {
+      const int i = tq + q * kThreads;
+      const double r = rv[q];
+      const double E = r < 0.0 ? 0.0
+                               : (P3 ? Emin + (E0 - Emin) * (r * r * r)
+                                     : simp_modulus(r, E0, Emin, penal));
+      if (i < kFN) Eh[i] = E;
+    }
+    __syncthreads();
+    double tr[8][3];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) tr[a][0] = tr[a][1] = tr[a][2] = 0.0;
+    h8_rows(tr, &xh[0][hc], &xh[1][hc], &xh[2][hc], K, std::make_integer_sequence<int, 27>{});
+    double yv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int cx = corner_bit(a, 0), cy = corner_bit(a, 1), cz = corner_bit(a, 2);
+      const double E = Eh[ec + (1 - cx) + kFX * ((1 - cy) + kFY * (1 - cz))];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) yv[i] += (corner_bit(a, i) ? -E : E) * tr[a][i];
+    }
+    const int X = x0 + lx, Y = y0 + ly, Z = z0 + lz;
+    if (X < nnx && Y < nny && Z < nnz) {
+      const int64_t n = X + nnx * (Y + (int64_t)nny * Z);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double pv = xh[i][hc];   // P x at the node
+        const double yi = fixed[3 * n + i] ? 0.0 : yv[i];
+        ys[3 * n + i] = yi;
+        if (DIR) ps[3 * n + i] = pv;   // the new p
+        if (parts) acc += pv * yi;
+      }
     }
   }
   if (parts) {
@@ -269,9 +437,38 @@ bool q4_structured(const double* K0) {
   return true;
 }
 
+bool h8_structured(const double* K0, double* q) {
+  double mx = 0.0;
+  for (int i = 0; i < 576; ++i) mx = std::max(mx, std::fabs(K0[i]));
+  // each class's value from a corner-0 entry of sign +1
+  bool seen[12] = {};
+  for (int e = 0; e < 8; ++e)
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 3; ++c) {
+        const H8Cls k = h8_class(corner_bit(e, 0), corner_bit(e, 1), corner_bit(e, 2), i, c);
+        if (k.s > 0 && !seen[k.q]) {
+          q[k.q] = K0[i * 24 + 3 * e + c];
+          seen[k.q] = true;
+        }
+      }
+  for (int j = 0; j < 12; ++j)
+    if (!seen[j]) return false;
+  for (int a = 0; a < 8; ++a)
+    for (int b = 0; b < 8; ++b)
+      for (int i = 0; i < 3; ++i)
+        for (int c = 0; c < 3; ++c) {
+          const int ex = corner_bit(a, 0) ^ corner_bit(b, 0), ey = corner_bit(a, 1) ^ corner_bit(b, 1),
+                    ez = corner_bit(a, 2) ^ corner_bit(b, 2);
+          const H8Cls k = h8_class(ex, ey, ez, i, c);
+          const int sg = k.s * (corner_bit(a, i) ? -1 : 1) * (corner_bit(a, c) ? -1 : 1);
+          if (std::fabs(K0[(3 * a + i) * 24 + 3 * b + c] - sg * q[k.q]) > 1e-14 * mx) return false;
+        }
+  return true;
+}
+
 int apply_parts(const Geometry& g) {
   if (g.dim == 2) return std::min(q4_tiles(g), kMaxParts);
-  return parts_for(g.nnodes);
+  return std::min(h8_tiles(g), kMaxParts);
 }
 
 void launch_apply_K(const Handle& h, const double* rho, const double* x, double* y, int nsys,
@@ -302,8 +499,19 @@ void launch_apply_K_dir(const Handle& h, const double* rho, const double* z, con
     }
 #undef TPCG_Q4
   } else {
-    hipLaunchKernelGGL(k_apply_h8, grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, h.K0,
-                       pr.E0, pr.Emin, pr.penal, parts, gate);
+    H8Row q;
+    std::copy(h.K0h8, h.K0h8 + 12, q.q);
+#define TPCG_H8(P3, DIR)                                                                      \
+  hipLaunchKernelGGL((k_apply_h8<P3, DIR>), grid, dim3(kThreads), 0, st, g, rho, x, y, h.fixed, \
+                     q, pr.E0, pr.Emin, pr.penal, parts, gate, z, pnew, beta, first)
+    if (z) {
+      if (pr.penal == 3.0) TPCG_H8(true, true);
+      else TPCG_H8(false, true);
+    } else {
+      if (pr.penal == 3.0) TPCG_H8(true, false);
+      else TPCG_H8(false, false);
+    }
+#undef TPCG_H8
   }
 }
 

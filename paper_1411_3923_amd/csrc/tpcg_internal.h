@@ -97,6 +97,7 @@ struct Handle {
   uint8_t* fixed = nullptr;          // [ndof]
   double* K0 = nullptr;              // [ndpe * ndpe]
   double K0q4[64] = {};              // host copy of the Q4 element matrix (2-d)
+  double K0h8[12] = {};              // the H8 element matrix's twelve class values (3-d)
 
   // preconditioner state
   int basis_ready = 0;
@@ -137,7 +138,7 @@ struct Handle {
   double* r = nullptr;               // [nsys_max][ndof]
   double* z = nullptr;
   double* p = nullptr;
-  double* p2 = nullptr;              // second direction buffer (fused update, 2-d)
+  double* p2 = nullptr;              // second direction buffer (fused update)
   double* q = nullptr;
   void* zloc = nullptr;              // [nsys][nsub][nloc], double or float
   double* yc = nullptr;              // [nsys][nt]
@@ -327,6 +328,9 @@ int apply_parts(const Geometry& g);
 // whether a Q4 element matrix has the eight-value structure of the unit
 // square's element, which the Q4 product relies on
 bool q4_structured(const double* K0);
+// true when K0 (24 x 24, row-major) has the trilinear cube's structure; then
+// q holds its twelve class values
+bool h8_structured(const double* K0, double* q);
 void launch_apply_K(const Handle& h, const double* rho, const double* x, double* y, int nsys,
                     int dot_slot, const Gate& gate, hipStream_t st);
 // 2-d only: y = P K P p with the direction update fused, p = z + beta x (beta
@@ -344,8 +348,6 @@ void launch_update_xr(const Handle& h, double* u, const double* p, int nsys, con
 // rz_slot (first: beta = 0), into the scalar slots; flags a breakdown
 void launch_beta(const Handle& h, int nsys, const Gate& gate, int rz_slot, int flexible,
                  int first, hipStream_t st);
-// p = z + beta p with the beta of launch_beta (first: p = z)
-void launch_update_p(const Handle& h, int nsys, const Gate& gate, int first, hipStream_t st);
 // running flags into kStPoll; advances the kStIter counter by `advance`
 void launch_poll(const Handle& h, int nsys, const Gate& gate, int advance, hipStream_t st);
 // residual test of gate.rr_slot into the kStRun flags

@@ -149,24 +149,6 @@ __global__ __launch_bounds__(kThreads) void k_beta(Gate gate, int rz_slot, int f
   }
 }
 
-// p = z + beta p (beta from k_beta; p = z on the first update, when beta = 0
-// and p may hold anything)
-__global__ __launch_bounds__(kThreads) void k_update_p(Geometry g, double* __restrict__ p,
-                                                       const double* __restrict__ z,
-                                                       const double* __restrict__ parts, Gate gate,
-                                                       int first) {
-  const int sys = blockIdx.y;
-  if (!gate_running(gate, sys)) return;
-  const double beta = scal_slot(const_cast<double*>(parts), kScBeta)[sys];
-  const size_t off = (size_t)sys * g.ndof;
-  const int64_t nv = g.nnodes * g.dim;
-  // DOF-contiguous sweep: nothing is reduced, so the node partition of the
-  // other kernels is not needed
-  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nv;
-       i += (int64_t)gridDim.x * kThreads)
-    p[off + i] = first ? z[off + i] : z[off + i] + beta * p[off + i];
-}
-
 // the residual test of the gate, once per iteration: kStRun = r.r > tol2 ||Pf||^2
 __global__ __launch_bounds__(kThreads) void k_gate(Gate gate, int* __restrict__ istate) {
   __shared__ double sh[4];
@@ -266,12 +248,6 @@ void launch_beta(const Handle& h, int nsys, const Gate& gate, int rz_slot, int f
                  int first, hipStream_t st) {
   hipLaunchKernelGGL(k_beta, dim3(nsys), dim3(kThreads), 0, st, gate, rz_slot, flexible, first,
                      h.istate);
-}
-
-void launch_update_p(const Handle& h, int nsys, const Gate& gate, int first, hipStream_t st) {
-  dim3 grid(parts_for(h.g.nnodes), nsys);
-  hipLaunchKernelGGL(k_update_p, grid, dim3(kThreads), 0, st, h.g, h.p, h.z, h.parts, gate,
-                     first);
 }
 
 void launch_gate(const Handle& h, int nsys, const Gate& gate, hipStream_t st) {
