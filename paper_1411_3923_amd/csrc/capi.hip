@@ -149,6 +149,7 @@ Sizes sizes(const tpcg_problem& pr, const Geometry& g, int nsys) {
   p += 5 * sizeof(double) * nsys * g.ndof;
   p += ts * nsys * (size_t)g.nsub * g.nloc;
   p += 2 * sizeof(double) * nsys * (size_t)g.nt;
+  if (restrict_splits(g) > 1) p += sizeof(double) * restrict_splits(g) * kMaxSys * (size_t)g.nt;
   p += sizeof(double) * kNumPartSlots * kMaxSys * kMaxParts + 4096;
   return {p, sizeof(double) * build_ws_elems(pr, g, big, msub)};
 }
@@ -211,7 +212,7 @@ void release(Handle* h) {
                   h->p,     h->p2,   h->q,    h->zloc,  h->yc,   h->xc,   h->parts, h->istate,
                   h->dflag, h->build_ws, h->gm_V, h->gm_w, h->gm_i, h->gm_flags, h->gm_out,
                   h->cell_sig, h->submap_d, h->dedup_pairs, h->dedup_flag, h->fscratch,
-                  h->cband, h->cband_w};
+                  h->cband, h->cband_w, h->ycp};
   for (void* p : ptrs)
     if (p) hipFree(p);
   if (h->hpoll) hipHostFree(h->hpoll);
@@ -595,6 +596,7 @@ int tpcg_build_coarse_basis(tpcg_handle* hh, const double* rho_phys, int32_t nsy
     a.add_bytes(h->zloc, ts * ns * (size_t)g.nsub * g.nloc);
     a.add(h->yc, ns * (size_t)g.nt);
     a.add(h->xc, ns * (size_t)g.nt);
+    if (restrict_splits(g) > 1) a.add(h->ycp, (size_t)restrict_splits(g) * kMaxSys * g.nt);
     if (a.commit() != TPCG_OK)
       return fail(hh, TPCG_ENOMEM, "out of device memory for the preconditioner");
   }

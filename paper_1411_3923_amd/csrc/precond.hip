@@ -2,7 +2,7 @@
 // additive form; coarse space of Sec. 2.4):
 //   z = sum_j R_j^T A_j^-1 R_j r + Phi K_c^-1 Phi^T r
 // in four launches:
-//   1. restriction y_c = Phi^T r            (one workgroup per subdomain)
+//   1. restriction y_c = Phi^T r            (one or more workgroups per subdomain)
 //   2. local solves A_j^-1 R_j r for every (system, subdomain)   } concurrent:
 //   3. coarse solve x_c = K_c^-1 y_c                             } forked stream
 //   4. extension z(n) = sum_{j owns n} (zloc_j(n) + (Phi_j x_c,j)(n)), with
@@ -17,13 +17,19 @@ namespace {
 constexpr int kSubThreads = 256;    // restriction: one workgroup per subdomain
 constexpr int kXcStage = 2048;      // extension: coarse-solution entries staged per workgroup
 
-// One workgroup per subdomain, all running systems together (Phi, mode-major,
-// read once); KM >= k bounds the accumulators.
+// nsplit workgroups per subdomain (restrict_splits: more than one where a
+// launch of one per subdomain would leave the chip unevenly loaded), all
+// running systems together (Phi, mode-major, read once); KM >= k bounds the
+// accumulators. Part s of box j takes the box DOFs [s nloc / nsplit,
+// (s + 1) nloc / nsplit); with nsplit = 1 the sums go to y_c, else to ycp
+// [nsplit][kMaxSys][nt], which k_restrict_sum adds up in part order.
 template <typename P, int KM>
 __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* __restrict__ phim,
                                                           const double* __restrict__ r,
-                                                          double* __restrict__ yc, int nsys,
-                                                          Gate gate) {
+                                                          double* __restrict__ yc,
+                                                          double* __restrict__ ycp,
+                                                          const int* __restrict__ kj, int nsys,
+                                                          int nsplit, Gate gate) {
   constexpr int NW = kSubThreads / 64;
   __shared__ double red[NW][kMaxSys * KM];
   // systems still running after the previous test (a superset of those that
@@ -36,11 +42,17 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
   // and take a contiguous range of boxes, whose shared faces of r meet in
   // one L2
   const int W = gridDim.x, grp = blockIdx.x % 8, per = W / 8, rem = W % 8;
-  const int j = (grp < rem ? grp * (per + 1) : rem * (per + 1) + (grp - rem) * per) +
-                blockIdx.x / 8;
+  const int slot = (grp < rem ? grp * (per + 1) : rem * (per + 1) + (grp - rem) * per) +
+                   blockIdx.x / 8;
+  const int j = slot / nsplit, part = slot - (slot / nsplit) * nsplit;
+  const int lbeg = (int)((int64_t)part * g.nloc / nsplit);
+  const int lend = (int)((int64_t)(part + 1) * g.nloc / nsplit);
   int jx, jy, jz;
   sub_coords(g, j, jx, jy, jz);
   const int k = g.k;
+  // the box's vectors in use: the other columns of Phi_j are zero, their
+  // entries of y_c stay zero
+  const int ku = kj[j];
   const P* ph = phim + (size_t)j * k * g.nloc;
   double acc[kMaxSys][KM];
 #pragma unroll
@@ -50,26 +62,34 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
   // kRU box DOFs per thread at a time, all their loads issued before use
   // (one with the wide accumulators, which fill the registers)
   constexpr int kRU = KM <= 8 ? 5 : 1;
-  for (int l0 = threadIdx.x; l0 < g.nloc; l0 += kRU * kSubThreads) {
+  for (int l0 = lbeg + threadIdx.x; l0 < lend; l0 += kRU * kSubThreads) {
     double rv[kRU][kMaxSys];
 #pragma unroll
     for (int u = 0; u < kRU; ++u) {
       const int l = l0 + u * kSubThreads;
-      const int64_t dof = l < g.nloc ? box_dof(g, jx, jy, jz, l) : 0;
+      const int64_t dof = l < lend ? box_dof(g, jx, jy, jz, l) : 0;
 #pragma unroll
       for (int q = 0; q < kMaxSys; ++q)
-        rv[u][q] = (l < g.nloc && ((run >> q) & 1u)) ? r[q * g.ndof + dof] : 0.0;
+        rv[u][q] = (l < lend && ((run >> q) & 1u)) ? r[q * g.ndof + dof] : 0.0;
     }
+    // modes in groups of eight, the group's loads issued together
 #pragma unroll
-    for (int m = 0; m < KM; ++m)
-      if (m < k) {
+    for (int m0 = 0; m0 < KM; m0 += 8)
+      if (m0 < ku) {
+        double pv[8][kRU];
 #pragma unroll
-        for (int u = 0; u < kRU; ++u) {
-          const int l = l0 + u * kSubThreads;
-          const double p = l < g.nloc ? (double)ph[(size_t)m * g.nloc + l] : 0.0;
+        for (int mm = 0; mm < 8; ++mm)
 #pragma unroll
-          for (int q = 0; q < kMaxSys; ++q) acc[q][m] += p * rv[u][q];
-        }
+          for (int u = 0; u < kRU; ++u) {
+            const int l = l0 + u * kSubThreads, m = m0 + mm;
+            pv[mm][u] = (m < ku && l < lend) ? (double)ph[(size_t)m * g.nloc + l] : 0.0;
+          }
+#pragma unroll
+        for (int mm = 0; mm < 8; ++mm)
+#pragma unroll
+          for (int u = 0; u < kRU; ++u)
+#pragma unroll
+            for (int q = 0; q < kMaxSys; ++q) acc[q][m0 + mm] += pv[mm][u] * rv[u][q];
       }
   }
   const int w = threadIdx.x >> 6;
@@ -118,8 +138,25 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
     double s = 0.0;
 #pragma unroll
     for (int w2 = 0; w2 < NW; ++w2) s += red[w2][e];
-    yc[(size_t)q * g.nt + coarse_index(g, jx, jy, jz, m)] = s;
+    const int ci = coarse_index(g, jx, jy, jz, m);
+    if (nsplit == 1) yc[(size_t)q * g.nt + ci] = s;
+    else ycp[((size_t)part * kMaxSys + q) * g.nt + ci] = s;
   }
+}
+
+// y_c = the sum of the parts of k_restrict, in part order, for the systems
+// that passed the residual test taken there. grid (ceil(nt / 256), nsys).
+__global__ __launch_bounds__(kThreads) void k_restrict_sum(Geometry g,
+                                                          const double* __restrict__ ycp,
+                                                          double* __restrict__ yc, int nsplit,
+                                                          Gate gate) {
+  const int sys = blockIdx.y;
+  if (!gate_running(gate, sys)) return;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= g.nt) return;
+  double s = 0.0;
+  for (int p = 0; p < nsplit; ++p) s += ycp[((size_t)p * kMaxSys + sys) * g.nt + i];
+  yc[(size_t)sys * g.nt + i] = s;
 }
 
 // one workgroup per system
@@ -226,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_coarse_gemv_sum(Geometry g,
 template <typename T, int D, int KM>
 __global__ __launch_bounds__(kThreads) void k_extend(
     Geometry g, const double* __restrict__ r, double* __restrict__ z, const T* __restrict__ zloc,
-    const T* __restrict__ phim, const double* __restrict__ xc,
+    const T* __restrict__ phim, const double* __restrict__ xc, const int* __restrict__ kj,
     const uint8_t* __restrict__ fixed, double* __restrict__ parts, int rz_slot, int flexible,
     int nsys, Gate gate) {
   __shared__ double sh[4];
@@ -317,27 +354,29 @@ __global__ __launch_bounds__(kThreads) void k_extend(
                 for (int c = 0; c < D; ++c) acc[q][c] += (double)zj[q * zstride + c];
           }
           // modes in groups of eight: the group's basis values loaded together
+          // (only the box's vectors in use: the other columns are zero)
+          const int ku = kj[j];
 #pragma unroll
           for (int m0 = 0; m0 < KM; m0 += 8) {
-            if (m0 >= k) break;
+            if (m0 >= ku) break;
             double pv[8][D];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const int m = m0 + u;
               if constexpr (D == 2) {
                 typedef T T2 __attribute__((ext_vector_type(2)));
-                const T2 v = m < k ? *reinterpret_cast<const T2*>(pj + (size_t)m * g.nloc) : T2{0, 0};
+                const T2 v = m < ku ? *reinterpret_cast<const T2*>(pj + (size_t)m * g.nloc) : T2{0, 0};
                 pv[u][0] = (double)v.x;
                 pv[u][1] = (double)v.y;
               } else {
 #pragma unroll
-                for (int c = 0; c < D; ++c) pv[u][c] = m < k ? (double)pj[(size_t)m * g.nloc + c] : 0.0;
+                for (int c = 0; c < D; ++c) pv[u][c] = m < ku ? (double)pj[(size_t)m * g.nloc + c] : 0.0;
               }
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
               const int m = m0 + u;
-              if (m < k) {
+              if (m < ku) {
 #pragma unroll
                 for (int q = 0; q < kMaxSys; ++q)
                   if ((run >> q) & 1u) {
@@ -415,12 +454,20 @@ template <typename T>
 void restrict_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
   const Geometry& g = h.g;
   const T* pm = reinterpret_cast<const T*>(h.phim);
+  const int ns = restrict_splits(g);
+  const dim3 grid(g.nsub * ns);
   if (g.k <= 8)
-    hipLaunchKernelGGL((k_restrict<T, 8>), dim3(g.nsub), dim3(kSubThreads), 0, st, g, pm, r, h.yc,
-                       nsys, gate);
+    hipLaunchKernelGGL((k_restrict<T, 8>), grid, dim3(kSubThreads), 0, st, g, pm, r, h.yc, h.ycp,
+                       h.kj, nsys, ns, gate);
   else
-    hipLaunchKernelGGL((k_restrict<T, kMaxK>), dim3(g.nsub), dim3(kSubThreads), 0, st, g, pm, r,
-                       h.yc, nsys, gate);
+    hipLaunchKernelGGL((k_restrict<T, kMaxK>), grid, dim3(kSubThreads), 0, st, g, pm, r, h.yc,
+                       h.ycp, h.kj, nsys, ns, gate);
+  if (ns > 1) {
+    Gate gs = gate;
+    gs.test = 0;   // the test was taken in the restriction
+    hipLaunchKernelGGL(k_restrict_sum, dim3((g.nt + kThreads - 1) / kThreads, nsys),
+                       dim3(kThreads), 0, st, g, h.ycp, h.yc, ns, gs);
+  }
 }
 
 // z = P sum_j R_j^T (zloc_j + Phi_j x_c,j) with the r.z partials
@@ -433,7 +480,7 @@ void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& 
   const dim3 grid(parts_for(g.nnodes));
 #define TPCG_EXTEND(D, KM)                                                                     \
   hipLaunchKernelGGL((k_extend<T, D, KM>), grid, dim3(kThreads), 0, st, g, r, z, zl, pm, h.xc,  \
-                     h.fixed, h.parts, rz_slot, flexible, nsys, gate)
+                     h.kj, h.fixed, h.parts, rz_slot, flexible, nsys, gate)
   if (g.dim == 2) {
     if (g.k <= 8) TPCG_EXTEND(2, 8);
     else TPCG_EXTEND(2, kMaxK);
@@ -445,6 +492,13 @@ void extend_launch(Handle& h, const double* r, double* z, int nsys, const Gate& 
 }
 
 }  // namespace
+
+int restrict_splits(const Geometry& g) {
+  // about four workgroups per CU of 256, each part at least 2048 box DOFs
+  int s = (4 * 256 + g.nsub - 1) / g.nsub;
+  s = std::min(s, std::min(8, g.nloc / 2048));
+  return std::max(s, 1);
+}
 
 void launch_precond(Handle& h, const double* r, double* z, int nsys, const Gate& gate,
                     int rz_slot, int prof_it, int flexible, hipStream_t st) {

@@ -142,6 +142,7 @@ struct Handle {
   double* q = nullptr;
   void* zloc = nullptr;              // [nsys][nsub][nloc], double or float
   double* yc = nullptr;              // [nsys][nt]
+  double* ycp = nullptr;             // [restrict_splits][kMaxSys][nt] restriction parts (or null)
   double* xc = nullptr;              // [nsys][nt]
   double* parts = nullptr;           // reduction partials, see kParts* offsets
   int* istate = nullptr;             // per-system integer state, see kSt*
@@ -327,6 +328,8 @@ __host__ __device__ inline double* part_slot(double* parts, int slot, int sys) {
 int apply_parts(const Geometry& g);
 // whether a Q4 element matrix has the eight-value structure of the unit
 // square's element, which the Q4 product relies on
+// workgroups per subdomain of the coarse restriction
+int restrict_splits(const Geometry& g);
 bool q4_structured(const double* K0);
 // true when K0 (24 x 24, row-major) has the trilinear cube's structure; then
 // q holds its twelve class values
