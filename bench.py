@@ -104,18 +104,25 @@ def run_gpu(precision, args, p, rho_h, f_h):
             h.filter_project_adjoint(rt, p.rmin, p.beta, p.etas, dc, dcr)
         return info, (t1 - t0) * 1e3
 
-    for _ in range(args.warmup):
+    # long steps (3-d: seconds each) report their end on stderr
+    tw = time.perf_counter()
+    report = lambda what: (print(f"{'mixed' if precision == T.MIXED else 'fp64'} {what} done at "
+                                 f"{time.perf_counter() - tw:.1f} s", file=sys.stderr, flush=True)
+                           if p.dim == 3 else None)
+    for i in range(args.warmup):
         step()
+        report(f"warm-up step {i + 1}/{args.warmup}")
     torch.cuda.synchronize()
     h.set_profiling(True)
     infos, setup_ms, solve_ms = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         info, sm = step()
         infos.append(info)
         setup_ms.append(sm)
         solve_ms.append(info[0]["seconds"] * 1e3)
+        report(f"timed step {i + 1}/{args.steps}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = h.profile_block_solves()

@@ -139,3 +139,55 @@ def test_q4_matrix_takes_eight_values_of_its_first_row(nu):
     assert len(np.unique(np.round(row, 14))) == 8
     for v in K.ravel():
         assert np.min(np.abs(row - v)) < 1e-14
+
+
+def _corner(a):
+    """Position bits (x, y, z) of H8 corner a: counter-clockwise in x-y, bottom face first."""
+    return (int((a & 3) in (1, 2)), int((a & 3) >= 2), int(a >= 4))
+
+
+@pytest.mark.parametrize("nu", [0.17, 0.3, 0.45])
+def test_h8_matrix_has_twelve_entry_classes(nu):
+    """Reflecting the unit cube so that corner a becomes corner 0 maps corner
+    b to the corner at |p_b - p_a| and flips the displacement components along
+    the reflected axes: K0[(a,i),(b,c)] = tau_i(a) tau_c(a) R(e)[i][c], with
+    R(e) the block of corner 0's rows. The axis permutations (which fix
+    corner 0) and the symmetry of K0 leave twelve values in R up to sign. The
+    GPU product keeps those twelve values in scalar registers; the library
+    checks the structure on the host."""
+    K = fem.h8_K0(nu)
+    mx = np.abs(K).max()
+    R = {}
+    for e in range(8):
+        R[_corner(e)] = K[0:3, 3 * e:3 * e + 3]
+    for a in range(8):
+        pa = _corner(a)
+        for b in range(8):
+            pb = _corner(b)
+            e = tuple(x ^ y for x, y in zip(pa, pb))
+            for i in range(3):
+                for c in range(3):
+                    s = (-1 if pa[i] else 1) * (-1 if pa[c] else 1)
+                    assert abs(K[3 * a + i, 3 * b + c] - s * R[e][i][c]) < 1e-14 * mx
+    # the permutations of the axes map R(e)[i][c] to R(pi e)[pi i][pi c]
+    for perm in itertools.permutations(range(3)):
+        for e in R:
+            pe = tuple(e[perm.index(j)] for j in range(3))
+            for i in range(3):
+                for c in range(3):
+                    assert abs(R[e][i][c] - R[pe][perm[i]][perm[c]]) < 1e-14 * mx
+    # twelve magnitudes up to sign (with nu generic, no two classes coincide
+    # except by the value identities of the element, so count the orbits)
+    orbits = set()
+    for e in R:
+        for i in range(3):
+            for c in range(3):
+                key = min((tuple(e[perm.index(j)] for j in range(3)), perm[i], perm[c])
+                          for perm in itertools.permutations(range(3)))
+                # the transpose relation R(e)[i][c] = tau_i(e) tau_c(e) R(e)[c][i]
+                s = (-1 if e[i] else 1) * (-1 if e[c] else 1)
+                assert abs(R[e][i][c] - s * R[e][c][i]) < 1e-14 * mx
+                key2 = min((tuple(e[perm.index(j)] for j in range(3)), perm[c], perm[i])
+                           for perm in itertools.permutations(range(3)))
+                orbits.add(min(key, key2))
+    assert len(orbits) == 12
