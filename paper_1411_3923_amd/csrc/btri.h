@@ -206,6 +206,41 @@ __device__ inline T layer_coupling(int d, int bn, const T* __restrict__ K0s,
   return acc;
 }
 
+// layer_coupling with the dimension fixed at compile time and the DOF's
+// position in the layer (node lx, ly, component c) decoded once by the
+// caller: the loops unroll, so the LDS reads of a call are issued together
+// instead of one after another. Same terms, same order of summation.
+template <int D, typename T>
+__device__ inline T layer_coupling_at(int bn, const T* __restrict__ K0s, const T* __restrict__ E,
+                                      const T* __restrict__ v, int lx, int ly, int c, bool top) {
+  constexpr int nd = D == 3 ? 24 : 8, ny = D == 3 ? 2 : 1;
+  const int ylim = D == 3 ? bn : 1;
+  T acc = 0;
+#pragma unroll
+  for (int hy = 0; hy < ny; ++hy)
+#pragma unroll
+    for (int hx = 0; hx < 2; ++hx) {
+      const int ex = lx - hx, ey = ly - hy;
+      const T Ee = E[(ex + 1) + (D == 3 ? (bn + 1) * (ey + 1) : 0)];
+      const int ca = D == 3 ? corner_of(hx, hy, top) : corner_of(hx, top, 0);
+      T s = 0;
+#pragma unroll
+      for (int oy = 0; oy < ny; ++oy)
+#pragma unroll
+        for (int ox = 0; ox < 2; ++ox) {
+          const int px = ex + ox, py = ey + oy;
+          if (px < 0 || px >= bn || py < 0 || py >= ylim) continue;
+          const int cb = D == 3 ? corner_of(ox, oy, !top) : corner_of(ox, !top, 0);
+          const T* kr = K0s + (D * ca + c) * nd + D * cb;
+          const T* vp = v + D * (px + bn * py);
+#pragma unroll
+          for (int c2 = 0; c2 < D; ++c2) s += kr[c2] * vp[c2];
+        }
+      acc += Ee * s;
+    }
+  return acc;
+}
+
 // LDS element count of btri_solve for shape s and NR right-hand sides
 __host__ __device__ inline size_t btri_solve_lds_elems(const BtriShape& s, int nr) {
   return (size_t)s.bstride + 2 * (size_t)s.nb * nr + (size_t)kThreads * nr;

@@ -72,7 +72,7 @@ size_t local_solve_lds_bytes(const Geometry& g, size_t elem) {
 // tau + 256 when TPT = 2) of both chains' records; DOF o of chain c's node
 // layer belongs to thread 128 c + o. zloc receives s and then x, in box
 // order.
-template <typename T, int TPT>
+template <typename T, int TPT, int D>
 __global__ __launch_bounds__(kThreads) void k_local_solves(
     Geometry g, const double* __restrict__ r, const T* __restrict__ lfac,
     const T* __restrict__ emod, const uint8_t* __restrict__ fixed, const double* __restrict__ K0,
@@ -84,7 +84,8 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
   const int sys = id / g.nsub, j = id - (id / g.nsub) * g.nsub;
   if (!gate_running(gate, sys)) return;   // uniform over the workgroup
 
-  const int d = g.dim, nb = g.nb, nblk = g.nblk, bn = g.bn, nd = g.ndpe;
+  constexpr int d = D, nd = D == 3 ? 24 : 8;
+  const int nb = g.nb, nblk = g.nblk, bn = g.bn;
   const TileShape ts = tile_shape(nb);
   const int nt = ts.nt, np = 4 * ts.nt, nl = ts.nl;
   const int sw = strip_width(g);
@@ -174,14 +175,31 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
         }
       }
   };
+  // row o's partials, added in order K = 0 .. nt - 1 (unrolled by four, so
+  // that four reads are in flight ahead of their sums)
   auto row_sum = [&](int c, int oo) {
     T s = 0;
+#pragma unroll 4
     for (int K = 0; K < nt; ++K) s += red[c][(size_t)K * np + oo];
     return s;
   };
-  auto rhs = [&](int b, int oo) { return (T)rs[box_dof(g, jx, jy, jz, b * nb + oo)]; };
-  auto coupling = [&](int L, const T* v, int oo, bool top) {
-    return layer_coupling(d, bn, K0s, strip + (size_t)L * sw, v, oo, top);
+  // the box DOFs of chain c's row in block b: one stride per block (a node
+  // row in 2-d, a node layer in 3-d) from the row's DOF in block 0
+  const int64_t lstride = (int64_t)d * g.nnx * (d == 3 ? g.nny : 1);
+  int64_t dof0[CH];
+  int lxo[CH], lyo[CH], co[CH];   // the row's node in the layer and its component
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int oc = ow[c] ? o[c] : 0;
+    dof0[c] = box_dof(g, jx, jy, jz, oc);
+    const int m = oc / d;
+    co[c] = oc - m * d;
+    lxo[c] = m % bn;
+    lyo[c] = d == 3 ? m / bn : 0;
+  }
+  auto rhs = [&](int c, int b) { return (T)rs[dof0[c] + b * lstride]; };
+  auto coupling = [&](int c, int L, const T* v, bool top) {
+    return layer_coupling_at<D>(bn, K0s, strip + (size_t)L * sw, v, lxo[c], lyo[c], co[c], top);
   };
 
   // set-up: first records, K0, layer moduli, support flags, zeroed vectors,
@@ -214,8 +232,8 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
   for (int c = 0; c < CH; ++c) {
     if (!ow[c] || (c == 1 && !lower_runs)) continue;
     const int b0 = c == 0 ? 0 : nblk - 1, b1 = c == 0 ? 1 : nblk - 2;
-    va[c][o[c]] = rhs(b0, o[c]);              // t_b0 = r_b0
-    if (c == 0 ? b1 <= mid : b1 >= mid + 1) rn[c] = rhs(b1, o[c]);
+    va[c][o[c]] = rhs(c, b0);                 // t_b0 = r_b0
+    if (c == 0 ? b1 <= mid : b1 >= mid + 1) rn[c] = rhs(c, b1);
   }
 
   for (int K = 0; K <= 2 * mid; ++K) {
@@ -228,7 +246,7 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
     if (K == mid + 1 && lower_runs) {
       // lower chain: w_{mid+1} = A_{mid+1,mid} x_mid, s_{mid+1} from the forward pass
       if (ow[1]) {
-        va[1][o[1]] = fx[(mid + 1) * nb + o[1]] ? (T)0 : coupling(mid, xm, o[1], true);
+        va[1][o[1]] = fx[(mid + 1) * nb + o[1]] ? (T)0 : coupling(1, mid, xm, true);
         yb[1] = zs[(mid + 1) * nb + o[1]];
       }
       lds_barrier();
@@ -276,27 +294,25 @@ __global__ __launch_bounds__(kThreads) void k_local_solves(
       const int bc = b[0];
       if (fwd[0]) {
         // t_{b+1} = r_{b+1} - A_{b+1,b} s_b
-        va[0][o[0]] = fx[(bc + 1) * nb + o[0]] ? rn[0]
-                                                : rn[0] - coupling(bc, vc[0], o[0], true);
-        if (bc + 2 <= mid) rn[0] = rhs(bc + 2, o[0]);
+        va[0][o[0]] = fx[(bc + 1) * nb + o[0]] ? rn[0] : rn[0] - coupling(0, bc, vc[0], true);
+        if (bc + 2 <= mid) rn[0] = rhs(0, bc + 2);
       } else if (bc >= 1) {
         // w_{b-1} = A_{b-1,b} x_b, and s_{b-1} back from the forward pass
-        va[0][o[0]] = fx[(bc - 1) * nb + o[0]] ? (T)0 : coupling(bc - 1, vc[0], o[0], false);
+        va[0][o[0]] = fx[(bc - 1) * nb + o[0]] ? (T)0 : coupling(0, bc - 1, vc[0], false);
         yb[0] = zs[(bc - 1) * nb + o[0]];
       }
     }
     if (act[1] && ow[1]) {
       const int bc = b[1];
       if (fwd[1] && bc == mid + 1) {
-        cm[o[1]] = coupling(mid, vc[1], o[1], false);   // A_{mid,mid+1} s_{mid+1}
+        cm[o[1]] = coupling(1, mid, vc[1], false);   // A_{mid,mid+1} s_{mid+1}
       } else if (fwd[1]) {
         // t_{b-1} = r_{b-1} - A_{b-1,b} s_b
-        va[1][o[1]] = fx[(bc - 1) * nb + o[1]] ? rn[1]
-                                                : rn[1] - coupling(bc - 1, vc[1], o[1], false);
-        if (bc - 2 >= mid + 1) rn[1] = rhs(bc - 2, o[1]);
+        va[1][o[1]] = fx[(bc - 1) * nb + o[1]] ? rn[1] : rn[1] - coupling(1, bc - 1, vc[1], false);
+        if (bc - 2 >= mid + 1) rn[1] = rhs(1, bc - 2);
       } else if (bc + 1 < nblk) {
         // w_{b+1} = A_{b+1,b} x_b, and s_{b+1} back from the forward pass
-        va[1][o[1]] = fx[(bc + 1) * nb + o[1]] ? (T)0 : coupling(bc, vc[1], o[1], true);
+        va[1][o[1]] = fx[(bc + 1) * nb + o[1]] ? (T)0 : coupling(1, bc, vc[1], true);
         yb[1] = zs[(bc + 1) * nb + o[1]];
       }
     }
@@ -312,13 +328,13 @@ void allow_lds(K kernel, bool& done) {
   done = true;
 }
 
-template <typename T, int TPT>
+template <typename T, int TPT, int D>
 void local_launch_as(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
   const Geometry& g = h.g;
   const int nchains = nsys * g.nsub;
   static bool done = false;
-  allow_lds(&k_local_solves<T, TPT>, done);
-  hipLaunchKernelGGL((k_local_solves<T, TPT>), dim3(nchains), dim3(kThreads),
+  allow_lds(&k_local_solves<T, TPT, D>, done);
+  hipLaunchKernelGGL((k_local_solves<T, TPT, D>), dim3(nchains), dim3(kThreads),
                      local_solve_lds_bytes(g, sizeof(T)), st, g, r,
                      reinterpret_cast<const T*>(h.lfac), reinterpret_cast<const T*>(h.emod),
                      h.fixed, h.K0, reinterpret_cast<T*>(h.zloc), nchains, gate);
@@ -327,8 +343,14 @@ void local_launch_as(Handle& h, const double* r, int nsys, const Gate& gate, hip
 template <typename T>
 void local_launch(Handle& h, const double* r, int nsys, const Gate& gate, hipStream_t st) {
   // one tile per thread where it suffices
-  if (tile_shape(h.g.nb).nl <= kThreads) local_launch_as<T, 1>(h, r, nsys, gate, st);
-  else local_launch_as<T, 2>(h, r, nsys, gate, st);
+  const bool one = tile_shape(h.g.nb).nl <= kThreads;
+  if (h.g.dim == 2) {
+    if (one) local_launch_as<T, 1, 2>(h, r, nsys, gate, st);
+    else local_launch_as<T, 2, 2>(h, r, nsys, gate, st);
+  } else {
+    if (one) local_launch_as<T, 1, 3>(h, r, nsys, gate, st);
+    else local_launch_as<T, 2, 3>(h, r, nsys, gate, st);
+  }
 }
 
 }  // namespace
