@@ -68,14 +68,6 @@ __device__ inline d4 mfma_nt(const double* A, const double* Bm, int ld, int nb, 
 }
 
 
-// value of v in lane `lane` (uniform index) for every lane
-__device__ inline double bcast_lane(double v, int lane) {
-  const long long bits = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // orders the LDS traffic of one wave
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

@@ -88,9 +88,8 @@ __device__ void gram_waves(const double* __restrict__ A, const double* __restric
 __global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __restrict__ X,
                                                         const double* __restrict__ dis, int m) {
   __shared__ double part[4][256];
-  __shared__ double R[16 * 16];
-  __shared__ double G[16 * 16];
   __shared__ double U[16 * 16];
+  __shared__ double ip[16];   // inverse pivots 1 / U[b][b]
   const int j = blockIdx.x;
   double* Xj = X + (size_t)j * g.nloc * m;
   const double* dj = dis + (size_t)j * g.nloc;
@@ -102,53 +101,59 @@ __global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __r
   for (int pass = 0; pass < 2; ++pass) {
     gram_waves(Xj, Xj, g.nloc, m, part);   // G = X^T X
     __syncthreads();
-    if (t == 0) {
-      double tr = 0.0;
-      for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b)
-          G[a * 16 + b] = (part[0][a * 16 + b] + part[1][a * 16 + b]) +
-                          (part[2][a * 16 + b] + part[3][a * 16 + b]);
-      for (int a = 0; a < m; ++a) tr += G[a * 16 + a];
+    // G + shift I = U^T U (upper Cholesky) on wave 0, lane b holding column
+    // b of U; every pivot and every entry of a pivot's column reaches the
+    // other lanes by readlane
+    if (t < 64) {
+      const int b = t;
+      double g[16], u[16];
+#pragma unroll
+      for (int a = 0; a < 16; ++a) {
+        const int e = a * 16 + (b & 15);
+        g[a] = (a < m && b < m) ? (part[0][e] + part[1][e]) + (part[2][e] + part[3][e]) : 0.0;
+        u[a] = 0.0;
+      }
+      double tr = 0.0;   // trace of G: lane a holds G[a][a] in g[a]
+#pragma unroll
+      for (int a = 0; a < 16; ++a)
+        if (a < m) tr += bcast_lane(g[a], a);
       const double shift = 1e-14 * tr;
-      // upper Cholesky G + shift I = R^T R, then R^-1 (upper) into R
-      for (int a = 0; a < m; ++a)
-        for (int b = 0; b < m; ++b) U[a * 16 + b] = 0.0;
-      for (int a = 0; a < m; ++a) {
-        double s = G[a * 16 + a] + shift;
-        for (int c = 0; c < a; ++c) s -= U[c * 16 + a] * U[c * 16 + a];
-        const double d = s > 0.0 ? sqrt(s) : 1.0;
-        U[a * 16 + a] = d;
-        for (int b = a + 1; b < m; ++b) {
-          double v = G[a * 16 + b];
-          for (int c = 0; c < a; ++c) v -= U[c * 16 + a] * U[c * 16 + b];
-          U[a * 16 + b] = v / d;
+#pragma unroll
+      for (int a = 0; a < 16; ++a) {
+        if (a < m) {
+          double sd = g[a] + shift;   // meaningful in lane a
+#pragma unroll
+          for (int c = 0; c < a; ++c) sd -= u[c] * u[c];
+          const double d = bcast_lane(sd > 0.0 ? sqrt(sd) : 1.0, a);
+          double v = g[a];   // G[a][b] in lane b
+#pragma unroll
+          for (int c = 0; c < a; ++c) v -= bcast_lane(u[c], a) * u[c];
+          u[a] = b == a ? d : (b > a ? v / d : 0.0);
         }
       }
-      for (int a = 0; a < 16 * 16; ++a) R[a] = 0.0;
-      for (int b = 0; b < m; ++b) {          // column b of U^-1 by back substitution
-        for (int a = b; a >= 0; --a) {
-          double v = a == b ? 1.0 : 0.0;
-          for (int c = a + 1; c <= b; ++c) v -= U[a * 16 + c] * R[c * 16 + b];
-          R[a * 16 + b] = v / U[a * 16 + a];
-        }
-      }
+      if (b < 16)
+#pragma unroll
+        for (int a = 0; a < 16; ++a) U[a * 16 + b] = u[a];
+      if (b < 16) ip[b] = b < m ? 1.0 / u[b] : 0.0;
     }
     __syncthreads();
-    // X <- X R^-1 row by row
+    // X <- X U^-1 row by row: forward substitution x_new U = x
     for (int r = t; r < g.nloc; r += kThreads) {
-      int oz = 0;   // opaque: R is read per row, not held in registers
+      int oz = 0;   // opaque: U is read per row, not held in registers
       asm volatile("" : "+v"(oz));
-      const double* Rv = R + oz;
+      const double* Uv = U + oz;
+      const double* iv = ip + oz;
       double x[kMaxSub];
 #pragma unroll
       for (int c = 0; c < kMaxSub; ++c) x[c] = c < m ? Xj[(size_t)r * m + c] : 0.0;
 #pragma unroll
       for (int b = 0; b < kMaxSub; ++b) {
         if (b < m) {
-          double v = 0.0;
+          double v = x[b];
 #pragma unroll
-          for (int a = 0; a <= b; ++a) v += x[a] * Rv[a * 16 + b];
-          Xj[(size_t)r * m + b] = v;
+          for (int a = 0; a < b; ++a) v -= x[a] * Uv[a * 16 + b];
+          x[b] = v * iv[b];
+          Xj[(size_t)r * m + b] = x[b];
         }
       }
     }

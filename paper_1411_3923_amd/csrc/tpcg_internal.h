@@ -247,6 +247,14 @@ __device__ inline double wave_sum(double v) {
 // Sum over the threads of a workgroup (blockDim.x a multiple of 64, at most
 // 256); every thread gets the same value. `sh` needs 4 doubles of LDS. Fixed
 // reduction tree: deterministic.
+// value of v in lane `lane` (uniform index) for every lane
+__device__ inline double bcast_lane(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double block_sum(double v, double* sh) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
