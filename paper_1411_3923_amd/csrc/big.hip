@@ -623,11 +623,15 @@ inline size_t pass_lds_bytes(const Geometry& g) {
 
 // Y = A_{b,p} X over the node rows y of layer b (3 node rows of X's layer p
 // in a window), 32 columns per workgroup, X's rows read by load(row, col).
-// emit(i, col, value) takes each result.
-template <typename Load, typename Emit>
+// emit(i, col, value) takes each result. The dimension is a compile-time
+// constant: the neighbour terms unroll with constant offsets, and a row's
+// coefficients are read together ahead of the products (same terms, same
+// order of summation, exact zeros skipped as they come).
+template <int D, typename Load, typename Emit>
 __device__ void stencil_rows(const Geometry& g, const double* __restrict__ cf, double* Xw, int col0,
                              Load load, Emit emit) {
-  const int d = g.dim, bn = g.bn, rl = row_len(g), ny = d == 3 ? bn : 1, nw = win_rows(g);
+  constexpr int d = D, nw = D == 3 ? 3 : 1, ntt = D == 3 ? 27 : 6;
+  const int bn = g.bn, rl = d * bn, ny = D == 3 ? bn : 1;
   const int t = threadIdx.x;
   auto fill = [&](int yy) {
     double* dst = Xw + (size_t)(yy % nw) * rl * kPC;
@@ -640,22 +644,28 @@ __device__ void stencil_rows(const Geometry& g, const double* __restrict__ cf, d
   if (ny > 1) fill(1);
   __syncthreads();
   for (int y = 0; y < ny; ++y) {
+    // window rows of node rows y - 1, y, y + 1 (y - 1 = -1 is never read)
+    const double* wr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wr[k] = Xw + (size_t)(((y + k - 1) % nw + nw) % nw) * rl * kPC;
     for (int e = t; e < rl * kPC; e += kThreads) {
       const int rr = e / kPC, cc = e - (e / kPC) * kPC;
       const int i = y * rl + rr;
-      const int x = (rr / d), c = rr - (rr / d) * d;
-      (void)c;
+      const int x = rr / d;
       const double* ci = cf + (size_t)i * 27;
+      double cv[ntt];
+#pragma unroll
+      for (int tt = 0; tt < ntt; ++tt) cv[tt] = ci[tt];
       double acc = 0.0;
-      const int ntt = d == 3 ? 27 : 6;
+#pragma unroll
       for (int tt = 0; tt < ntt; ++tt) {
         int dx, dy, c2;
         nbr_of(d, tt, dx, dy, c2);
         const int x2 = x + dx, y2 = y + dy;
         if (x2 < 0 || x2 >= bn || y2 < 0 || y2 >= ny) continue;
-        const double a = ci[tt];
+        const double a = cv[tt];
         if (a == 0.0) continue;
-        acc += a * Xw[((size_t)(y2 % nw) * rl + d * x2 + c2) * kPC + cc];
+        acc += a * wr[dy + 1][(d * x2 + c2) * kPC + cc];
       }
       emit(i, col0 + cc, acc);
     }
@@ -668,6 +678,7 @@ __device__ void stencil_rows(const Geometry& g, const double* __restrict__ cf, d
 // Pass 1 of term tr: T = (A_{b,p} C_p)^T into Tb [idx][npad][npad] (row =
 // column of C_p). C_p comes from the sweep's -C_p (negated here), zero past
 // nb. grid (npad / kPC, nmat).
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_big_pass1(BigFactorIn in, BigLevel lv, int tr,
                                                        const double* __restrict__ coef,
                                                        const double* __restrict__ Cb0,
@@ -685,7 +696,7 @@ __global__ __launch_bounds__(kThreads) void k_big_pass1(BigFactorIn in, BigLevel
   const double* Cp = (buf ? Cb1 : Cb0) + (size_t)slot * matE;
   const int nb = g.nb, npad = bs.npad;
   double* Tm = Tb + (size_t)idx * npad * npad;
-  stencil_rows(
+  stencil_rows<D>(
       g, coef + (size_t)idx * nb * 27, Xw, blockIdx.x * kPC,
       [&](int l, int col) -> double {
         if (col >= nb) return 0.0;
@@ -700,6 +711,7 @@ __global__ __launch_bounds__(kThreads) void k_big_pass1(BigFactorIn in, BigLevel
 // Pass 2 of term tr: S_b = A_bb - A_{b,p} T (first term; A_bb alone when
 // has_y = 0) or S_b -= A_{b,p} T (second term), lower tiles in C layout;
 // the first writes the padding rows too (unit diagonal). grid (npad / kPC, nmat).
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_big_pass2(BigFactorIn in, BigLevel lv, int tr,
                                                        const double* __restrict__ coef,
                                                        const double* __restrict__ Tb,
@@ -741,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void k_big_pass2(BigFactorIn in, BigLevel
     }
   };
   if (has_y) {
-    stencil_rows(
+    stencil_rows<D>(
         g, coef + (size_t)idx * nb * 27, Xw, col0,
         [&](int l, int col) -> double { return col < nb ? Tm[(size_t)l * npad + col] : 0.0; },
         emit);
@@ -1423,10 +1435,13 @@ void big_factor(const BigFactorIn& in, T* out, double* ws, int* flag, hipStream_
   double* sws = coef + nmax * (size_t)g.nb * 27;
   static bool attr = false;
   if (!attr) {
-    allow_lds_big(&k_big_pass1);
-    allow_lds_big(&k_big_pass2);
+    allow_lds_big(&k_big_pass1<2>);
+    allow_lds_big(&k_big_pass2<2>);
+    allow_lds_big(&k_big_pass1<3>);
+    allow_lds_big(&k_big_pass2<3>);
     attr = true;
   }
+  const bool three = g.dim == 3;
   const size_t plds = pass_lds_bytes(g);
   if (in.neumann) hipLaunchKernelGGL(k_big_dis, dim3(g.nsub), dim3(kThreads), 0, st, in);
   const int mid = g.nblk / 2, nbot = g.nblk - 1 - mid;
@@ -1446,16 +1461,27 @@ void big_factor(const BigFactorIn& in, T* out, double* ws, int* flag, hipStream_
       if (nbot >= 1) terms[nterm++] = 1;
     }
     if (nterm == 0) {
-      hipLaunchKernelGGL(k_big_pass2, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv, 0,
-                         coef, Tb, S, 1, 0);
+      if (three)
+        hipLaunchKernelGGL(k_big_pass2<3>, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv, 0,
+                           coef, Tb, S, 1, 0);
+      else
+        hipLaunchKernelGGL(k_big_pass2<2>, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv, 0,
+                           coef, Tb, S, 1, 0);
     }
     for (int k = 0; k < nterm; ++k) {
       const int tr = terms[k];
       hipLaunchKernelGGL(k_big_coef, dim3(nmat), dim3(kThreads), 0, st, in, lv, tr, coef);
-      hipLaunchKernelGGL(k_big_pass1, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv, tr,
-                         coef, Cb[0], Cb[1], Tb);
-      hipLaunchKernelGGL(k_big_pass2, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv, tr,
-                         coef, Tb, S, k == 0 ? 1 : 0, 1);
+      if (three) {
+        hipLaunchKernelGGL(k_big_pass1<3>, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv,
+                           tr, coef, Cb[0], Cb[1], Tb);
+        hipLaunchKernelGGL(k_big_pass2<3>, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv,
+                           tr, coef, Tb, S, k == 0 ? 1 : 0, 1);
+      } else {
+        hipLaunchKernelGGL(k_big_pass1<2>, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv,
+                           tr, coef, Cb[0], Cb[1], Tb);
+        hipLaunchKernelGGL(k_big_pass2<2>, dim3(nchunk, nmat), dim3(kThreads), plds, st, in, lv,
+                           tr, coef, Tb, S, k == 0 ? 1 : 0, 1);
+      }
     }
     // the matrices of this level sit in slots 2 ss + half: contiguous with
     // two halves, every second slot with one
