@@ -614,28 +614,32 @@ __global__ __launch_bounds__(kThreads) void k_coarse_W(Geometry g, const double*
   }
 }
 
-// Blocks Phi_l^T W_j of K_c for every neighbour l of j, one pass over the
-// nodes for all k x k mode pairs (k <= KM): thread-local outer products,
-// then one reduction per pair. grid.x = nsub * 3^d, grid.y = system.
-// Unused modes (zero columns of Phi, threshold mode) get a unit diagonal, so
-// that K_c stays nonsingular and their coarse unknowns stay zero.
-template <int KM>
-__global__ __launch_bounds__(kThreads) void k_coarse_assemble_all(Geometry g,
+// Blocks Phi_l^T W_j of K_c for every neighbour l of j whose coarse block is
+// j's block or the next one (the lower part of the block-tridiagonal
+// storage), every k <= 16, on the FP64 matrix cores. Unused modes (zero
+// columns of Phi, threshold mode) get a unit diagonal, so that K_c stays
+// nonsingular and their coarse unknowns stay zero. The rows of the product are the (node, component) pairs of box l
+// inside the extended box of j; lane (i, kk) of a wave feeds mode i of row
+// kk of a four-row chunk of Phi_l and of W_j to v_mfma_f64_16x16x4f64, the
+// four waves taking every fourth chunk and eight chunks' loads issued ahead
+// of their products. grid.x = nsub * 3^d, grid.y = system.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_coarse_assemble_mma(Geometry g,
                                                                   const double* __restrict__ phi,
                                                                   const double* __restrict__ W,
                                                                   size_t wstride,
                                                                   double* __restrict__ cf,
                                                                   size_t cstride,
                                                                   const int* __restrict__ kj) {
-  __shared__ double red[kThreads / 64][KM * KM];
-  const int nnb = g.dim == 3 ? 27 : 9;
+  __shared__ double part[kThreads / 64][256];
+  constexpr int d = D, nnb = D == 3 ? 27 : 9;
   const int j = blockIdx.x / nnb;
   const int o = blockIdx.x - j * nnb;
   const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
-  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = g.dim == 3 ? o / 9 - 1 : 0;
+  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = D == 3 ? o / 9 - 1 : 0;
   const int lx = jx + ox, ly = jy + oy, lz = jz + oz;
   if (lx < 0 || lx >= g.gx || ly < 0 || ly >= g.gy || lz < 0 || lz >= g.gz) return;
-  const int k = g.k, d = g.dim;
+  const int k = g.k;
   const int Rb = coarse_index(g, lx, ly, lz, 0), Cb = coarse_index(g, jx, jy, jz, 0);
   const int rblk = Rb / g.nbc, cblk = Cb / g.nbc;
   int slot;
@@ -648,111 +652,46 @@ __global__ __launch_bounds__(kThreads) void k_coarse_assemble_all(Geometry g,
   const int x0 = max(g.s * lx, g.s * jx - 1), x1 = min(g.s * lx + g.s, g.s * jx + g.s + 1);
   const int y0 = max(g.s * ly, g.s * jy - 1), y1 = min(g.s * ly + g.s, g.s * jy + g.s + 1);
   int z0 = 0, z1 = 0;
-  if (d == 3) { z0 = max(g.s * lz, g.s * jz - 1); z1 = min(g.s * lz + g.s, g.s * jz + g.s + 1); }
+  if (D == 3) { z0 = max(g.s * lz, g.s * jz - 1); z1 = min(g.s * lz + g.s, g.s * jz + g.s + 1); }
   const int nxr = x1 - x0 + 1, nyr = y1 - y0 + 1, nzr = z1 - z0 + 1;
-  const int cnt = nxr * nyr * nzr;
+  const int nrow = nxr * nyr * nzr * d;
   double* blk = cf + blockIdx.y * cstride + ((size_t)rblk * 2 + slot) * g.nbc * g.nbc;
   const int rin = Rb - rblk * g.nbc, cin = Cb - cblk * g.nbc;
   const int e = g.ebn;
-  double acc[KM][KM];
+  const int t = threadIdx.x, wv = t >> 6, ln = t & 63, li = ln & 15, lq = ln >> 4;
+  constexpr int kU = 8;
+  dv4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 4 * wv; r0 < nrow; r0 += 16 * kU) {
+    double va[kU], vb[kU];
 #pragma unroll
-  for (int a = 0; a < KM; ++a)
-#pragma unroll
-    for (int b = 0; b < KM; ++b) acc[a][b] = 0.0;
-  for (int idx = threadIdx.x; idx < cnt; idx += kThreads) {
-    const int nx = x0 + idx % nxr, ny = y0 + (idx / nxr) % nyr, nz = z0 + idx / (nxr * nyr);
-    const int lb = (nx - g.s * lx) + g.bn * ((ny - g.s * ly) + g.bn * (nz - g.s * lz));
-    const int eb = (nx - g.s * jx + 1) + e * ((ny - g.s * jy + 1) + e * (d == 3 ? nz - g.s * jz + 1 : 0));
-    for (int c = 0; c < d; ++c) {
-      const double* pv = pl + ((size_t)d * lb + c) * k;
-      const double* wv = Wj + ((size_t)eb * d + c) * k;
-      double p[KM], w[KM];
-#pragma unroll
-      for (int a = 0; a < KM; ++a) {
-        p[a] = a < k ? pv[a] : 0.0;
-        w[a] = a < k ? wv[a] : 0.0;
+    for (int u = 0; u < kU; ++u) {
+      const int row = r0 + 16 * u + lq;
+      va[u] = vb[u] = 0.0;
+      if (row < nrow && li < k) {
+        const int idx = row / d, c = row - (row / d) * d;
+        const int nx = x0 + idx % nxr, ny = y0 + (idx / nxr) % nyr, nz = z0 + idx / (nxr * nyr);
+        const int lb = (nx - g.s * lx) + g.bn * ((ny - g.s * ly) + g.bn * (nz - g.s * lz));
+        const int eb = (nx - g.s * jx + 1) +
+                       e * ((ny - g.s * jy + 1) + e * (D == 3 ? nz - g.s * jz + 1 : 0));
+        va[u] = pl[((size_t)d * lb + c) * k + li];
+        vb[u] = Wj[((size_t)eb * d + c) * k + li];
       }
-#pragma unroll
-      for (int a = 0; a < KM; ++a)
-#pragma unroll
-        for (int b = 0; b < KM; ++b) acc[a][b] += p[a] * w[b];
     }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], vb[u], acc, 0, 0, 0);
   }
-  const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int a = 0; a < KM; ++a)
-#pragma unroll
-    for (int b = 0; b < KM; ++b) {
-      const double v = wave_sum(acc[a][b]);
-      if ((threadIdx.x & 63) == 0) red[wv][a * KM + b] = v;
-    }
+  for (int q = 0; q < 4; ++q) part[wv][(4 * q + lq) * 16 + li] = acc[q];
   __syncthreads();
-  for (int i = threadIdx.x; i < k * k; i += kThreads) {
-    const int a = i / k, b = i - (i / k) * k;
-    double v = 0.0;
-#pragma unroll
-    for (int w2 = 0; w2 < kThreads / 64; ++w2) v += red[w2][a * KM + b];
-    if (l == j && a == b && a >= kj[j]) v = 1.0;
-    blk[(size_t)(rin + a) * g.nbc + cin + b] = v;
-  }
-}
-
-// Blocks Phi_l^T W_j of K_c for every neighbour l of j whose coarse block is
-// j's block or the next one (the lower part of the block-tridiagonal
-// storage). grid.x = nsub * 3^d.
-__global__ __launch_bounds__(kThreads) void k_coarse_assemble(Geometry g, const double* __restrict__ phi,
-                                                             const double* __restrict__ W,
-                                                             double* __restrict__ cf,
-                                                             const int* __restrict__ kj) {
-  __shared__ double sh[4];
-  const int nnb = g.dim == 3 ? 27 : 9;
-  const int j = blockIdx.x / nnb;
-  const int o = blockIdx.x - j * nnb;
-  const int jx = j % g.gx, jy = (j / g.gx) % g.gy, jz = j / (g.gx * g.gy);
-  const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = g.dim == 3 ? o / 9 - 1 : 0;
-  const int lx = jx + ox, ly = jy + oy, lz = jz + oz;
-  if (lx < 0 || lx >= g.gx || ly < 0 || ly >= g.gy || lz < 0 || lz >= g.gz) return;
-  const int k = g.k, d = g.dim;
-  const int Rb = coarse_index(g, lx, ly, lz, 0), Cb = coarse_index(g, jx, jy, jz, 0);
-  const int rblk = Rb / g.nbc, cblk = Cb / g.nbc;
-  int slot;
-  if (rblk == cblk) slot = 0;
-  else if (rblk == cblk + 1) slot = 1;
-  else return;
-  const int l = lx + g.gx * (ly + g.gy * lz);
-  const double* pl = phi + (size_t)l * g.nloc * k;
-  const double* Wj = W + (size_t)j * g.nebox * d * k;
-  // nodes of box l inside the extended box of j
-  const int x0 = max(g.s * lx, g.s * jx - 1), x1 = min(g.s * lx + g.s, g.s * jx + g.s + 1);
-  const int y0 = max(g.s * ly, g.s * jy - 1), y1 = min(g.s * ly + g.s, g.s * jy + g.s + 1);
-  int z0 = 0, z1 = 0;
-  if (d == 3) { z0 = max(g.s * lz, g.s * jz - 1); z1 = min(g.s * lz + g.s, g.s * jz + g.s + 1); }
-  const int nxr = x1 - x0 + 1, nyr = y1 - y0 + 1, nzr = z1 - z0 + 1;
-  const int cnt = nxr * nyr * nzr;
-  double* blk = cf + ((size_t)rblk * 2 + slot) * g.nbc * g.nbc;
-  const int rin = Rb - rblk * g.nbc, cin = Cb - cblk * g.nbc;
-  const int e = g.ebn;
-  for (int mr = 0; mr < k; ++mr) {
-    double acc[kMaxK];
-    for (int mm = 0; mm < kMaxK; ++mm) acc[mm] = 0.0;
-    for (int idx = threadIdx.x; idx < cnt; idx += kThreads) {
-      const int nx = x0 + idx % nxr, ny = y0 + (idx / nxr) % nyr, nz = z0 + idx / (nxr * nyr);
-      const int lb = (nx - g.s * lx) + g.bn * ((ny - g.s * ly) + g.bn * (nz - g.s * lz));
-      const int eb = (nx - g.s * jx + 1) + e * ((ny - g.s * jy + 1) + e * (d == 3 ? nz - g.s * jz + 1 : 0));
-      for (int c = 0; c < d; ++c) {
-        const double pv = pl[((size_t)d * lb + c) * k + mr];
-        const double* wv = Wj + ((size_t)eb * d + c) * k;
-        for (int mm = 0; mm < k; ++mm) acc[mm] += pv * wv[mm];
-      }
-    }
-    for (int mm = 0; mm < k; ++mm) {
-      double v = block_sum(acc[mm], sh);
-      if (l == j && mr == mm && mr >= kj[j]) v = 1.0;
-      if (threadIdx.x == 0) blk[(size_t)(rin + mr) * g.nbc + cin + mm] = v;
+  if (t < 256) {
+    const int a = t >> 4, b = t & 15;
+    if (a < k && b < k) {
+      double v = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+      if (l == j && a == b && a >= kj[j]) v = 1.0;
+      blk[(size_t)(rin + a) * g.nbc + cin + b] = v;
     }
   }
 }
-
 
 // moduli E_e of the systems the local factors are built from
 template <typename T>
@@ -1003,14 +942,12 @@ int build_preconditioner(Handle& h, const double* rho, int nsys, int rep, int wi
       hipLaunchKernelGGL((k_coarse_W<3, kMaxK>), wgrid, dim3(kThreads), 0, st, g, rho, h.K0,
                          h.fixed, h.phi, W, wsz, mp);
   }
-  if (g.k <= 8) {
-    hipLaunchKernelGGL(k_coarse_assemble_all<8>, dim3(g.nsub * nnb, nsys), dim3(kThreads), 0, st,
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_coarse_assemble_mma<2>, dim3(g.nsub * nnb, nsys), dim3(kThreads), 0, st,
                        g, h.phi, W, wsz, Ac, asm_coarse, h.kj);
-  } else {
-    for (int sys = 0; sys < nsys; ++sys)
-      hipLaunchKernelGGL(k_coarse_assemble, dim3(g.nsub * nnb), dim3(kThreads), 0, st, g, h.phi,
-                         W + sys * wsz, Ac + sys * asm_coarse, h.kj);
-  }
+  else
+    hipLaunchKernelGGL(k_coarse_assemble_mma<3>, dim3(g.nsub * nnb, nsys), dim3(kThreads), 0, st,
+                       g, h.phi, W, wsz, Ac, asm_coarse, h.kj);
   hipEventRecord(h.fork, st);
   hipStreamWaitEvent(h.side, h.fork, 0);
 
