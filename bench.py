@@ -770,8 +770,9 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64 outer CG, f32 local solves and coarse-basis products", "data": "synthetic",
             "config": {"workload": "serving_stream_q4_h8_mixed",
-                       "step": "one request: admission, 10 warm-started robust design updates "
-                               "(density pipeline, basis rule, batched PCG, sensitivities)",
+                       "step": f"one request: admission, {args.serving_updates} warm-started robust "
+                               "design updates (density pipeline, basis rule, batched PCG, "
+                               "sensitivities)",
                        "rtol": args.rtol},
             "serving_mixed": mixed, "serving_fp64": fp64,
             "roofline": None, "cpu_baseline": None,

@@ -31,9 +31,20 @@ def small_3d():
     return p
 
 
-@pytest.mark.parametrize("which", ["c1", "cantilever", "h8"])
+def tiled_3d():
+    # 41 x 13 x 9 nodes: 3 x 4 x 3 operator tiles of 16 x 4 x 4 nodes, ragged on every axis
+    return W.cantilever3d(40, 12, 8, sub=4, k=6)
+
+
+def small_3d_penal():
+    # a SIMP exponent other than 3 (the general power in the kernels)
+    return dataclasses.replace(small_3d(), penal=2.5)
+
+
+@pytest.mark.parametrize("which", ["c1", "cantilever", "h8", "h8_tiles", "h8_penal"])
 def test_apply_K_matches_assembled_operator(which):
-    p = {"c1": c1, "cantilever": small_cantilever, "h8": small_3d}[which]()
+    p = {"c1": c1, "cantilever": small_cantilever, "h8": small_3d, "h8_tiles": tiled_3d,
+         "h8_penal": small_3d_penal}[which]()
     rng = np.random.default_rng(11)
     rho = rng.uniform(0.0, 1.0, p.n_el)
     x = rng.standard_normal(p.n_dof)
