@@ -161,53 +161,6 @@ __global__ __launch_bounds__(kThreads) void k_eig_cholqr(Geometry g, double* __r
   }
 }
 
-// Classical Gram-Schmidt applied twice, column by column, on X[j] (nloc x m,
-// row-major) in place; supported DOFs are zeroed first.
-__global__ __launch_bounds__(kThreads) void k_eig_orth(Geometry g, double* __restrict__ X,
-                                                      const double* __restrict__ dis, int m) {
-  __shared__ double sh[4];
-  __shared__ double hq[kMaxSub];
-  const int j = blockIdx.x;
-  double* Xj = X + (size_t)j * g.nloc * m;
-  const double* dj = dis + (size_t)j * g.nloc;
-  for (int l = threadIdx.x; l < g.nloc; l += kThreads)
-    if (dj[l] == 0.0)
-      for (int r = 0; r < m; ++r) Xj[(size_t)l * m + r] = 0.0;
-  __syncthreads();
-  for (int r = 0; r < m; ++r) {
-    for (int pass = 0; pass < 2; ++pass) {
-      if (r > 0) {
-        double acc[kMaxSub];
-        for (int q = 0; q < kMaxSub; ++q) acc[q] = 0.0;
-        for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
-          const double xr = Xj[(size_t)l * m + r];
-          for (int q = 0; q < r; ++q) acc[q] += Xj[(size_t)l * m + q] * xr;
-        }
-        for (int q = 0; q < r; ++q) {
-          const double v = block_sum(acc[q], sh);
-          if (threadIdx.x == 0) hq[q] = v;
-        }
-        __syncthreads();
-        for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
-          double v = Xj[(size_t)l * m + r];
-          for (int q = 0; q < r; ++q) v -= hq[q] * Xj[(size_t)l * m + q];
-          Xj[(size_t)l * m + r] = v;
-        }
-        __syncthreads();
-      }
-    }
-    double a = 0.0;
-    for (int l = threadIdx.x; l < g.nloc; l += kThreads) {
-      const double v = Xj[(size_t)l * m + r];
-      a += v * v;
-    }
-    const double nr = sqrt(block_sum(a, sh));
-    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
-    for (int l = threadIdx.x; l < g.nloc; l += kThreads) Xj[(size_t)l * m + r] *= inv;
-    __syncthreads();
-  }
-}
-
 // Y = (L L^T)^-1 X for every subdomain, m right-hand sides (FP64).
 // D = g.dim as a constant, so that the accumulators are indexed statically
 // and stay in registers
