@@ -77,13 +77,36 @@ __global__ __launch_bounds__(kSubThreads) void k_restrict(Geometry g, const P* _
     for (int m0 = 0; m0 < KM; m0 += 8)
       if (m0 < ku) {
         double pv[8][kRU];
+        if constexpr (sizeof(P) == 4) {
+          // FP32 copy: every load from a valid address (entry 0 of the box
+          // when out of range) and no branch around it, all issued before the
+          // first product; a load guarded by a branch was waited for inside
+          // the branch, where its conversion sat, which serialised the group
+          P raw[8][kRU];
 #pragma unroll
-        for (int mm = 0; mm < 8; ++mm)
+          for (int mm = 0; mm < 8; ++mm)
 #pragma unroll
-          for (int u = 0; u < kRU; ++u) {
-            const int l = l0 + u * kSubThreads, m = m0 + mm;
-            pv[mm][u] = (m < ku && l < lend) ? (double)ph[(size_t)m * g.nloc + l] : 0.0;
-          }
+            for (int u = 0; u < kRU; ++u) {
+              const int l = l0 + u * kSubThreads, m = m0 + mm;
+              raw[mm][u] = ph[(m < ku && l < lend) ? (size_t)m * g.nloc + l : 0];
+            }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int mm = 0; mm < 8; ++mm)
+#pragma unroll
+            for (int u = 0; u < kRU; ++u) {
+              const int l = l0 + u * kSubThreads, m = m0 + mm;
+              pv[mm][u] = (m < ku && l < lend) ? (double)raw[mm][u] : 0.0;
+            }
+        } else {
+#pragma unroll
+          for (int mm = 0; mm < 8; ++mm)
+#pragma unroll
+            for (int u = 0; u < kRU; ++u) {
+              const int l = l0 + u * kSubThreads, m = m0 + mm;
+              pv[mm][u] = (m < ku && l < lend) ? (double)ph[(size_t)m * g.nloc + l] : 0.0;
+            }
+        }
 #pragma unroll
         for (int mm = 0; mm < 8; ++mm)
 #pragma unroll
@@ -368,6 +391,14 @@ __global__ __launch_bounds__(kThreads) void k_extend(
                 const T2 v = m < ku ? *reinterpret_cast<const T2*>(pj + (size_t)m * g.nloc) : T2{0, 0};
                 pv[u][0] = (double)v.x;
                 pv[u][1] = (double)v.y;
+              } else if constexpr (sizeof(T) == 4) {
+                // FP32 copy: loads from a valid address without a branch (as
+                // in the restriction), then the conversion
+                T raw[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) raw[c] = pj[m < ku ? (size_t)m * g.nloc + c : 0];
+#pragma unroll
+                for (int c = 0; c < D; ++c) pv[u][c] = m < ku ? (double)raw[c] : 0.0;
               } else {
 #pragma unroll
                 for (int c = 0; c < D; ++c) pv[u][c] = m < ku ? (double)pj[(size_t)m * g.nloc + c] : 0.0;
