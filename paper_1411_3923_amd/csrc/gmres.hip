@@ -62,7 +62,8 @@ __device__ inline void corner_offsets(int b, int& bx, int& by, int& bz) {
 
 // x_n += D_n^-1 (r_n - (P K P x)_n) for every node n of `colour`, D_n the
 // node's diagonal block of P K P with unit rows and columns on its fixed
-// components; fixed components of x stay zero. grid (parts, nsys).
+// components; fixed components of x stay zero. grid (parts, nsys). The 3-d
+// cycle launches it; 2-d meshes take the tiled form k_sgs_colour_q4.
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_sgs_colour(Geometry g, const double* __restrict__ rho,
                                                          const double* __restrict__ K0, double E0,
@@ -161,6 +162,116 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour(Geometry g, const doubl
 #pragma unroll
     for (int c = 0; c < D; ++c) xs[D * n + c] = fx[c] ? 0.0 : xs[D * n + c] + dl[c];
   }
+}
+
+// 2-d form of k_sgs_colour: the colour's nodes of a tile of kSX x kSY nodes,
+// one per thread (the colour takes every second node along each axis). The
+// workgroup stages the tile's one-node halo of P x in LDS, so that the
+// neighbours are read once and coalesced instead of gathered per node; the
+// four moduli of a node come from global memory, their loads issued before
+// the staging barrier (staging them too took LDS that kept fewer tiles
+// resident). Two nodes of one colour never share an element, so the staged
+// values are the current ones for every neighbour a node reads. The same
+// operations in the same order as k_sgs_colour<2>. grid (tiles, nsys).
+constexpr int kSX = 64, kSY = 16;
+static_assert((kSX / 2) * (kSY / 2) == kThreads, "one colour node per thread");
+
+__global__ __launch_bounds__(kThreads) void k_sgs_colour_q4(Geometry g, const double* __restrict__ rho,
+                                                            const double* __restrict__ K0, double E0,
+                                                            double Emin, double penal,
+                                                            const uint8_t* __restrict__ fixed,
+                                                            const double* __restrict__ r,
+                                                            double* __restrict__ x, int colour,
+                                                            Gate gate) {
+  constexpr int HX = kSX + 2, HY = kSY + 2;
+  __shared__ double K0s[64];
+  __shared__ double xh[HY * HX * 2];
+  const int sys = blockIdx.y;
+  if (!gate_running(gate, sys)) return;
+  const int t = threadIdx.x;
+  if (t < 64) K0s[t] = K0[t];
+  const int cx = colour & 1, cy = (colour >> 1) & 1;
+  const int ntx = (g.nnx + kSX - 1) / kSX;
+  const int x0 = (blockIdx.x % ntx) * kSX, y0 = (blockIdx.x / ntx) * kSY;
+  const double* rs = rho + (size_t)sys * g.nel;
+  const double* bs = r + (size_t)sys * g.ndof;
+  double* xs = x + (size_t)sys * g.ndof;
+  for (int i = t; i < HY * HX; i += kThreads) {
+    const int X = x0 - 1 + i % HX, Y = y0 - 1 + i / HX;
+    double v0 = 0.0, v1 = 0.0;
+    if (X >= 0 && X < g.nnx && Y >= 0 && Y < g.nny) {
+      const int64_t m = X + (int64_t)g.nnx * Y;
+      v0 = fixed[2 * m] ? 0.0 : xs[2 * m];
+      v1 = fixed[2 * m + 1] ? 0.0 : xs[2 * m + 1];
+    }
+    xh[2 * i] = v0;
+    xh[2 * i + 1] = v1;
+  }
+  const int ix = x0 + 2 * (t % (kSX / 2)) + cx, iy = y0 + 2 * (t / (kSX / 2)) + cy;
+  double Ev[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ex = ix - 1 + (e & 1), ey = iy - 1 + ((e >> 1) & 1);
+    const bool in = ex >= 0 && ex < g.nelx && ey >= 0 && ey < g.nely && ix < g.nnx && iy < g.nny;
+    const double rv = rs[in ? ex + (int64_t)g.nelx * ey : 0];
+    Ev[e] = in ? simp_modulus(rv, E0, Emin, penal) : 0.0;
+  }
+  __syncthreads();
+  if (ix >= g.nnx || iy >= g.nny) return;
+  const int64_t n = ix + (int64_t)g.nnx * iy;
+  double kx[2] = {0.0, 0.0}, blk[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int ox = e & 1, oy = (e >> 1) & 1;
+    const int ex = ix - 1 + ox, ey = iy - 1 + oy;
+    if (ex < 0 || ex >= g.nelx || ey < 0 || ey >= g.nely) continue;
+    const double E = Ev[e];
+    const int a = corner_of(1 - ox, 1 - oy, 0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int bx, by, bz;
+      corner_offsets(b, bx, by, bz);
+      const int hi = (ex + bx - x0 + 1) + HX * (ey + by - y0 + 1);
+      const double xm[2] = {xh[2 * hi], xh[2 * hi + 1]};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) s += K0s[(2 * a + c) * 8 + 2 * b + c2] * xm[c2];
+        kx[c] += E * s;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int c2 = 0; c2 < 2; ++c2) blk[c][c2] += E * K0s[(2 * a + c) * 8 + 2 * a + c2];
+  }
+  bool fx[2];
+  double rhs[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    fx[c] = fixed[2 * n + c] != 0;
+    rhs[c] = fx[c] ? 0.0 : bs[2 * n + c] - kx[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2)
+      if (fx[c] || fx[c2]) blk[c][c2] = (c == c2) ? 1.0 : 0.0;
+  // the 2 x 2 block solve of k_sgs_colour
+  {
+    const double piv = 1.0 / blk[0][0];
+    const double f = blk[1][0] * piv;
+    blk[1][0] -= f * blk[0][0];
+    blk[1][1] -= f * blk[0][1];
+    rhs[1] -= f * rhs[0];
+  }
+  double dl[2];
+  dl[1] = rhs[1] / blk[1][1];
+  dl[0] = (rhs[0] - blk[0][1] * dl[1]) / blk[0][0];
+  const int hn = (ix - x0 + 1) + HX * (iy - y0 + 1);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) xs[2 * n + c] = fx[c] ? 0.0 : xh[2 * hn + c] + dl[c];
 }
 
 // x += Phi x_c (the prolongation of the coarse correction) for every
@@ -594,10 +705,11 @@ void launch_msfem_cycle(Handle& h, const double* rho, const double* rin, double*
     const int64_t cnt = (int64_t)((g.nnx + 1) / 2) * ((g.nny + 1) / 2) * (g.dim == 3 ? (g.nnz + 1) / 2 : 1);
     const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((cnt + kThreads - 1) / kThreads, 4096)),
                     nsys);
-    if (g.dim == 2)
-      hipLaunchKernelGGL(k_sgs_colour<2>, grid, dim3(kThreads), 0, st, g, rho, h.K0, pr.E0,
-                         pr.Emin, pr.penal, h.fixed, rin, xout, c, gate);
-    else
+    if (g.dim == 2) {
+      const unsigned ntile = (unsigned)(((g.nnx + kSX - 1) / kSX) * ((g.nny + kSY - 1) / kSY));
+      hipLaunchKernelGGL(k_sgs_colour_q4, dim3(ntile, nsys), dim3(kThreads), 0, st, g, rho, h.K0,
+                         pr.E0, pr.Emin, pr.penal, h.fixed, rin, xout, c, gate);
+    } else
       hipLaunchKernelGGL(k_sgs_colour<3>, grid, dim3(kThreads), 0, st, g, rho, h.K0, pr.E0,
                          pr.Emin, pr.penal, h.fixed, rin, xout, c, gate);
   };
