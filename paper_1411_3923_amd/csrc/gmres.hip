@@ -439,6 +439,69 @@ __global__ __launch_bounds__(kThreads) void k_gm_orth(const double* __restrict__
   }
 }
 
+// The first pass's update fused with the second pass's dots: w -= sum_q V_q
+// h_q, then the partials of V_q . w (q < nvec), reading each basis value
+// once for both. Each workgroup takes tiles of 64 consecutive entries; wave
+// wv owns the vectors q = wv c + u (u < c = ceil(nvec / 4) <= C), keeps their
+// values of the tile in registers, and leaves its partial sum of V_q h_q in
+// LDS; after the barrier every wave forms the same updated entries (the four
+// partials in a fixed order) and adds its vectors' products. Partials per
+// workgroup in k_gm_dots's layout. grid (np, nsys).
+template <int C>
+__global__ __launch_bounds__(kThreads) void k_gm_orth_dots(const double* __restrict__ V, int nvec,
+                                                           int nsys, const double* __restrict__ h,
+                                                           double* __restrict__ w,
+                                                           double* __restrict__ part, int64_t n,
+                                                           Gate gate) {
+  __shared__ double pw[2][4][64];
+  const int sys = blockIdx.y;
+  if (!gate_running(gate, sys)) return;
+  const int t = threadIdx.x, wv = t >> 6, lane = t & 63;
+  const int c = (nvec + 3) / 4, q0 = wv * c;
+  double hq[C];
+  int qi[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    const bool ok = u < c && q0 + u < nvec;
+    hq[u] = ok ? h[(size_t)sys * kGmMaxVec + q0 + u] : 0.0;
+    qi[u] = ok ? q0 + u : 0;   // a valid vector whose h is zero
+  }
+  double* ws = w + (size_t)sys * n;
+  const double* vb = V + (size_t)sys * n;
+  const size_t vstep = (size_t)nsys * n;
+  double acc[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) acc[u] = 0.0;
+  int buf = 0;
+  for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < n; i0 += (int64_t)gridDim.x * 64) {
+    const int64_t i = i0 + lane;
+    const bool in = i < n;
+    const int64_t ii = in ? i : i0;
+    double x[C];
+#pragma unroll
+    for (int u = 0; u < C; ++u) x[u] = vb[(size_t)qi[u] * vstep + ii];
+    const double wi = ws[ii];
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < C; ++u) p += x[u] * hq[u];
+    pw[buf][wv][lane] = p;
+    __syncthreads();   // (double-buffered: the next tile writes the other half)
+    const double v =
+        wi - ((pw[buf][0][lane] + pw[buf][1][lane]) + (pw[buf][2][lane] + pw[buf][3][lane]));
+    if (wv == 0 && in) ws[i] = v;
+    const double vv = in ? v : 0.0;
+#pragma unroll
+    for (int u = 0; u < C; ++u) acc[u] += x[u] * vv;
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    const double sum = wave_sum(acc[u]);
+    if (lane == 0 && u < c && q0 + u < nvec)
+      part[((size_t)sys * kGmMaxVec + q0 + u) * kMaxParts + blockIdx.x] = sum;
+  }
+}
+
 // w *= inv (per system scalar)
 __global__ __launch_bounds__(kThreads) void k_gm_scale(double* __restrict__ w,
                                                        const double* __restrict__ sc, int64_t n,
@@ -656,6 +719,21 @@ void launch_dots(const Handle& h, int chunk, const double* V, int nv, int nsys, 
 #undef TPCG_DOTS
 }
 
+// the first pass's update and the second pass's dots in one launch (nv <= 64)
+void launch_orth_dots(const double* V, int nv, int nsys, const double* hv, double* w, double* part,
+                      int64_t n, int np, const Gate& gate, hipStream_t st) {
+  static_assert(kGmMaxRestart <= 64, "four waves of at most 16 vectors");
+  const int c = (nv + 3) / 4;
+#define TPCG_OD(C)                                                                    \
+  hipLaunchKernelGGL(k_gm_orth_dots<C>, dim3(np, nsys), dim3(kThreads), 0, st, V, nv, \
+                     nsys, hv, w, part, n, gate)
+  if (c <= 2) TPCG_OD(2);
+  else if (c <= 4) TPCG_OD(4);
+  else if (c <= 8) TPCG_OD(8);
+  else TPCG_OD(16);
+#undef TPCG_OD
+}
+
 }  // namespace
 
 double gmres_time_dots(Handle& h, int nsys, int nv, int chunk) {
@@ -713,9 +791,12 @@ void launch_msfem_cycle(Handle& h, const double* rho, const double* rin, double*
       hipLaunchKernelGGL(k_sgs_colour<3>, grid, dim3(kThreads), 0, st, g, rho, h.K0, pr.E0,
                          pr.Emin, pr.penal, h.fixed, rin, xout, c, gate);
   };
+  // the colours up, then down; the last colour is not solved twice in a
+  // row: its block equations hold after the first solve (its nodes share
+  // no element), so a second one would change x by rounding only
   auto sgs_step = [&]() {
     for (int c = 0; c < nc; ++c) colour(c);
-    for (int c = nc - 1; c >= 0; --c) colour(c);
+    for (int c = nc - 2; c >= 0; --c) colour(c);
   };
   hipLaunchKernelGGL(k_gm_zero, vgrid, dim3(kThreads), 0, st, xout, g.ndof, gate);
   sgs_step();
@@ -795,9 +876,7 @@ int gmres_solve(Handle& h, const double* rho, const double* f, double* u, int ns
       launch_dots(h, h.gm_chunk, V(0), nv, nsys, wj, w + kGmPart, np, run, st);
       hipLaunchKernelGGL(k_gm_sum, dim3(nv, nsys), dim3(kThreads), 0, st, w + kGmPart, np,
                          w + kGmHA, kGmMaxVec, run);
-      hipLaunchKernelGGL(k_gm_orth, vgrid, dim3(kThreads), 0, st, V(0), nv, nsys, w + kGmHA, wj,
-                         nullptr, n, run);
-      launch_dots(h, h.gm_chunk, V(0), nv, nsys, wj, w + kGmPart, np, run, st);
+      launch_orth_dots(V(0), nv, nsys, w + kGmHA, wj, w + kGmPart, n, np, run, st);
       hipLaunchKernelGGL(k_gm_sum, dim3(nv, nsys), dim3(kThreads), 0, st, w + kGmPart, np,
                          w + kGmHB, kGmMaxVec, run);
       hipLaunchKernelGGL(k_gm_orth, vgrid, dim3(kThreads), 0, st, V(0), nv, nsys, w + kGmHB, wj,
