@@ -166,8 +166,9 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour(Geometry g, const doubl
 
 // 2-d form of k_sgs_colour: the colour's nodes of a tile of kSX x kSY nodes,
 // one per thread (the colour takes every second node along each axis). The
-// workgroup stages the tile's one-node halo of P x in LDS, so that the
-// neighbours are read once and coalesced instead of gathered per node; the
+// workgroup stages the tile's one-node halo of x (node pairs as 16-byte
+// loads) in LDS, so that the neighbours are read once and coalesced instead
+// of gathered per node; the
 // four moduli of a node come from global memory, their loads issued before
 // the staging barrier (staging them too took LDS that kept fewer tiles
 // resident). Two nodes of one colour never share an element, so the staged
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour_q4(Geometry g, const do
                                                             Gate gate) {
   constexpr int HX = kSX + 2, HY = kSY + 2;
   __shared__ double K0s[64];
-  __shared__ double xh[HY * HX * 2];
+  __shared__ __align__(16) double xh[HY * HX * 2];
   const int sys = blockIdx.y;
   if (!gate_running(gate, sys)) return;
   const int t = threadIdx.x;
@@ -196,16 +197,14 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour_q4(Geometry g, const do
   const double* rs = rho + (size_t)sys * g.nel;
   const double* bs = r + (size_t)sys * g.ndof;
   double* xs = x + (size_t)sys * g.ndof;
+  // x is P x already: the cycle starts from zero and every kernel writing
+  // x leaves the supported components at zero
   for (int i = t; i < HY * HX; i += kThreads) {
     const int X = x0 - 1 + i % HX, Y = y0 - 1 + i / HX;
-    double v0 = 0.0, v1 = 0.0;
-    if (X >= 0 && X < g.nnx && Y >= 0 && Y < g.nny) {
-      const int64_t m = X + (int64_t)g.nnx * Y;
-      v0 = fixed[2 * m] ? 0.0 : xs[2 * m];
-      v1 = fixed[2 * m + 1] ? 0.0 : xs[2 * m + 1];
-    }
-    xh[2 * i] = v0;
-    xh[2 * i + 1] = v1;
+    double2 v = {0.0, 0.0};
+    if (X >= 0 && X < g.nnx && Y >= 0 && Y < g.nny)
+      v = *reinterpret_cast<const double2*>(xs + 2 * (X + (int64_t)g.nnx * Y));
+    *reinterpret_cast<double2*>(xh + 2 * i) = v;
   }
   const int ix = x0 + 2 * (t % (kSX / 2)) + cx, iy = y0 + 2 * (t / (kSX / 2)) + cy;
   double Ev[4];
@@ -248,10 +247,12 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour_q4(Geometry g, const do
   }
   bool fx[2];
   double rhs[2];
+  const double2 bv = *reinterpret_cast<const double2*>(bs + 2 * n);
+  const double bn[2] = {bv.x, bv.y};
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     fx[c] = fixed[2 * n + c] != 0;
-    rhs[c] = fx[c] ? 0.0 : bs[2 * n + c] - kx[c];
+    rhs[c] = fx[c] ? 0.0 : bn[c] - kx[c];
   }
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -270,8 +271,8 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour_q4(Geometry g, const do
   dl[1] = rhs[1] / blk[1][1];
   dl[0] = (rhs[0] - blk[0][1] * dl[1]) / blk[0][0];
   const int hn = (ix - x0 + 1) + HX * (iy - y0 + 1);
-#pragma unroll
-  for (int c = 0; c < 2; ++c) xs[2 * n + c] = fx[c] ? 0.0 : xh[2 * hn + c] + dl[c];
+  *reinterpret_cast<double2*>(xs + 2 * n) =
+      make_double2(fx[0] ? 0.0 : xh[2 * hn] + dl[0], fx[1] ? 0.0 : xh[2 * hn + 1] + dl[1]);
 }
 
 // x += Phi x_c (the prolongation of the coarse correction) for every
