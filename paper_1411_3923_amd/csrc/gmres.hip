@@ -310,26 +310,56 @@ __global__ __launch_bounds__(kThreads) void k_prolong_add(Geometry g, const P* _
           const int ln = (ix - s * jx) + g.bn * ((iy - s * jy) + g.bn * (iz - s * jz));
           const int ci = coarse_index(g, jx, jy, jz, 0);
           const P* ph = phim + (size_t)j * k * g.nloc + (size_t)D * ln;
-          for (int m = 0; m < k; ++m) {
-            double pv[D];
+          // modes in groups of eight, the group's loads issued together from
+          // valid addresses (modes past k read mode k - 1 and are zeroed)
+          for (int m0 = 0; m0 < KM; m0 += 8) {
+            if (m0 >= k) break;
+            double pv[8][D];
 #pragma unroll
-            for (int c = 0; c < D; ++c) pv[c] = (double)ph[(size_t)m * g.nloc + c];
+            for (int u = 0; u < 8; ++u) {
+              const int mm = min(m0 + u, k - 1);
+#pragma unroll
+              for (int c = 0; c < D; ++c) pv[u][c] = (double)ph[(size_t)mm * g.nloc + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              if (m0 + u >= k)
+#pragma unroll
+                for (int c = 0; c < D; ++c) pv[u][c] = 0.0;
 #pragma unroll
             for (int q = 0; q < kMaxSys; ++q)
               if ((run >> q) & 1u) {
-                const double xv = xc[(size_t)q * g.nt + ci + m];
+                double xv[8];
 #pragma unroll
-                for (int c = 0; c < D; ++c) acc[q][c] += pv[c] * xv;
+                for (int u = 0; u < 8; ++u) xv[u] = xc[(size_t)q * g.nt + ci + min(m0 + u, k - 1)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                  if (m0 + u < k)
+#pragma unroll
+                    for (int c = 0; c < D; ++c) acc[q][c] += pv[u][c] * xv[u];
               }
           }
         }
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      const int64_t i = D * n + c;
-      if (fixed[i]) continue;
+    if constexpr (D == 2) {
+      const bool f0 = fixed[2 * n] != 0, f1 = fixed[2 * n + 1] != 0;
 #pragma unroll
       for (int q = 0; q < kMaxSys; ++q)
-        if ((run >> q) & 1u) x[(size_t)q * g.ndof + i] += acc[q][c];
+        if ((run >> q) & 1u) {
+          double2* xp = reinterpret_cast<double2*>(x + (size_t)q * g.ndof + 2 * n);
+          double2 v = *xp;
+          if (!f0) v.x += acc[q][0];
+          if (!f1) v.y += acc[q][1];
+          *xp = v;
+        }
+    } else {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const int64_t i = D * n + c;
+        if (fixed[i]) continue;
+#pragma unroll
+        for (int q = 0; q < kMaxSys; ++q)
+          if ((run >> q) & 1u) x[(size_t)q * g.ndof + i] += acc[q][c];
+      }
     }
   }
 }
