@@ -168,12 +168,12 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour(Geometry g, const doubl
 // one per thread (the colour takes every second node along each axis). The
 // workgroup stages the tile's one-node halo of x (node pairs as 16-byte
 // loads) in LDS, so that the neighbours are read once and coalesced instead
-// of gathered per node; the
-// four moduli of a node come from global memory, their loads issued before
-// the staging barrier (staging them too took LDS that kept fewer tiles
-// resident). Two nodes of one colour never share an element, so the staged
-// values are the current ones for every neighbour a node reads. The same
-// operations in the same order as k_sgs_colour<2>. grid (tiles, nsys).
+// of gathered per node; the four moduli of a node come from global memory,
+// their loads issued before the staging barrier (staging them too took LDS
+// that kept fewer tiles resident). Two nodes of one colour never share an
+// element, so the staged values are the current ones for every neighbour a
+// node reads. The same operations in the same order as k_sgs_colour<2>.
+// grid (tiles, nsys).
 constexpr int kSX = 64, kSY = 16;
 static_assert((kSX / 2) * (kSY / 2) == kThreads, "one colour node per thread");
 
