@@ -382,8 +382,11 @@ __global__ __launch_bounds__(kThreads) void k_gm_resid(const double* __restrict_
   const double* bs = b ? b + (size_t)sys * n : nullptr;
   double* os = out + (size_t)sys * n;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kThreads)
-    os[i] = fixed[i] ? 0.0 : as[i] - (bs ? bs[i] : 0.0);
+       i += (int64_t)gridDim.x * kThreads) {
+    const bool f = fixed[i] != 0;
+    const double av = as[i], bv = bs ? bs[i] : 0.0;
+    os[i] = f ? 0.0 : av - bv;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_gm_zero(double* __restrict__ x, int64_t n, Gate gate) {
@@ -418,10 +421,14 @@ __global__ __launch_bounds__(kThreads) void k_gm_dots(const double* __restrict__
   for (int u = 0; u < kGmChunk; ++u) acc[u] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads) {
+    // every load issued before the products (vectors past nv read the last
+    // one; their sums are never written)
+    double x[kGmChunk];
+#pragma unroll
+    for (int u = 0; u < kGmChunk; ++u) x[u] = vb[(size_t)min(u, nv - 1) * vstep + i];
     const double wv = ws[i];
 #pragma unroll
-    for (int u = 0; u < kGmChunk; ++u)
-      if (u < nv) acc[u] += vb[u * vstep + i] * wv;
+    for (int u = 0; u < kGmChunk; ++u) acc[u] += x[u] * wv;
   }
   for (int u = 0; u < nv; ++u) {
     const double s = block_sum(acc[u], sh);
@@ -460,7 +467,16 @@ __global__ __launch_bounds__(kThreads) void k_gm_orth(const double* __restrict__
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads) {
     double v = ws[i];
-    for (int q = 0; q < nvec; ++q) v -= vb[q * vstep + i] * hs[q];
+    // vectors in groups of eight, the group's loads issued before its
+    // products (past nvec: the last vector, not used)
+    for (int q0 = 0; q0 < nvec; q0 += 8) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = vb[(size_t)min(q0 + u, nvec - 1) * vstep + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < nvec) v -= x[u] * hs[q0 + u];
+    }
     ws[i] = v;
     acc += v * v;
   }
