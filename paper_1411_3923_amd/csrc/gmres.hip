@@ -467,16 +467,7 @@ __global__ __launch_bounds__(kThreads) void k_gm_orth(const double* __restrict__
   for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads) {
     double v = ws[i];
-    // vectors in groups of eight, the group's loads issued before its
-    // products (past nvec: the last vector, not used)
-    for (int q0 = 0; q0 < nvec; q0 += 8) {
-      double x[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = vb[(size_t)min(q0 + u, nvec - 1) * vstep + i];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (q0 + u < nvec) v -= x[u] * hs[q0 + u];
-    }
+    for (int q = 0; q < nvec; ++q) v -= vb[q * vstep + i] * hs[q];
     ws[i] = v;
     acc += v * v;
   }
