@@ -555,11 +555,12 @@ __global__ __launch_bounds__(kThreads) void k_gm_scale(double* __restrict__ w,
 
 // Column j of the Hessenberg matrix (H[:j+1, j] = hA + hB, H[j+1, j] = ||w||),
 // the earlier rotations applied to it, the new rotation, the residual
-// estimate, and the stopping tests. One thread per system.
-__global__ void k_gm_givens(int j, double* __restrict__ w, double tol, int maxit, int nsys,
-                            int* __restrict__ istate, int* __restrict__ gi) {
-  const int sys = threadIdx.x;
-  if (sys >= nsys || !gm_active(istate, sys)) return;
+// estimate, and the stopping tests. One wave per system.
+__global__ __launch_bounds__(64) void k_gm_givens(int j, double* __restrict__ w, double tol,
+                                                   int maxit, int nsys, int* __restrict__ istate,
+                                                   int* __restrict__ gi) {
+  const int sys = blockIdx.x, lane = threadIdx.x;
+  if (sys >= nsys || !gm_active(istate, sys)) return;   // uniform over the wave
   double* col = w + kGmH + ((size_t)sys * kGmMaxRestart + j) * kGmMaxVec;
   double* cs = w + kGmCS + (size_t)sys * kGmMaxRestart;
   double* sn = w + kGmSN + (size_t)sys * kGmMaxRestart;
@@ -567,17 +568,27 @@ __global__ void k_gm_givens(int j, double* __restrict__ w, double tol, int maxit
   double* sc = w + kGmSc + (size_t)sys * 8;
   const double* hA = w + kGmHA + (size_t)sys * kGmMaxVec;
   const double* hB = w + kGmHB + (size_t)sys * kGmMaxVec;
-  for (int i = 0; i <= j; ++i) col[i] = hA[i] + hB[i];
+  // lane i holds the new column's entry i (i <= j < 64) and rotation i (i < j),
+  // loaded together; the rotations then run in order on values passed by
+  // readlane, the entry that rotation i leaves behind carried to the next
+  const double hv = lane <= j ? hA[lane] + hB[lane] : 0.0;
+  const double ci = lane < j ? cs[lane] : 0.0, si = lane < j ? sn[lane] : 0.0;
   // the norm's partials were summed into hA[kGmMaxVec - 1]
   const double hn = sqrt(w[kGmHA + (size_t)sys * kGmMaxVec + kGmMaxVec - 1]);
-  col[j + 1] = hn;
+  double carry = bcast_lane(hv, 0), mine = hv;
+  for (int i = 0; i < j; ++i) {
+    const double a = carry, b = bcast_lane(hv, i + 1);
+    const double c = bcast_lane(ci, i), s = bcast_lane(si, i);
+    const double ni = c * a + s * b;
+    carry = -s * a + c * b;
+    if (lane == i) mine = ni;
+  }
+  if (lane < j) col[lane] = mine;
+  if (lane != 0) return;
   sc[kScHn] = hn;
   sc[kScInv] = hn > 0.0 ? 1.0 / hn : 0.0;
-  for (int i = 0; i < j; ++i) {
-    const double a = col[i], b = col[i + 1];
-    col[i] = cs[i] * a + sn[i] * b;
-    col[i + 1] = -sn[i] * a + cs[i] * b;
-  }
+  col[j] = carry;
+  col[j + 1] = hn;
   const double den = hypot(col[j], col[j + 1]);
   cs[j] = col[j] / den;
   sn[j] = col[j + 1] / den;
@@ -923,7 +934,8 @@ int gmres_solve(Handle& h, const double* rho, const double* f, double* u, int ns
       // read by the rotation kernel below before anything overwrites them)
       hipLaunchKernelGGL(k_gm_sum, dim3(1, nsys), dim3(kThreads), 0, st, w + kGmPart, np,
                          w + kGmHA + kGmMaxVec - 1, kGmMaxVec, run);
-      hipLaunchKernelGGL(k_gm_givens, dim3(1), dim3(64), 0, st, j, w, rtol, maxit, nsys, istate, gi);
+      hipLaunchKernelGGL(k_gm_givens, dim3(nsys), dim3(64), 0, st, j, w, rtol, maxit, nsys, istate,
+                         gi);
       hipLaunchKernelGGL(k_gm_scale, vgrid, dim3(kThreads), 0, st, wj, w + kGmSc, n, run);
       // poll the running flags one step behind the launches
       const int slot = total & 1;
