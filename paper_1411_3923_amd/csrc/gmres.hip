@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour_q4(Geometry g, const do
                                                             const uint8_t* __restrict__ fixed,
                                                             const double* __restrict__ r,
                                                             double* __restrict__ x, int colour,
-                                                            Gate gate) {
+                                                            unsigned seen, Gate gate) {
   constexpr int HX = kSX + 2, HY = kSY + 2;
   __shared__ double K0s[64];
   __shared__ __align__(16) double xh[HY * HX * 2];
@@ -197,12 +197,14 @@ __global__ __launch_bounds__(kThreads) void k_sgs_colour_q4(Geometry g, const do
   const double* rs = rho + (size_t)sys * g.nel;
   const double* bs = r + (size_t)sys * g.ndof;
   double* xs = x + (size_t)sys * g.ndof;
-  // x is P x already: the cycle starts from zero and every kernel writing
-  // x leaves the supported components at zero
+  // x is P x already: every kernel writing x leaves the supported
+  // components at zero. Nodes of the colours outside `seen` are read as
+  // zero (the cycle's first sweep starts from x = 0 without clearing it:
+  // a colour's nodes hold values once its first launch has written them).
   for (int i = t; i < HY * HX; i += kThreads) {
     const int X = x0 - 1 + i % HX, Y = y0 - 1 + i / HX;
     double2 v = {0.0, 0.0};
-    if (X >= 0 && X < g.nnx && Y >= 0 && Y < g.nny)
+    if (X >= 0 && X < g.nnx && Y >= 0 && Y < g.nny && ((seen >> ((X & 1) | ((Y & 1) << 1))) & 1u))
       v = *reinterpret_cast<const double2*>(xs + 2 * (X + (int64_t)g.nnx * Y));
     *reinterpret_cast<double2*>(xh + 2 * i) = v;
   }
@@ -828,14 +830,14 @@ void launch_msfem_cycle(Handle& h, const double* rho, const double* rin, double*
   const tpcg_problem& pr = h.prob;
   const dim3 vgrid(vec_parts(g), nsys);
   const int nc = 1 << g.dim;
-  auto colour = [&](int c) {
+  auto colour = [&](int c, unsigned seen) {
     const int64_t cnt = (int64_t)((g.nnx + 1) / 2) * ((g.nny + 1) / 2) * (g.dim == 3 ? (g.nnz + 1) / 2 : 1);
     const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((cnt + kThreads - 1) / kThreads, 4096)),
                     nsys);
     if (g.dim == 2) {
       const unsigned ntile = (unsigned)(((g.nnx + kSX - 1) / kSX) * ((g.nny + kSY - 1) / kSY));
       hipLaunchKernelGGL(k_sgs_colour_q4, dim3(ntile, nsys), dim3(kThreads), 0, st, g, rho, h.K0,
-                         pr.E0, pr.Emin, pr.penal, h.fixed, rin, xout, c, gate);
+                         pr.E0, pr.Emin, pr.penal, h.fixed, rin, xout, c, seen, gate);
     } else
       hipLaunchKernelGGL(k_sgs_colour<3>, grid, dim3(kThreads), 0, st, g, rho, h.K0, pr.E0,
                          pr.Emin, pr.penal, h.fixed, rin, xout, c, gate);
@@ -843,12 +845,14 @@ void launch_msfem_cycle(Handle& h, const double* rho, const double* rin, double*
   // the colours up, then down; the last colour is not solved twice in a
   // row: its block equations hold after the first solve (its nodes share
   // no element), so a second one would change x by rounding only
-  auto sgs_step = [&]() {
-    for (int c = 0; c < nc; ++c) colour(c);
-    for (int c = nc - 2; c >= 0; --c) colour(c);
+  // (from zero: in 2-d the first sweep reads the colours not yet written as
+  // zero instead of clearing x first)
+  auto sgs_step = [&](bool from_zero) {
+    for (int c = 0; c < nc; ++c) colour(c, from_zero ? (1u << c) - 1u : 0xfu);
+    for (int c = nc - 2; c >= 0; --c) colour(c, 0xfu);
   };
-  hipLaunchKernelGGL(k_gm_zero, vgrid, dim3(kThreads), 0, st, xout, g.ndof, gate);
-  sgs_step();
+  if (g.dim != 2) hipLaunchKernelGGL(k_gm_zero, vgrid, dim3(kThreads), 0, st, xout, g.ndof, gate);
+  sgs_step(true);
   launch_apply_K(h, rho, xout, h.q, nsys, -1, gate, st);
   hipLaunchKernelGGL(k_gm_resid, vgrid, dim3(kThreads), 0, st, rin, h.q, h.fixed, h.z, g.ndof,
                      gate);
@@ -865,7 +869,7 @@ void launch_msfem_cycle(Handle& h, const double* rho, const double* rin, double*
     else TPCG_PROLONG(3, double, kMaxK);
   }
 #undef TPCG_PROLONG
-  sgs_step();
+  sgs_step(false);
 }
 
 int gmres_solve(Handle& h, const double* rho, const double* f, double* u, int nsys, double rtol,
