@@ -121,6 +121,30 @@ def test_gmres_matches_oracle(name, pc):
     assert abs(info["true_relres"] - tr) <= 1e-3 * tr + 1e-15
 
 
+def test_gmres_longest_cycle():
+    """One full cycle of the longest restart (64 steps: 64 basis vectors in
+    the Gram-Schmidt passes and 63 earlier rotations in the last column),
+    stopped by maxit before its tolerance, against the oracle's GMRES with
+    the same restart and step count on the GPU basis."""
+    p = case("c1")
+    h, rb = built(p)
+    fixed, f = W.fixed_mask(p), W.load_vector(p)
+    Phi = gpu_basis(h, p)
+    K = fem.assemble(p, fem.simp_modulus(rb[0], p.E0, p.Emin, p.penal))
+    Kc = fem.constrained(K, fixed)
+    M = schwarz.TwoLevelSchwarz(p, K, fixed, Phi)
+    fp = np.where(fixed == 0, f, 0.0)
+    x_o, it_o, rr_o, _ = msfem.gmres(lambda v: Kc @ v, M.apply, fp, rtol=1e-14, restart=64,
+                                     maxit=64)
+    assert it_o == 64 and rr_o > 1e-14   # the case runs the whole cycle
+    u = dev(np.zeros((1, p.n_dof)))
+    info = h.gmres_solve(dev(rb), dev(f[None, :]), u, rtol=1e-14, maxit=64, restart=64,
+                         precond=T.PC_ADDITIVE)[0]
+    assert info["status"] == 1 and info["iters"] == 64, info
+    assert info["relres"] < 1e-9, info
+    assert rel(host(u)[0], x_o) < 1e-7
+
+
 def test_gmres_restarts_three_realisations_and_batch_invariance():
     p = case("prod")
     rho = W.design_field(p)
